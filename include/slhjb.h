@@ -1,0 +1,151 @@
+/*
+ * slhjb — semi-Lagrangian solver for second order HJB equations on MI355X (gfx950).
+ *
+ * The method is the semi-Lagrangian Markov-chain scheme of Cacace & Falcone, "A dynamic
+ * domain decomposition for a class of second order semi-linear equations" (arXiv
+ * 1502.01629), Section 3, eqs. SLscheme2 and SLscheme3, in a discounted (Kruzkov) form:
+ *
+ *   feet    y = x_i + h f(x_i,a) + s sqrt(h) sigma_k(x_i,a),   s = +-1, k = 1..d,  f = c(x) a
+ *   SL2     v_i = min_a [ beta (1/2d) sum_{k,s} I[v](y) + rho ]
+ *   SL3     v_i = min_a (beta Lambda1(a) + rho) / (1 - beta Lambda0(a))
+ *
+ * with beta = exp(-lambda h) rounded to float, rho = (1 - beta) l / lambda, I[.] the
+ * bilinear reconstruction on the grid (v_out outside the closed box), Lambda0 the node's own
+ * interpolation weight averaged over the feet and Lambda1 the rest (eq. SLimplicit).
+ *
+ * Conventions for every entry point:
+ *  - Grids are n x n nodes on [x_lo, x_hi]^2, node (i,j) at (x_lo + i dx, x_lo + j dx),
+ *    dx = (x_hi - x_lo)/(n-1), stored row-major at j*n + i (x1 fastest).
+ *  - Arrays named "device" are HIP device pointers owned by the caller; the library never
+ *    frees or keeps them beyond the call (except where a call says otherwise). Arrays named
+ *    "host" are read during the call only.
+ *  - All work is enqueued on the context's stream. Calls that return host results
+ *    synchronise that stream once before returning.
+ *  - Every argument is validated before anything is launched; on error nothing is
+ *    launched and the function returns SLHJB_E_INVALID_ARG (or another negative status).
+ *    No C++ exception ever crosses this interface.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef SLHJB_H
+#define SLHJB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------------------- */
+enum {
+    SLHJB_OK = 0,
+    SLHJB_NOT_CONVERGED = 1,   /* soft: the result is a valid iterate, tolerance not met   */
+    SLHJB_E_INVALID_ARG = -1,
+    SLHJB_E_UNSUPPORTED = -2,
+    SLHJB_E_HIP = -3,          /* a HIP runtime call failed; see slhjb_last_hip_error      */
+    SLHJB_E_NOMEM = -4,
+    SLHJB_E_NONFINITE = -5     /* a NaN or infinity appeared in the iterate                */
+};
+
+/* Static description of a status code. Never NULL. */
+const char* slhjb_status_string(int status);
+/* Interface version (increments on any change of a declaration in this header). */
+int slhjb_version(void);
+
+/* ---- context ------------------------------------------------------------------------ */
+typedef struct slhjb_ctx slhjb_ctx;
+
+/* Create a context on HIP device `hip_device` that enqueues on `hip_stream` (a hipStream_t,
+ * NULL = the device's null stream). The context owns its scratch memory (iterate buffers,
+ * residual slots, control tables) and frees it in slhjb_ctx_destroy. */
+int slhjb_ctx_create(slhjb_ctx** out, int hip_device, void* hip_stream);
+int slhjb_ctx_destroy(slhjb_ctx* ctx);
+/* Raw hipError_t behind the last SLHJB_E_HIP returned on this context (0 if none). */
+int slhjb_last_hip_error(const slhjb_ctx* ctx);
+/* Human-readable detail of the last error on this context ("" if none). Never NULL. */
+const char* slhjb_last_error_message(const slhjb_ctx* ctx);
+
+/* ---- problem -------------------------------------------------------------------------- */
+enum { SLHJB_DIFF_NONE = 0,   /* sigma = 0: one foot per control (Section 4.3)                  */
+       SLHJB_DIFF_ISO = 1,    /* sigma = sqrt(2 eps) I: 4 feet x + h f +- sqrt(2 eps h) e_k (4.1) */
+       SLHJB_DIFF_RANK1 = 2   /* sigma = sqrt(2 eps) a: 2 feet x + h f +- sqrt(2 eps h) a (5.3)  */ };
+enum { SLHJB_SCHEME_SL2 = 0,  /* eq. SLscheme2                                                  */
+       SLHJB_SCHEME_SL3 = 1   /* eq. SLscheme3: the node's dependence on itself removed          */ };
+enum { SLHJB_FREE = 0, SLHJB_TARGET = 1, SLHJB_OBSTACLE = 2 };
+
+/* The discrete problem (Section 3: domain, dynamics, diffusion, cost, control set, h, dx;
+ * plus the discount lambda of the Kruzkov form). */
+typedef struct {
+    int32_t n;                  /* nodes per side, 3 <= n <= 32769                             */
+    float x_lo, x_hi;           /* the box [x_lo, x_hi]^2, x_lo < x_hi                           */
+    float h;                    /* time step, > 0                                                */
+    float lambda;               /* discount rate, > 0 (1 = Kruzkov minimum time)                 */
+    float eps;                  /* diffusion coefficient, >= 0 (ignored for SLHJB_DIFF_NONE)     */
+    int32_t diffusion;          /* SLHJB_DIFF_*                                                  */
+    int32_t scheme;             /* SLHJB_SCHEME_*                                                */
+    int32_t n_controls;         /* 1 <= N_A <= 256                                               */
+    const float* controls;      /* host float[2*N_A]: a_m = (controls[2m], controls[2m+1])       */
+    const float* speed;         /* device float[n*n], c(x_i) > 0 finite; NULL = speed_const      */
+    float speed_const;          /* c when speed == NULL, > 0                                     */
+    float running_cost;         /* l > 0 (constant)                                              */
+    const uint8_t* node_class;  /* device uint8[n*n] of SLHJB_FREE / _TARGET / _OBSTACLE         */
+    float target_value;         /* g on TARGET nodes                                             */
+    float v_out;                /* value at feet outside the closed box and on OBSTACLE nodes    */
+} slhjb_problem;
+
+typedef struct {
+    int64_t sweeps;             /* sweeps performed                                              */
+    int64_t converged_sweep;    /* first sweep whose residual was <= tol (-1 if none)            */
+    int64_t node_updates;       /* FREE-node Bellman updates performed                           */
+    double residual;            /* sup-norm change of the last sweep                              */
+    double seconds;             /* device time of the whole call (HIP events on the ctx stream)   */
+    double sweep_seconds;       /* device time spent in the batches of sweep kernels              */
+    int64_t sweep_launches;     /* sweep kernel launches inside sweep_seconds                     */
+    int32_t status;             /* SLHJB_OK / SLHJB_NOT_CONVERGED / error                         */
+    int32_t kernel_path;        /* 0 general halo-tile kernel, 1 first-ring register kernel       */
+    int32_t halo;               /* interpolation halo of the LDS tile, in cells                   */
+    int32_t pad;
+} slhjb_stats;
+
+/* One Jacobi sweep of the scheme (eq. SLscheme2 or SLscheme3 per problem->scheme):
+ * v_out = T(v_in) on FREE nodes; TARGET nodes get target_value, OBSTACLE nodes v_out.
+ * v_in, v_out: device float[n*n], distinct. residual_host (nullable): receives
+ * max over FREE nodes of |v_out - v_in|. Synchronises the stream. */
+int slhjb_sweep(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_in, float* v_out,
+                double* residual_host);
+
+/* Jacobi value iteration from the guess in v (device float[n*n], overwritten with the result)
+ * until the sup-norm change of a sweep is <= tol, or max_sweeps. The residual is read back
+ * every `check_every` sweeps (1..256, 0 = automatic), so up to check_every-1 sweeps may run
+ * past the converged one; stats->converged_sweep reports the first converged sweep.
+ * Returns SLHJB_OK, SLHJB_NOT_CONVERGED (v holds the last iterate) or an error.
+ * stats (nullable) is filled in every case where the call got past validation. */
+int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
+                int32_t check_every, slhjb_stats* stats);
+
+/* ---- parameter theory (host only, no GPU needed) --------------------------------------- */
+/* The upwind diffusion ball analysis of Section 4.1 for dynamics bounded by f_min <= |f| <= f_max
+ * and diffusion rows of length at most sigma_inf (eq. upper-bound, lower-bound, upper-alpha,
+ * lower-alpha, hyperbolicity). */
+typedef struct {
+    double omega;               /* f_min / sigma_inf^2 (= f_min / 2 eps for sigma = sqrt(2 eps) I) */
+    double upsilon;             /* f_max / f_min                                                 */
+    double alpha_lower;         /* 1 / (omega dx)                       (eq. lower-alpha)         */
+    double alpha_upper;         /* 1/Upsilon - (sqrt(1+4 omega dx Upsilon)-1)/(2 omega dx Upsilon^2) */
+    double alpha_opt;           /* 1 / (1 + Upsilon)                                              */
+    double tau_dx;              /* dx / (1 + Upsilon): the threshold on 1/omega                   */
+    double h_alpha;             /* alpha_opt dx / f_min                                           */
+    double h_upper;             /* the largest h with h f_max + sqrt(h) sigma_inf <= dx           */
+    int32_t hyperbolic;         /* 1 if 1/omega < dx/(1+Upsilon)        (eq. hyperbolicity)       */
+    int32_t pad;
+} slhjb_regime;
+
+int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx, slhjb_regime* out);
+
+/* Largest distance, in cells along either axis, between a FREE node and any of its feet, for
+ * speeds bounded by speed_max (host computation). Used to size the interpolation halo. */
+double slhjb_foot_reach(const slhjb_problem* problem, float speed_max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLHJB_H */

@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libslhjb (include/slhjb.h): argument marshalling only.
+
+Device arrays are torch tensors on the context's device; every step of the method runs in
+the library's HIP kernels. The library is built in-tree by ``paper_1502_01629_amd.build``;
+if it is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslhjb.so")
+
+OK, NOT_CONVERGED, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NOMEM, E_NONFINITE = 0, 1, -1, -2, -3, -4, -5
+DIFF_NONE, DIFF_ISO, DIFF_RANK1 = 0, 1, 2
+SL2, SL3 = 0, 1
+FREE, TARGET, OBSTACLE = 0, 1, 2
+
+
+class SlhjbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"slhjb status {status}: {message}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("x_lo", ctypes.c_float),
+        ("x_hi", ctypes.c_float),
+        ("h", ctypes.c_float),
+        ("lam", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("diffusion", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("n_controls", ctypes.c_int32),
+        ("controls", ctypes.c_void_p),
+        ("speed", ctypes.c_void_p),
+        ("speed_const", ctypes.c_float),
+        ("running_cost", ctypes.c_float),
+        ("node_class", ctypes.c_void_p),
+        ("target_value", ctypes.c_float),
+        ("v_out", ctypes.c_float),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int64),
+        ("converged_sweep", ctypes.c_int64),
+        ("node_updates", ctypes.c_int64),
+        ("residual", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("sweep_seconds", ctypes.c_double),
+        ("sweep_launches", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("kernel_path", ctypes.c_int32),
+        ("halo", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Regime(ctypes.Structure):
+    _fields_ = [
+        ("omega", ctypes.c_double),
+        ("upsilon", ctypes.c_double),
+        ("alpha_lower", ctypes.c_double),
+        ("alpha_upper", ctypes.c_double),
+        ("alpha_opt", ctypes.c_double),
+        ("tau_dx", ctypes.c_double),
+        ("h_alpha", ctypes.c_double),
+        ("h_upper", ctypes.c_double),
+        ("hyperbolic", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+# name -> (restype, argtypes); every symbol include/slhjb.h declares
+_vp, _i32, _i64, _f64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+_PP = ctypes.POINTER(Problem)
+SIGNATURES = {
+    "slhjb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "slhjb_version": (ctypes.c_int, []),
+    "slhjb_ctx_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "slhjb_ctx_destroy": (ctypes.c_int, [_vp]),
+    "slhjb_last_hip_error": (ctypes.c_int, [_vp]),
+    "slhjb_last_error_message": (ctypes.c_char_p, [_vp]),
+    "slhjb_sweep": (ctypes.c_int, [_vp, _PP, _vp, _vp, ctypes.POINTER(_f64)]),
+    "slhjb_solve": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
+    "slhjb_regime_analyze": (ctypes.c_int, [_f64, _f64, _f64, _f64, ctypes.POINTER(Regime)]),
+    "slhjb_foot_reach": (_f64, [_PP, _f32]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1502_01629_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().slhjb_status_string(status).decode()
+
+
+def regime(f_min: float, f_max: float, sigma_inf: float, dx: float) -> dict:
+    out = Regime()
+    st = lib().slhjb_regime_analyze(f_min, f_max, sigma_inf, dx, ctypes.byref(out))
+    if st != OK:
+        raise SlhjbError(st, "invalid regime arguments")
+    return out.as_dict()
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class DeviceProblem:
+    """Device-resident arrays of a problem instance plus the ctypes struct pointing at them."""
+
+    def __init__(self, inst, scheme: int = SL3, device="cuda"):
+        import torch
+
+        self.inst = inst
+        self.controls = np.ascontiguousarray(inst.controls, dtype=np.float32).reshape(-1)
+        self.speed = torch.from_numpy(np.ascontiguousarray(inst.speed, dtype=np.float32).reshape(-1)).to(device)
+        self.node_class = torch.from_numpy(np.ascontiguousarray(inst.node_class, dtype=np.uint8).reshape(-1)).to(device)
+        self.scheme = scheme
+        self.struct = self._make()
+
+    def _make(self) -> Problem:
+        inst = self.inst
+        return Problem(
+            n=inst.n, x_lo=float(inst.x_lo), x_hi=float(inst.x_hi), h=float(inst.h), lam=float(inst.lam),
+            eps=float(inst.eps), diffusion=int(inst.diffusion), scheme=int(self.scheme),
+            n_controls=int(self.controls.size // 2), controls=self.controls.ctypes.data, speed=_ptr(self.speed),
+            speed_const=1.0, running_cost=float(inst.running_cost), node_class=_ptr(self.node_class),
+            target_value=float(inst.target_value), v_out=float(inst.v_out))
+
+    def with_scheme(self, scheme: int) -> "DeviceProblem":
+        self.scheme = scheme
+        self.struct = self._make()
+        return self
+
+
+class Context:
+    """A library context bound to a device and a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = lib().slhjb_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise SlhjbError(st, "slhjb_ctx_create failed")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().slhjb_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, allow=(OK,)) -> int:
+        if st not in allow:
+            msg = lib().slhjb_last_error_message(self.handle).decode()
+            raise SlhjbError(st, msg or status_string(st))
+        return st
+
+    def sweep(self, prob: DeviceProblem, v_in, v_out) -> float:
+        r = ctypes.c_double()
+        self._check(lib().slhjb_sweep(self.handle, ctypes.byref(prob.struct), _ptr(v_in), _ptr(v_out), ctypes.byref(r)))
+        return r.value
+
+    def solve(self, prob: DeviceProblem, v, tol: float = 1e-6, max_sweeps: int = 1_000_000, check_every: int = 0):
+        stats = Stats()
+        st = lib().slhjb_solve(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_sweeps, check_every,
+                               ctypes.byref(stats))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return stats.as_dict()

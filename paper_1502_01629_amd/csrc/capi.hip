@@ -1,0 +1,439 @@
+// C-ABI of libslhjb: argument validation, context and scratch management, the Jacobi
+// value-iteration driver, and the host-side parameter theory of Section 4.1.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/slhjb.h"
+#include "internal.h"
+
+using namespace slhjb;
+
+struct slhjb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int last_hip = 0;
+  std::string last_msg;
+  // scratch
+  float* buf = nullptr;          // second iterate buffer
+  size_t buf_elems = 0;
+  float* vbuf[2] = {nullptr, nullptr};  // single-sweep staging buffers
+  size_t vbuf_elems = 0;
+  unsigned* small = nullptr;     // [0] residual bits, [1] flags, [2..4] speed stats
+  unsigned* small_host = nullptr;  // pinned mirror
+  float4* ctrl = nullptr;
+  int ctrl_cap = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
+};
+
+namespace {
+
+constexpr int kSmallWords = 16;
+
+int fail(slhjb_ctx* ctx, int status, const std::string& msg) {
+  if (ctx) ctx->last_msg = msg;
+  return status;
+}
+
+int hip_fail(slhjb_ctx* ctx, hipError_t e, const char* what) {
+  if (ctx) {
+    ctx->last_hip = (int)e;
+    ctx->last_msg = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return SLHJB_E_HIP;
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
+  } while (0)
+
+// Everything a sweep launch needs, derived once per call from a validated problem.
+struct Prepared {
+  SweepArgs args{};
+  int diffusion = 0, scheme = 0, path = 0;
+  float vstar = 1.0f;
+  double reach = 0.0;
+  int64_t free_nodes = 0;
+};
+
+int validate(slhjb_ctx* ctx, const slhjb_problem* p) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!p) return fail(ctx, SLHJB_E_INVALID_ARG, "problem is NULL");
+  if (p->n < 3 || p->n > 32769) return fail(ctx, SLHJB_E_INVALID_ARG, "n must be in [3, 32769]");
+  if (!(isfinite(p->x_lo) && isfinite(p->x_hi) && p->x_lo < p->x_hi))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "need finite x_lo < x_hi");
+  if (!(p->h > 0.0f) || !isfinite(p->h)) return fail(ctx, SLHJB_E_INVALID_ARG, "h must be finite and > 0");
+  if (!(p->lambda > 0.0f) || !isfinite(p->lambda))
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "only the discounted form (lambda > 0) is implemented");
+  if (!(p->eps >= 0.0f) || !isfinite(p->eps)) return fail(ctx, SLHJB_E_INVALID_ARG, "eps must be finite and >= 0");
+  if (p->diffusion < 0 || p->diffusion > 2) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown diffusion kind");
+  if (p->scheme < 0 || p->scheme > 1) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown scheme");
+  if (p->n_controls < 1 || p->n_controls > 256) return fail(ctx, SLHJB_E_INVALID_ARG, "n_controls must be in [1, 256]");
+  if (!p->controls) return fail(ctx, SLHJB_E_INVALID_ARG, "controls is NULL");
+  for (int m = 0; m < 2 * p->n_controls; ++m)
+    if (!isfinite(p->controls[m])) return fail(ctx, SLHJB_E_INVALID_ARG, "non-finite control");
+  if (!p->speed && (!(p->speed_const > 0.0f) || !isfinite(p->speed_const)))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "speed_const must be finite and > 0");
+  if (!(p->running_cost > 0.0f) || !isfinite(p->running_cost))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "running_cost must be finite and > 0");
+  if (!p->node_class) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class is NULL");
+  if (!isfinite(p->target_value) || !isfinite(p->v_out))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "target_value and v_out must be finite");
+  return SLHJB_OK;
+}
+
+double grid_dx(const slhjb_problem* p) { return ((double)p->x_hi - (double)p->x_lo) / (double)(p->n - 1); }
+
+double reach_for(const slhjb_problem* p, double speed_max) {
+  // distance in cells along either axis between a node and its farthest foot
+  const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
+  const double r = (double)(p->h / dx32);
+  const double k = r * speed_max;
+  double amax = 0.0;
+  for (int m = 0; m < 2 * p->n_controls; ++m) amax = std::max(amax, fabs((double)p->controls[m]));
+  const double d = p->diffusion == SLHJB_DIFF_NONE ? 0.0 : sqrt(2.0 * (double)p->eps * (double)p->h) / grid_dx(p);
+  if (p->diffusion == SLHJB_DIFF_RANK1) return (k + d) * amax;
+  return k * amax + d;
+}
+
+int ensure_small(slhjb_ctx* ctx) {
+  if (!ctx->small) {
+    HIP_TRY(ctx, hipMalloc(&ctx->small, sizeof(unsigned) * kSmallWords));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->small_host, sizeof(unsigned) * kSmallWords, hipHostMallocDefault));
+  }
+  return SLHJB_OK;
+}
+
+int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
+  int st = validate(ctx, p);
+  if (st != SLHJB_OK) return st;
+  st = ensure_small(ctx);
+  if (st != SLHJB_OK) return st;
+  const int n = p->n;
+  const int64_t N = (int64_t)n * n;
+  // speed bounds, FREE count and class validity (one device pass, one read-back)
+  HIP_TRY(ctx, launch_fill_u32(ctx->small + 2, 0x7f7fffffu, 1, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32(ctx->small + 3, 0u, 4, ctx->stream));
+  HIP_TRY(ctx, launch_problem_stats(p->speed, p->node_class, N, ctx->small + 2, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 2, ctx->small + 2, sizeof(unsigned) * 5, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->small_host[4]) return fail(ctx, SLHJB_E_INVALID_ARG, "speed has a non-finite or non-positive value");
+  if (ctx->small_host[6]) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class has a value other than 0, 1, 2");
+  double speed_max = p->speed_const;
+  if (p->speed) {
+    float hi;
+    memcpy(&hi, &ctx->small_host[3], sizeof(float));
+    speed_max = hi;
+  }
+  const int64_t free_nodes = ctx->small_host[5];
+  const double reach = reach_for(p, speed_max);
+  Prepared P;
+  P.diffusion = p->eps > 0.0f ? p->diffusion : SLHJB_DIFF_NONE;
+  P.scheme = p->scheme;
+  P.reach = reach;
+  P.free_nodes = free_nodes;
+  if (P.diffusion == SLHJB_DIFF_NONE && reach <= 1.0 + 1e-6) {
+    P.path = 1;
+  } else {
+    P.path = 0;
+  }
+  const int halo = P.path == 1 ? 2 : (int)floor(reach * (1.0 + 1e-6) + 1e-6) + 1;
+  if (halo > kMaxHalo)
+    return fail(ctx, SLHJB_E_UNSUPPORTED,
+                "feet reach more than " + std::to_string(kMaxHalo - 1) + " cells; reduce h or eps");
+  // control table, grouped by quadrant for the first-ring kernel
+  std::vector<int> order(p->n_controls);
+  for (int m = 0; m < p->n_controls; ++m) order[m] = m;
+  int quad[5] = {0, 0, 0, 0, 0};
+  if (P.path == 1) {
+    auto qof = [&](int m) {
+      const float ax = p->controls[2 * m], ay = p->controls[2 * m + 1];
+      if (ay >= 0.0f) return ax >= 0.0f ? 0 : 1;
+      return ax < 0.0f ? 2 : 3;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return qof(a) < qof(b); });
+    int q = 0;
+    for (int t = 0; t < p->n_controls; ++t)
+      while (q < qof(order[t])) quad[++q] = t;
+    while (q < 4) quad[++q] = p->n_controls;
+  } else {
+    quad[4] = p->n_controls;
+  }
+  if (ctx->ctrl_cap < p->n_controls) {
+    if (ctx->ctrl) hipFree(ctx->ctrl);
+    ctx->ctrl = nullptr;
+    ctx->ctrl_cap = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->ctrl, sizeof(float4) * 256));
+    ctx->ctrl_cap = 256;
+  }
+  std::vector<float4> tab(p->n_controls);
+  for (int t = 0; t < p->n_controls; ++t) {
+    const float ax = p->controls[2 * order[t]], ay = p->controls[2 * order[t] + 1];
+    tab[t] = make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice, ctx->stream));
+  // The copy reads `tab` asynchronously from pageable memory; make it complete before `tab` dies.
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+
+  const double dx = grid_dx(p);
+  // h/dx in float arithmetic, exactly as the foot displacements of the labeler are defined
+  const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
+  const float vstar = (float)((double)p->running_cost / (double)p->lambda);
+  SweepArgs& a = P.args;
+  a.speed = p->speed;
+  a.cls = p->node_class;
+  a.ctrl = ctx->ctrl;
+  a.resid = nullptr;
+  a.flags = ctx->small + 1;
+  a.n = n;
+  a.n_controls = p->n_controls;
+  a.halo = halo;
+  for (int q = 0; q < 5; ++q) a.quad[q] = quad[q];
+  a.r = p->h / dx32;
+  a.speed_const = p->speed_const;
+  a.d = P.diffusion == SLHJB_DIFF_NONE ? 0.0f : (float)(sqrt(2.0 * (double)p->eps * (double)p->h) / dx);
+  a.beta = (float)exp(-(double)p->lambda * (double)p->h);
+  a.w_outside = vstar - p->v_out;
+  a.w_target = vstar - p->target_value;
+  a.w_obstacle = vstar - p->v_out;
+  P.vstar = vstar;
+  *out = P;
+  return SLHJB_OK;
+}
+
+int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
+  if (*cap >= elems) return SLHJB_OK;
+  if (*b) hipFree(*b);
+  *b = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc(b, sizeof(float) * elems);
+  if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, "scratch allocation failed");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
+  *cap = elems;
+  return SLHJB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* slhjb_status_string(int status) {
+  switch (status) {
+  case SLHJB_OK: return "ok";
+  case SLHJB_NOT_CONVERGED: return "not converged (valid iterate returned)";
+  case SLHJB_E_INVALID_ARG: return "invalid argument";
+  case SLHJB_E_UNSUPPORTED: return "unsupported configuration";
+  case SLHJB_E_HIP: return "HIP runtime error";
+  case SLHJB_E_NOMEM: return "out of device memory";
+  case SLHJB_E_NONFINITE: return "non-finite value in the iterate";
+  default: return "unknown status";
+  }
+}
+
+int slhjb_version(void) { return 1; }
+
+int slhjb_ctx_create(slhjb_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return SLHJB_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return SLHJB_E_INVALID_ARG;
+  slhjb_ctx* ctx = new (std::nothrow) slhjb_ctx();
+  if (!ctx) return SLHJB_E_NOMEM;
+  ctx->device = hip_device;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(hip_device) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
+      hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->eva) != hipSuccess ||
+      hipEventCreate(&ctx->evb) != hipSuccess) {
+    slhjb_ctx_destroy(ctx);
+    return SLHJB_E_HIP;
+  }
+  *out = ctx;
+  return SLHJB_OK;
+}
+
+int slhjb_ctx_destroy(slhjb_ctx* ctx) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  else hipDeviceSynchronize();
+  if (ctx->buf) hipFree(ctx->buf);
+  for (auto* b : ctx->vbuf)
+    if (b) hipFree(b);
+  if (ctx->small) hipFree(ctx->small);
+  if (ctx->small_host) hipHostFree(ctx->small_host);
+  if (ctx->ctrl) hipFree(ctx->ctrl);
+  if (ctx->ev0) hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) hipEventDestroy(ctx->ev1);
+  if (ctx->eva) hipEventDestroy(ctx->eva);
+  if (ctx->evb) hipEventDestroy(ctx->evb);
+  delete ctx;
+  return SLHJB_OK;
+}
+
+int slhjb_last_hip_error(const slhjb_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+const char* slhjb_last_error_message(const slhjb_ctx* ctx) { return ctx ? ctx->last_msg.c_str() : ""; }
+
+int slhjb_sweep(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_in, float* v_out,
+                double* residual_host) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v_in || !v_out || v_in == v_out) return fail(ctx, SLHJB_E_INVALID_ARG, "v_in and v_out must be distinct non-NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  const int64_t N = (int64_t)problem->n * problem->n;
+  st = ensure_buf(ctx, &ctx->vbuf[0], &ctx->vbuf_elems, (size_t)N);
+  if (st != SLHJB_OK) return st;
+  if (!ctx->vbuf[1] || ctx->vbuf_elems < (size_t)N) {
+    if (ctx->vbuf[1]) hipFree(ctx->vbuf[1]);
+    ctx->vbuf[1] = nullptr;
+    hipError_t e = hipMalloc(&ctx->vbuf[1], sizeof(float) * ctx->vbuf_elems);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
+  }
+  HIP_TRY(ctx, launch_fill_u32(ctx->small, 0u, 2, ctx->stream));
+  HIP_TRY(ctx, launch_v_to_w(v_in, ctx->vbuf[0], problem->node_class, N, P.vstar, P.args.w_target,
+                             P.args.w_obstacle, ctx->stream));
+  SweepArgs a = P.args;
+  a.w_in = ctx->vbuf[0];
+  a.w_out = ctx->vbuf[1];
+  a.resid = ctx->small;
+  HIP_TRY(ctx, launch_sweep(a, P.diffusion, P.scheme, P.path, ctx->stream));
+  HIP_TRY(ctx, launch_w_to_v(ctx->vbuf[1], v_out, N, P.vstar, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->small_host[1] & 1u) return fail(ctx, SLHJB_E_NONFINITE, "sweep produced a non-finite value");
+  if (residual_host) {
+    float r;
+    memcpy(&r, &ctx->small_host[0], sizeof(float));
+    *residual_host = r;
+  }
+  return SLHJB_OK;
+}
+
+int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
+                int32_t check_every, slhjb_stats* stats) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v) return fail(ctx, SLHJB_E_INVALID_ARG, "v is NULL");
+  if (!(tol >= 0.0) || max_sweeps < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol >= 0 and max_sweeps >= 1");
+  if (check_every < 0 || check_every > 256) return fail(ctx, SLHJB_E_INVALID_ARG, "check_every must be in [0, 256]");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  const int64_t N = (int64_t)problem->n * problem->n;
+  st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)N);
+  if (st != SLHJB_OK) return st;
+  if (check_every == 0) check_every = N >= (1 << 20) ? 8 : 16;
+
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  // the caller's array holds w during the iteration
+  HIP_TRY(ctx, launch_v_to_w(v, v, problem->node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle, ctx->stream));
+  float* cur = v;
+  float* nxt = ctx->buf;
+  int64_t sweeps = 0, converged = -1;
+  double resid = INFINITY, sweep_sec = 0.0;
+  int status = SLHJB_NOT_CONVERGED;
+  while (sweeps < max_sweeps) {
+    const int64_t batch = std::min<int64_t>(check_every, max_sweeps - sweeps);
+    HIP_TRY(ctx, launch_fill_u32(ctx->small, 0u, 2, ctx->stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->eva, ctx->stream));
+    for (int64_t b = 0; b < batch; ++b) {
+      SweepArgs a = P.args;
+      a.w_in = cur;
+      a.w_out = nxt;
+      a.resid = b == batch - 1 ? ctx->small : nullptr;
+      HIP_TRY(ctx, launch_sweep(a, P.diffusion, P.scheme, P.path, ctx->stream));
+      std::swap(cur, nxt);
+    }
+    sweeps += batch;
+    HIP_TRY(ctx, hipEventRecord(ctx->evb, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    float bms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&bms, ctx->eva, ctx->evb));
+    sweep_sec += bms * 1e-3;
+    float r;
+    memcpy(&r, &ctx->small_host[0], sizeof(float));
+    resid = r;
+    if (ctx->small_host[1] & 1u) {
+      status = SLHJB_E_NONFINITE;
+      break;
+    }
+    if (resid <= tol) {
+      converged = sweeps;
+      status = SLHJB_OK;
+      break;
+    }
+  }
+  if (cur != v) HIP_TRY(ctx, hipMemcpyAsync(v, cur, sizeof(float) * N, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
+  float ms = 0.0f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->converged_sweep = converged;
+    stats->node_updates = sweeps * P.free_nodes;
+    stats->residual = resid;
+    stats->seconds = ms * 1e-3;
+    stats->sweep_seconds = sweep_sec;
+    stats->sweep_launches = sweeps;
+    stats->status = status;
+    stats->kernel_path = P.path;
+    stats->halo = P.args.halo;
+    stats->pad = 0;
+  }
+  if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
+  return status;
+}
+
+int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx, slhjb_regime* out) {
+  if (!out || !(f_min > 0.0) || !(f_max >= f_min) || !(sigma_inf >= 0.0) || !(dx > 0.0) || !isfinite(f_max) ||
+      !isfinite(sigma_inf) || !isfinite(dx))
+    return SLHJB_E_INVALID_ARG;
+  slhjb_regime r;
+  memset(&r, 0, sizeof(r));
+  r.upsilon = f_max / f_min;
+  r.alpha_opt = 1.0 / (1.0 + r.upsilon);
+  r.tau_dx = dx / (1.0 + r.upsilon);
+  if (sigma_inf > 0.0) {
+    r.omega = f_min / (sigma_inf * sigma_inf);
+    const double od = r.omega * dx;
+    r.alpha_lower = 1.0 / od;
+    r.alpha_upper = 1.0 / r.upsilon - (sqrt(1.0 + 4.0 * od * r.upsilon) - 1.0) / (2.0 * od * r.upsilon * r.upsilon);
+    r.hyperbolic = (1.0 / r.omega < r.tau_dx) ? 1 : 0;
+  } else {
+    r.omega = INFINITY;
+    r.alpha_lower = 0.0;
+    r.alpha_upper = 1.0 / r.upsilon;
+    r.hyperbolic = 1;
+  }
+  r.h_alpha = r.alpha_opt * dx / f_min;
+  // largest h with h f_max + sqrt(h) sigma_inf <= dx: a quadratic in sqrt(h)
+  const double b = sigma_inf;
+  const double sq = (-b + sqrt(b * b + 4.0 * f_max * dx)) / (2.0 * f_max);
+  r.h_upper = sq * sq;
+  *out = r;
+  return SLHJB_OK;
+}
+
+double slhjb_foot_reach(const slhjb_problem* problem, float speed_max) {
+  if (!problem || problem->n < 3 || !(problem->x_hi > problem->x_lo) || !problem->controls ||
+      problem->n_controls < 1 || !(speed_max > 0.0f))
+    return -1.0;
+  slhjb_problem p = *problem;
+  if (!(p.eps > 0.0f)) p.diffusion = SLHJB_DIFF_NONE;
+  return reach_for(&p, speed_max);
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code of libslhjb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slhjb {
+
+enum : int { kFree = 0, kTarget = 1, kObstacle = 2 };
+enum : int { kDiffNone = 0, kDiffIso = 1, kDiffRank1 = 2 };
+enum : int { kSL2 = 0, kSL3 = 1 };
+
+// Tile of the sweep kernels: one wavefront spans 64 consecutive nodes of a row, four
+// wavefronts per workgroup, each wavefront walks kTileH / 4 rows.
+constexpr int kTileW = 64;
+constexpr int kTileH = 16;
+constexpr int kThreads = 256;
+constexpr int kMaxHalo = 12;  // largest interpolation halo the general kernel accepts
+
+// Per-control constants, precomputed on the host: (a_x, a_y, a_x a_y, |a_x| + |a_y|).
+// The iterate is held as w = V* - v with V* = l / lambda, so that the update is the
+// homogeneous w_i = beta max_a mean_feet I[w](y) (SL2) or its self-weight-free quotient (SL3).
+struct SweepArgs {
+  const float* w_in;
+  float* w_out;
+  const float* speed;      // nullable: speed_const then
+  const uint8_t* cls;
+  const float4* ctrl;      // [n_controls]
+  unsigned* resid;         // nullable: float bits of max |w_out - w_in| over FREE nodes
+  unsigned* flags;         // bit 0: non-finite value produced
+  int n;
+  int n_controls;
+  int halo;                // interpolation halo radius of the LDS tile (cells)
+  int quad[5];             // first-ring kernel: controls [quad[q], quad[q+1]) lie in quadrant q
+  float r;                 // h / dx
+  float speed_const;
+  float d;                 // sqrt(2 eps h) / dx
+  float beta;
+  float w_outside;         // w at feet outside the closed box
+  float w_target;
+  float w_obstacle;
+};
+
+// Launchers (sweep.hip). `path` 0 = general halo tile, 1 = first-ring register stencil.
+hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path, hipStream_t s);
+hipError_t launch_v_to_w(const float* v, float* w, const uint8_t* cls, int64_t count, float vstar,
+                         float w_target, float w_obstacle, hipStream_t s);
+hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, hipStream_t s);
+hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t count, unsigned* out,
+                                hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, unsigned value, int count, hipStream_t s);
+
+}  // namespace slhjb

@@ -1,0 +1,406 @@
+// Jacobi sweep kernels of the semi-Lagrangian Markov-chain scheme (Cacace & Falcone,
+// Section 3, eqs. SLscheme2 / SLscheme3) for gfx950.
+//
+// The iterate is w = V* - v (V* = l / lambda), in which the discounted update is
+//   SL2:  w_i = beta * max_a (1/K) sum_feet I[w](y)
+//   SL3:  w_i = beta * max_a (sum_feet I[w](y) - L0 w_i) / (K - beta L0)
+// where L0 is the sum over the feet of node i's own bilinear weight (K Lambda0 of
+// eq. SLimplicit). Feet outside the closed box read w_outside and carry no self weight.
+//
+// Two kernels:
+//  * sweep_general: any diffusion, any foot reach up to kMaxHalo-1 cells. The workgroup
+//    stages its 64 x 16 node tile plus a halo in LDS and gathers the four cell corners of
+//    every foot from there.
+//  * sweep_ring1: sigma = 0 with every foot inside the first ring of cells (|h c a| <= dx
+//    per axis, the regime the paper prescribes by eq. upper-bound). The interpolant in each
+//    of the four cells around a node is a bilinear form A + B s + C t + D s t; with the
+//    node's 3x3 neighbourhood in registers and the controls grouped by quadrant, a control
+//    costs three FMAs (SL2) instead of a gather.
+#include "internal.h"
+
+namespace slhjb {
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ void block_reduce_and_publish(float local, bool bad, const SweepArgs& a) {
+  __shared__ float red[kThreads / 64];
+  __shared__ int anybad;
+  if (threadIdx.x == 0) anybad = 0;
+  __syncthreads();
+  if (a.resid) {
+    const float wm = wave_max(local);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
+  }
+  if (bad) anybad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (a.resid) {
+      float m = red[0];
+#pragma unroll
+      for (int k = 1; k < kThreads / 64; ++k) m = fmaxf(m, red[k]);
+      // residuals are >= 0, so the float order equals the unsigned order of the bits
+      atomicMax(a.resid, __float_as_uint(m));
+    }
+    if (anybad) atomicOr(a.flags, 1u);
+  }
+}
+
+// Stage the node tile [tx0 - halo, tx0 + kTileW + halo) x [ty0 - halo, ty0 + kTileH + halo)
+// in LDS; nodes outside the grid are stored as 0 and never carry weight.
+__device__ __forceinline__ void load_tile(float* tile, const SweepArgs& a, int tx0, int ty0, int LW, int LH) {
+  const int n = a.n;
+  const int total = LW * LH;
+  for (int t = threadIdx.x; t < total; t += kThreads) {
+    const int ly = t / LW;
+    const int lx = t - ly * LW;
+    const int gx = tx0 - a.halo + lx;
+    const int gy = ty0 - a.halo + ly;
+    float val = 0.0f;
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = a.w_in[(size_t)gy * n + gx];
+    tile[t] = val;
+  }
+}
+
+template <int DIFF>
+struct Feet;
+template <>
+struct Feet<kDiffNone> {
+  static constexpr int K = 1;
+  __device__ static __forceinline__ void get(int, float bx, float by, float, float, float, float& fx, float& fy) {
+    fx = bx;
+    fy = by;
+  }
+};
+template <>
+struct Feet<kDiffIso> {
+  static constexpr int K = 4;
+  __device__ static __forceinline__ void get(int f, float bx, float by, float, float, float d, float& fx, float& fy) {
+    fx = bx + (f == 0 ? d : (f == 1 ? -d : 0.0f));
+    fy = by + (f == 2 ? d : (f == 3 ? -d : 0.0f));
+  }
+};
+template <>
+struct Feet<kDiffRank1> {
+  static constexpr int K = 2;
+  __device__ static __forceinline__ void get(int f, float bx, float by, float ax, float ay, float d, float& fx,
+                                             float& fy) {
+    const float s = f == 0 ? d : -d;
+    fx = __builtin_fmaf(s, ax, bx);
+    fy = __builtin_fmaf(s, ay, by);
+  }
+};
+
+// Bellman update of one FREE node from the LDS tile (general kernel). Feet are handled as
+// offsets from the node in cell units, so positions keep full precision on large grids.
+// `node_li` is the node's index in the tile.
+template <int DIFF, int SCHEME>
+__device__ __forceinline__ float general_update(const float* __restrict__ tile, int LW, int node_li, int i, int j,
+                                                float k, float wself, const SweepArgs& a) {
+  using F = Feet<DIFF>;
+  const float fi = (float)i, fj = (float)j;
+  const float nm1 = (float)(a.n - 1);
+  const float nm2 = (float)(a.n - 2);
+  // offsets that stay inside the closed box, and the largest cell offset (cell n-2)
+  const float lox = -fi, hix = nm1 - fi, loy = -fj, hiy = nm1 - fj;
+  const float cmx = nm2 - fi, cmy = nm2 - fj;
+  const float LWf = (float)LW;
+  float best2 = 0.0f;                 // SL2: max over controls of the feet sum
+  float bnum = -1.0f, bden = 1.0f;    // SL3: best quotient num / den
+  for (int m = 0; m < a.n_controls; ++m) {
+    const float4 cm = a.ctrl[m];
+    const float bx = k * cm.x;
+    const float by = k * cm.y;
+    float acc = 0.0f, lam0 = 0.0f;
+#pragma unroll
+    for (int f = 0; f < F::K; ++f) {
+      float ox, oy;
+      F::get(f, bx, by, cm.x, cm.y, a.d, ox, oy);
+      const bool inside = (ox >= lox) & (ox <= hix) & (oy >= loy) & (oy <= hiy);
+      const float cx = fminf(fmaxf(ox, lox), hix);
+      const float cy = fminf(fmaxf(oy, loy), hiy);
+      const float flx = fminf(floorf(cx), cmx);
+      const float fly = fminf(floorf(cy), cmy);
+      const float s = cx - flx;
+      const float t = cy - fly;
+      const int li = node_li + (int)__builtin_fmaf(fly, LWf, flx);
+      const float v00 = tile[li], v10 = tile[li + 1];
+      const float v01 = tile[li + LW], v11 = tile[li + LW + 1];
+      const float lo = __builtin_fmaf(s, v10 - v00, v00);
+      const float hi = __builtin_fmaf(s, v11 - v01, v01);
+      const float val = __builtin_fmaf(t, hi - lo, lo);
+      acc += inside ? val : a.w_outside;
+      if (SCHEME == kSL3) {
+        const float hx = fmaxf(0.0f, 1.0f - fabsf(cx));
+        const float hy = fmaxf(0.0f, 1.0f - fabsf(cy));
+        lam0 += inside ? hx * hy : 0.0f;
+      }
+    }
+    if (SCHEME == kSL2) {
+      best2 = fmaxf(best2, acc);
+    } else {
+      const float num = __builtin_fmaf(-lam0, wself, acc);
+      const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
+      if (num * bden > bnum * den) {
+        bnum = num;
+        bden = den;
+      }
+    }
+  }
+  if (SCHEME == kSL2) return a.beta * best2 * (1.0f / (float)F::K);
+  return a.beta * bnum / bden;
+}
+
+template <int DIFF, int SCHEME>
+__global__ __launch_bounds__(kThreads) void sweep_general(SweepArgs a) {
+  extern __shared__ float tile[];
+  const int tx0 = blockIdx.x * kTileW;
+  const int ty0 = blockIdx.y * kTileH;
+  const int LW = kTileW + 2 * a.halo;
+  const int LH = kTileH + 2 * a.halo;
+  load_tile(tile, a, tx0, ty0, LW, LH);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int i = tx0 + lane;
+  const int n = a.n;
+  float local = 0.0f;
+  bool bad = false;
+  for (int row = wave; row < kTileH; row += kThreads / 64) {
+    const int j = ty0 + row;
+    if (i < n && j < n) {
+      const size_t idx = (size_t)j * n + i;
+      const int c = a.cls[idx];
+      float wn;
+      if (c == kFree) {
+        const float k = a.r * (a.speed ? a.speed[idx] : a.speed_const);
+        const int node_li = (row + a.halo) * LW + lane + a.halo;
+        const float wself = tile[node_li];
+        wn = general_update<DIFF, SCHEME>(tile, LW, node_li, i, j, k, wself, a);
+        local = fmaxf(local, fabsf(wn - wself));
+        bad |= !isfinite(wn);
+      } else {
+        wn = c == kTarget ? a.w_target : a.w_obstacle;
+      }
+      a.w_out[idx] = wn;
+    }
+  }
+  block_reduce_and_publish(local, bad, a);
+}
+
+// First-ring update of one node. T points at the node in the LDS tile. EDGE adds the test for
+// feet that leave the box, which only happens on the outermost nodes.
+template <int SCHEME, bool EDGE>
+__device__ __forceinline__ float ring1_update(const float* __restrict__ T, int LW, float k, const SweepArgs& a,
+                                              bool lft, bool rgt, bool bot, bool top) {
+  const float w00 = T[0];
+  const float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
+  const float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
+  const float k2 = k * k;
+  // quadrant order: (+x,+y), (-x,+y), (-x,-y), (+x,-y)
+  const float wX[4] = {wE, wW, wW, wE};
+  const float wY[4] = {wN, wN, wS, wS};
+  const float wXY[4] = {wNE, wNW, wSW, wSE};
+  const float sx[4] = {1.0f, -1.0f, -1.0f, 1.0f};
+  const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
+  float best2 = -INFINITY;
+  float bnum = -1.0f, bden = 1.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float B, C, D;
+    if (SCHEME == kSL2) {
+      // I = w00 + a_x B + a_y C + a_x a_y D over the quadrant's cell
+      B = k * sx[q] * (wX[q] - w00);
+      C = k * sy[q] * (wY[q] - w00);
+      D = k2 * (sx[q] * sy[q]) * ((wXY[q] - wX[q]) - (wY[q] - w00));
+    } else {
+      // I - (1-s)(1-t) w00 = a_x B + a_y C + a_x a_y D  (self weight removed)
+      B = k * sx[q] * wX[q];
+      C = k * sy[q] * wY[q];
+      D = k2 * (sx[q] * sy[q]) * (wXY[q] - wX[q] - wY[q]);
+    }
+    for (int m = a.quad[q]; m < a.quad[q + 1]; ++m) {
+      const float4 cm = a.ctrl[m];
+      float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
+      if (SCHEME == kSL2) {
+        if (EDGE) {
+          const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+          val = out ? a.w_outside - w00 : val;
+        }
+        best2 = fmaxf(best2, val);
+      } else {
+        // own weight (1 - k|a_x|)(1 - k|a_y|) = 1 - k(|a_x|+|a_y|) + k^2 |a_x a_y|
+        float lam0 = __builtin_fmaf(k2, fabsf(cm.z), __builtin_fmaf(-k, cm.w, 1.0f));
+        if (EDGE) {
+          const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+          val = out ? a.w_outside : val;
+          lam0 = out ? 0.0f : lam0;
+        }
+        const float den = __builtin_fmaf(-a.beta, lam0, 1.0f);
+        if (val * bden > bnum * den) {
+          bnum = val;
+          bden = den;
+        }
+      }
+    }
+  }
+  if (SCHEME == kSL2) return a.beta * (w00 + best2);
+  return a.beta * bnum / bden;
+}
+
+template <int SCHEME>
+__global__ __launch_bounds__(kThreads) void sweep_ring1(SweepArgs a) {
+  extern __shared__ float tile[];
+  const int tx0 = blockIdx.x * kTileW;
+  const int ty0 = blockIdx.y * kTileH;
+  const int LW = kTileW + 2 * a.halo;
+  const int LH = kTileH + 2 * a.halo;
+  load_tile(tile, a, tx0, ty0, LW, LH);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int i = tx0 + lane;
+  const int n = a.n;
+  const bool cols_interior = tx0 >= 1 && tx0 + kTileW - 1 <= n - 2;
+  float local = 0.0f;
+  bool bad = false;
+  for (int row = wave; row < kTileH; row += kThreads / 64) {
+    const int j = ty0 + row;
+    if (j >= n) break;
+    const bool interior = cols_interior && j >= 1 && j <= n - 2;  // uniform across the wavefront
+    if (i < n) {
+      const size_t idx = (size_t)j * n + i;
+      const int c = a.cls[idx];
+      float wn;
+      if (c == kFree) {
+        const float k = a.r * (a.speed ? a.speed[idx] : a.speed_const);
+        const float* T = tile + (row + a.halo) * LW + lane + a.halo;
+        if (interior) {
+          wn = ring1_update<SCHEME, false>(T, LW, k, a, false, false, false, false);
+        } else {
+          wn = ring1_update<SCHEME, true>(T, LW, k, a, i == 0, i == n - 1, j == 0, j == n - 1);
+        }
+        local = fmaxf(local, fabsf(wn - T[0]));
+        bad |= !isfinite(wn);
+      } else {
+        wn = c == kTarget ? a.w_target : a.w_obstacle;
+      }
+      a.w_out[idx] = wn;
+    }
+  }
+  block_reduce_and_publish(local, bad, a);
+}
+
+hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path, hipStream_t s) {
+  dim3 grid((a.n + kTileW - 1) / kTileW, (a.n + kTileH - 1) / kTileH);
+  const size_t lds = sizeof(float) * (kTileW + 2 * a.halo) * (kTileH + 2 * a.halo);
+  if (path == 1) {
+    if (scheme == kSL2) sweep_ring1<kSL2><<<grid, kThreads, lds, s>>>(a);
+    else sweep_ring1<kSL3><<<grid, kThreads, lds, s>>>(a);
+    return hipGetLastError();
+  }
+#define SLHJB_LAUNCH(D, S) sweep_general<D, S><<<grid, kThreads, lds, s>>>(a)
+  switch (diffusion * 2 + scheme) {
+  case kDiffNone * 2 + kSL2: SLHJB_LAUNCH(kDiffNone, kSL2); break;
+  case kDiffNone * 2 + kSL3: SLHJB_LAUNCH(kDiffNone, kSL3); break;
+  case kDiffIso * 2 + kSL2: SLHJB_LAUNCH(kDiffIso, kSL2); break;
+  case kDiffIso * 2 + kSL3: SLHJB_LAUNCH(kDiffIso, kSL3); break;
+  case kDiffRank1 * 2 + kSL2: SLHJB_LAUNCH(kDiffRank1, kSL2); break;
+  default: SLHJB_LAUNCH(kDiffRank1, kSL3); break;
+  }
+#undef SLHJB_LAUNCH
+  return hipGetLastError();
+}
+
+// ---- small helper kernels -------------------------------------------------------------
+
+__global__ void v_to_w_kernel(const float* __restrict__ v, float* __restrict__ w, const uint8_t* __restrict__ cls,
+                              int64_t count, float vstar, float w_target, float w_obstacle) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cls[t];
+    w[t] = c == kFree ? vstar - v[t] : (c == kTarget ? w_target : w_obstacle);
+  }
+}
+
+__global__ void w_to_v_kernel(const float* __restrict__ w, float* __restrict__ v, int64_t count, float vstar) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+    v[t] = vstar - w[t];
+}
+
+// Problem statistics in one pass: out[0] = bits of the minimum speed, out[1] = bits of the
+// maximum speed (positive floats order like their bits), out[2] |= 1 if a speed is not finite
+// or not > 0, out[3] += number of FREE nodes, out[4] |= 1 if a class value is not 0, 1 or 2.
+// The caller initialises out to (0x7f7fffff, 0, 0, 0, 0). speed may be NULL.
+__global__ void problem_stats_kernel(const float* __restrict__ speed, const uint8_t* __restrict__ cls, int64_t count,
+                                     unsigned* out) {
+  float lo = INFINITY, hi = 0.0f;
+  bool bad_speed = false, bad_cls = false;
+  unsigned nfree = 0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cls[t];
+    nfree += c == kFree ? 1u : 0u;
+    bad_cls |= c > kObstacle;
+    if (speed) {
+      const float v = speed[t];
+      if (!(v > 0.0f) || !isfinite(v)) bad_speed = true;
+      else {
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+    nfree += __shfl_xor(nfree, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (speed) {
+      if (lo < INFINITY) atomicMin(&out[0], __float_as_uint(lo));
+      atomicMax(&out[1], __float_as_uint(hi));
+    }
+    atomicAdd(&out[3], nfree);
+  }
+  if (bad_speed) atomicOr(&out[2], 1u);
+  if (bad_cls) atomicOr(&out[4], 1u);
+}
+
+__global__ void fill_u32_kernel(unsigned* p, unsigned value, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+static int grid_for(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_v_to_w(const float* v, float* w, const uint8_t* cls, int64_t count, float vstar, float w_target,
+                         float w_obstacle, hipStream_t s) {
+  v_to_w_kernel<<<grid_for(count), 256, 0, s>>>(v, w, cls, count, vstar, w_target, w_obstacle);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, hipStream_t s) {
+  w_to_v_kernel<<<grid_for(count), 256, 0, s>>>(w, v, count, vstar);
+  return hipGetLastError();
+}
+
+hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t count, unsigned* out,
+                                hipStream_t s) {
+  problem_stats_kernel<<<grid_for(count), 256, 0, s>>>(speed, cls, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, unsigned value, int count, hipStream_t s) {
+  fill_u32_kernel<<<(count + 255) / 256, 256, 0, s>>>(p, value, count);
+  return hipGetLastError();
+}
+
+}  // namespace slhjb

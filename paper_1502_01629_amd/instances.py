@@ -58,7 +58,9 @@ def control_table(n_controls: int) -> np.ndarray:
     """a_m = (cos 2 pi m/N, sin 2 pi m/N), m = 0..N-1, as float32. When 8 divides N the table
     is built from its first octant by exact swaps and 90-degree rotations, so it is closed
     under the symmetries of the square in float32 (axis directions are exactly (+-1,0),
-    (0,+-1))."""
+    (0,+-1)). Components that are zero in exact arithmetic (|c| < 1e-6 after rounding, e.g.
+    sin(pi)) are stored as exact zeros, so a foot of a boundary node moving along the boundary
+    stays on it."""
     N = int(n_controls)
     out = np.zeros((N, 2), dtype=np.float32)
     if N % 8 == 0:
@@ -77,6 +79,7 @@ def control_table(n_controls: int) -> np.ndarray:
         for m in range(N):
             th = 2.0 * math.pi * m / N
             out[m] = (np.float32(math.cos(th)), np.float32(math.sin(th)))
+    out[np.abs(out) < 1e-6] = 0.0
     return out
 
 

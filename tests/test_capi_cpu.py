@@ -1,0 +1,104 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its host-side
+parameter theory (Section 4.1) reproduces the numbers printed in Section 5.4."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_01629_amd import capi
+from paper_1502_01629_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(slhjb_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = capi.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(capi.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings_and_version():
+    for st in (0, 1, -1, -2, -3, -4, -5):
+        assert capi.status_string(st)
+    assert capi.status_string(99) == "unknown status"
+    assert capi.lib().slhjb_version() >= 1
+
+
+def _exact_eps(printed, thresholds):
+    """The tables print the eps values that sit on a threshold as its leading digits (1.6e-4 for
+    1.6666..e-4, Section 5.4); those runs used the threshold itself."""
+    for t in thresholds:
+        if 0.0 <= (t - printed) / t < 0.05:
+            return t
+    return printed
+
+
+@pytest.mark.parametrize("case", ["eikonal", "zermelo"])
+def test_upwind_ball_thresholds_match_section_5_4(case):
+    g = json.load(open(os.path.join(GOLDEN, "upwind_thresholds.json")))[case]
+    for dx, tau in zip(g["dx"], g["eps_threshold"]):
+        # sigma = sqrt(2 eps) I: hyperbolic iff 1/omega = 2 eps / f_min < dx / (1 + Upsilon)
+        r = capi.regime(g["f_min"], g["f_max"], 1.0, dx)
+        eps_star = r["tau_dx"] * g["f_min"] / 2.0
+        assert abs(eps_star - tau) <= 1e-12 * tau
+        assert abs(r["upsilon"] - g["f_max"] / g["f_min"]) < 1e-12
+    key = "table1" if case == "eikonal" else "table2"
+    eps_list = g[key + "_eps"]
+    for dx, last_bold in g[key + "_bold_up_to_index"].items():
+        dx = float(dx)
+        for idx, eps in enumerate(eps_list):
+            eps = _exact_eps(eps, g["eps_threshold"])
+            r = capi.regime(g["f_min"], g["f_max"], np.sqrt(2.0 * eps), dx)
+            assert bool(r["hyperbolic"]) == (idx <= last_bold), (dx, eps)
+
+
+def test_alpha_window_contains_one_over_one_plus_upsilon():
+    """Whenever eq. hyperbolicity holds, alpha_lower < 1/(1+Upsilon) < alpha_upper (Section 4.1, Fig. alpha-opt),
+    and then h = alpha dx / f_min satisfies both eq. upper-bound and eq. lower-bound."""
+    rng = np.random.default_rng(0)
+    hits = 0
+    for _ in range(2000):
+        f_min = rng.uniform(0.1, 2.0)
+        f_max = f_min * rng.uniform(1.0, 10.0)
+        dx = 10 ** rng.uniform(-3.5, -1)
+        sigma = 10 ** rng.uniform(-4, -0.5)
+        r = capi.regime(f_min, f_max, sigma, dx)
+        if r["hyperbolic"]:
+            hits += 1
+            assert r["alpha_lower"] < r["alpha_opt"] < r["alpha_upper"] < 1.0 / r["upsilon"]
+            h = r["h_alpha"]
+            assert h * f_max + np.sqrt(h) * sigma < dx
+            assert h * f_min - np.sqrt(h) * sigma > 0
+        else:
+            assert not (r["alpha_lower"] < r["alpha_upper"])
+        hu = r["h_upper"]
+        assert abs(hu * f_max + np.sqrt(hu) * sigma - dx) <= 1e-9 * dx
+    assert hits > 100
+
+
+def test_foot_reach():
+    inst = I.disc_problem(129, 0.01)
+    p = capi.Problem(n=129, x_lo=-1.0, x_hi=1.0, h=float(inst.h), lam=1.0, eps=0.01, diffusion=capi.DIFF_ISO,
+                     scheme=1, n_controls=32, controls=np.ascontiguousarray(inst.controls).ctypes.data,
+                     speed=None, speed_const=1.0, running_cost=1.0, node_class=None, target_value=0.0, v_out=1.0)
+    ctrl = np.ascontiguousarray(inst.controls)
+    p.controls = ctrl.ctypes.data
+    reach = capi.lib().slhjb_foot_reach(p, 1.0)
+    dx = 2.0 / 128
+    assert abs(reach - (1.0 + np.sqrt(2 * 0.01 * dx) / dx)) < 1e-6

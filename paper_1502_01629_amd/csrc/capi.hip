@@ -34,6 +34,7 @@ struct slhjb_ctx {
 namespace {
 
 constexpr int kSmallWords = 16;
+constexpr int kCtrlCap = 256 + 16;  // padded control table entries
 
 int fail(slhjb_ctx* ctx, int status, const std::string& msg) {
   if (ctx) ctx->last_msg = msg;
@@ -167,17 +168,24 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   } else {
     quad[4] = p->n_controls;
   }
-  if (ctx->ctrl_cap < p->n_controls) {
-    if (ctx->ctrl) hipFree(ctx->ctrl);
-    ctx->ctrl = nullptr;
-    ctx->ctrl_cap = 0;
-    HIP_TRY(ctx, hipMalloc(&ctx->ctrl, sizeof(float4) * 256));
-    ctx->ctrl_cap = 256;
+  // Pad every quadrant's list (or the whole list for the general kernel) to a multiple of 4 by
+  // repeating its last control: a repeat cannot change a max, and the kernels then fetch the
+  // table four entries at a time.
+  std::vector<float4> tab;
+  int pquad[5] = {0, 0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    pquad[q] = (int)tab.size();
+    for (int t = quad[q]; t < quad[q + 1]; ++t) {
+      const float ax = p->controls[2 * order[t]], ay = p->controls[2 * order[t] + 1];
+      tab.push_back(make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay)));
+    }
+    while (tab.size() % 4 != 0) tab.push_back(tab.back());
   }
-  std::vector<float4> tab(p->n_controls);
-  for (int t = 0; t < p->n_controls; ++t) {
-    const float ax = p->controls[2 * order[t]], ay = p->controls[2 * order[t] + 1];
-    tab[t] = make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay));
+  pquad[4] = (int)tab.size();
+  for (int q = 0; q < 5; ++q) quad[q] = pquad[q];
+  if (!ctx->ctrl) {
+    HIP_TRY(ctx, hipMalloc(&ctx->ctrl, sizeof(float4) * kCtrlCap));
+    ctx->ctrl_cap = kCtrlCap;
   }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice, ctx->stream));
   // The copy reads `tab` asynchronously from pageable memory; make it complete before `tab` dies.
@@ -194,7 +202,7 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   a.resid = nullptr;
   a.flags = ctx->small + 1;
   a.n = n;
-  a.n_controls = p->n_controls;
+  a.n_controls = quad[4];
   a.halo = halo;
   for (int q = 0; q < 5; ++q) a.quad[q] = quad[q];
   a.r = p->h / dx32;

@@ -26,32 +26,34 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-__device__ __forceinline__ void block_reduce_and_publish(float local, bool bad, const SweepArgs& a) {
+__device__ __forceinline__ void block_reduce_and_publish(float local, bool bad, unsigned* __restrict__ resid,
+                                                         unsigned* __restrict__ flags) {
   __shared__ float red[kThreads / 64];
   __shared__ int anybad;
   if (threadIdx.x == 0) anybad = 0;
   __syncthreads();
-  if (a.resid) {
+  if (resid) {
     const float wm = wave_max(local);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
   }
   if (bad) anybad = 1;
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (a.resid) {
+    if (resid) {
       float m = red[0];
 #pragma unroll
       for (int k = 1; k < kThreads / 64; ++k) m = fmaxf(m, red[k]);
       // residuals are >= 0, so the float order equals the unsigned order of the bits
-      atomicMax(a.resid, __float_as_uint(m));
+      atomicMax(resid, __float_as_uint(m));
     }
-    if (anybad) atomicOr(a.flags, 1u);
+    if (anybad) atomicOr(flags, 1u);
   }
 }
 
 // Stage the node tile [tx0 - halo, tx0 + kTileW + halo) x [ty0 - halo, ty0 + kTileH + halo)
 // in LDS; nodes outside the grid are stored as 0 and never carry weight.
-__device__ __forceinline__ void load_tile(float* tile, const SweepArgs& a, int tx0, int ty0, int LW, int LH) {
+__device__ __forceinline__ void load_tile(float* tile, const float* __restrict__ w_in, const SweepArgs& a, int tx0,
+                                          int ty0, int LW, int LH) {
   const int n = a.n;
   const int total = LW * LH;
   for (int t = threadIdx.x; t < total; t += kThreads) {
@@ -60,7 +62,7 @@ __device__ __forceinline__ void load_tile(float* tile, const SweepArgs& a, int t
     const int gx = tx0 - a.halo + lx;
     const int gy = ty0 - a.halo + ly;
     float val = 0.0f;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = a.w_in[(size_t)gy * n + gx];
+    if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = w_in[(size_t)gy * n + gx];
     tile[t] = val;
   }
 }
@@ -99,7 +101,8 @@ struct Feet<kDiffRank1> {
 // `node_li` is the node's index in the tile.
 template <int DIFF, int SCHEME>
 __device__ __forceinline__ float general_update(const float* __restrict__ tile, int LW, int node_li, int i, int j,
-                                                float k, float wself, const SweepArgs& a) {
+                                                float k, float wself, const float4* __restrict__ ctrl,
+                                                const SweepArgs& a) {
   using F = Feet<DIFF>;
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
@@ -110,8 +113,11 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
   const float LWf = (float)LW;
   float best2 = 0.0f;                 // SL2: max over controls of the feet sum
   float bnum = -1.0f, bden = 1.0f;    // SL3: best quotient num / den
+  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
+  // the host pads the control list to a multiple of 4 with repeats of its last control
+#pragma unroll 4
   for (int m = 0; m < a.n_controls; ++m) {
-    const float4 cm = a.ctrl[m];
+    const float4 cm = ctab[m];
     const float bx = k * cm.x;
     const float by = k * cm.y;
     float acc = 0.0f, lam0 = 0.0f;
@@ -154,14 +160,21 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
   return a.beta * bnum / bden;
 }
 
+// All pointers are separate __restrict__ kernel arguments: the compiler can then prove that the
+// control table is never written during the kernel and fetch it with scalar loads.
+#define SLHJB_SWEEP_PARAMS                                                                           \
+  SweepArgs a, const float* __restrict__ w_in, float* __restrict__ w_out, const float* __restrict__ speed, \
+      const uint8_t* __restrict__ cls, const float4* __restrict__ ctrl, unsigned* __restrict__ resid,        \
+      unsigned* __restrict__ flags
+
 template <int DIFF, int SCHEME>
-__global__ __launch_bounds__(kThreads) void sweep_general(SweepArgs a) {
+__global__ __launch_bounds__(kThreads) void sweep_general(SLHJB_SWEEP_PARAMS) {
   extern __shared__ float tile[];
   const int tx0 = blockIdx.x * kTileW;
   const int ty0 = blockIdx.y * kTileH;
   const int LW = kTileW + 2 * a.halo;
   const int LH = kTileH + 2 * a.halo;
-  load_tile(tile, a, tx0, ty0, LW, LH);
+  load_tile(tile, w_in, a, tx0, ty0, LW, LH);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -173,29 +186,30 @@ __global__ __launch_bounds__(kThreads) void sweep_general(SweepArgs a) {
     const int j = ty0 + row;
     if (i < n && j < n) {
       const size_t idx = (size_t)j * n + i;
-      const int c = a.cls[idx];
+      const int c = cls[idx];
       float wn;
       if (c == kFree) {
-        const float k = a.r * (a.speed ? a.speed[idx] : a.speed_const);
+        const float k = a.r * (speed ? speed[idx] : a.speed_const);
         const int node_li = (row + a.halo) * LW + lane + a.halo;
         const float wself = tile[node_li];
-        wn = general_update<DIFF, SCHEME>(tile, LW, node_li, i, j, k, wself, a);
+        wn = general_update<DIFF, SCHEME>(tile, LW, node_li, i, j, k, wself, ctrl, a);
         local = fmaxf(local, fabsf(wn - wself));
         bad |= !isfinite(wn);
       } else {
         wn = c == kTarget ? a.w_target : a.w_obstacle;
       }
-      a.w_out[idx] = wn;
+      w_out[idx] = wn;
     }
   }
-  block_reduce_and_publish(local, bad, a);
+  block_reduce_and_publish(local, bad, resid, flags);
 }
 
 // First-ring update of one node. T points at the node in the LDS tile. EDGE adds the test for
 // feet that leave the box, which only happens on the outermost nodes.
 template <int SCHEME, bool EDGE>
-__device__ __forceinline__ float ring1_update(const float* __restrict__ T, int LW, float k, const SweepArgs& a,
-                                              bool lft, bool rgt, bool bot, bool top) {
+__device__ __forceinline__ float ring1_update(const float* __restrict__ T, int LW, float k,
+                                              const float4* __restrict__ ctrl, const SweepArgs& a, bool lft, bool rgt,
+                                              bool bot, bool top) {
   const float w00 = T[0];
   const float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
   const float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
@@ -208,6 +222,9 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
   const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
   float best2 = -INFINITY;
   float bnum = -1.0f, bden = 1.0f;
+  // SL3 denominator 1 - beta (1 - k|a_x|)(1 - k|a_y|) = (1 - beta) + beta k (|a_x|+|a_y|) - beta k^2 |a_x a_y|
+  const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
+  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     float B, C, D;
@@ -222,27 +239,27 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
       C = k * sy[q] * wY[q];
       D = k2 * (sx[q] * sy[q]) * (wXY[q] - wX[q] - wY[q]);
     }
-    for (int m = a.quad[q]; m < a.quad[q + 1]; ++m) {
-      const float4 cm = a.ctrl[m];
-      float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
-      if (SCHEME == kSL2) {
-        if (EDGE) {
-          const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
-          val = out ? a.w_outside - w00 : val;
-        }
-        best2 = fmaxf(best2, val);
-      } else {
-        // own weight (1 - k|a_x|)(1 - k|a_y|) = 1 - k(|a_x|+|a_y|) + k^2 |a_x a_y|
-        float lam0 = __builtin_fmaf(k2, fabsf(cm.z), __builtin_fmaf(-k, cm.w, 1.0f));
-        if (EDGE) {
-          const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
-          val = out ? a.w_outside : val;
-          lam0 = out ? 0.0f : lam0;
-        }
-        const float den = __builtin_fmaf(-a.beta, lam0, 1.0f);
-        if (val * bden > bnum * den) {
-          bnum = val;
-          bden = den;
+    // the host pads every quadrant's list to a multiple of 4 with repeats of its last control
+    for (int m0 = a.quad[q]; m0 < a.quad[q + 1]; m0 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 cm = ctab[m0 + u];
+        float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
+        bool out = false;
+        if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+        if (SCHEME == kSL2) {
+          if (EDGE) val = out ? a.w_outside - w00 : val;
+          best2 = fmaxf(best2, val);
+        } else {
+          float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
+          if (EDGE) {
+            val = out ? a.w_outside : val;
+            den = out ? 1.0f : den;
+          }
+          if (val * bden > bnum * den) {
+            bnum = val;
+            bden = den;
+          }
         }
       }
     }
@@ -252,13 +269,13 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
 }
 
 template <int SCHEME>
-__global__ __launch_bounds__(kThreads) void sweep_ring1(SweepArgs a) {
+__global__ __launch_bounds__(kThreads) void sweep_ring1(SLHJB_SWEEP_PARAMS) {
   extern __shared__ float tile[];
   const int tx0 = blockIdx.x * kTileW;
   const int ty0 = blockIdx.y * kTileH;
   const int LW = kTileW + 2 * a.halo;
   const int LH = kTileH + 2 * a.halo;
-  load_tile(tile, a, tx0, ty0, LW, LH);
+  load_tile(tile, w_in, a, tx0, ty0, LW, LH);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -273,36 +290,38 @@ __global__ __launch_bounds__(kThreads) void sweep_ring1(SweepArgs a) {
     const bool interior = cols_interior && j >= 1 && j <= n - 2;  // uniform across the wavefront
     if (i < n) {
       const size_t idx = (size_t)j * n + i;
-      const int c = a.cls[idx];
+      const int c = cls[idx];
       float wn;
       if (c == kFree) {
-        const float k = a.r * (a.speed ? a.speed[idx] : a.speed_const);
+        const float k = a.r * (speed ? speed[idx] : a.speed_const);
         const float* T = tile + (row + a.halo) * LW + lane + a.halo;
         if (interior) {
-          wn = ring1_update<SCHEME, false>(T, LW, k, a, false, false, false, false);
+          wn = ring1_update<SCHEME, false>(T, LW, k, ctrl, a, false, false, false, false);
         } else {
-          wn = ring1_update<SCHEME, true>(T, LW, k, a, i == 0, i == n - 1, j == 0, j == n - 1);
+          wn = ring1_update<SCHEME, true>(T, LW, k, ctrl, a, i == 0, i == n - 1, j == 0, j == n - 1);
         }
         local = fmaxf(local, fabsf(wn - T[0]));
         bad |= !isfinite(wn);
       } else {
         wn = c == kTarget ? a.w_target : a.w_obstacle;
       }
-      a.w_out[idx] = wn;
+      w_out[idx] = wn;
     }
   }
-  block_reduce_and_publish(local, bad, a);
+  block_reduce_and_publish(local, bad, resid, flags);
 }
+
+#define SLHJB_SWEEP_ARGS a, a.w_in, a.w_out, a.speed, a.cls, a.ctrl, a.resid, a.flags
 
 hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path, hipStream_t s) {
   dim3 grid((a.n + kTileW - 1) / kTileW, (a.n + kTileH - 1) / kTileH);
   const size_t lds = sizeof(float) * (kTileW + 2 * a.halo) * (kTileH + 2 * a.halo);
   if (path == 1) {
-    if (scheme == kSL2) sweep_ring1<kSL2><<<grid, kThreads, lds, s>>>(a);
-    else sweep_ring1<kSL3><<<grid, kThreads, lds, s>>>(a);
+    if (scheme == kSL2) sweep_ring1<kSL2><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS);
+    else sweep_ring1<kSL3><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS);
     return hipGetLastError();
   }
-#define SLHJB_LAUNCH(D, S) sweep_general<D, S><<<grid, kThreads, lds, s>>>(a)
+#define SLHJB_LAUNCH(D, S) sweep_general<D, S><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS)
   switch (diffusion * 2 + scheme) {
   case kDiffNone * 2 + kSL2: SLHJB_LAUNCH(kDiffNone, kSL2); break;
   case kDiffNone * 2 + kSL3: SLHJB_LAUNCH(kDiffNone, kSL3); break;

@@ -122,6 +122,52 @@ int slhjb_sweep(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_in,
 int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
                 int32_t check_every, slhjb_stats* stats);
 
+/* ---- pre-computation of the patchy method (Section 4.3) --------------------------------- */
+
+/* u_hat: bilinear interpolation of a coarse grid solution onto a fine grid of the same box
+ * (Section 4.3, "build u_hat on G by interpolation of u_c"). v_c: device float[n_c*n_c],
+ * v_f: device float[n_f*n_f]. Fine node i lies at coarse coordinate i (n_c-1)/(n_f-1); the
+ * grids need not be nested. Enqueued only (no synchronisation). */
+int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f);
+
+/* Discrete synthesis of the feedback control (eq. discrete-synthesis) with sigma = 0 and a
+ * constant running cost: for every FREE node, the index m of the control minimising
+ * I[v_hat](x_i + h c(x_i) a_m) (feet outside the box read v_out; the first minimum in the
+ * caller's control order wins). v_hat: device float[n*n]; ctrl_out: device int16[n*n], -1 on
+ * TARGET and OBSTACLE nodes. Enqueued after one synchronising validation pass. */
+int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_hat, int16_t* ctrl_out);
+
+/* Split the TARGET nodes (the sources of information in a target problem, standing in for the
+ * boundary nodes of Section 4.3 "divide the boundary nodes of G in N_P sub-sets") into
+ * n_patches sets. Host-only. Targets are the 4-connected components of TARGET nodes, numbered
+ * in row-major order of their first node; each gets one patch plus a largest-remainder share
+ * (by node count, ties to the lower component) of the remaining n_patches - T; within a
+ * component, patch = floor(P_t (atan2(j - cj, i - ci) + pi) / 2 pi) with (ci, cj) the
+ * component's centroid in grid units. node_class: host uint8[n*n]; source_patch: host
+ * int16[n*n] (patch id on TARGET nodes, -1 elsewhere). Needs n_patches >= number of targets. */
+int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
+                            int32_t* n_targets_out);
+
+/* Patch construction (eq. discrete-advection iterated to its fixed point, then the argmax that
+ * turns the fuzzy indicators into patches), in exact integer arithmetic:
+ *   phi_p in [0, 2^15]; 2^15 on TARGET nodes whose source_patch is p, 0 on other TARGET
+ *   nodes, OBSTACLE nodes and outside the grid; a FREE node takes the bilinear value of phi_p
+ *   at its synthesized foot x + h c(x) a_ctrl(x), with the foot offset quantised per axis to
+ *   D = round_half_even(256 fl(fl(h/dx32) c) a) (dx32 = fl((x_hi-x_lo)/(n-1)), float
+ *   arithmetic), cell offset D >> 8, weights (256 - f or f), f = D & 255, and
+ *   phi' = (sum_c W_c phi(c) + 2^15) >> 16.
+ * The map is monotone, so the iteration (in place, any order) stops at its least fixed point
+ * above the start: the result is exact and does not depend on the schedule.
+ * label_out[x] = argmax_p phi_p(x) (lowest p on ties), -1 where every phi_p is 0.
+ * overlap_out (nullable) bit p set where phi_p >= tau_q15 (0 = no bits: sharp interfaces).
+ * ctrl: device int16[n*n] from slhjb_synthesize (or any field, -1 = not advected);
+ * source_patch: device int16[n*n]; phi_out (nullable): device uint16[n*n*n_patches].
+ * Needs sigma = 0 feet inside the first ring of cells (h c_max |a| <= dx), else
+ * SLHJB_E_UNSUPPORTED; 1 <= n_patches <= 64. Synchronises. */
+int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const int16_t* source_patch,
+                int32_t n_patches, uint16_t tau_q15, int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out,
+                int64_t* passes_out);
+
 /* ---- parameter theory (host only, no GPU needed) --------------------------------------- */
 /* The upwind diffusion ball analysis of Section 4.1 for dynamics bounded by f_min <= |f| <= f_max
  * and diffusion rows of length at most sigma_inf (eq. upper-bound, lower-bound, upper-alpha,

@@ -96,6 +96,10 @@ SIGNATURES = {
     "slhjb_last_error_message": (ctypes.c_char_p, [_vp]),
     "slhjb_sweep": (ctypes.c_int, [_vp, _PP, _vp, _vp, ctypes.POINTER(_f64)]),
     "slhjb_solve": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
+    "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
+    "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
+    "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
+    "slhjb_label": (ctypes.c_int, [_vp, _PP, _vp, _vp, _i32, ctypes.c_uint16, _vp, _vp, _vp, ctypes.POINTER(_i64)]),
     "slhjb_regime_analyze": (ctypes.c_int, [_f64, _f64, _f64, _f64, ctypes.POINTER(Regime)]),
     "slhjb_foot_reach": (_f64, [_PP, _f32]),
 }
@@ -131,6 +135,18 @@ def regime(f_min: float, f_max: float, sigma_inf: float, dx: float) -> dict:
 
 def _ptr(t) -> int:
     return int(t.data_ptr())
+
+
+def partition_sources(node_class: np.ndarray, n_patches: int):
+    """Host-side split of the TARGET nodes into n_patches source sets (see include/slhjb.h)."""
+    cls = np.ascontiguousarray(node_class, dtype=np.uint8)
+    n = int(cls.shape[0])
+    out = np.empty(n * n, dtype=np.int16)
+    nt = ctypes.c_int32()
+    st = lib().slhjb_partition_sources(n, cls.ctypes.data, n_patches, out.ctypes.data, ctypes.byref(nt))
+    if st != OK:
+        raise SlhjbError(st, "slhjb_partition_sources failed")
+    return out.reshape(n, n), nt.value
 
 
 class DeviceProblem:
@@ -197,6 +213,21 @@ class Context:
         r = ctypes.c_double()
         self._check(lib().slhjb_sweep(self.handle, ctypes.byref(prob.struct), _ptr(v_in), _ptr(v_out), ctypes.byref(r)))
         return r.value
+
+    def upsample(self, v_c, n_c: int, v_f, n_f: int):
+        self._check(lib().slhjb_upsample(self.handle, n_c, _ptr(v_c), n_f, _ptr(v_f)))
+
+    def synthesize(self, prob: DeviceProblem, v_hat, ctrl_out):
+        self._check(lib().slhjb_synthesize(self.handle, ctypes.byref(prob.struct), _ptr(v_hat), _ptr(ctrl_out)))
+
+    def label(self, prob: DeviceProblem, ctrl, source_patch, n_patches: int, label_out, tau_q15: int = 0,
+              overlap_out=None, phi_out=None) -> int:
+        passes = ctypes.c_int64()
+        self._check(lib().slhjb_label(self.handle, ctypes.byref(prob.struct), _ptr(ctrl), _ptr(source_patch),
+                                      n_patches, tau_q15, _ptr(label_out),
+                                      _ptr(overlap_out) if overlap_out is not None else None,
+                                      _ptr(phi_out) if phi_out is not None else None, ctypes.byref(passes)))
+        return passes.value
 
     def solve(self, prob: DeviceProblem, v, tol: float = 1e-6, max_sweeps: int = 1_000_000, check_every: int = 0):
         stats = Stats()

@@ -28,6 +28,15 @@ struct slhjb_ctx {
   unsigned* small_host = nullptr;  // pinned mirror
   float4* ctrl = nullptr;
   int ctrl_cap = 0;
+  float2* ctrl2 = nullptr;        // controls in the caller's order (synthesis, labeling)
+  // labeler scratch
+  uint32_t* phi = nullptr;
+  size_t phi_words = 0;
+  uint8_t* tflag = nullptr;       // per-tile flags
+  int* tlist = nullptr;           // compacted tile list
+  int* tcount = nullptr;          // [0] list length
+  int* tcount_host = nullptr;
+  size_t tiles_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
 
@@ -188,6 +197,9 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
     ctx->ctrl_cap = kCtrlCap;
   }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->ctrl2) HIP_TRY(ctx, hipMalloc(&ctx->ctrl2, sizeof(float2) * 256));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl2, p->controls, sizeof(float2) * p->n_controls, hipMemcpyHostToDevice,
+                              ctx->stream));
   // The copy reads `tab` asynchronously from pageable memory; make it complete before `tab` dies.
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
@@ -226,6 +238,23 @@ int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
   if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, "scratch allocation failed");
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
   *cap = elems;
+  return SLHJB_OK;
+}
+
+int ensure_tiles(slhjb_ctx* ctx, size_t tiles) {
+  if (!ctx->tcount) {
+    HIP_TRY(ctx, hipMalloc(&ctx->tcount, sizeof(int) * 4));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->tcount_host, sizeof(int) * 4, hipHostMallocDefault));
+  }
+  if (ctx->tiles_cap >= tiles) return SLHJB_OK;
+  if (ctx->tflag) hipFree(ctx->tflag);
+  if (ctx->tlist) hipFree(ctx->tlist);
+  ctx->tflag = nullptr;
+  ctx->tlist = nullptr;
+  ctx->tiles_cap = 0;
+  HIP_TRY(ctx, hipMalloc(&ctx->tflag, tiles));
+  HIP_TRY(ctx, hipMalloc(&ctx->tlist, sizeof(int) * tiles));
+  ctx->tiles_cap = tiles;
   return SLHJB_OK;
 }
 
@@ -278,6 +307,12 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->small) hipFree(ctx->small);
   if (ctx->small_host) hipHostFree(ctx->small_host);
   if (ctx->ctrl) hipFree(ctx->ctrl);
+  if (ctx->ctrl2) hipFree(ctx->ctrl2);
+  if (ctx->phi) hipFree(ctx->phi);
+  if (ctx->tflag) hipFree(ctx->tflag);
+  if (ctx->tlist) hipFree(ctx->tlist);
+  if (ctx->tcount) hipFree(ctx->tcount);
+  if (ctx->tcount_host) hipHostFree(ctx->tcount_host);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
   if (ctx->eva) hipEventDestroy(ctx->eva);
@@ -403,6 +438,168 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
   }
   if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
   return status;
+}
+
+int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (n_c < 3 || n_f < 3 || n_c > 32769 || n_f > 32769 || !v_c || !v_f)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "need 3 <= n_c, n_f <= 32769 and non-NULL arrays");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_upsample(v_c, n_c, v_f, n_f, ctx->stream));
+  return SLHJB_OK;
+}
+
+int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_hat, int16_t* ctrl_out) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v_hat || !ctrl_out) return fail(ctx, SLHJB_E_INVALID_ARG, "v_hat and ctrl_out must be non-NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  HIP_TRY(ctx, launch_synthesize(v_hat, problem->speed, problem->node_class, ctx->ctrl2, problem->n_controls,
+                                 problem->n, P.args.r, problem->speed_const, problem->v_out, ctrl_out, ctx->stream));
+  return SLHJB_OK;
+}
+
+int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const int16_t* source_patch,
+                int32_t n_patches, uint16_t tau_q15, int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out,
+                int64_t* passes_out) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
+  if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
+  if (tau_q15 > (1u << 15)) return fail(ctx, SLHJB_E_INVALID_ARG, "tau_q15 must be <= 2^15");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
+  slhjb_problem p0 = *problem;
+  p0.diffusion = SLHJB_DIFF_NONE;
+  float speed_max = 0.0f;
+  memcpy(&speed_max, &ctx->small_host[3], sizeof(float));
+  if (!problem->speed) speed_max = problem->speed_const;
+  if (reach_for(&p0, speed_max) > 1.0 + 1e-6)
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labeling needs h c |a| <= dx (feet in the first ring of cells)");
+  const int n = problem->n;
+  const int64_t N = (int64_t)n * n;
+  int Ppad = 2;
+  while (Ppad < n_patches) Ppad *= 2;
+  const int half = Ppad / 2;
+  const size_t words = (size_t)N * half;
+  if (ctx->phi_words < words) {
+    if (ctx->phi) hipFree(ctx->phi);
+    ctx->phi = nullptr;
+    ctx->phi_words = 0;
+    hipError_t e = hipMalloc(&ctx->phi, sizeof(uint32_t) * words);
+    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, "labeler scratch allocation failed");
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
+    ctx->phi_words = words;
+  }
+  const int tiles_x = (n + kLabelTile - 1) / kLabelTile;
+  const int tiles = tiles_x * tiles_x;
+  st = ensure_tiles(ctx, (size_t)tiles);
+  if (st != SLHJB_OK) return st;
+  HIP_TRY(ctx, launch_label_init(problem->node_class, source_patch, N, Ppad, ctx->phi, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
+  const int grid = std::min(tiles, 1024);
+  const int max_inner = 4 * kLabelTile;
+  int64_t passes = 0;
+  // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
+  // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
+  const int64_t max_passes = 4000000;
+  for (;;) {
+    for (int b = 0; b < 8; ++b) {
+      HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount, 0u, 1, ctx->stream));
+      HIP_TRY(ctx, launch_compact_flags(ctx->tflag, tiles, ctx->tlist, ctx->tcount, ctx->stream));
+      HIP_TRY(ctx, launch_label_pass(ctx->phi, problem->node_class, ctrl, problem->speed, problem->speed_const,
+                                     ctx->ctrl2, P.args.r, n, Ppad, ctx->tlist, ctx->tcount, tiles_x, tiles_x,
+                                     ctx->tflag, max_inner, ctx->small + 1, grid, ctx->stream));
+    }
+    passes += 8;
+    // a pass that found no flagged tile means the previous one changed nothing
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->tcount_host, ctx->tcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->tcount_host[0] == 0) break;
+    if (passes > max_passes) return fail(ctx, SLHJB_E_HIP, "labeler did not settle (internal error)");
+  }
+  HIP_TRY(ctx, launch_label_argmax((const uint16_t*)ctx->phi, N, Ppad, label_out, overlap_out, tau_q15, ctx->stream));
+  if (phi_out)
+    HIP_TRY(ctx, hipMemcpy2DAsync(phi_out, sizeof(uint16_t) * n_patches, ctx->phi, sizeof(uint16_t) * Ppad,
+                                  sizeof(uint16_t) * n_patches, (size_t)N, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (passes_out) *passes_out = passes;
+  return SLHJB_OK;
+}
+
+int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
+                            int32_t* n_targets_out) {
+  if (n < 3 || n > 32769 || !node_class || !source_patch || n_patches < 1 || n_patches > 32767)
+    return SLHJB_E_INVALID_ARG;
+  const int64_t N = (int64_t)n * n;
+  std::vector<int32_t> comp(N, -1);
+  std::vector<int64_t> cnt, si, sj;
+  std::vector<int64_t> stack;
+  for (int64_t start = 0; start < N; ++start) {
+    if (node_class[start] != SLHJB_TARGET || comp[start] >= 0) continue;
+    const int32_t id = (int32_t)cnt.size();
+    cnt.push_back(0);
+    si.push_back(0);
+    sj.push_back(0);
+    comp[start] = id;
+    stack.assign(1, start);
+    while (!stack.empty()) {
+      const int64_t v = stack.back();
+      stack.pop_back();
+      const int64_t i = v % n, j = v / n;
+      cnt[id] += 1;
+      si[id] += i;
+      sj[id] += j;
+      const int64_t nb[4] = {i > 0 ? v - 1 : -1, i < n - 1 ? v + 1 : -1, j > 0 ? v - n : -1, j < n - 1 ? v + n : -1};
+      for (int64_t u : nb)
+        if (u >= 0 && node_class[u] == SLHJB_TARGET && comp[u] < 0) {
+          comp[u] = id;
+          stack.push_back(u);
+        }
+    }
+  }
+  const int T = (int)cnt.size();
+  if (n_targets_out) *n_targets_out = T;
+  for (int64_t v = 0; v < N; ++v) source_patch[v] = -1;
+  if (T == 0) return SLHJB_OK;
+  if (n_patches < T) return SLHJB_E_INVALID_ARG;
+  // one patch per target, the remaining n_patches - T apportioned by node count (largest remainder)
+  int64_t total = 0;
+  for (int t = 0; t < T; ++t) total += cnt[t];
+  const int extra = n_patches - T;
+  std::vector<int> share(T);
+  std::vector<std::pair<double, int>> rem(T);
+  int given = 0;
+  for (int t = 0; t < T; ++t) {
+    const double quota = (double)extra * (double)cnt[t] / (double)total;
+    share[t] = (int)floor(quota);
+    given += share[t];
+    rem[t] = {quota - share[t], t};
+  }
+  std::stable_sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first;
+  });
+  for (int k = 0; k < extra - given; ++k) share[rem[k].second] += 1;
+  std::vector<int> offset(T + 1, 0);
+  for (int t = 0; t < T; ++t) offset[t + 1] = offset[t] + 1 + share[t];
+  // within a target: equal angular sectors around its centroid, in grid units
+  const double two_pi = 2.0 * M_PI;
+  for (int64_t v = 0; v < N; ++v) {
+    const int32_t t = comp[v];
+    if (t < 0) continue;
+    const int Pt = offset[t + 1] - offset[t];
+    const double ci = (double)si[t] / (double)cnt[t], cj = (double)sj[t] / (double)cnt[t];
+    const double th = atan2((double)(v / n) - cj, (double)(v % n) - ci);
+    int sec = (int)floor((double)Pt * (th + M_PI) / two_pi);
+    if (sec > Pt - 1) sec = Pt - 1;
+    if (sec < 0) sec = 0;
+    source_patch[v] = (int16_t)(offset[t] + sec);
+  }
+  return SLHJB_OK;
 }
 
 int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx, slhjb_regime* out) {

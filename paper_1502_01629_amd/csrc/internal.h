@@ -50,4 +50,22 @@ hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t 
                                 hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned value, int count, hipStream_t s);
 
+// Pre-computation kernels (pipeline.hip).
+hipError_t launch_upsample(const float* vc, int nc, float* vf, int nf, hipStream_t s);
+hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_t* cls, const float2* ctrl,
+                             int n_controls, int n, float r, float speed_const, float v_out, int16_t* out,
+                             hipStream_t s);
+hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t count, int P, uint32_t* phi32,
+                             hipStream_t s);
+size_t label_pass_lds_bytes(int P);
+hipError_t launch_label_pass(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
+                             float speed_const, const float2* ctab, float r, int n, int P, const int* list,
+                             const int* count, int tiles_x, int tiles_y, uint8_t* next_flag, int max_inner,
+                             unsigned* changed_any, int grid, hipStream_t s);
+hipError_t launch_compact_flags(uint8_t* flag, int count, int* list, int* out_count, hipStream_t s);
+hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
+                               uint16_t tau, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int count, hipStream_t s);
+constexpr int kLabelTile = 16;
+
 }  // namespace slhjb

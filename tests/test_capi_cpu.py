@@ -102,3 +102,52 @@ def test_foot_reach():
     reach = capi.lib().slhjb_foot_reach(p, 1.0)
     dx = 2.0 / 128
     assert abs(reach - (1.0 + np.sqrt(2 * 0.01 * dx) / dx)) < 1e-6
+
+
+def _partition_reference(cls: np.ndarray, P: int) -> np.ndarray:
+    """Independent restatement of the source split: scipy component labels (raster order), one
+    patch per target plus a largest-remainder share by node count, angular sectors around each
+    centroid in grid units."""
+    import math
+
+    from scipy import ndimage
+
+    n = cls.shape[0]
+    lab, T = ndimage.label(cls == I.TARGET, structure=[[0, 1, 0], [1, 1, 1], [0, 1, 0]])
+    out = np.full((n, n), -1, dtype=np.int16)
+    if T == 0:
+        return out
+    jj, ii = np.nonzero(lab)
+    comp = lab[jj, ii] - 1
+    cnt = np.bincount(comp, minlength=T)
+    si = np.bincount(comp, weights=ii.astype(np.float64), minlength=T)
+    sj = np.bincount(comp, weights=jj.astype(np.float64), minlength=T)
+    extra = P - T
+    quota = [extra * int(cnt[t]) / int(cnt.sum()) for t in range(T)]
+    share = [math.floor(q) for q in quota]
+    order = sorted(range(T), key=lambda t: -(quota[t] - share[t]))
+    for k in range(extra - sum(share)):
+        share[order[k]] += 1
+    offset = np.concatenate([[0], np.cumsum([1 + s for s in share])])
+    for j, i, t in zip(jj, ii, comp):
+        Pt = int(offset[t + 1] - offset[t])
+        th = math.atan2(j - int(sj[t]) / int(cnt[t]), i - int(si[t]) / int(cnt[t]))
+        sec = min(max(math.floor(Pt * (th + math.pi) / (2.0 * math.pi)), 0), Pt - 1)
+        out[j, i] = offset[t] + sec
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_partition_sources_matches_reference(seed):
+    fine, coarse = I.scattered_problem(seed, n=257)
+    for inst, P in ((fine, 64), (coarse, 7), (I.disc_problem(129), 8)):
+        got, T = capi.partition_sources(inst.node_class, P)
+        ref = _partition_reference(inst.node_class, P)
+        assert np.array_equal(got, ref)
+        assert set(np.unique(got[inst.node_class == I.TARGET])) <= set(range(P))
+        assert (got[inst.node_class != I.TARGET] == -1).all()
+    # every patch is used when each target is large enough
+    got, T = capi.partition_sources(I.disc_problem(129).node_class, 16)
+    assert T == 1 and len(np.unique(got[got >= 0])) == 16
+    got, T = capi.partition_sources(fine.node_class, 64)
+    assert T == 3

@@ -122,6 +122,36 @@ int slhjb_sweep(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_in,
 int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
                 int32_t check_every, slhjb_stats* stats);
 
+/* ---- active-tile solve (Sections 4.2-4.3, computation step) ----------------------------- */
+enum { SLHJB_ORDER_NONE = 0,   /* every flagged tile each pass (static order)                     */
+       SLHJB_ORDER_KEYS = 1    /* frontier by the arrival time of the start (u_hat order)         */ };
+enum { SLHJB_MODE_TRANSMISSION = 0,  /* one shared iterate: sharp interfaces, transmission by the
+                                        shared values (Section 4.3)                               */
+       SLHJB_MODE_INDEPENDENT = 1    /* each patch alone: a node reads grid values of other patches
+                                        as v_out (state constraints at the interfaces, Section 2) */ };
+typedef struct {
+    int32_t order;              /* SLHJB_ORDER_*                                                  */
+    int32_t mode;               /* SLHJB_MODE_*                                                   */
+    const int16_t* label;       /* device int16[n*n] patch labels; needed for INDEPENDENT         */
+    float key_slack;            /* frontier slack in time units; < 0 = one tile height at c_min   */
+    int32_t max_inner;          /* Jacobi iterations per tile visit; 0 = 96                      */
+} slhjb_tile_opts;
+
+/* Solve from the guess in v (device float[n*n], overwritten) with the active-tile method: the
+ * grid is cut into 32x16-node tiles; a pass iterates each selected tile in LDS against its frozen
+ * halo until no node moves by more than tol/2, commits, and flags the tile and its neighbours
+ * when it moved by more than tol/2. The first pass takes every tile; with SLHJB_ORDER_KEYS a
+ * flagged tile waits while a flagged neighbour's key (minimum arrival time -ln(1 - v/V*)/lambda
+ * of the start over its FREE nodes, V* = l/lambda) is smaller by more than key_slack: the
+ * nodes are processed by increasing u_hat, as the paper prescribes, at tile granularity.
+ * When no tile is flagged, one Jacobi sweep of the whole grid checks the sup-norm change; the
+ * call returns SLHJB_OK when it is <= tol (stats->residual), else continues.
+ * stats->sweeps counts passes (the checks included), stats->node_updates the FREE-node Bellman
+ * updates actually performed. In INDEPENDENT mode the fixed point is that of the per-patch
+ * problems (the decomposition error is its distance to the global solution). */
+int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
+                      const slhjb_tile_opts* opts, slhjb_stats* stats);
+
 /* ---- pre-computation of the patchy method (Section 4.3) --------------------------------- */
 
 /* u_hat: bilinear interpolation of a coarse grid solution onto a fine grid of the same box

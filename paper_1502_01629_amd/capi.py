@@ -66,6 +66,20 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TileOpts(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("label", ctypes.c_void_p),
+        ("key_slack", ctypes.c_float),
+        ("max_inner", ctypes.c_int32),
+    ]
+
+
+ORDER_NONE, ORDER_KEYS = 0, 1
+MODE_TRANSMISSION, MODE_INDEPENDENT = 0, 1
+
+
 class Regime(ctypes.Structure):
     _fields_ = [
         ("omega", ctypes.c_double),
@@ -96,6 +110,7 @@ SIGNATURES = {
     "slhjb_last_error_message": (ctypes.c_char_p, [_vp]),
     "slhjb_sweep": (ctypes.c_int, [_vp, _PP, _vp, _vp, ctypes.POINTER(_f64)]),
     "slhjb_solve": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
+    "slhjb_solve_tiles": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, ctypes.POINTER(TileOpts), ctypes.POINTER(Stats)]),
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
@@ -213,6 +228,16 @@ class Context:
         r = ctypes.c_double()
         self._check(lib().slhjb_sweep(self.handle, ctypes.byref(prob.struct), _ptr(v_in), _ptr(v_out), ctypes.byref(r)))
         return r.value
+
+    def solve_tiles(self, prob: DeviceProblem, v, tol: float = 1e-6, max_passes: int = 1_000_000,
+                    order: int = ORDER_NONE, mode: int = MODE_TRANSMISSION, label=None, key_slack: float = -1.0,
+                    max_inner: int = 0):
+        opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner)
+        stats = Stats()
+        st = lib().slhjb_solve_tiles(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_passes,
+                                     ctypes.byref(opts), ctypes.byref(stats))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return stats.as_dict()
 
     def upsample(self, v_c, n_c: int, v_f, n_f: int):
         self._check(lib().slhjb_upsample(self.handle, n_c, _ptr(v_c), n_f, _ptr(v_f)))

@@ -37,6 +37,11 @@ struct slhjb_ctx {
   int* tcount = nullptr;          // [0] list length
   int* tcount_host = nullptr;
   size_t tiles_cap = 0;
+  // active-tile solver scratch
+  float* tkey = nullptr;
+  float* tchange = nullptr;
+  unsigned long long* tupdates = nullptr;
+  size_t stiles_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
 
@@ -313,6 +318,9 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tlist) hipFree(ctx->tlist);
   if (ctx->tcount) hipFree(ctx->tcount);
   if (ctx->tcount_host) hipHostFree(ctx->tcount_host);
+  if (ctx->tkey) hipFree(ctx->tkey);
+  if (ctx->tchange) hipFree(ctx->tchange);
+  if (ctx->tupdates) hipFree(ctx->tupdates);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
   if (ctx->eva) hipEventDestroy(ctx->eva);
@@ -529,6 +537,123 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (passes_out) *passes_out = passes;
   return SLHJB_OK;
+}
+
+int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
+                      const slhjb_tile_opts* opts, slhjb_stats* stats) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v || !opts) return fail(ctx, SLHJB_E_INVALID_ARG, "v and opts must be non-NULL");
+  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
+  if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
+  if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  float speed_min = problem->speed_const;
+  if (problem->speed) memcpy(&speed_min, &ctx->small_host[2], sizeof(float));
+  const int n = problem->n;
+  const int64_t N = (int64_t)n * n;
+  const int tiles_x = (n + kSolveTileW - 1) / kSolveTileW, tiles_y = (n + kSolveTileH - 1) / kSolveTileH;
+  const int tiles = tiles_x * tiles_y;
+  st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)tiles * kSolveTileW * kSolveTileH);
+  if (st != SLHJB_OK) return st;
+  st = ensure_tiles(ctx, (size_t)tiles);
+  if (st != SLHJB_OK) return st;
+  if (ctx->stiles_cap < (size_t)tiles) {
+    if (ctx->tkey) hipFree(ctx->tkey);
+    if (ctx->tchange) hipFree(ctx->tchange);
+    ctx->tkey = ctx->tchange = nullptr;
+    ctx->stiles_cap = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
+    HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
+    ctx->stiles_cap = tiles;
+  }
+  if (!ctx->tupdates) HIP_TRY(ctx, hipMalloc(&ctx->tupdates, sizeof(unsigned long long)));
+  const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;
+  const bool keyed = opts->order == SLHJB_ORDER_KEYS;
+  const int max_inner = opts->max_inner > 0 ? opts->max_inner : 2 * (kSolveTileW + kSolveTileH);
+  const float tol_inner = (float)(0.5 * tol), act = (float)(0.5 * tol);
+  // frontier slack: the time to cross one tile height at the slowest speed
+  const float slack = opts->key_slack >= 0.0f ? opts->key_slack
+                                               : (float)(kSolveTileH * grid_dx(problem) / (double)speed_min);
+  const int grid = std::min(tiles, 2048);
+  const size_t lds = tile_pass_lds_bytes(P.args.halo, indep);
+  if (lds > 64 * 1024) return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
+
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  HIP_TRY(ctx, launch_v_to_w(v, v, problem->node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle, ctx->stream));
+  if (keyed)
+    HIP_TRY(ctx, launch_tile_keys(v, problem->node_class, n, tiles_x, tiles_y, P.vstar, problem->lambda, ctx->tkey,
+                                  ctx->stream));
+  HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tupdates, 0u, 2, ctx->stream));
+  SweepArgs a = P.args;
+  a.w_in = v;
+  int64_t passes = 0, converged = -1;
+  double resid = INFINITY;
+  int status = SLHJB_NOT_CONVERGED;
+  for (;;) {
+    // a batch of passes, then one read-back of the last list length
+    for (int b = 0; b < 8 && passes < max_passes; ++b, ++passes) {
+      HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount, 0u, 1, ctx->stream));
+      HIP_TRY(ctx, launch_tile_select(ctx->tflag, keyed ? ctx->tkey : nullptr, tiles_x, tiles_y, slack, ctx->tlist,
+                                      ctx->tcount, ctx->stream));
+      HIP_TRY(ctx, launch_tile_pass(a, P.diffusion, P.scheme, P.path, indep, opts->label, ctx->tlist, ctx->tcount,
+                                    tiles_x, ctx->buf, ctx->tchange, ctx->tflag, max_inner, tol_inner, ctx->tupdates,
+                                    grid, ctx->stream));
+      HIP_TRY(ctx, launch_tile_commit(ctx->tlist, ctx->tcount, tiles_x, tiles_y, n, ctx->buf, ctx->tchange, act,
+                                      problem->node_class, v, ctx->tflag, nullptr, grid, ctx->stream));
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->tcount_host, ctx->tcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->tcount_host[0] != 0) {
+      if (passes >= max_passes) break;
+      continue;
+    }
+    // no tile is active: verify with one Jacobi sweep of every tile (one iteration each)
+    HIP_TRY(ctx, launch_iota(ctx->tlist, tiles, ctx->tcount, ctx->stream));
+    HIP_TRY(ctx, launch_fill_u32(ctx->small, 0u, 1, ctx->stream));
+    HIP_TRY(ctx, launch_tile_pass(a, P.diffusion, P.scheme, P.path, indep, opts->label, ctx->tlist, ctx->tcount,
+                                  tiles_x, ctx->buf, ctx->tchange, ctx->tflag, 1, 0.0f, ctx->tupdates, grid,
+                                  ctx->stream));
+    HIP_TRY(ctx, launch_tile_commit(ctx->tlist, ctx->tcount, tiles_x, tiles_y, n, ctx->buf, ctx->tchange, act,
+                                    problem->node_class, v, ctx->tflag, ctx->small, grid, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    float r;
+    memcpy(&r, &ctx->small_host[0], sizeof(float));
+    resid = r;
+    ++passes;
+    if (resid <= tol) {
+      converged = passes;
+      status = SLHJB_OK;
+      break;
+    }
+    if (passes >= max_passes) break;
+  }
+  HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  unsigned long long upd = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&ctx->small_host[8], ctx->tupdates, sizeof(upd), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  memcpy(&upd, &ctx->small_host[8], sizeof(upd));
+  float ms = 0.0f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->sweeps = passes;
+    stats->converged_sweep = converged;
+    stats->node_updates = (int64_t)upd;
+    stats->residual = resid;
+    stats->seconds = ms * 1e-3;
+    stats->status = status;
+    stats->kernel_path = P.path;
+    stats->halo = P.args.halo;
+  }
+  return status;
 }
 
 int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,

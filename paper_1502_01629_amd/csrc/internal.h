@@ -68,4 +68,20 @@ hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int count, hipStream_t s);
 constexpr int kLabelTile = 16;
 
+// Active-tile solver (tiles.hip): 32 x 16 node tiles.
+constexpr int kSolveTileW = 32, kSolveTileH = 16;
+size_t tile_pass_lds_bytes(int halo, bool indep);
+hipError_t launch_tile_pass(const SweepArgs& a, int diffusion, int scheme, int path, bool indep, const int16_t* label,
+                            const int* list, const int* count, int tiles_x, float* outbuf, float* tchange,
+                            uint8_t* flag, int max_inner, float tol_inner, unsigned long long* updates, int grid,
+                            hipStream_t s);
+hipError_t launch_tile_commit(const int* list, const int* count, int tiles_x, int tiles_y, int n, const float* outbuf,
+                              const float* tchange, float act, const uint8_t* cls, float* w, uint8_t* flag,
+                              unsigned* resid, int grid, hipStream_t s);
+hipError_t launch_tile_select(const uint8_t* flag, const float* key, int tiles_x, int tiles_y, float slack, int* list,
+                              int* count, hipStream_t s);
+hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int n, int tiles_x, int tiles_y, float vstar,
+                            float lambda, float* key, hipStream_t s);
+hipError_t launch_iota(int* p, int count, int* count_out, hipStream_t s);
+
 }  // namespace slhjb

@@ -16,39 +16,9 @@
 //    of the four cells around a node is a bilinear form A + B s + C t + D s t; with the
 //    node's 3x3 neighbourhood in registers and the controls grouped by quadrant, a control
 //    costs three FMAs (SL2) instead of a gather.
-#include "internal.h"
+#include "sweep_device.h"
 
 namespace slhjb {
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-__device__ __forceinline__ void block_reduce_and_publish(float local, bool bad, unsigned* __restrict__ resid,
-                                                         unsigned* __restrict__ flags) {
-  __shared__ float red[kThreads / 64];
-  __shared__ int anybad;
-  if (threadIdx.x == 0) anybad = 0;
-  __syncthreads();
-  if (resid) {
-    const float wm = wave_max(local);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
-  }
-  if (bad) anybad = 1;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (resid) {
-      float m = red[0];
-#pragma unroll
-      for (int k = 1; k < kThreads / 64; ++k) m = fmaxf(m, red[k]);
-      // residuals are >= 0, so the float order equals the unsigned order of the bits
-      atomicMax(resid, __float_as_uint(m));
-    }
-    if (anybad) atomicOr(flags, 1u);
-  }
-}
 
 // Stage the node tile [tx0 - halo, tx0 + kTileW + halo) x [ty0 - halo, ty0 + kTileH + halo)
 // in LDS; nodes outside the grid are stored as 0 and never carry weight.
@@ -65,99 +35,6 @@ __device__ __forceinline__ void load_tile(float* tile, const float* __restrict__
     if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = w_in[(size_t)gy * n + gx];
     tile[t] = val;
   }
-}
-
-template <int DIFF>
-struct Feet;
-template <>
-struct Feet<kDiffNone> {
-  static constexpr int K = 1;
-  __device__ static __forceinline__ void get(int, float bx, float by, float, float, float, float& fx, float& fy) {
-    fx = bx;
-    fy = by;
-  }
-};
-template <>
-struct Feet<kDiffIso> {
-  static constexpr int K = 4;
-  __device__ static __forceinline__ void get(int f, float bx, float by, float, float, float d, float& fx, float& fy) {
-    fx = bx + (f == 0 ? d : (f == 1 ? -d : 0.0f));
-    fy = by + (f == 2 ? d : (f == 3 ? -d : 0.0f));
-  }
-};
-template <>
-struct Feet<kDiffRank1> {
-  static constexpr int K = 2;
-  __device__ static __forceinline__ void get(int f, float bx, float by, float ax, float ay, float d, float& fx,
-                                             float& fy) {
-    const float s = f == 0 ? d : -d;
-    fx = __builtin_fmaf(s, ax, bx);
-    fy = __builtin_fmaf(s, ay, by);
-  }
-};
-
-// Bellman update of one FREE node from the LDS tile (general kernel). Feet are handled as
-// offsets from the node in cell units, so positions keep full precision on large grids.
-// `node_li` is the node's index in the tile.
-template <int DIFF, int SCHEME>
-__device__ __forceinline__ float general_update(const float* __restrict__ tile, int LW, int node_li, int i, int j,
-                                                float k, float wself, const float4* __restrict__ ctrl,
-                                                const SweepArgs& a) {
-  using F = Feet<DIFF>;
-  const float fi = (float)i, fj = (float)j;
-  const float nm1 = (float)(a.n - 1);
-  const float nm2 = (float)(a.n - 2);
-  // offsets that stay inside the closed box, and the largest cell offset (cell n-2)
-  const float lox = -fi, hix = nm1 - fi, loy = -fj, hiy = nm1 - fj;
-  const float cmx = nm2 - fi, cmy = nm2 - fj;
-  const float LWf = (float)LW;
-  float best2 = 0.0f;                 // SL2: max over controls of the feet sum
-  float bnum = -1.0f, bden = 1.0f;    // SL3: best quotient num / den
-  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
-  // the host pads the control list to a multiple of 4 with repeats of its last control
-#pragma unroll 4
-  for (int m = 0; m < a.n_controls; ++m) {
-    const float4 cm = ctab[m];
-    const float bx = k * cm.x;
-    const float by = k * cm.y;
-    float acc = 0.0f, lam0 = 0.0f;
-#pragma unroll
-    for (int f = 0; f < F::K; ++f) {
-      float ox, oy;
-      F::get(f, bx, by, cm.x, cm.y, a.d, ox, oy);
-      const bool inside = (ox >= lox) & (ox <= hix) & (oy >= loy) & (oy <= hiy);
-      const float cx = fminf(fmaxf(ox, lox), hix);
-      const float cy = fminf(fmaxf(oy, loy), hiy);
-      const float flx = fminf(floorf(cx), cmx);
-      const float fly = fminf(floorf(cy), cmy);
-      const float s = cx - flx;
-      const float t = cy - fly;
-      const int li = node_li + (int)__builtin_fmaf(fly, LWf, flx);
-      const float v00 = tile[li], v10 = tile[li + 1];
-      const float v01 = tile[li + LW], v11 = tile[li + LW + 1];
-      const float lo = __builtin_fmaf(s, v10 - v00, v00);
-      const float hi = __builtin_fmaf(s, v11 - v01, v01);
-      const float val = __builtin_fmaf(t, hi - lo, lo);
-      acc += inside ? val : a.w_outside;
-      if (SCHEME == kSL3) {
-        const float hx = fmaxf(0.0f, 1.0f - fabsf(cx));
-        const float hy = fmaxf(0.0f, 1.0f - fabsf(cy));
-        lam0 += inside ? hx * hy : 0.0f;
-      }
-    }
-    if (SCHEME == kSL2) {
-      best2 = fmaxf(best2, acc);
-    } else {
-      const float num = __builtin_fmaf(-lam0, wself, acc);
-      const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
-      if (num * bden > bnum * den) {
-        bnum = num;
-        bden = den;
-      }
-    }
-  }
-  if (SCHEME == kSL2) return a.beta * best2 * (1.0f / (float)F::K);
-  return a.beta * bnum / bden;
 }
 
 // All pointers are separate __restrict__ kernel arguments: the compiler can then prove that the
@@ -202,70 +79,6 @@ __global__ __launch_bounds__(kThreads) void sweep_general(SLHJB_SWEEP_PARAMS) {
     }
   }
   block_reduce_and_publish(local, bad, resid, flags);
-}
-
-// First-ring update of one node. T points at the node in the LDS tile. EDGE adds the test for
-// feet that leave the box, which only happens on the outermost nodes.
-template <int SCHEME, bool EDGE>
-__device__ __forceinline__ float ring1_update(const float* __restrict__ T, int LW, float k,
-                                              const float4* __restrict__ ctrl, const SweepArgs& a, bool lft, bool rgt,
-                                              bool bot, bool top) {
-  const float w00 = T[0];
-  const float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
-  const float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
-  const float k2 = k * k;
-  // quadrant order: (+x,+y), (-x,+y), (-x,-y), (+x,-y)
-  const float wX[4] = {wE, wW, wW, wE};
-  const float wY[4] = {wN, wN, wS, wS};
-  const float wXY[4] = {wNE, wNW, wSW, wSE};
-  const float sx[4] = {1.0f, -1.0f, -1.0f, 1.0f};
-  const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
-  float best2 = -INFINITY;
-  float bnum = -1.0f, bden = 1.0f;
-  // SL3 denominator 1 - beta (1 - k|a_x|)(1 - k|a_y|) = (1 - beta) + beta k (|a_x|+|a_y|) - beta k^2 |a_x a_y|
-  const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
-  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float B, C, D;
-    if (SCHEME == kSL2) {
-      // I = w00 + a_x B + a_y C + a_x a_y D over the quadrant's cell
-      B = k * sx[q] * (wX[q] - w00);
-      C = k * sy[q] * (wY[q] - w00);
-      D = k2 * (sx[q] * sy[q]) * ((wXY[q] - wX[q]) - (wY[q] - w00));
-    } else {
-      // I - (1-s)(1-t) w00 = a_x B + a_y C + a_x a_y D  (self weight removed)
-      B = k * sx[q] * wX[q];
-      C = k * sy[q] * wY[q];
-      D = k2 * (sx[q] * sy[q]) * (wXY[q] - wX[q] - wY[q]);
-    }
-    // the host pads every quadrant's list to a multiple of 4 with repeats of its last control
-    for (int m0 = a.quad[q]; m0 < a.quad[q + 1]; m0 += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float4 cm = ctab[m0 + u];
-        float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
-        bool out = false;
-        if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
-        if (SCHEME == kSL2) {
-          if (EDGE) val = out ? a.w_outside - w00 : val;
-          best2 = fmaxf(best2, val);
-        } else {
-          float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
-          if (EDGE) {
-            val = out ? a.w_outside : val;
-            den = out ? 1.0f : den;
-          }
-          if (val * bden > bnum * den) {
-            bnum = val;
-            bden = den;
-          }
-        }
-      }
-    }
-  }
-  if (SCHEME == kSL2) return a.beta * (w00 + best2);
-  return a.beta * bnum / bden;
 }
 
 template <int SCHEME>

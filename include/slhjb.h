@@ -133,17 +133,23 @@ typedef struct {
     int32_t order;              /* SLHJB_ORDER_*                                                  */
     int32_t mode;               /* SLHJB_MODE_*                                                   */
     const int16_t* label;       /* device int16[n*n] patch labels; needed for INDEPENDENT         */
-    float key_slack;            /* frontier slack in time units; < 0 = one tile height at c_min   */
-    int32_t max_inner;          /* Jacobi iterations per tile visit; 0 = 96                      */
+    float key_slack;            /* band width of arrival times (ORDER_KEYS); < 0 = the time to
+                                   cross one tile height at the fastest speed                     */
+    int32_t max_inner;          /* Jacobi iterations per tile visit; 0 = 2 (tile width + height)  */
+    int32_t tile_shape;         /* 0: 32x16 nodes, 1: 16x16 nodes, 2: 8x8 nodes with the control
+                                   set split over the workgroup's four wavefronts                 */
+    int32_t persistent;         /* 1: the whole iteration in one cooperative launch (grid barriers
+                                   between phases); 0: one launch per phase, driven by the host   */
+    int32_t max_workgroups;     /* persistent launch: cap on co-resident workgroups; 0 = 1024     */
 } slhjb_tile_opts;
 
 /* Solve from the guess in v (device float[n*n], overwritten) with the active-tile method: the
- * grid is cut into 32x16-node tiles; a pass iterates each selected tile in LDS against its frozen
+ * grid is cut into tiles (opts->tile_shape); a pass iterates each selected tile in LDS against its frozen
  * halo until no node moves by more than tol/2, commits, and flags the tile and its neighbours
  * when it moved by more than tol/2. The first pass takes every tile; with SLHJB_ORDER_KEYS a
- * flagged tile waits while a flagged neighbour's key (minimum arrival time -ln(1 - v/V*)/lambda
- * of the start over its FREE nodes, V* = l/lambda) is smaller by more than key_slack: the
- * nodes are processed by increasing u_hat, as the paper prescribes, at tile granularity.
+ * pass takes only the flagged tiles whose key (minimum arrival time -ln(1 - v/V*)/lambda of the
+ * start over the tile's FREE nodes, V* = l/lambda) is within key_slack of the smallest flagged
+ * key: the nodes are processed by increasing u_hat, as the paper prescribes, in bands of tiles.
  * When no tile is flagged, one Jacobi sweep of the whole grid checks the sup-norm change; the
  * call returns SLHJB_OK when it is <= tol (stats->residual), else continues.
  * stats->sweeps counts passes (the checks included), stats->node_updates the FREE-node Bellman
@@ -151,6 +157,42 @@ typedef struct {
  * problems (the decomposition error is its distance to the global solution). */
 int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
                       const slhjb_tile_opts* opts, slhjb_stats* stats);
+
+/* ---- the patchy method end to end (Section 4.3) ------------------------------------------- */
+enum { SLHJB_PATCHY_TRANSMISSION = 0,  /* patchy decomposition, one shared iterate             */
+       SLHJB_PATCHY_INDEPENDENT = 1,   /* patchy decomposition, state constraints at interfaces */
+       SLHJB_PATCHY_STATIC = 2         /* static decomposition: no pre-computation, fixed tile
+                                          order, cold start (the comparison of Section 5.4)     */ };
+typedef struct {
+    int32_t mode;                 /* SLHJB_PATCHY_*                                               */
+    int32_t n_patches;            /* N_P (labels only)                                            */
+    const int16_t* source_patch;  /* device int16[n*n] from slhjb_partition_sources (labels only) */
+    double tol;                   /* fine tolerance (sup-norm change of a full sweep)             */
+    double tol_coarse;            /* coarse tolerance                                             */
+    int64_t max_passes;           /* per solve                                                    */
+    float key_window;             /* band width of the u_hat order, < 0 = automatic               */
+    int32_t tile_shape;           /* as slhjb_tile_opts.tile_shape                                */
+} slhjb_patchy_opts;
+
+typedef struct {
+    double t_coarse, t_upsample, t_synthesize, t_label, t_solve, t_total;  /* seconds (events)    */
+    int64_t coarse_passes, node_updates_coarse, label_passes, passes, node_updates;
+    double residual;              /* of the final check sweep on the fine grid                    */
+    int32_t status;
+    int32_t pad;
+} slhjb_patchy_stats;
+
+/* The algorithm of Section 4.3 on one GPU. Patchy modes: (1) coarse solve of `coarse` with
+ * sigma = 0 from v = V* (the Kruzkov "+infinity") to tol_coarse by the active-tile solver;
+ * (2) u_hat = bilinear interpolation on the fine grid, written to v; (3) synthesis of the
+ * feedback control from u_hat and (4) integer patch labels (when label_out is given or the mode
+ * is INDEPENDENT); (5) the fine solve from u_hat, tiles by increasing u_hat
+ * (SLHJB_ORDER_KEYS), sharing one iterate (TRANSMISSION) or with state constraints at the patch
+ * interfaces (INDEPENDENT). STATIC: the fine solve from v = V* with every flagged tile each pass.
+ * v: device float[n*n] output; label_out (nullable): device int16[n*n].
+ * `coarse` must cover the same box; its eps/diffusion are ignored (sigma = 0). Synchronises. */
+int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_problem* coarse,
+                       const slhjb_patchy_opts* opts, float* v, int16_t* label_out, slhjb_patchy_stats* stats);
 
 /* ---- pre-computation of the patchy method (Section 4.3) --------------------------------- */
 

@@ -73,10 +73,49 @@ class TileOpts(ctypes.Structure):
         ("label", ctypes.c_void_p),
         ("key_slack", ctypes.c_float),
         ("max_inner", ctypes.c_int32),
+        ("tile_shape", ctypes.c_int32),
+        ("persistent", ctypes.c_int32),
+        ("max_workgroups", ctypes.c_int32),
     ]
 
 
 ORDER_NONE, ORDER_KEYS = 0, 1
+PATCHY_TRANSMISSION, PATCHY_INDEPENDENT, PATCHY_STATIC = 0, 1, 2
+
+
+class PatchyOpts(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32),
+        ("n_patches", ctypes.c_int32),
+        ("source_patch", ctypes.c_void_p),
+        ("tol", ctypes.c_double),
+        ("tol_coarse", ctypes.c_double),
+        ("max_passes", ctypes.c_int64),
+        ("key_window", ctypes.c_float),
+        ("tile_shape", ctypes.c_int32),
+    ]
+
+
+class PatchyStats(ctypes.Structure):
+    _fields_ = [
+        ("t_coarse", ctypes.c_double),
+        ("t_upsample", ctypes.c_double),
+        ("t_synthesize", ctypes.c_double),
+        ("t_label", ctypes.c_double),
+        ("t_solve", ctypes.c_double),
+        ("t_total", ctypes.c_double),
+        ("coarse_passes", ctypes.c_int64),
+        ("node_updates_coarse", ctypes.c_int64),
+        ("label_passes", ctypes.c_int64),
+        ("passes", ctypes.c_int64),
+        ("node_updates", ctypes.c_int64),
+        ("residual", ctypes.c_double),
+        ("status", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 MODE_TRANSMISSION, MODE_INDEPENDENT = 0, 1
 
 
@@ -111,6 +150,8 @@ SIGNATURES = {
     "slhjb_sweep": (ctypes.c_int, [_vp, _PP, _vp, _vp, ctypes.POINTER(_f64)]),
     "slhjb_solve": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
     "slhjb_solve_tiles": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, ctypes.POINTER(TileOpts), ctypes.POINTER(Stats)]),
+    "slhjb_solve_patchy": (ctypes.c_int, [_vp, _PP, _PP, ctypes.POINTER(PatchyOpts), _vp, _vp,
+                                          ctypes.POINTER(PatchyStats)]),
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
@@ -231,11 +272,25 @@ class Context:
 
     def solve_tiles(self, prob: DeviceProblem, v, tol: float = 1e-6, max_passes: int = 1_000_000,
                     order: int = ORDER_NONE, mode: int = MODE_TRANSMISSION, label=None, key_slack: float = -1.0,
-                    max_inner: int = 0):
-        opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner)
+                    max_inner: int = 0, tile_shape: int = 1, persistent: int = 0, max_workgroups: int = 0):
+        opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner, tile_shape,
+                        persistent, max_workgroups)
         stats = Stats()
         st = lib().slhjb_solve_tiles(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_passes,
                                      ctypes.byref(opts), ctypes.byref(stats))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return stats.as_dict()
+
+    def solve_patchy(self, fine: DeviceProblem, coarse: DeviceProblem | None, v, mode: int = PATCHY_TRANSMISSION,
+                     tol: float = 1e-6, tol_coarse: float = 1e-7, source_patch=None, n_patches: int = 0,
+                     label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = 1):
+        opts = PatchyOpts(mode, n_patches, _ptr(source_patch) if source_patch is not None else None, tol, tol_coarse,
+                          max_passes, key_window, tile_shape)
+        stats = PatchyStats()
+        st = lib().slhjb_solve_patchy(self.handle, ctypes.byref(fine.struct),
+                                      ctypes.byref(coarse.struct) if coarse is not None else None,
+                                      ctypes.byref(opts), _ptr(v), _ptr(label_out) if label_out is not None else None,
+                                      ctypes.byref(stats))
         self._check(st, allow=(OK, NOT_CONVERGED))
         return stats.as_dict()
 

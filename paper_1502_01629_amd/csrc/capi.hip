@@ -42,6 +42,11 @@ struct slhjb_ctx {
   float* tchange = nullptr;
   unsigned long long* tupdates = nullptr;
   size_t stiles_cap = 0;
+  void* coop = nullptr;           // persistent-solver state (device)
+  unsigned* coop_host = nullptr;  // pinned mirror
+  void* tctl = nullptr;           // device-driven pass state
+  unsigned* tctl_host = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
 
@@ -246,6 +251,14 @@ int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
   return SLHJB_OK;
 }
 
+double speed_max_of(slhjb_ctx* ctx, const slhjb_problem* p) {
+  // valid right after prepare(): small_host[3] holds the bits of the largest speed
+  if (!p->speed) return p->speed_const;
+  float hi;
+  memcpy(&hi, &ctx->small_host[3], sizeof(float));
+  return hi;
+}
+
 int ensure_tiles(slhjb_ctx* ctx, size_t tiles) {
   if (!ctx->tcount) {
     HIP_TRY(ctx, hipMalloc(&ctx->tcount, sizeof(int) * 4));
@@ -321,6 +334,11 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tkey) hipFree(ctx->tkey);
   if (ctx->tchange) hipFree(ctx->tchange);
   if (ctx->tupdates) hipFree(ctx->tupdates);
+  if (ctx->coop) hipFree(ctx->coop);
+  if (ctx->tctl) hipFree(ctx->tctl);
+  if (ctx->tctl_host) hipHostFree(ctx->tctl_host);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->coop_host) hipHostFree(ctx->coop_host);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
   if (ctx->eva) hipEventDestroy(ctx->eva);
@@ -448,6 +466,141 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
   return status;
 }
 
+int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_problem* coarse,
+                       const slhjb_patchy_opts* opts, float* v, int16_t* label_out, slhjb_patchy_stats* stats) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!fine || !opts || !v) return fail(ctx, SLHJB_E_INVALID_ARG, "fine, opts and v must be non-NULL");
+  if (opts->mode < 0 || opts->mode > 2) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown patchy mode");
+  if (!(opts->tol > 0.0) || opts->max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0, max_passes >= 1");
+  const bool pdd = opts->mode != SLHJB_PATCHY_STATIC;
+  const bool need_labels = opts->mode == SLHJB_PATCHY_INDEPENDENT || label_out;
+  if (pdd) {
+    if (!coarse) return fail(ctx, SLHJB_E_INVALID_ARG, "the patchy modes need a coarse problem");
+    if (coarse->x_lo != fine->x_lo || coarse->x_hi != fine->x_hi)
+      return fail(ctx, SLHJB_E_INVALID_ARG, "coarse and fine grids must cover the same box");
+    if (!(opts->tol_coarse > 0.0)) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol_coarse > 0");
+    if (need_labels && (!opts->source_patch || opts->n_patches < 1))
+      return fail(ctx, SLHJB_E_INVALID_ARG, "labels need source_patch and n_patches >= 1");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int n = fine->n;
+  const int64_t N = (int64_t)n * n;
+  slhjb_patchy_stats S;
+  memset(&S, 0, sizeof(S));
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  auto lap = [&](double* slot) -> hipError_t {
+    hipError_t er = hipEventRecord(e1, ctx->stream);
+    if (er != hipSuccess) return er;
+    er = hipEventSynchronize(e1);
+    if (er != hipSuccess) return er;
+    float ms = 0.0f;
+    er = hipEventElapsedTime(&ms, e0, e1);
+    if (er != hipSuccess) return er;
+    *slot = ms * 1e-3;
+    return hipEventRecord(e0, ctx->stream);
+  };
+  int st = SLHJB_OK;
+  hipError_t he = hipEventRecord(e0, ctx->stream);
+  hipEvent_t t0 = nullptr;
+  if (he == hipSuccess) he = hipEventCreate(&t0);
+  if (he == hipSuccess) he = hipEventRecord(t0, ctx->stream);
+  slhjb_tile_opts to;
+  memset(&to, 0, sizeof(to));
+  to.tile_shape = opts->tile_shape;
+  to.key_slack = opts->key_window;
+  slhjb_stats ts;
+  int16_t* ctrl = nullptr;
+  float* vc = nullptr;
+  int16_t* lab = label_out;
+  if (he != hipSuccess) {
+    st = hip_fail(ctx, he, "event");
+  } else if (pdd) {
+    // (1) coarse solve with sigma = 0, from v = 1 (the Kruzkov "+infinity")
+    const int64_t Nc = (int64_t)coarse->n * coarse->n;
+    he = hipMalloc(&vc, sizeof(float) * Nc);
+    if (he == hipSuccess) he = hipMalloc(&ctrl, sizeof(int16_t) * N);
+    if (he == hipSuccess && need_labels && !lab) he = hipMalloc(&lab, sizeof(int16_t) * N);
+    if (he != hipSuccess) st = hip_fail(ctx, he, "pipeline scratch");
+    if (st == SLHJB_OK) {
+      // start value V* on every node; the solver overwrites TARGET and OBSTACLE nodes
+      const float vstar = (float)((double)coarse->running_cost / (double)coarse->lambda);
+      unsigned bits;
+      memcpy(&bits, &vstar, sizeof(bits));
+      he = launch_fill_u32((unsigned*)vc, bits, (int)Nc, ctx->stream);
+      if (he != hipSuccess) st = hip_fail(ctx, he, "coarse start");
+    }
+    if (st == SLHJB_OK) {
+      slhjb_problem pc = *coarse;
+      pc.diffusion = SLHJB_DIFF_NONE;
+      pc.eps = 0.0f;
+      slhjb_tile_opts co;
+      memset(&co, 0, sizeof(co));
+      co.tile_shape = 2;
+      st = slhjb_solve_tiles(ctx, &pc, vc, opts->tol_coarse, opts->max_passes, &co, &ts);
+      if (st == SLHJB_NOT_CONVERGED) st = SLHJB_OK;  // a rough coarse solution is still a valid start
+      S.coarse_passes = ts.sweeps;
+      S.node_updates_coarse = ts.node_updates;
+    }
+    if (st == SLHJB_OK && (he = lap(&S.t_coarse)) != hipSuccess) st = hip_fail(ctx, he, "event");
+    // (2) u_hat on the fine grid
+    if (st == SLHJB_OK) st = slhjb_upsample(ctx, coarse->n, vc, n, v);
+    if (st == SLHJB_OK && (he = lap(&S.t_upsample)) != hipSuccess) st = hip_fail(ctx, he, "event");
+    // (3) synthesis of the control and (4) patch labels
+    if (st == SLHJB_OK && need_labels) {
+      st = slhjb_synthesize(ctx, fine, v, ctrl);
+      if (st == SLHJB_OK && (he = lap(&S.t_synthesize)) != hipSuccess) st = hip_fail(ctx, he, "event");
+      if (st == SLHJB_OK) {
+        int64_t lp = 0;
+        st = slhjb_label(ctx, fine, ctrl, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &lp);
+        S.label_passes = lp;
+      }
+      if (st == SLHJB_OK && (he = lap(&S.t_label)) != hipSuccess) st = hip_fail(ctx, he, "event");
+    }
+    // (5) computation: tiles by increasing u_hat, from u_hat
+    if (st == SLHJB_OK) {
+      to.order = SLHJB_ORDER_KEYS;
+      to.mode = opts->mode == SLHJB_PATCHY_INDEPENDENT ? SLHJB_MODE_INDEPENDENT : SLHJB_MODE_TRANSMISSION;
+      to.label = opts->mode == SLHJB_PATCHY_INDEPENDENT ? lab : nullptr;
+      st = slhjb_solve_tiles(ctx, fine, v, opts->tol, opts->max_passes, &to, &ts);
+    }
+  } else {
+    // static decomposition: no pre-computation, tiles in their fixed order, from v = 1
+    const float vstar = (float)((double)fine->running_cost / (double)fine->lambda);
+    unsigned bits;
+    memcpy(&bits, &vstar, sizeof(bits));
+    he = launch_fill_u32((unsigned*)v, bits, (int)N, ctx->stream);
+    if (he != hipSuccess) st = hip_fail(ctx, he, "static start");
+    if (st == SLHJB_OK && (he = lap(&S.t_coarse)) != hipSuccess) st = hip_fail(ctx, he, "event");
+    if (st == SLHJB_OK) {
+      to.order = SLHJB_ORDER_NONE;
+      to.mode = SLHJB_MODE_TRANSMISSION;
+      st = slhjb_solve_tiles(ctx, fine, v, opts->tol, opts->max_passes, &to, &ts);
+    }
+  }
+  if (st == SLHJB_OK || st == SLHJB_NOT_CONVERGED) {
+    S.passes = ts.sweeps;
+    S.node_updates = ts.node_updates;
+    S.residual = ts.residual;
+    S.t_solve = ts.seconds;
+    float ms = 0.0f;
+    hipEventRecord(e1, ctx->stream);
+    hipEventSynchronize(e1);
+    hipEventElapsedTime(&ms, t0, e1);
+    S.t_total = ms * 1e-3;
+  }
+  S.status = st;
+  if (stats) *stats = S;
+  if (vc) hipFree(vc);
+  if (ctrl) hipFree(ctrl);
+  if (lab && lab != label_out) hipFree(lab);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (t0) hipEventDestroy(t0);
+  return st;
+}
+
 int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (n_c < 3 || n_f < 3 || n_c > 32769 || n_f > 32769 || !v_c || !v_f)
@@ -544,7 +697,9 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (!v || !opts) return fail(ctx, SLHJB_E_INVALID_ARG, "v and opts must be non-NULL");
   if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
-  if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0)
+  if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
+      opts->tile_shape < 0 || opts->tile_shape > 2 || opts->persistent < 0 || opts->persistent > 1 ||
+      opts->max_workgroups < 0)
     return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
   if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
     return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
@@ -556,9 +711,11 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (problem->speed) memcpy(&speed_min, &ctx->small_host[2], sizeof(float));
   const int n = problem->n;
   const int64_t N = (int64_t)n * n;
-  const int tiles_x = (n + kSolveTileW - 1) / kSolveTileW, tiles_y = (n + kSolveTileH - 1) / kSolveTileH;
+  const int shape = opts->tile_shape;
+  const int tw = shape == 2 ? 8 : (shape == 1 ? 16 : 32), th = shape == 2 ? 8 : 16;
+  const int tiles_x = (n + tw - 1) / tw, tiles_y = (n + th - 1) / th;
   const int tiles = tiles_x * tiles_y;
-  st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)tiles * kSolveTileW * kSolveTileH);
+  st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)tiles * tw * th);
   if (st != SLHJB_OK) return st;
   st = ensure_tiles(ctx, (size_t)tiles);
   if (st != SLHJB_OK) return st;
@@ -574,65 +731,113 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!ctx->tupdates) HIP_TRY(ctx, hipMalloc(&ctx->tupdates, sizeof(unsigned long long)));
   const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;
   const bool keyed = opts->order == SLHJB_ORDER_KEYS;
-  const int max_inner = opts->max_inner > 0 ? opts->max_inner : 2 * (kSolveTileW + kSolveTileH);
+  const int max_inner = opts->max_inner > 0 ? opts->max_inner : 2 * (tw + th);
   const float tol_inner = (float)(0.5 * tol), act = (float)(0.5 * tol);
-  // frontier slack: the time to cross one tile height at the slowest speed
-  const float slack = opts->key_slack >= 0.0f ? opts->key_slack
-                                               : (float)(kSolveTileH * grid_dx(problem) / (double)speed_min);
+  // band width of arrival times: the time to cross 1/16 of the box (at least 16 cells) at the
+  // fastest speed
+  const float window = opts->key_slack >= 0.0f
+                           ? opts->key_slack
+                           : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max_of(ctx, problem));
+  (void)speed_min;
   const int grid = std::min(tiles, 2048);
-  const size_t lds = tile_pass_lds_bytes(P.args.halo, indep);
+  const size_t lds = tile_pass_lds_bytes(tw, th, P.args.halo, indep);
   if (lds > 64 * 1024) return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
 
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
   HIP_TRY(ctx, launch_v_to_w(v, v, problem->node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle, ctx->stream));
   if (keyed)
-    HIP_TRY(ctx, launch_tile_keys(v, problem->node_class, n, tiles_x, tiles_y, P.vstar, problem->lambda, ctx->tkey,
-                                  ctx->stream));
+    HIP_TRY(ctx, launch_tile_keys(v, problem->node_class, tw, th, n, tiles_x, tiles_y, P.vstar, problem->lambda,
+                                  ctx->tkey, ctx->stream));
   HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
   HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tupdates, 0u, 2, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount + 2, 0xff800000u, 1, ctx->stream));  // band bound -inf
+  HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount + 3, 0u, 1, ctx->stream));           // passes with work
   SweepArgs a = P.args;
   a.w_in = v;
   int64_t passes = 0, converged = -1;
   double resid = INFINITY;
   int status = SLHJB_NOT_CONVERGED;
-  for (;;) {
-    // a batch of passes, then one read-back of the last list length
-    for (int b = 0; b < 8 && passes < max_passes; ++b, ++passes) {
-      HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount, 0u, 1, ctx->stream));
-      HIP_TRY(ctx, launch_tile_select(ctx->tflag, keyed ? ctx->tkey : nullptr, tiles_x, tiles_y, slack, ctx->tlist,
-                                      ctx->tcount, ctx->stream));
-      HIP_TRY(ctx, launch_tile_pass(a, P.diffusion, P.scheme, P.path, indep, opts->label, ctx->tlist, ctx->tcount,
-                                    tiles_x, ctx->buf, ctx->tchange, ctx->tflag, max_inner, tol_inner, ctx->tupdates,
-                                    grid, ctx->stream));
-      HIP_TRY(ctx, launch_tile_commit(ctx->tlist, ctx->tcount, tiles_x, tiles_y, n, ctx->buf, ctx->tchange, act,
-                                      problem->node_class, v, ctx->tflag, nullptr, grid, ctx->stream));
+  int64_t coop_updates = -1;
+  if (opts->persistent) {
+    if (!ctx->coop) {
+      HIP_TRY(ctx, hipMalloc(&ctx->coop, coop_state_bytes()));
+      HIP_TRY(ctx, hipHostMalloc(&ctx->coop_host, 64, hipHostMallocDefault));
     }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->tcount_host, ctx->tcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, launch_coop_state_init(ctx->coop, ctx->stream));
+    const int mp = (int)std::min<int64_t>(max_passes, 1 << 30);
+    int grid_used = 0;
+    HIP_TRY(ctx, launch_tile_solve_coop(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label,
+                                        keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf,
+                                        ctx->tchange, ctx->tflag, max_inner, tol_inner, act, window, (float)tol, mp,
+                                        ctx->coop, opts->max_workgroups > 0 ? opts->max_workgroups : 1024, &grid_used,
+                                        ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->coop_host, ctx->coop, coop_state_bytes(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->tcount_host[0] != 0) {
-      if (passes >= max_passes) break;
-      continue;
-    }
-    // no tile is active: verify with one Jacobi sweep of every tile (one iteration each)
-    HIP_TRY(ctx, launch_iota(ctx->tlist, tiles, ctx->tcount, ctx->stream));
-    HIP_TRY(ctx, launch_fill_u32(ctx->small, 0u, 1, ctx->stream));
-    HIP_TRY(ctx, launch_tile_pass(a, P.diffusion, P.scheme, P.path, indep, opts->label, ctx->tlist, ctx->tcount,
-                                  tiles_x, ctx->buf, ctx->tchange, ctx->tflag, 1, 0.0f, ctx->tupdates, grid,
-                                  ctx->stream));
-    HIP_TRY(ctx, launch_tile_commit(ctx->tlist, ctx->tcount, tiles_x, tiles_y, n, ctx->buf, ctx->tchange, act,
-                                    problem->node_class, v, ctx->tflag, ctx->small, grid, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const unsigned* cs = ctx->coop_host;
     float r;
-    memcpy(&r, &ctx->small_host[0], sizeof(float));
-    resid = r;
-    ++passes;
-    if (resid <= tol) {
-      converged = passes;
+    memcpy(&r, &cs[3], sizeof(float));
+    passes = cs[4];
+    resid = cs[5] == 1 ? (double)r : (r > 0.0f ? (double)r : INFINITY);
+    if (cs[5] == 1) {
       status = SLHJB_OK;
-      break;
+      converged = passes;
     }
-    if (passes >= max_passes) break;
+    unsigned long long u;
+    memcpy(&u, &cs[6], sizeof(u));
+    coop_updates = (int64_t)u;
+  }
+  if (!opts->persistent) {
+    // device-driven passes, captured once into a graph of kBatch passes and replayed
+    constexpr int kBatch = 16;
+    if (!ctx->tctl) {
+      HIP_TRY(ctx, hipMalloc(&ctx->tctl, tilectl_bytes()));
+      HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host, 64, hipHostMallocDefault));
+    }
+    if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(ctx, launch_tilectl_init(ctx->tctl, ctx->stream));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int b = 0; b < kBatch && ce == hipSuccess; ++b)
+      ce = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label, keyed ? ctx->tkey : nullptr,
+                               ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange, ctx->tflag, max_inner, tol_inner,
+                               act, window, (float)tol, b & 1, ctx->tctl, grid, ctx->cap_stream);
+    hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (ce != hipSuccess) return hip_fail(ctx, ce, "capture of the tile passes");
+    if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      hipGraphDestroy(graph);
+      return hip_fail(ctx, ie, "hipGraphInstantiate");
+    }
+    hipError_t le = hipSuccess;
+    unsigned done = 0, dev_passes = 0;
+    while (true) {
+      le = hipGraphLaunch(exec, ctx->stream);
+      if (le != hipSuccess) break;
+      le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
+      if (le != hipSuccess) break;
+      le = hipStreamSynchronize(ctx->stream);
+      if (le != hipSuccess) break;
+      done = ctx->tctl_host[9];
+      dev_passes = ctx->tctl_host[10];
+      if (done || (int64_t)dev_passes >= max_passes) break;
+    }
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    if (le != hipSuccess) return hip_fail(ctx, le, "tile pass graph");
+    passes = dev_passes;
+    float r;
+    memcpy(&r, &ctx->tctl_host[7], sizeof(float));
+    if (done) {
+      status = SLHJB_OK;
+      converged = passes;
+      resid = r;
+    }
+    unsigned long long u;
+    memcpy(&u, &ctx->tctl_host[12], sizeof(u));
+    coop_updates = (int64_t)u;
   }
   HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -640,6 +845,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   HIP_TRY(ctx, hipMemcpyAsync(&ctx->small_host[8], ctx->tupdates, sizeof(upd), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   memcpy(&upd, &ctx->small_host[8], sizeof(upd));
+  if (coop_updates >= 0) upd = (unsigned long long)coop_updates;
   float ms = 0.0f;
   HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   if (stats) {

@@ -68,20 +68,36 @@ hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int count, hipStream_t s);
 constexpr int kLabelTile = 16;
 
-// Active-tile solver (tiles.hip): 32 x 16 node tiles.
-constexpr int kSolveTileW = 32, kSolveTileH = 16;
-size_t tile_pass_lds_bytes(int halo, bool indep);
-hipError_t launch_tile_pass(const SweepArgs& a, int diffusion, int scheme, int path, bool indep, const int16_t* label,
-                            const int* list, const int* count, int tiles_x, float* outbuf, float* tchange,
-                            uint8_t* flag, int max_inner, float tol_inner, unsigned long long* updates, int grid,
-                            hipStream_t s);
-hipError_t launch_tile_commit(const int* list, const int* count, int tiles_x, int tiles_y, int n, const float* outbuf,
-                              const float* tchange, float act, const uint8_t* cls, float* w, uint8_t* flag,
-                              unsigned* resid, int grid, hipStream_t s);
-hipError_t launch_tile_select(const uint8_t* flag, const float* key, int tiles_x, int tiles_y, float slack, int* list,
-                              int* count, hipStream_t s);
-hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int n, int tiles_x, int tiles_y, float vstar,
-                            float lambda, float* key, hipStream_t s);
+// Active-tile solver (tiles.hip). Tile shapes: 0 = 32 x 16 nodes, 1 = 16 x 16 nodes.
+size_t tile_pass_lds_bytes(int tw, int th, int halo, bool indep);
+hipError_t launch_tile_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
+                            const int16_t* label, const int* list, const int* count, int tiles_x, float* outbuf,
+                            float* tchange, uint8_t* flag, int max_inner, float tol_inner, unsigned long long* updates,
+                            int grid, hipStream_t s);
+hipError_t launch_tile_commit(const int* list, const int* count, int tw, int th, int tiles_x, int tiles_y, int n,
+                              const float* outbuf, const float* tchange, float act, const uint8_t* cls, float* w,
+                              uint8_t* flag, unsigned* resid, unsigned* pass_counter, int grid, hipStream_t s);
+hipError_t launch_tile_select(const uint8_t* flag, const float* key, int tiles, unsigned* kmin, unsigned* bound,
+                              float window, int* list, int* count, hipStream_t s);
+hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int tw, int th, int n, int tiles_x, int tiles_y,
+                            float vstar, float lambda, float* key, hipStream_t s);
 hipError_t launch_iota(int* p, int count, int* count_out, hipStream_t s);
+// The whole iteration in one cooperative launch; `state` is device memory of coop_state_bytes(),
+// initialised by the caller: {count 0, kmin +inf, bound -inf, resid 0, passes 0, status 0, updates 0}.
+size_t coop_state_bytes();
+hipError_t launch_coop_state_init(void* state, hipStream_t s);
+// Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes(). Layout of
+// the words the host reads: [9] done, [10] passes, [7] resid bits, [12..13] updates.
+size_t tilectl_bytes();
+hipError_t launch_tilectl_init(void* ctl, hipStream_t s);
+hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
+                               const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
+                               float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
+                               float window, float tol, int q, void* ctl, int grid, hipStream_t s);
+hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
+                                  const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
+                                  float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
+                                  float act, float window, float tol, int max_passes, void* state, int max_grid,
+                                  int* grid_used, hipStream_t s);
 
 }  // namespace slhjb

@@ -217,4 +217,158 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
   return a.beta * bnum / bden;
 }
 
+
+// ---- partial updates over a subset of the controls ---------------------------------------------
+// The workgroup of the 8x8-tile solver gives each of its four wavefronts one quarter of the
+// control set for the same 64 nodes; the partial results are combined through LDS. For the
+// first-ring path a quarter is one quadrant, for the general path a contiguous quarter of the
+// (padded) control list, so every wavefront still walks a uniform control range with scalar loads.
+// Partial of SL2 (first ring): max over the range of I - w00; of SL2 (general): max of the feet
+// sum; of SL3: the best quotient as (num, den).
+template <int SCHEME, bool EDGE, bool INDEP>
+__device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int LW, float k,
+                                              const float4* __restrict__ ctrl, const SweepArgs& a, bool lft, bool rgt,
+                                              bool bot, bool top, const int16_t* __restrict__ L, int qsel,
+                                              float& pnum, float& pden) {
+  const float w00 = T[0];
+  float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
+  float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
+  if (INDEP) {
+    const int me = L[0];
+    const float wo = a.w_outside;
+    wE = L[1] == me ? wE : wo;
+    wW = L[-1] == me ? wW : wo;
+    wN = L[LW] == me ? wN : wo;
+    wS = L[-LW] == me ? wS : wo;
+    wNE = L[LW + 1] == me ? wNE : wo;
+    wNW = L[LW - 1] == me ? wNW : wo;
+    wSE = L[-LW + 1] == me ? wSE : wo;
+    wSW = L[-LW - 1] == me ? wSW : wo;
+  }
+  const float k2 = k * k;
+  const float wX[4] = {wE, wW, wW, wE};
+  const float wY[4] = {wN, wN, wS, wS};
+  const float wXY[4] = {wNE, wNW, wSW, wSE};
+  const float sx[4] = {1.0f, -1.0f, -1.0f, 1.0f};
+  const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
+  float best2 = -INFINITY;
+  float bnum = -1.0f, bden = 1.0f;
+  const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
+  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q != qsel) continue;  // uniform across the wavefront
+    float B, C, D;
+    if (SCHEME == kSL2) {
+      B = k * sx[q] * (wX[q] - w00);
+      C = k * sy[q] * (wY[q] - w00);
+      D = k2 * (sx[q] * sy[q]) * ((wXY[q] - wX[q]) - (wY[q] - w00));
+    } else {
+      B = k * sx[q] * wX[q];
+      C = k * sy[q] * wY[q];
+      D = k2 * (sx[q] * sy[q]) * (wXY[q] - wX[q] - wY[q]);
+    }
+    for (int m0 = a.quad[q]; m0 < a.quad[q + 1]; m0 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 cm = ctab[m0 + u];
+        float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
+        bool out = false;
+        if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+        if (SCHEME == kSL2) {
+          if (EDGE) val = out ? a.w_outside - w00 : val;
+          best2 = fmaxf(best2, val);
+        } else {
+          float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
+          if (EDGE) {
+            val = out ? a.w_outside : val;
+            den = out ? 1.0f : den;
+          }
+          if (val * bden > bnum * den) {
+            bnum = val;
+            bden = den;
+          }
+        }
+      }
+    }
+  }
+  if (SCHEME == kSL2) {
+    pnum = best2;
+    pden = 1.0f;
+  } else {
+    pnum = bnum;
+    pden = bden;
+  }
+}
+
+template <int DIFF, int SCHEME, bool INDEP>
+__device__ __forceinline__ void general_partial(const float* __restrict__ tile, int LW, int node_li, int i, int j,
+                                                float k, float wself, const float4* __restrict__ ctrl,
+                                                const SweepArgs& a, const int16_t* __restrict__ lab, int mylab,
+                                                int m_lo, int m_hi, float& pnum, float& pden) {
+  using F = Feet<DIFF>;
+  const float fi = (float)i, fj = (float)j;
+  const float nm1 = (float)(a.n - 1);
+  const float nm2 = (float)(a.n - 2);
+  const float lox = -fi, hix = nm1 - fi, loy = -fj, hiy = nm1 - fj;
+  const float cmx = nm2 - fi, cmy = nm2 - fj;
+  const float LWf = (float)LW;
+  float best2 = -INFINITY;
+  float bnum = -1.0f, bden = 1.0f;
+  const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
+#pragma unroll 4
+  for (int m = m_lo; m < m_hi; ++m) {
+    const float4 cm = ctab[m];
+    const float bx = k * cm.x;
+    const float by = k * cm.y;
+    float acc = 0.0f, lam0 = 0.0f;
+#pragma unroll
+    for (int f = 0; f < F::K; ++f) {
+      float ox, oy;
+      F::get(f, bx, by, cm.x, cm.y, a.d, ox, oy);
+      const bool inside = (ox >= lox) & (ox <= hix) & (oy >= loy) & (oy <= hiy);
+      const float cx = fminf(fmaxf(ox, lox), hix);
+      const float cy = fminf(fmaxf(oy, loy), hiy);
+      const float flx = fminf(floorf(cx), cmx);
+      const float fly = fminf(floorf(cy), cmy);
+      const float s = cx - flx;
+      const float t = cy - fly;
+      const int li = node_li + (int)__builtin_fmaf(fly, LWf, flx);
+      float v00 = tile[li], v10 = tile[li + 1];
+      float v01 = tile[li + LW], v11 = tile[li + LW + 1];
+      if (INDEP) {
+        v00 = lab[li] == mylab ? v00 : a.w_outside;
+        v10 = lab[li + 1] == mylab ? v10 : a.w_outside;
+        v01 = lab[li + LW] == mylab ? v01 : a.w_outside;
+        v11 = lab[li + LW + 1] == mylab ? v11 : a.w_outside;
+      }
+      const float lo = __builtin_fmaf(s, v10 - v00, v00);
+      const float hi = __builtin_fmaf(s, v11 - v01, v01);
+      const float val = __builtin_fmaf(t, hi - lo, lo);
+      acc += inside ? val : a.w_outside;
+      if (SCHEME == kSL3) {
+        const float hx = fmaxf(0.0f, 1.0f - fabsf(cx));
+        const float hy = fmaxf(0.0f, 1.0f - fabsf(cy));
+        lam0 += inside ? hx * hy : 0.0f;
+      }
+    }
+    if (SCHEME == kSL2) {
+      best2 = fmaxf(best2, acc);
+    } else {
+      const float num = __builtin_fmaf(-lam0, wself, acc);
+      const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
+      if (num * bden > bnum * den) {
+        bnum = num;
+        bden = den;
+      }
+    }
+  }
+  if (SCHEME == kSL2) {
+    pnum = best2;
+    pden = 1.0f;
+  } else {
+    pnum = bnum;
+    pden = bden;
+  }
+}
 }  // namespace slhjb

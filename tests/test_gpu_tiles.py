@@ -30,10 +30,11 @@ def _uhat(fine, coarse):
     return oracle.upsample_bilinear(vc, fine.n).astype(np.float32)
 
 
+@pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("eps", [0.0, 0.01])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_tiles_transmission_matches_global_fixed_point(ctx, order, eps, scheme):
+def test_tiles_transmission_matches_global_fixed_point(ctx, order, eps, scheme, shape):
     from paper_1502_01629_amd import capi
 
     inst = I.disc_problem(129, eps)
@@ -45,7 +46,7 @@ def test_tiles_transmission_matches_global_fixed_point(ctx, order, eps, scheme):
         v = _dev(_uhat(inst, coarse))
     else:
         v = _dev(inst.initial())
-    st = ctx.solve_tiles(dp, v, tol=5e-7, order=order)
+    st = ctx.solve_tiles(dp, v, tol=5e-7, order=order, max_passes=20000, tile_shape=shape)
     print(st, flush=True)
     assert st["status"] == 0 and st["residual"] <= 5e-7
     ref, _, _, _ = oracle.Problem.from_instance(inst, scheme).solve(tol=1e-10, threads=8)
@@ -54,15 +55,16 @@ def test_tiles_transmission_matches_global_fixed_point(ctx, order, eps, scheme):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("order", [0, 1])
-def test_tiles_scattered_obstacles(ctx, order):
+def test_tiles_scattered_obstacles(ctx, order, shape):
     """Point targets, obstacles and variable speed on 257^2 (ragged tiles), cold and u_hat starts."""
     from paper_1502_01629_amd import capi
 
     fine, coarse = I.scattered_problem(1, n=257, n_coarse=65)
     dp = capi.DeviceProblem(fine, 1)
     v = _dev(_uhat(fine, coarse) if order == 1 else fine.initial())
-    st = ctx.solve_tiles(dp, v, tol=5e-7, order=order)
+    st = ctx.solve_tiles(dp, v, tol=5e-7, order=order, max_passes=20000, tile_shape=shape)
     print(st, flush=True)
     assert st["status"] == 0
     ref, sweeps, _, _ = oracle.Problem.from_instance(fine, 1).solve(tol=1e-10, threads=8)
@@ -81,8 +83,9 @@ def _independent_fixed_point(p, label):
     return w
 
 
+@pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("layout", ["sectors", "stripes"])
-def test_tiles_independent_patches_match_oracle(ctx, layout):
+def test_tiles_independent_patches_match_oracle(ctx, layout, shape):
     """State constraints at patch interfaces: the fixed point of the per-patch problems. Sectors around
     the target are invariant under the optimal (radial) dynamics, so the constraint costs nothing
     (the property the patchy decomposition is built for, Section 2); stripes cut the characteristics
@@ -98,7 +101,8 @@ def test_tiles_independent_patches_match_oracle(ctx, layout):
         label = ((np.arange(n)[None, :] // 24) % 3 + np.zeros((n, 1), dtype=np.int64)).astype(np.int16)
     dp = capi.DeviceProblem(inst, 1)
     v = _dev(inst.initial())
-    st = ctx.solve_tiles(dp, v, tol=5e-7, mode=capi.MODE_INDEPENDENT, label=_dev(label, np.int16))
+    st = ctx.solve_tiles(dp, v, tol=5e-7, mode=capi.MODE_INDEPENDENT, label=_dev(label, np.int16), max_passes=20000,
+                         tile_shape=shape)
     assert st["status"] == 0
     p = oracle.Problem.from_instance(inst, 1)
     w = _independent_fixed_point(p, label)
@@ -112,3 +116,25 @@ def test_tiles_independent_patches_match_oracle(ctx, layout):
         assert dec < 1e-9
     else:
         assert dec > 1e-2
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_persistent_and_host_driven_agree_bit_for_bit(ctx, order, shape):
+    """Both drivers read the previous pass's iterate in every visit and commit after all visits, so the
+    result does not depend on which workgroup visits which tile, nor on the driver."""
+    from paper_1502_01629_amd import capi
+
+    fine, coarse = I.scattered_problem(2, n=257, n_coarse=65)
+    dp = capi.DeviceProblem(fine, 1)
+    start = _uhat(fine, coarse) if order == 1 else fine.initial()
+    out = []
+    for persistent in (0, 1):
+        v = _dev(start)
+        st = ctx.solve_tiles(dp, v, tol=5e-7, order=order, tile_shape=shape, persistent=persistent,
+                             max_passes=20000)
+        print("persistent", persistent, st, flush=True)
+        assert st["status"] == 0
+        out.append((v.cpu().numpy(), st["sweeps"], st["node_updates"]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]

@@ -141,6 +141,8 @@ typedef struct {
     int32_t persistent;         /* 1: the whole iteration in one cooperative launch (grid barriers
                                    between phases); 0: one launch per phase, driven by the host   */
     int32_t max_workgroups;     /* persistent launch: cap on co-resident workgroups; 0 = 1024     */
+    int32_t collect_kernel_time;/* 1: time every visit launch with events (stats->sweep_seconds,
+                                   sweep_launches = passes); graph driver only                    */
 } slhjb_tile_opts;
 
 /* Solve from the guess in v (device float[n*n], overwritten) with the active-tile method: the
@@ -172,10 +174,12 @@ typedef struct {
     int64_t max_passes;           /* per solve                                                    */
     float key_window;             /* band width of the u_hat order, < 0 = automatic               */
     int32_t tile_shape;           /* as slhjb_tile_opts.tile_shape                                */
+    int32_t collect_kernel_time;  /* as slhjb_tile_opts.collect_kernel_time (fine solve)          */
 } slhjb_patchy_opts;
 
 typedef struct {
     double t_coarse, t_upsample, t_synthesize, t_label, t_solve, t_total;  /* seconds (events)    */
+    double t_visit;               /* fine solve: time inside the tile-visit kernels (if collected)*/
     int64_t coarse_passes, node_updates_coarse, label_passes, passes, node_updates;
     double residual;              /* of the final check sweep on the fine grid                    */
     int32_t status;
@@ -233,12 +237,14 @@ int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patc
  * label_out[x] = argmax_p phi_p(x) (lowest p on ties), -1 where every phi_p is 0.
  * overlap_out (nullable) bit p set where phi_p >= tau_q15 (0 = no bits: sharp interfaces).
  * ctrl: device int16[n*n] from slhjb_synthesize (or any field, -1 = not advected);
+ * v_hat (nullable): device float[n*n] u_hat; when given, 16x16-node tiles are visited in bands of
+ * increasing arrival time of u_hat (the result does not depend on it, only the work);
  * source_patch: device int16[n*n]; phi_out (nullable): device uint16[n*n*n_patches].
  * Needs sigma = 0 feet inside the first ring of cells (h c_max |a| <= dx), else
  * SLHJB_E_UNSUPPORTED; 1 <= n_patches <= 64. Synchronises. */
-int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const int16_t* source_patch,
-                int32_t n_patches, uint16_t tau_q15, int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out,
-                int64_t* passes_out);
+int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const float* v_hat,
+                const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15, int16_t* label_out,
+                uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out);
 
 /* ---- parameter theory (host only, no GPU needed) --------------------------------------- */
 /* The upwind diffusion ball analysis of Section 4.1 for dynamics bounded by f_min <= |f| <= f_max

@@ -76,6 +76,7 @@ class TileOpts(ctypes.Structure):
         ("tile_shape", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
         ("max_workgroups", ctypes.c_int32),
+        ("collect_kernel_time", ctypes.c_int32),
     ]
 
 
@@ -93,6 +94,7 @@ class PatchyOpts(ctypes.Structure):
         ("max_passes", ctypes.c_int64),
         ("key_window", ctypes.c_float),
         ("tile_shape", ctypes.c_int32),
+        ("collect_kernel_time", ctypes.c_int32),
     ]
 
 
@@ -104,6 +106,7 @@ class PatchyStats(ctypes.Structure):
         ("t_label", ctypes.c_double),
         ("t_solve", ctypes.c_double),
         ("t_total", ctypes.c_double),
+        ("t_visit", ctypes.c_double),
         ("coarse_passes", ctypes.c_int64),
         ("node_updates_coarse", ctypes.c_int64),
         ("label_passes", ctypes.c_int64),
@@ -155,7 +158,8 @@ SIGNATURES = {
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
-    "slhjb_label": (ctypes.c_int, [_vp, _PP, _vp, _vp, _i32, ctypes.c_uint16, _vp, _vp, _vp, ctypes.POINTER(_i64)]),
+    "slhjb_label": (ctypes.c_int, [_vp, _PP, _vp, _vp, _vp, _i32, ctypes.c_uint16, _vp, _vp, _vp,
+                                   ctypes.POINTER(_i64)]),
     "slhjb_regime_analyze": (ctypes.c_int, [_f64, _f64, _f64, _f64, ctypes.POINTER(Regime)]),
     "slhjb_foot_reach": (_f64, [_PP, _f32]),
 }
@@ -272,9 +276,10 @@ class Context:
 
     def solve_tiles(self, prob: DeviceProblem, v, tol: float = 1e-6, max_passes: int = 1_000_000,
                     order: int = ORDER_NONE, mode: int = MODE_TRANSMISSION, label=None, key_slack: float = -1.0,
-                    max_inner: int = 0, tile_shape: int = 1, persistent: int = 0, max_workgroups: int = 0):
+                    max_inner: int = 0, tile_shape: int = 1, persistent: int = 0, max_workgroups: int = 0,
+                    collect_kernel_time: int = 0):
         opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner, tile_shape,
-                        persistent, max_workgroups)
+                        persistent, max_workgroups, collect_kernel_time)
         stats = Stats()
         st = lib().slhjb_solve_tiles(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_passes,
                                      ctypes.byref(opts), ctypes.byref(stats))
@@ -283,9 +288,10 @@ class Context:
 
     def solve_patchy(self, fine: DeviceProblem, coarse: DeviceProblem | None, v, mode: int = PATCHY_TRANSMISSION,
                      tol: float = 1e-6, tol_coarse: float = 1e-7, source_patch=None, n_patches: int = 0,
-                     label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = 1):
+                     label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = 1,
+                     collect_kernel_time: int = 0):
         opts = PatchyOpts(mode, n_patches, _ptr(source_patch) if source_patch is not None else None, tol, tol_coarse,
-                          max_passes, key_window, tile_shape)
+                          max_passes, key_window, tile_shape, collect_kernel_time)
         stats = PatchyStats()
         st = lib().slhjb_solve_patchy(self.handle, ctypes.byref(fine.struct),
                                       ctypes.byref(coarse.struct) if coarse is not None else None,
@@ -301,9 +307,10 @@ class Context:
         self._check(lib().slhjb_synthesize(self.handle, ctypes.byref(prob.struct), _ptr(v_hat), _ptr(ctrl_out)))
 
     def label(self, prob: DeviceProblem, ctrl, source_patch, n_patches: int, label_out, tau_q15: int = 0,
-              overlap_out=None, phi_out=None) -> int:
+              overlap_out=None, phi_out=None, v_hat=None) -> int:
         passes = ctypes.c_int64()
-        self._check(lib().slhjb_label(self.handle, ctypes.byref(prob.struct), _ptr(ctrl), _ptr(source_patch),
+        self._check(lib().slhjb_label(self.handle, ctypes.byref(prob.struct), _ptr(ctrl),
+                                      _ptr(v_hat) if v_hat is not None else None, _ptr(source_patch),
                                       n_patches, tau_q15, _ptr(label_out),
                                       _ptr(overlap_out) if overlap_out is not None else None,
                                       _ptr(phi_out) if phi_out is not None else None, ctypes.byref(passes)))

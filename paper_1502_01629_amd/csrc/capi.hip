@@ -45,8 +45,11 @@ struct slhjb_ctx {
   void* coop = nullptr;           // persistent-solver state (device)
   unsigned* coop_host = nullptr;  // pinned mirror
   void* tctl = nullptr;           // device-driven pass state
+  void* lctl = nullptr;           // labeler pass state
+  unsigned* lctl_host = nullptr;
   unsigned* tctl_host = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  hipEvent_t tev[32] = {};           // visit-kernel timing events of one captured batch
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
 
@@ -336,8 +339,12 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tupdates) hipFree(ctx->tupdates);
   if (ctx->coop) hipFree(ctx->coop);
   if (ctx->tctl) hipFree(ctx->tctl);
+  if (ctx->lctl) hipFree(ctx->lctl);
+  if (ctx->lctl_host) hipHostFree(ctx->lctl_host);
   if (ctx->tctl_host) hipHostFree(ctx->tctl_host);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  for (auto& e : ctx->tev)
+    if (e) hipEventDestroy(e);
   if (ctx->coop_host) hipHostFree(ctx->coop_host);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
@@ -510,6 +517,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   memset(&to, 0, sizeof(to));
   to.tile_shape = opts->tile_shape;
   to.key_slack = opts->key_window;
+  to.collect_kernel_time = opts->collect_kernel_time;
   slhjb_stats ts;
   int16_t* ctrl = nullptr;
   float* vc = nullptr;
@@ -553,7 +561,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
       if (st == SLHJB_OK && (he = lap(&S.t_synthesize)) != hipSuccess) st = hip_fail(ctx, he, "event");
       if (st == SLHJB_OK) {
         int64_t lp = 0;
-        st = slhjb_label(ctx, fine, ctrl, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &lp);
+        st = slhjb_label(ctx, fine, ctrl, v, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &lp);
         S.label_passes = lp;
       }
       if (st == SLHJB_OK && (he = lap(&S.t_label)) != hipSuccess) st = hip_fail(ctx, he, "event");
@@ -584,6 +592,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     S.node_updates = ts.node_updates;
     S.residual = ts.residual;
     S.t_solve = ts.seconds;
+    S.t_visit = ts.sweep_seconds;
     float ms = 0.0f;
     hipEventRecord(e1, ctx->stream);
     hipEventSynchronize(e1);
@@ -622,9 +631,9 @@ int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* 
   return SLHJB_OK;
 }
 
-int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const int16_t* source_patch,
-                int32_t n_patches, uint16_t tau_q15, int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out,
-                int64_t* passes_out) {
+int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const float* v_hat,
+                const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15, int16_t* label_out,
+                uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
   if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
@@ -662,27 +671,48 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
   if (st != SLHJB_OK) return st;
   HIP_TRY(ctx, launch_label_init(problem->node_class, source_patch, N, Ppad, ctx->phi, ctx->stream));
   HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
+  if (!ctx->lctl) {
+    HIP_TRY(ctx, hipMalloc(&ctx->lctl, labctl_bytes()));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host, 64, hipHostMallocDefault));
+  }
+  HIP_TRY(ctx, launch_labctl_init(ctx->lctl, ctx->stream));
+  // optional u_hat order: tiles by increasing arrival time of v_hat, in bands
+  const float* key = nullptr;
+  float window = INFINITY;
+  if (v_hat) {
+    if (ctx->stiles_cap < (size_t)tiles) {
+      if (ctx->tkey) hipFree(ctx->tkey);
+      if (ctx->tchange) hipFree(ctx->tchange);
+      ctx->tkey = ctx->tchange = nullptr;
+      ctx->stiles_cap = 0;
+      HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
+      HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
+      ctx->stiles_cap = tiles;
+    }
+    const float vstar = (float)((double)problem->running_cost / (double)problem->lambda);
+    HIP_TRY(ctx, launch_label_keys(v_hat, problem->node_class, n, tiles_x, tiles_x, vstar, problem->lambda, ctx->tkey,
+                                   ctx->stream));
+    key = ctx->tkey;
+    window = (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max);
+  }
   const int grid = std::min(tiles, 1024);
   const int max_inner = 4 * kLabelTile;
-  int64_t passes = 0;
   // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
   // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
   const int64_t max_passes = 4000000;
+  int64_t launched = 0;
   for (;;) {
-    for (int b = 0; b < 8; ++b) {
-      HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount, 0u, 1, ctx->stream));
-      HIP_TRY(ctx, launch_compact_flags(ctx->tflag, tiles, ctx->tlist, ctx->tcount, ctx->stream));
-      HIP_TRY(ctx, launch_label_pass(ctx->phi, problem->node_class, ctrl, problem->speed, problem->speed_const,
-                                     ctx->ctrl2, P.args.r, n, Ppad, ctx->tlist, ctx->tcount, tiles_x, tiles_x,
-                                     ctx->tflag, max_inner, ctx->small + 1, grid, ctx->stream));
-    }
-    passes += 8;
-    // a pass that found no flagged tile means the previous one changed nothing
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->tcount_host, ctx->tcount, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    for (int b = 0; b < 16; ++b)
+      HIP_TRY(ctx, launch_label_pass2(ctx->phi, problem->node_class, ctrl, problem->speed, problem->speed_const,
+                                      ctx->ctrl2, P.args.r, n, Ppad, key, ctx->tlist, tiles_x, tiles_x, ctx->tflag,
+                                      max_inner, window, b & 1, ctx->lctl, grid, ctx->stream));
+    launched += 16;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->lctl_host, ctx->lctl, labctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->tcount_host[0] == 0) break;
-    if (passes > max_passes) return fail(ctx, SLHJB_E_HIP, "labeler did not settle (internal error)");
+    if (ctx->lctl_host[7]) break;  // done
+    if (launched > max_passes) return fail(ctx, SLHJB_E_HIP, "labeler did not settle (internal error)");
   }
+  const int64_t passes = ctx->lctl_host[8];
   HIP_TRY(ctx, launch_label_argmax((const uint16_t*)ctx->phi, N, Ppad, label_out, overlap_out, tau_q15, ctx->stream));
   if (phi_out)
     HIP_TRY(ctx, hipMemcpy2DAsync(phi_out, sizeof(uint16_t) * n_patches, ctx->phi, sizeof(uint16_t) * Ppad,
@@ -699,7 +729,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
   if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
       opts->tile_shape < 0 || opts->tile_shape > 2 || opts->persistent < 0 || opts->persistent > 1 ||
-      opts->max_workgroups < 0)
+      opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1)
     return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
   if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
     return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
@@ -758,6 +788,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   double resid = INFINITY;
   int status = SLHJB_NOT_CONVERGED;
   int64_t coop_updates = -1;
+  double visit_sec = 0.0;
   if (opts->persistent) {
     if (!ctx->coop) {
       HIP_TRY(ctx, hipMalloc(&ctx->coop, coop_state_bytes()));
@@ -795,37 +826,57 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     }
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HIP_TRY(ctx, launch_tilectl_init(ctx->tctl, ctx->stream));
+    const bool timing = opts->collect_kernel_time != 0;
+    if (timing && !ctx->tev[0])
+      for (auto& e : ctx->tev) HIP_TRY(ctx, hipEventCreate(&e));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
-    for (int b = 0; b < kBatch && ce == hipSuccess; ++b)
-      ce = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label, keyed ? ctx->tkey : nullptr,
-                               ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange, ctx->tflag, max_inner, tol_inner,
-                               act, window, (float)tol, b & 1, ctx->tctl, grid, ctx->cap_stream);
-    hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
-    if (ce != hipSuccess) return hip_fail(ctx, ce, "capture of the tile passes");
-    if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-      hipGraphDestroy(graph);
-      return hip_fail(ctx, ie, "hipGraphInstantiate");
+    // With kernel timing the same passes are launched directly on the context stream with events
+    // around every visit launch (events recorded inside a captured graph cannot be timed).
+    auto enqueue_batch = [&](hipStream_t s, bool ev) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int b = 0; b < kBatch && e == hipSuccess; ++b)
+        e = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label,
+                                keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange,
+                                ctx->tflag, max_inner, tol_inner, act, window, (float)tol, b & 1, ctx->tctl, grid,
+                                ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr, s);
+      return e;
+    };
+    if (!timing) {
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = enqueue_batch(ctx->cap_stream, false);
+      hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+      if (ce != hipSuccess) return hip_fail(ctx, ce, "capture of the tile passes");
+      if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(ctx, ie, "hipGraphInstantiate");
+      }
     }
     hipError_t le = hipSuccess;
     unsigned done = 0, dev_passes = 0;
     while (true) {
-      le = hipGraphLaunch(exec, ctx->stream);
+      le = timing ? enqueue_batch(ctx->stream, true) : hipGraphLaunch(exec, ctx->stream);
       if (le != hipSuccess) break;
       le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
       if (le != hipSuccess) break;
       le = hipStreamSynchronize(ctx->stream);
       if (le != hipSuccess) break;
+      if (timing) {
+        for (int b = 0; b < kBatch && le == hipSuccess; ++b) {
+          float ms = 0.0f;
+          le = hipEventElapsedTime(&ms, ctx->tev[2 * b], ctx->tev[2 * b + 1]);
+          visit_sec += ms * 1e-3;
+        }
+        if (le != hipSuccess) break;
+      }
       done = ctx->tctl_host[9];
       dev_passes = ctx->tctl_host[10];
       if (done || (int64_t)dev_passes >= max_passes) break;
     }
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
     if (le != hipSuccess) return hip_fail(ctx, le, "tile pass graph");
     passes = dev_passes;
     float r;
@@ -858,6 +909,8 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     stats->status = status;
     stats->kernel_path = P.path;
     stats->halo = P.args.halo;
+    stats->sweep_seconds = visit_sec;
+    stats->sweep_launches = visit_sec > 0.0 ? passes : 0;
   }
   return status;
 }

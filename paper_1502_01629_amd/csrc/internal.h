@@ -58,10 +58,14 @@ hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_
 hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t count, int P, uint32_t* phi32,
                              hipStream_t s);
 size_t label_pass_lds_bytes(int P);
-hipError_t launch_label_pass(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
-                             float speed_const, const float2* ctab, float r, int n, int P, const int* list,
-                             const int* count, int tiles_x, int tiles_y, uint8_t* next_flag, int max_inner,
-                             unsigned* changed_any, int grid, hipStream_t s);
+size_t labctl_bytes();
+hipError_t launch_labctl_init(void* c, hipStream_t s);
+hipError_t launch_label_keys(const float* vhat, const uint8_t* cls, int n, int tiles_x, int tiles_y, float vstar,
+                             float lambda, float* key, hipStream_t s);
+hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
+                              float speed_const, const float2* ctab, float r, int n, int P, const float* key, int* list,
+                              int tiles_x, int tiles_y, uint8_t* flag, int max_inner, float window, int q, void* ctl,
+                              int grid, hipStream_t s);
 hipError_t launch_compact_flags(uint8_t* flag, int count, int* list, int* out_count, hipStream_t s);
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
                                uint16_t tau, hipStream_t s);
@@ -93,7 +97,8 @@ hipError_t launch_tilectl_init(void* ctl, hipStream_t s);
 hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
-                               float window, float tol, int q, void* ctl, int grid, hipStream_t s);
+                               float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
+                               hipEvent_t ev_after, hipStream_t s);
 hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,

@@ -115,36 +115,119 @@ constexpr int kLabTile = 16;  // 16 x 16 nodes per tile
 constexpr int kLabHalo = 2;
 constexpr int kLabSpan = kLabTile + 2 * kLabHalo;
 
-// One pass over the active tiles of the labeler. Each workgroup loads its tile plus a halo of
-// phi into LDS, iterates the in-place update on its FREE nodes until nothing changes (or
-// max_inner iterations), writes the tile back, and flags itself and its neighbours for the next
-// pass if anything changed. P <= 64 and even.
-__global__ __launch_bounds__(256) void label_pass_kernel(uint32_t* __restrict__ phi32, const uint8_t* __restrict__ cls,
-                                                         const int16_t* __restrict__ ctrl,
-                                                         const float* __restrict__ speed, float speed_const,
-                                                         const float2* __restrict__ ctab, float r, int n, int P,
-                                                         const int* __restrict__ list, const int* __restrict__ count,
-                                                         int tiles_x, int tiles_y, uint8_t* __restrict__ next_flag,
-                                                         int max_inner, unsigned* __restrict__ changed_any) {
+// Labeler pass control, driven on the device (as the solver's passes): `select` takes the flagged
+// tiles whose u_hat key is within the band, `visit` runs them; an empty band with flagged tiles
+// left moves the band up to their smallest key, and no flagged tile at all ends the iteration.
+struct LabCtl {
+  unsigned count[2];
+  unsigned nflag[2];
+  unsigned kmin[2];
+  unsigned bound;
+  unsigned done;
+  unsigned passes;
+  unsigned pad;
+};
+
+__global__ void labctl_init_kernel(LabCtl* c) {
+  c->count[0] = c->count[1] = 0u;
+  c->nflag[0] = c->nflag[1] = 0u;
+  c->kmin[0] = c->kmin[1] = 0x7f800000u;
+  c->bound = 0xff800000u;
+  c->done = 0u;
+  c->passes = 0u;
+  c->pad = 0u;
+}
+
+// A selected tile's flag is cleared here, not in the visit kernel: visits set the flags of
+// their neighbours, and a clear in the same launch could erase a neighbour's request.
+__global__ void labctl_select_kernel(uint8_t* __restrict__ flag, const float* __restrict__ key, int tiles, int q,
+                                     int* __restrict__ list, LabCtl* __restrict__ c) {
+  if (c->done) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const float B = key ? __uint_as_float(c->bound) : INFINITY;
+  bool fl = false, on = false;
+  float k = INFINITY;
+  if (t < tiles && flag[t]) {
+    fl = true;
+    if (key) k = key[t];
+    on = !key || k <= B;
+  }
+  const unsigned long long fmask = __ballot(fl), mask = __ballot(on);
+  const int lane = threadIdx.x & 63;
+  if (key) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
+  }
+  int base = 0;
+  if (lane == 0) {
+    if (fmask) atomicAdd(&c->nflag[q], (unsigned)__popcll(fmask));
+    if (key && k < INFINITY) atomicMin(&c->kmin[q], __float_as_uint(k));
+    if (mask) base = atomicAdd(&c->count[q], (unsigned)__popcll(mask));
+  }
+  base = __shfl(base, 0, 64);
+  if (on) {
+    list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
+    flag[t] = 0;
+  }
+}
+
+// One visit per selected tile: stage phi of the tile and a halo in LDS, iterate the in-place
+// update on the tile's FREE nodes until nothing changes (or max_inner), write the tile back and
+// flag the neighbours (and the tile itself if it did not settle) when anything changed. Only the
+// words (patch pairs) that are nonzero somewhere in the staged region can become nonzero, so the
+// iteration walks those words only. P <= 64, even.
+__global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__ phi32, const uint8_t* __restrict__ cls,
+                                                          const int16_t* __restrict__ ctrl,
+                                                          const float* __restrict__ speed, float speed_const,
+                                                          const float2* __restrict__ ctab, float r, int n, int P,
+                                                          const int* __restrict__ list, int tiles_x, int tiles_y,
+                                                          uint8_t* __restrict__ flag, int max_inner, float window, int q,
+                                                          LabCtl* __restrict__ c) {
+  if (c->done) return;
   extern __shared__ uint32_t lds[];
+  __shared__ unsigned smask;
+  __shared__ int act[32];
+  __shared__ int nact;
+  const int cnt = (int)c->count[q];
+  const int nf = (int)c->nflag[q];
+  if (cnt == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (nf > 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
+      else c->done = 1u;
+      c->count[q ^ 1] = 0u;
+      c->nflag[q ^ 1] = 0u;
+      c->kmin[q ^ 1] = 0x7f800000u;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->passes += 1u;
+    c->count[q ^ 1] = 0u;
+    c->nflag[q ^ 1] = 0u;
+    c->kmin[q ^ 1] = 0x7f800000u;
+  }
   const int half = P >> 1;
   uint32_t* tile = lds;                                               // kLabSpan^2 * half words
   int* fbase = (int*)(lds + kLabSpan * kLabSpan * half);              // 256 ints
   uint32_t* fw = (uint32_t*)(fbase + kLabTile * kLabTile);            // 256 packed (fx | fy << 16)
-  const int total = *count;
-  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
     const int tid = list[slot];
     const int tx = tid % tiles_x, ty = tid / tiles_x;
     const int x0 = tx * kLabTile - kLabHalo, y0 = ty * kLabTile - kLabHalo;
-    // stage phi of the tile and its halo; nodes outside the grid read 0
+    if (threadIdx.x == 0) smask = 0u;
+    __syncthreads();
+    // stage phi of the tile and its halo (nodes outside the grid read 0), noting nonzero words
+    unsigned mymask = 0u;
     for (int w = threadIdx.x; w < kLabSpan * kLabSpan * half; w += blockDim.x) {
-      const int node = w / half, q = w - node * half;
+      const int node = w / half, qw = w - node * half;
       const int ly = node / kLabSpan, lx = node - ly * kLabSpan;
       const int gx = x0 + lx, gy = y0 + ly;
       uint32_t val = 0u;
-      if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[((size_t)gy * n + gx) * half + q];
+      if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[((size_t)gy * n + gx) * half + qw];
       tile[w] = val;
+      mymask |= (val != 0u ? 1u : 0u) << qw;
     }
+    if (mymask) atomicOr(&smask, mymask);
     // feet of the tile's FREE nodes
     {
       const int ln = threadIdx.x;  // 256 threads = 256 tile nodes
@@ -172,62 +255,116 @@ __global__ __launch_bounds__(256) void label_pass_kernel(uint32_t* __restrict__ 
       fw[ln] = packed;
     }
     __syncthreads();
-    // in-place iteration: thread -> (node, word); the block covers blockDim/half nodes per step
-    const int per_step = blockDim.x / half;
-    const int q = threadIdx.x % half;
+    if (threadIdx.x == 0) {
+      int k = 0;
+      for (int b = 0; b < half; ++b)
+        if (smask & (1u << b)) act[k++] = b;
+      nact = k;
+    }
+    __syncthreads();
+    const int A = nact;
     int it = 0, last = 0, ever = 0;
-    for (;;) {
-      int ch = 0;
-      for (int ln = threadIdx.x / half; ln < kLabTile * kLabTile; ln += per_step) {
-        const int base = fbase[ln];
-        if (base < 0) continue;
-        const uint32_t pk = fw[ln];
-        const uint32_t fx = pk & 0xffffu, fy = pk >> 16;
-        const uint32_t w00 = (256u - fx) * (256u - fy), w10 = fx * (256u - fy);
-        const uint32_t w01 = (256u - fx) * fy, w11 = fx * fy;
-        const uint32_t c00 = tile[base * half + q], c10 = tile[(base + 1) * half + q];
-        const uint32_t c01 = tile[(base + kLabSpan) * half + q], c11 = tile[(base + kLabSpan + 1) * half + q];
-        const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
-                              w11 * (c11 & 0xffffu) + 32768u) >> 16);
-        const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
-                              32768u) >> 16);
-        const uint32_t nv = lo | (hi << 16);
-        const int ly = ln >> 4, lx = ln & (kLabTile - 1);
-        const int self = ((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + q;
-        if (nv != tile[self]) {
-          tile[self] = nv;
-          ch = 1;
+    if (A > 0) {
+      for (;;) {
+        int ch = 0;
+        for (int item = threadIdx.x; item < kLabTile * kLabTile * A; item += blockDim.x) {
+          const int ln = item / A;
+          const int qw = act[item - ln * A];
+          const int base = fbase[ln];
+          if (base < 0) continue;
+          const uint32_t pk = fw[ln];
+          const uint32_t fx = pk & 0xffffu, fy = pk >> 16;
+          const uint32_t w00 = (256u - fx) * (256u - fy), w10 = fx * (256u - fy);
+          const uint32_t w01 = (256u - fx) * fy, w11 = fx * fy;
+          const uint32_t c00 = tile[base * half + qw], c10 = tile[(base + 1) * half + qw];
+          const uint32_t c01 = tile[(base + kLabSpan) * half + qw], c11 = tile[(base + kLabSpan + 1) * half + qw];
+          const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
+                                w11 * (c11 & 0xffffu) + 32768u) >> 16);
+          const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
+                                32768u) >> 16);
+          const uint32_t nv = lo | (hi << 16);
+          const int ly = ln >> 4, lx = ln & (kLabTile - 1);
+          const int self = ((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + qw;
+          if (nv != tile[self]) {
+            tile[self] = nv;
+            ch = 1;
+          }
         }
+        last = __syncthreads_or(ch);  // barrier + block-wide OR
+        ever |= last;
+        ++it;
+        if (!last || it >= max_inner) break;
       }
-      last = __syncthreads_or(ch);  // barrier + block-wide OR
-      ever |= last;
-      ++it;
-      if (!last || it >= max_inner) break;
     }
     const bool converged_here = (last == 0);
-    // write the tile back (interior nodes only)
-    for (int w = threadIdx.x; w < kLabTile * kLabTile * half; w += blockDim.x) {
-      const int node = w / half, q = w - node * half;
-      const int ly = node / kLabTile, lx = node - ly * kLabTile;
-      const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
-      if (gx < n && gy < n)
-        phi32[((size_t)gy * n + gx) * half + q] = tile[((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + q];
-    }
-    if (threadIdx.x == 0) {
-      if (ever) {
-        // neighbours read this tile as their halo; the tile itself continues if it did not settle
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int nx = tx + dx, ny = ty + dy;
-            if (nx < 0 || ny < 0 || nx >= tiles_x || ny >= tiles_y) continue;
-            if (dx == 0 && dy == 0 && converged_here) continue;
-            next_flag[ny * tiles_x + nx] = 1;
-          }
-        atomicOr(changed_any, 1u);
+    // write back the words that can have changed (interior nodes only)
+    if (ever) {
+      for (int item = threadIdx.x; item < kLabTile * kLabTile * A; item += blockDim.x) {
+        const int node = item / A, qw = act[item - node * A];
+        const int ly = node / kLabTile, lx = node - ly * kLabTile;
+        const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
+        if (gx < n && gy < n)
+          phi32[((size_t)gy * n + gx) * half + qw] = tile[((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + qw];
       }
+    }
+    if (threadIdx.x == 0 && ever) {
+      // neighbours read this tile as their halo; the tile itself continues if it did not settle
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int nx = tx + dx, ny = ty + dy;
+          if (nx < 0 || ny < 0 || nx >= tiles_x || ny >= tiles_y) continue;
+          if (dx == 0 && dy == 0 && converged_here) continue;
+          flag[ny * tiles_x + nx] = 1;
+        }
     }
     __syncthreads();
   }
+}
+
+// u_hat key of a labeler tile: the smallest arrival time -ln(1 - v/V*)/lambda over its FREE nodes.
+__global__ __launch_bounds__(256) void label_keys_kernel(const float* __restrict__ vhat, const uint8_t* __restrict__ cls,
+                                                         int n, int tiles_x, float vstar, float lambda,
+                                                         float* __restrict__ key) {
+  __shared__ float red[4];
+  const int tid = blockIdx.x;
+  const int tx = tid % tiles_x, ty = tid / tiles_x;
+  const int gx = tx * kLabTile + (threadIdx.x & (kLabTile - 1)), gy = ty * kLabTile + (threadIdx.x >> 4);
+  float best = INFINITY;
+  if (gx < n && gy < n) {
+    const size_t idx = (size_t)gy * n + gx;
+    const float w = vstar - vhat[idx];
+    if (cls[idx] == kFree && w > 0.0f) best = -logf(w / vstar) / lambda;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) key[tid] = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+}
+
+size_t labctl_bytes() { return sizeof(LabCtl); }
+
+hipError_t launch_labctl_init(void* c, hipStream_t s) {
+  labctl_init_kernel<<<1, 1, 0, s>>>((LabCtl*)c);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_keys(const float* vhat, const uint8_t* cls, int n, int tiles_x, int tiles_y, float vstar,
+                             float lambda, float* key, hipStream_t s) {
+  label_keys_kernel<<<tiles_x * tiles_y, 256, 0, s>>>(vhat, cls, n, tiles_x, vstar, lambda, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
+                              float speed_const, const float2* ctab, float r, int n, int P, const float* key, int* list,
+                              int tiles_x, int tiles_y, uint8_t* flag, int max_inner, float window, int q, void* ctl,
+                              int grid, hipStream_t s) {
+  const int tiles = tiles_x * tiles_y;
+  labctl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, q, list, (LabCtl*)ctl);
+  label_visit_kernel<<<grid, 256, label_pass_lds_bytes(P), s>>>(phi32, cls, ctrl, speed, speed_const, ctab, r, n, P,
+                                                                list, tiles_x, tiles_y, flag, max_inner, window, q,
+                                                                (LabCtl*)ctl);
+  return hipGetLastError();
 }
 
 // Compact the flagged tiles into a list (order irrelevant: the fixed point does not depend on
@@ -276,16 +413,6 @@ hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t cou
 
 size_t label_pass_lds_bytes(int P) {
   return sizeof(uint32_t) * (size_t)kLabSpan * kLabSpan * (P / 2) + sizeof(int) * 256 + sizeof(uint32_t) * 256;
-}
-
-hipError_t launch_label_pass(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
-                             float speed_const, const float2* ctab, float r, int n, int P, const int* list,
-                             const int* count, int tiles_x, int tiles_y, uint8_t* next_flag, int max_inner,
-                             unsigned* changed_any, int grid, hipStream_t s) {
-  label_pass_kernel<<<grid, 256, label_pass_lds_bytes(P), s>>>(phi32, cls, ctrl, speed, speed_const, ctab, r, n, P,
-                                                               list, count, tiles_x, tiles_y, next_flag, max_inner,
-                                                               changed_any);
-  return hipGetLastError();
 }
 
 hipError_t launch_compact_flags(uint8_t* flag, int count, int* list, int* out_count, hipStream_t s) {

@@ -828,10 +828,11 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                       const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                       float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                       float act, float window, float tol, int q, TileCtl* c, int grid,
-                                      hipStream_t s) {
+                                      hipEvent_t ev_before, hipEvent_t ev_after, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   tilectl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, tol, q, list, c);
   const size_t lds = tile_pass_lds_bytes(TW, TH, a.halo, indep);
+  if (ev_before) hipEventRecord(ev_before, s);
 #define SLHJB_TV(D, S, PA, IN)                                                                                     \
   tilectl_visit_kernel<TW, TH, D, S, PA, IN><<<grid, kThreads, lds, s>>>(a, a.w_in, a.speed, a.cls, a.ctrl, label, \
                                                                          list, tiles_x, tiles, outbuf, tchange,    \
@@ -853,6 +854,7 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
 #undef SLHJB_TV_I
 #undef SLHJB_TV_S
 #undef SLHJB_TV
+  if (ev_after) hipEventRecord(ev_after, s);
   tilectl_commit_kernel<<<grid, kThreads, 0, s>>>(list, TW, TH, tiles_x, tiles_y, a.n, outbuf, tchange, act, a.cls,
                                                   const_cast<float*>(a.w_in), flag, q, c);
 }
@@ -860,16 +862,20 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
 hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
-                               float window, float tol, int q, void* ctl, int grid, hipStream_t s) {
+                               float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
+                               hipEvent_t ev_after, hipStream_t s) {
   if (shape == 2)
     launch_tilectl_pass_shape<8, 8>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                    tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, s);
+                                    tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
+                                    ev_after, s);
   else if (shape == 1)
     launch_tilectl_pass_shape<16, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, s);
+                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
+                                    ev_after, s);
   else
     launch_tilectl_pass_shape<32, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, s);
+                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
+                                    ev_after, s);
   return hipGetLastError();
 }
 

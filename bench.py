@@ -150,7 +150,7 @@ def main():
     flop_per_update = RL.sweep_flops_per_node_update(fine.diffusion, scheme, fine.n_controls)
     avg_launch = visit_s / visit_launches
     achieved = fine_updates * flop_per_update / visit_s / 1e12
-    kernel = "tilectl_visit_kernel<16,16,NONE,SL3,first-ring>"
+    kernel = "tilectl_visit_kernel<16,16,split 2,NONE,SL3,first-ring>"
     traffic = measured_traffic(kernel)
 
     out = {

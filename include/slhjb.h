@@ -134,10 +134,12 @@ typedef struct {
     int32_t mode;               /* SLHJB_MODE_*                                                   */
     const int16_t* label;       /* device int16[n*n] patch labels; needed for INDEPENDENT         */
     float key_slack;            /* band width of arrival times (ORDER_KEYS); < 0 = the time to
-                                   cross one tile height at the fastest speed                     */
+                                   cross max(16, (n-1)/16) cells at the fastest speed             */
     int32_t max_inner;          /* Jacobi iterations per tile visit; 0 = 2 (tile width + height)  */
-    int32_t tile_shape;         /* 0: 32x16 nodes, 1: 16x16 nodes, 2: 8x8 nodes with the control
-                                   set split over the workgroup's four wavefronts                 */
+    int32_t tile_shape;         /* 0: 32x16 nodes, 1: 16x16 nodes (one node per thread, 256
+                                   threads); 2: 8x8 nodes with the control set split over four
+                                   groups of wavefronts (256 threads); 3: 16x16 split over four
+                                   (1024 threads); 4: 16x16 split over two (512 threads)      */
     int32_t persistent;         /* 1: the whole iteration in one cooperative launch (grid barriers
                                    between phases); 0: one launch per phase, driven by the host   */
     int32_t max_workgroups;     /* persistent launch: cap on co-resident workgroups; 0 = 1024     */

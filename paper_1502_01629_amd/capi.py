@@ -81,6 +81,8 @@ class TileOpts(ctypes.Structure):
 
 
 ORDER_NONE, ORDER_KEYS = 0, 1
+# tile shapes of the active-tile solver (slhjb_tile_opts.tile_shape)
+TILE_32x16, TILE_16x16, TILE_8x8_SPLIT4, TILE_16x16_SPLIT4, TILE_16x16_SPLIT2 = 0, 1, 2, 3, 4
 PATCHY_TRANSMISSION, PATCHY_INDEPENDENT, PATCHY_STATIC = 0, 1, 2
 
 
@@ -276,7 +278,7 @@ class Context:
 
     def solve_tiles(self, prob: DeviceProblem, v, tol: float = 1e-6, max_passes: int = 1_000_000,
                     order: int = ORDER_NONE, mode: int = MODE_TRANSMISSION, label=None, key_slack: float = -1.0,
-                    max_inner: int = 0, tile_shape: int = 1, persistent: int = 0, max_workgroups: int = 0,
+                    max_inner: int = 0, tile_shape: int = TILE_16x16_SPLIT2, persistent: int = 0, max_workgroups: int = 0,
                     collect_kernel_time: int = 0):
         opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner, tile_shape,
                         persistent, max_workgroups, collect_kernel_time)
@@ -288,7 +290,7 @@ class Context:
 
     def solve_patchy(self, fine: DeviceProblem, coarse: DeviceProblem | None, v, mode: int = PATCHY_TRANSMISSION,
                      tol: float = 1e-6, tol_coarse: float = 1e-7, source_patch=None, n_patches: int = 0,
-                     label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = 1,
+                     label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = TILE_16x16_SPLIT2,
                      collect_kernel_time: int = 0):
         opts = PatchyOpts(mode, n_patches, _ptr(source_patch) if source_patch is not None else None, tol, tol_coarse,
                           max_passes, key_window, tile_shape, collect_kernel_time)

@@ -728,7 +728,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!v || !opts) return fail(ctx, SLHJB_E_INVALID_ARG, "v and opts must be non-NULL");
   if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
   if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
-      opts->tile_shape < 0 || opts->tile_shape > 2 || opts->persistent < 0 || opts->persistent > 1 ||
+      opts->tile_shape < 0 || opts->tile_shape >= kTileShapes || opts->persistent < 0 || opts->persistent > 1 ||
       opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1)
     return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
   if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
@@ -742,7 +742,8 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   const int n = problem->n;
   const int64_t N = (int64_t)n * n;
   const int shape = opts->tile_shape;
-  const int tw = shape == 2 ? 8 : (shape == 1 ? 16 : 32), th = shape == 2 ? 8 : 16;
+  const TileShape sh = tile_shape_of(shape);
+  const int tw = sh.tw, th = sh.th;
   const int tiles_x = (n + tw - 1) / tw, tiles_y = (n + th - 1) / th;
   const int tiles = tiles_x * tiles_y;
   st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)tiles * tw * th);
@@ -770,7 +771,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
                            : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max_of(ctx, problem));
   (void)speed_min;
   const int grid = std::min(tiles, 2048);
-  const size_t lds = tile_pass_lds_bytes(tw, th, P.args.halo, indep);
+  const size_t lds = tile_pass_lds_bytes(sh, P.args.halo, indep);
   if (lds > 64 * 1024) return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
 
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));

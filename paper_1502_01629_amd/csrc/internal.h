@@ -66,26 +66,22 @@ hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t
                               float speed_const, const float2* ctab, float r, int n, int P, const float* key, int* list,
                               int tiles_x, int tiles_y, uint8_t* flag, int max_inner, float window, int q, void* ctl,
                               int grid, hipStream_t s);
-hipError_t launch_compact_flags(uint8_t* flag, int count, int* list, int* out_count, hipStream_t s);
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
                                uint16_t tau, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int count, hipStream_t s);
 constexpr int kLabelTile = 16;
 
-// Active-tile solver (tiles.hip). Tile shapes: 0 = 32 x 16 nodes, 1 = 16 x 16 nodes.
-size_t tile_pass_lds_bytes(int tw, int th, int halo, bool indep);
-hipError_t launch_tile_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
-                            const int16_t* label, const int* list, const int* count, int tiles_x, float* outbuf,
-                            float* tchange, uint8_t* flag, int max_inner, float tol_inner, unsigned long long* updates,
-                            int grid, hipStream_t s);
-hipError_t launch_tile_commit(const int* list, const int* count, int tw, int th, int tiles_x, int tiles_y, int n,
-                              const float* outbuf, const float* tchange, float act, const uint8_t* cls, float* w,
-                              uint8_t* flag, unsigned* resid, unsigned* pass_counter, int grid, hipStream_t s);
-hipError_t launch_tile_select(const uint8_t* flag, const float* key, int tiles, unsigned* kmin, unsigned* bound,
-                              float window, int* list, int* count, hipStream_t s);
+// Active-tile solver (tiles.hip). Tile shapes: 0 = 32 x 16 nodes, 1 = 16 x 16 nodes (one node
+// per lane, 256 threads), 2 = 8 x 8 nodes with the controls split over 4 groups of wavefronts
+// (256 threads), 3 = 16 x 16 split over 4 (1024 threads), 4 = 16 x 16 split over 2 (512 threads).
+struct TileShape {
+  int tw, th, split, threads;
+};
+constexpr int kTileShapes = 5;
+TileShape tile_shape_of(int shape);
+size_t tile_pass_lds_bytes(const TileShape& sh, int halo, bool indep);
 hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int tw, int th, int n, int tiles_x, int tiles_y,
                             float vstar, float lambda, float* key, hipStream_t s);
-hipError_t launch_iota(int* p, int count, int* count_out, hipStream_t s);
 // The whole iteration in one cooperative launch; `state` is device memory of coop_state_bytes(),
 // initialised by the caller: {count 0, kmin +inf, bound -inf, resid 0, passes 0, status 0, updates 0}.
 size_t coop_state_bytes();

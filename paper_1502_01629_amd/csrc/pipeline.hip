@@ -367,24 +367,6 @@ hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t
   return hipGetLastError();
 }
 
-// Compact the flagged tiles into a list (order irrelevant: the fixed point does not depend on
-// it), clearing the flags.
-__global__ void compact_flags_kernel(uint8_t* __restrict__ flag, int count, int* __restrict__ list,
-                                     int* __restrict__ out_count) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool on = false;
-  if (t < count) {
-    on = flag[t] != 0;
-    if (on) flag[t] = 0;
-  }
-  const unsigned long long mask = __ballot(on);
-  const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0 && mask) base = atomicAdd(out_count, __popcll(mask));
-  base = __shfl(base, 0, 64);
-  if (on) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
-}
-
 __global__ void label_argmax_kernel(const uint16_t* __restrict__ phi, int64_t count, int P, int16_t* __restrict__ label,
                                     uint64_t* __restrict__ overlap, uint16_t tau) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -413,11 +395,6 @@ hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t cou
 
 size_t label_pass_lds_bytes(int P) {
   return sizeof(uint32_t) * (size_t)kLabSpan * kLabSpan * (P / 2) + sizeof(int) * 256 + sizeof(uint32_t) * 256;
-}
-
-hipError_t launch_compact_flags(uint8_t* flag, int count, int* list, int* out_count, hipStream_t s) {
-  compact_flags_kernel<<<(count + 255) / 256, 256, 0, s>>>(flag, count, list, out_count);
-  return hipGetLastError();
 }
 
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,

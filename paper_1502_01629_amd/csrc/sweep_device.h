@@ -219,17 +219,17 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
 
 
 // ---- partial updates over a subset of the controls ---------------------------------------------
-// The workgroup of the 8x8-tile solver gives each of its four wavefronts one quarter of the
-// control set for the same 64 nodes; the partial results are combined through LDS. For the
-// first-ring path a quarter is one quadrant, for the general path a contiguous quarter of the
-// (padded) control list, so every wavefront still walks a uniform control range with scalar loads.
+// The split-tile visits give each group of wavefronts one part of the control set for the same
+// nodes; the partial results are combined through LDS. For the first-ring path a part is a range
+// of whole quadrants [q_lo, q_hi), for the general path a contiguous slice of the (padded)
+// control list, so every wavefront still walks a uniform control range with scalar loads.
 // Partial of SL2 (first ring): max over the range of I - w00; of SL2 (general): max of the feet
 // sum; of SL3: the best quotient as (num, den).
 template <int SCHEME, bool EDGE, bool INDEP>
 __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int LW, float k,
                                               const float4* __restrict__ ctrl, const SweepArgs& a, bool lft, bool rgt,
-                                              bool bot, bool top, const int16_t* __restrict__ L, int qsel,
-                                              float& pnum, float& pden) {
+                                              bool bot, bool top, const int16_t* __restrict__ L, int q_lo,
+                                              int q_hi, float& pnum, float& pden) {
   const float w00 = T[0];
   float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
   float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
@@ -257,7 +257,7 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (q != qsel) continue;  // uniform across the wavefront
+    if (q < q_lo || q >= q_hi) continue;  // uniform across the wavefront
     float B, C, D;
     if (SCHEME == kSL2) {
       B = k * sx[q] * (wX[q] - w00);

@@ -1,7 +1,7 @@
 // Active-tile solver: the GPU form of the paper's per-patch computation with a fast-marching-like
 // order (Section 4.2 "The role of causality", Section 4.3 computation step).
 //
-// The grid is cut into 32 x 16 node tiles. A pass takes a list of tiles; each workgroup stages
+// The grid is cut into tiles (32 x 16, 16 x 16 or 8 x 8 nodes). A pass takes a list of tiles; each workgroup stages
 // its tile and an interpolation halo in LDS and runs Jacobi iterations of the scheme on the
 // tile's FREE nodes, with the halo frozen, until no node moves by more than tol_inner (or
 // max_inner iterations). Results go to a staging buffer, so every tile of a pass reads the
@@ -18,11 +18,13 @@
 
 namespace slhjb {
 
-// Visit of an 8x8 tile by a 256-thread workgroup: lane = node, wavefront = a quarter of the
-// controls (a quadrant on the first-ring path, a quarter of the list otherwise). Per inner
-// iteration the four partial maxima go through LDS and wavefront 0 combines them in a fixed
-// order, so the result does not depend on timing.
-template <int DIFF, int SCHEME, int PATH, bool INDEP>
+// Visit of a T x T tile by T*T*S threads: lane = node, S groups of wavefronts each walk one S-th
+// of the controls (whole quadrants on the first-ring path, a contiguous slice of the list
+// otherwise) for all nodes of the tile. Per inner iteration the S partial optima go through LDS
+// and the first group combines them in a fixed order, so the result does not depend on timing.
+// Splitting the controls shortens one inner iteration S times, which is what bounds a pass when
+// few tiles are selected.
+template <int T, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
 __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float* __restrict__ w,
                                                  const float* __restrict__ speed, const uint8_t* __restrict__ cls,
                                                  const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
@@ -30,20 +32,21 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
                                                  float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                                  float tol_inner, unsigned long long* __restrict__ updates, float* lds,
                                                  float* red) {
-  constexpr int kT = 8;
+  constexpr int TT = T * T, NT = TT * S;
+  static_assert(TT % 64 == 0 && (S == 2 || S == 4), "split tile shape");
   const int R = a.halo;
-  const int LW = kT + 2 * R, span = LW * LW;
+  const int LW = T + 2 * R, span = LW * LW;
   float* bufA = lds;
   float* bufB = lds + span;
   float* pn = lds + 2 * span;
-  float* pd = pn + 256;
-  int16_t* labs = (int16_t*)(pd + 256);
+  float* pd = pn + NT;
+  int16_t* labs = (int16_t*)(pd + NT);
   const int n = a.n;
-  const int node = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int node = threadIdx.x % TT, part = threadIdx.x / TT;
   const int tx = tid % tiles_x, ty = tid / tiles_x;
-  const int x0 = tx * kT, y0 = ty * kT;
+  const int x0 = tx * T, y0 = ty * T;
   if (threadIdx.x == 0) flag[tid] = 0;
-  for (int e = threadIdx.x; e < span; e += kThreads) {
+  for (int e = threadIdx.x; e < span; e += NT) {
     const int ly = e / LW, lx = e - ly * LW;
     const int gx = x0 - R + lx, gy = y0 - R + ly;
     const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
@@ -52,7 +55,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     bufB[e] = val;
     if (INDEP) labs[e] = in ? label[(size_t)gy * n + gx] : (int16_t)-32768;
   }
-  const int lx = node & (kT - 1), ly = node / kT;
+  const int lx = node % T, ly = node / T;
   const int gi = x0 + lx, gj = y0 + ly;
   const int li = (ly + R) * LW + lx + R;
   bool fr = false;
@@ -62,8 +65,9 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     fr = cls[idx] == kFree;
     if (fr) kk = a.r * (speed ? speed[idx] : a.speed_const);
   }
-  const bool interior = x0 >= 1 && x0 + kT - 1 <= n - 2 && y0 >= 1 && y0 + kT - 1 <= n - 2;
-  const int quarter = a.n_controls / 4;  // the padded list length is a multiple of 4
+  const bool interior = x0 >= 1 && x0 + T - 1 <= n - 2 && y0 >= 1 && y0 + T - 1 <= n - 2;
+  const int slice = a.n_controls / S;  // the padded list length is a multiple of 4
+  constexpr int QP = 4 / S;            // quadrants per part on the first-ring path
   __syncthreads();
   float* cur = bufA;
   float* nxt = bufB;
@@ -72,33 +76,36 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     if (fr) {
       float num, den;
       if (PATH == 1) {
-        const float* T = cur + li;
+        const float* Tp = cur + li;
         const int16_t* L = INDEP ? labs + li : nullptr;
         if (interior)
-          ring1_partial<SCHEME, false, INDEP>(T, LW, kk, ctrl, a, false, false, false, false, L, part, num, den);
+          ring1_partial<SCHEME, false, INDEP>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
+                                              part * QP + QP, num, den);
         else
-          ring1_partial<SCHEME, true, INDEP>(T, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1, L, part,
-                                             num, den);
+          ring1_partial<SCHEME, true, INDEP>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1, L,
+                                             part * QP, part * QP + QP, num, den);
       } else {
         general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                             INDEP ? labs[li] : 0, part * quarter, (part + 1) * quarter, num, den);
+                                             INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den);
       }
-      pn[part * 64 + node] = num;
-      pd[part * 64 + node] = den;
+      pn[part * TT + node] = num;
+      pd[part * TT + node] = den;
     }
     __syncthreads();
     float lmax = 0.0f;
     if (part == 0 && fr) {
       float v;
       if (SCHEME == kSL2) {
-        const float m = fmaxf(fmaxf(pn[node], pn[64 + node]), fmaxf(pn[128 + node], pn[192 + node]));
+        float m = pn[node];
+#pragma unroll
+        for (int q = 1; q < S; ++q) m = fmaxf(m, pn[q * TT + node]);
         constexpr int K = Feet<DIFF>::K;
         v = PATH == 1 ? a.beta * (cur[li] + m) : a.beta * m * (1.0f / (float)K);
       } else {
         float bn = pn[node], bd = pd[node];
 #pragma unroll
-        for (int q = 1; q < 4; ++q) {
-          const float qn = pn[q * 64 + node], qd = pd[q * 64 + node];
+        for (int q = 1; q < S; ++q) {
+          const float qn = pn[q * TT + node], qd = pd[q * TT + node];
           if (qn * bd > bn * qd) {
             bn = qn;
             bd = qd;
@@ -118,14 +125,16 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   }
   float moved = 0.0f;
   if (part == 0) {
-    outbuf[(size_t)slot * 64 + node] = cur[li];
+    outbuf[(size_t)slot * TT + node] = cur[li];
     if (fr) moved = fabsf(cur[li] - w[(size_t)gj * n + gi]);
   }
   moved = wave_max(moved);
-  if ((threadIdx.x & 63) == 0) red[part] = moved;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = moved;
   const int free_total = __syncthreads_count(part == 0 && fr);
   if (threadIdx.x == 0) {
-    const float m = red[0];
+    float m = red[0];
+#pragma unroll
+    for (int k = 1; k < TT / 64; ++k) m = fmaxf(m, red[k]);
     const bool unsettled = it >= max_inner && max_inner > 1;
     tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
     atomicAdd(updates, (unsigned long long)it * (unsigned long long)free_total);
@@ -135,7 +144,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
 
 // One visit of tile `tid`, staged into slot `slot` of outbuf/tchange: Jacobi iterations in LDS
 // against the frozen halo until no node moves by more than tol_inner (or max_inner).
-template <int TW, int TH, int DIFF, int SCHEME, int PATH, bool INDEP>
+template <int TW, int TH, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
 __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __restrict__ w,
                                            const float* __restrict__ speed, const uint8_t* __restrict__ cls,
                                            const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
@@ -143,9 +152,10 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                            float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                            float tol_inner, unsigned long long* __restrict__ updates, float* lds,
                                            float* red) {
-  if constexpr (TW * TH == 64) {
-    visit_tile_split<DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf, tchange,
-                                                flag, max_inner, tol_inner, updates, lds, red);
+  if constexpr (S > 1) {
+    static_assert(TW == TH, "split tiles are square");
+    visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf,
+                                                       tchange, flag, max_inner, tol_inner, updates, lds, red);
     return;
   } else {
   constexpr int kTW = TW, kTH = TH, kTN = TW * TH, NPT = kTN / kThreads;  // NPT nodes per thread
@@ -255,20 +265,6 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
   }
 }
 
-template <int TW, int TH, int DIFF, int SCHEME, int PATH, bool INDEP>
-__global__ __launch_bounds__(kThreads) void tile_pass_kernel(
-    SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
-    const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list,
-    const int* __restrict__ count, int tiles_x, float* __restrict__ outbuf, float* __restrict__ tchange,
-    uint8_t* __restrict__ flag, int max_inner, float tol_inner, unsigned long long* __restrict__ updates) {
-  extern __shared__ float lds[];
-  __shared__ float red[kThreads / 64];
-  const int total = *count;
-  for (int slot = blockIdx.x; slot < total; slot += gridDim.x)
-    visit_tile<TW, TH, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                  tchange, flag, max_inner, tol_inner, updates, lds, red);
-}
-
 // Write staged tile `tid` (slot `slot`) back and flag the neighbourhood of a tile that moved by
 // more than `act`; the tile itself is flagged again only if its visit stopped before settling.
 __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, int tiles_x, int tiles_y, int n,
@@ -299,59 +295,6 @@ __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, i
   }
 }
 
-__global__ __launch_bounds__(kThreads) void tile_commit_kernel(const int* __restrict__ list, const int* __restrict__ count,
-                                                               int tw, int th, int tiles_x, int tiles_y, int n,
-                                                               const float* __restrict__ outbuf,
-                                                               const float* __restrict__ tchange, float act,
-                                                               const uint8_t* __restrict__ cls, float* __restrict__ w,
-                                                               uint8_t* __restrict__ flag, unsigned* __restrict__ resid,
-                                                               unsigned* __restrict__ pass_counter) {
-  const int total = *count;
-  if (pass_counter && blockIdx.x == 0 && threadIdx.x == 0 && total > 0) atomicAdd(pass_counter, 1u);
-  for (int slot = blockIdx.x; slot < total; slot += gridDim.x)
-    commit_tile(slot, list[slot], tw, th, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, resid);
-}
-
-// Smallest key among the flagged tiles (keys are >= 0 or +inf, so their bits order like the
-// values). `kmin` must hold +inf bits before the launch.
-__global__ void tile_kmin_kernel(const uint8_t* __restrict__ flag, const float* __restrict__ key, int tiles,
-                                 unsigned* __restrict__ kmin) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  float k = INFINITY;
-  if (t < tiles && flag[t]) k = key[t];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
-  if ((threadIdx.x & 63) == 0 && k < INFINITY) atomicMin(kmin, __float_as_uint(k));
-}
-
-// The next pass: the flagged tiles; with keys only those whose key is at most the band bound B
-// (buckets of arrival times processed in increasing order: the paper's order by u_hat). B only
-// grows: when no flagged tile is left at or below it, it jumps to the smallest flagged key plus
-// `window`. Tiles re-flagged below B (their halo moved) rejoin at once. The flagged tile of
-// smallest key is always selected, so every pass makes progress. `bound` holds B (float bits,
-// -inf before the first pass); every thread derives the same new bound, block 0 stores it.
-__global__ void tile_select_kernel(const uint8_t* __restrict__ flag, const float* __restrict__ key, int tiles,
-                                   const unsigned* __restrict__ kmin, unsigned* __restrict__ bound, float window,
-                                   int* __restrict__ list, int* __restrict__ count) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool on = false;
-  float B = INFINITY;
-  if (key) {
-    const float lo = __uint_as_float(*kmin);
-    B = __uint_as_float(*bound);
-    if (lo > B) B = lo + window;
-    if (lo == INFINITY) B = INFINITY;  // only tiles without a finite key remain
-  }
-  if (t < tiles && flag[t]) on = !key || key[t] <= B;
-  const unsigned long long mask = __ballot(on);
-  const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0 && mask) base = atomicAdd(count, __popcll(mask));
-  base = __shfl(base, 0, 64);
-  if (on) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
-  if (key && t == 0 && B < INFINITY) *bound = __float_as_uint(B);
-}
-
 // Key of a tile: the smallest arrival time T = -ln(w / V*) / lambda over its FREE nodes
 // (+inf where w <= 0, i.e. not reached).
 __global__ __launch_bounds__(kThreads) void tile_keys_kernel(const float* __restrict__ w, const uint8_t* __restrict__ cls,
@@ -380,88 +323,20 @@ __global__ __launch_bounds__(kThreads) void tile_keys_kernel(const float* __rest
   }
 }
 
-size_t tile_pass_lds_bytes(int tw, int th, int halo, bool indep) {
-  const size_t span = (size_t)(tw + 2 * halo) * (th + 2 * halo);
-  const size_t partials = tw * th == 64 ? 2 * 256 * sizeof(float) : 0;
+size_t tile_pass_lds_bytes(const TileShape& sh, int halo, bool indep) {
+  const size_t span = (size_t)(sh.tw + 2 * halo) * (sh.th + 2 * halo);
+  const size_t partials = sh.split > 1 ? 2 * (size_t)sh.threads * sizeof(float) : 0;
   return 2 * span * sizeof(float) + partials + (indep ? span * sizeof(int16_t) : 0);
 }
 
-template <int TW, int TH>
-static void launch_tile_pass_shape(const SweepArgs& a, int diffusion, int scheme, int path, bool indep,
-                                   const int16_t* label, const int* list, const int* count, int tiles_x, float* outbuf,
-                                   float* tchange, uint8_t* flag, int max_inner, float tol_inner,
-                                   unsigned long long* updates, int grid, hipStream_t s) {
-  const size_t lds = tile_pass_lds_bytes(TW, TH, a.halo, indep);
-#define SLHJB_TP(D, S, PA, IN)                                                                                      \
-  tile_pass_kernel<TW, TH, D, S, PA, IN><<<grid, kThreads, lds, s>>>(a, a.w_in, a.speed, a.cls, a.ctrl, label, list, \
-                                                                     count, tiles_x, outbuf, tchange, flag, max_inner, \
-                                                                     tol_inner, updates)
-#define SLHJB_TP_S(D, PA, IN)                      \
-  do {                                             \
-    if (scheme == kSL2) SLHJB_TP(D, kSL2, PA, IN); \
-    else SLHJB_TP(D, kSL3, PA, IN);                \
-  } while (0)
-#define SLHJB_TP_I(D, PA)               \
-  do {                                  \
-    if (indep) SLHJB_TP_S(D, PA, true); \
-    else SLHJB_TP_S(D, PA, false);      \
-  } while (0)
-  if (path == 1) {
-    SLHJB_TP_I(kDiffNone, 1);
-  } else if (diffusion == kDiffNone) {
-    SLHJB_TP_I(kDiffNone, 0);
-  } else if (diffusion == kDiffIso) {
-    SLHJB_TP_I(kDiffIso, 0);
-  } else {
-    SLHJB_TP_I(kDiffRank1, 0);
+TileShape tile_shape_of(int shape) {
+  switch (shape) {
+    case 0: return {32, 16, 1, kThreads};
+    case 1: return {16, 16, 1, kThreads};
+    case 2: return {8, 8, 4, 256};
+    case 3: return {16, 16, 4, 1024};
+    default: return {16, 16, 2, 512};
   }
-#undef SLHJB_TP_I
-#undef SLHJB_TP_S
-#undef SLHJB_TP
-}
-
-hipError_t launch_tile_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
-                            const int16_t* label, const int* list, const int* count, int tiles_x, float* outbuf,
-                            float* tchange, uint8_t* flag, int max_inner, float tol_inner, unsigned long long* updates,
-                            int grid, hipStream_t s) {
-  if (shape == 2)
-    launch_tile_pass_shape<8, 8>(a, diffusion, scheme, path, indep, label, list, count, tiles_x, outbuf, tchange,
-                                 flag, max_inner, tol_inner, updates, grid, s);
-  else if (shape == 1)
-    launch_tile_pass_shape<16, 16>(a, diffusion, scheme, path, indep, label, list, count, tiles_x, outbuf, tchange,
-                                   flag, max_inner, tol_inner, updates, grid, s);
-  else
-    launch_tile_pass_shape<32, 16>(a, diffusion, scheme, path, indep, label, list, count, tiles_x, outbuf, tchange,
-                                   flag, max_inner, tol_inner, updates, grid, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_commit(const int* list, const int* count, int tw, int th, int tiles_x, int tiles_y, int n,
-                              const float* outbuf, const float* tchange, float act, const uint8_t* cls, float* w,
-                              uint8_t* flag, unsigned* resid, unsigned* pass_counter, int grid, hipStream_t s) {
-  tile_commit_kernel<<<grid, kThreads, 0, s>>>(list, count, tw, th, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w,
-                                               flag, resid, pass_counter);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_select(const uint8_t* flag, const float* key, int tiles, unsigned* kmin, unsigned* bound,
-                              float window, int* list, int* count, hipStream_t s) {
-  if (key) {
-    tile_kmin_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, kmin);
-  }
-  tile_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, kmin, bound, window, list, count);
-  return hipGetLastError();
-}
-
-__global__ void iota_kernel(int* p, int count, int* count_out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < count) p[t] = t;
-  if (t == 0) *count_out = count;
-}
-
-hipError_t launch_iota(int* p, int count, int* count_out, hipStream_t s) {
-  iota_kernel<<<(count + 255) / 256, 256, 0, s>>>(p, count, count_out);
-  return hipGetLastError();
 }
 
 hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int tw, int th, int n, int tiles_x, int tiles_y,
@@ -500,15 +375,16 @@ __device__ __forceinline__ void grid_barrier(cooperative_groups::grid_group& g) 
   __threadfence();
 }
 
-template <int TW, int TH, int DIFF, int SCHEME, int PATH, bool INDEP>
-__global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
+template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP,
+          int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
+__global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
     SweepArgs a, float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const float* __restrict__ key,
     int* __restrict__ list, int tiles_x, int tiles_y, float* __restrict__ outbuf, float* __restrict__ tchange,
     uint8_t* __restrict__ flag, int max_inner, float tol_inner, float act, float window, float tol, int max_passes,
     CoopState* __restrict__ st) {
   extern __shared__ float lds[];
-  __shared__ float red[kThreads / 64];
+  __shared__ float red[NT / 64];
   cooperative_groups::grid_group g = cooperative_groups::this_grid();
   const int tiles = tiles_x * tiles_y;
   const int n = a.n;
@@ -518,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
   while (passes < max_passes) {
     // (1) smallest flagged key
     if (keyed) {
-      for (int base = blockIdx.x * kThreads; base < tiles; base += gridDim.x * kThreads) {
+      for (int base = blockIdx.x * NT; base < tiles; base += gridDim.x * NT) {
         const int t = base + threadIdx.x;
         float k = (t < tiles && flag[t]) ? key[t] : INFINITY;
 #pragma unroll
@@ -535,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
       if (lo > B) B = lo + window;
       if (lo == INFINITY) B = INFINITY;
     }
-    for (int base = blockIdx.x * kThreads; base < tiles; base += gridDim.x * kThreads) {
+    for (int base = blockIdx.x * NT; base < tiles; base += gridDim.x * NT) {
       const int t = base + threadIdx.x;
       const bool on = t < tiles && flag[t] && (!keyed || key[t] <= B);
       const unsigned long long mask = __ballot(on);
@@ -551,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
     if (cnt > 0) {
       // (3) visits
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-        visit_tile<TW, TH, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
+        visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
                                                       tchange, flag, max_inner, tol_inner, &st->updates, lds, red);
       grid_barrier(g);
       // (4) commits; workgroup 0 resets the selection state for the next pass
@@ -567,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
     }
     // nothing flagged: check sweep of every tile, one Jacobi iteration each
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      visit_tile<TW, TH, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
                                                     flag, 1, 0.0f, &st->updates, lds, red);
     grid_barrier(g);
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
@@ -592,15 +468,16 @@ __global__ __launch_bounds__(kThreads) void tile_solve_coop_kernel(
   }
 }
 
-template <int TW, int TH, int DIFF, int SCHEME, int PATH, bool INDEP>
+template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP>
 static hipError_t launch_coop_one(const SweepArgs& a, const int16_t* label, const float* key, int* list, int tiles_x,
                                   int tiles_y, float* outbuf, float* tchange, uint8_t* flag, int max_inner,
                                   float tol_inner, float act, float window, float tol, int max_passes, CoopState* st,
                                   int max_grid, int* grid_used, hipStream_t s) {
-  auto kern = tile_solve_coop_kernel<TW, TH, DIFF, SCHEME, PATH, INDEP>;
-  const size_t lds = tile_pass_lds_bytes(TW, TH, a.halo, INDEP);
+  auto kern = tile_solve_coop_kernel<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>;
+  const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
+  const size_t lds = tile_pass_lds_bytes(sh, a.halo, INDEP);
   int per_cu = 0, dev = 0, cus = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, sh.threads, lds);
   if (e != hipSuccess) return e;
   e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -617,19 +494,19 @@ static hipError_t launch_coop_one(const SweepArgs& a, const int16_t* label, cons
   const float4* ct = a.ctrl;
   void* args[] = {&aa, &wp, &sp, &cp, &ct, (void*)&label, (void*)&key, &list, &tiles_x, &tiles_y, &outbuf,
                   &tchange, &flag, &max_inner, &tol_inner, &act, &window, &tol, &max_passes, &st};
-  return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(kThreads), args, (unsigned)lds, s);
+  return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(sh.threads), args, (unsigned)lds, s);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int SPL>
 static hipError_t launch_coop_shape(const SweepArgs& a, int diffusion, int scheme, int path, bool indep,
                                     const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                     float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                     float act, float window, float tol, int max_passes, CoopState* st, int max_grid,
                                     int* grid_used, hipStream_t s) {
-#define SLHJB_CO(D, S, PA, IN)                                                                                   \
-  return launch_coop_one<TW, TH, D, S, PA, IN>(a, label, key, list, tiles_x, tiles_y, outbuf, tchange, flag,     \
-                                               max_inner, tol_inner, act, window, tol, max_passes, st, max_grid, \
-                                               grid_used, s)
+#define SLHJB_CO(D, S, PA, IN)                                                                                        \
+  return launch_coop_one<TW, TH, SPL, D, S, PA, IN>(a, label, key, list, tiles_x, tiles_y, outbuf, tchange, flag,     \
+                                                    max_inner, tol_inner, act, window, tol, max_passes, st, max_grid, \
+                                                    grid_used, s)
 #define SLHJB_CO_S(D, PA, IN)                      \
   do {                                             \
     if (scheme == kSL2) SLHJB_CO(D, kSL2, PA, IN); \
@@ -649,23 +526,27 @@ static hipError_t launch_coop_shape(const SweepArgs& a, int diffusion, int schem
 #undef SLHJB_CO
 }
 
+#define SLHJB_FOR_SHAPE(shape, CALL) \
+  switch (shape) {                   \
+    case 0: CALL(32, 16, 1);         \
+    case 1: CALL(16, 16, 1);         \
+    case 2: CALL(8, 8, 4);           \
+    case 3: CALL(16, 16, 4);         \
+    default: CALL(16, 16, 2);        \
+  }
+
 hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                   float act, float window, float tol, int max_passes, void* state, int max_grid,
                                   int* grid_used, hipStream_t s) {
   CoopState* st = (CoopState*)state;
-  if (shape == 2)
-    return launch_coop_shape<8, 8>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                   tchange, flag, max_inner, tol_inner, act, window, tol, max_passes, st, max_grid,
-                                   grid_used, s);
-  if (shape == 1)
-    return launch_coop_shape<16, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                     tchange, flag, max_inner, tol_inner, act, window, tol, max_passes, st, max_grid,
-                                     grid_used, s);
-  return launch_coop_shape<32, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                   tchange, flag, max_inner, tol_inner, act, window, tol, max_passes, st, max_grid,
-                                   grid_used, s);
+#define SLHJB_COOP_CALL(TW, TH, SPL)                                                                                  \
+  return launch_coop_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf, \
+                                        tchange, flag, max_inner, tol_inner, act, window, tol, max_passes, st,       \
+                                        max_grid, grid_used, s)
+  SLHJB_FOR_SHAPE(shape, SLHJB_COOP_CALL)
+#undef SLHJB_COOP_CALL
 }
 
 size_t coop_state_bytes() { return sizeof(CoopState); }
@@ -759,20 +640,21 @@ __global__ void tilectl_select_kernel(const uint8_t* __restrict__ flag, const fl
   if (on) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
 }
 
-template <int TW, int TH, int DIFF, int SCHEME, int PATH, bool INDEP>
-__global__ __launch_bounds__(kThreads) void tilectl_visit_kernel(
+template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP,
+          int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
+__global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x,
     int tiles, float* __restrict__ outbuf, float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
     float tol_inner, float window, int q, TileCtl* __restrict__ c) {
   if (c->done) return;
   extern __shared__ float lds[];
-  __shared__ float red[kThreads / 64];
+  __shared__ float red[NT / 64];
   const int cnt = (int)c->count[q];
   const int nf = (int)c->nflag[q];
   if (cnt > 0) {
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-      visit_tile<TW, TH, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
                                                     tchange, flag, max_inner, tol_inner, &c->updates, lds, red);
   } else if (nf > 0) {
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
@@ -780,7 +662,7 @@ __global__ __launch_bounds__(kThreads) void tilectl_visit_kernel(
   } else {
     // nothing flagged: check sweep, one Jacobi iteration of every tile
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      visit_tile<TW, TH, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
                                                     flag, 1, 0.0f, &c->updates, lds, red);
   }
 }
@@ -823,7 +705,7 @@ hipError_t launch_tilectl_init(void* ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int SPL>
 static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int scheme, int path, bool indep,
                                       const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                       float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
@@ -831,12 +713,13 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                       hipEvent_t ev_before, hipEvent_t ev_after, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   tilectl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, tol, q, list, c);
-  const size_t lds = tile_pass_lds_bytes(TW, TH, a.halo, indep);
+  const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
+  const size_t lds = tile_pass_lds_bytes(sh, a.halo, indep);
   if (ev_before) hipEventRecord(ev_before, s);
-#define SLHJB_TV(D, S, PA, IN)                                                                                     \
-  tilectl_visit_kernel<TW, TH, D, S, PA, IN><<<grid, kThreads, lds, s>>>(a, a.w_in, a.speed, a.cls, a.ctrl, label, \
-                                                                         list, tiles_x, tiles, outbuf, tchange,    \
-                                                                         flag, max_inner, tol_inner, window, q, c)
+#define SLHJB_TV(D, S, PA, IN)                                                                              \
+  tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                            \
+      a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,     \
+      tol_inner, window, q, c)
 #define SLHJB_TV_S(D, PA, IN)                      \
   do {                                             \
     if (scheme == kSL2) SLHJB_TV(D, kSL2, PA, IN); \
@@ -864,18 +747,13 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
                                hipEvent_t ev_after, hipStream_t s) {
-  if (shape == 2)
-    launch_tilectl_pass_shape<8, 8>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                    tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
-                                    ev_after, s);
-  else if (shape == 1)
-    launch_tilectl_pass_shape<16, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
-                                    ev_after, s);
-  else
-    launch_tilectl_pass_shape<32, 16>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf,
-                                      tchange, flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid, ev_before,
-                                    ev_after, s);
+#define SLHJB_CTL_CALL(TW, TH, SPL)                                                                                  \
+  launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y,      \
+                                         outbuf, tchange, flag, max_inner, tol_inner, act, window, tol, q,           \
+                                         (TileCtl*)ctl, grid, ev_before, ev_after, s);                               \
+  break
+  SLHJB_FOR_SHAPE(shape, SLHJB_CTL_CALL)
+#undef SLHJB_CTL_CALL
   return hipGetLastError();
 }
 

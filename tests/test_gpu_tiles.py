@@ -30,7 +30,7 @@ def _uhat(fine, coarse):
     return oracle.upsample_bilinear(vc, fine.n).astype(np.float32)
 
 
-@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("eps", [0.0, 0.01])
 @pytest.mark.parametrize("scheme", [0, 1])
@@ -55,7 +55,7 @@ def test_tiles_transmission_matches_global_fixed_point(ctx, order, eps, scheme, 
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("order", [0, 1])
 def test_tiles_scattered_obstacles(ctx, order, shape):
     """Point targets, obstacles and variable speed on 257^2 (ragged tiles), cold and u_hat starts."""
@@ -83,7 +83,7 @@ def _independent_fixed_point(p, label):
     return w
 
 
-@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("shape", [1, 2, 3])
 @pytest.mark.parametrize("layout", ["sectors", "stripes"])
 def test_tiles_independent_patches_match_oracle(ctx, layout, shape):
     """State constraints at patch interfaces: the fixed point of the per-patch problems. Sectors around
@@ -119,7 +119,7 @@ def test_tiles_independent_patches_match_oracle(ctx, layout, shape):
 
 
 @pytest.mark.parametrize("order", [0, 1])
-@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_persistent_and_host_driven_agree_bit_for_bit(ctx, order, shape):
     """Both drivers read the previous pass's iterate in every visit and commit after all visits, so the
     result does not depend on which workgroup visits which tile, nor on the driver."""

@@ -97,18 +97,19 @@ hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_
 // and concurrently, climb to the same least fixed point: the kernels below update in place
 // and iterate until nothing changes.
 
-__global__ void label_init_kernel(const uint8_t* __restrict__ cls, const int16_t* __restrict__ src, int64_t count,
-                                  int P, uint32_t* __restrict__ phi32) {
-  // one thread per node; P even, so a node is P/2 uint32 words
+// One thread per uint32 word (two patches) of phi, so the stores of a wavefront are contiguous.
+__global__ void label_init_kernel(const uint8_t* __restrict__ cls, const int16_t* __restrict__ src, int64_t words,
+                                  int half, uint32_t* __restrict__ phi32) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const int half = P >> 1;
-  uint32_t* row = phi32 + t * half;
-  for (int q = 0; q < half; ++q) row[q] = 0u;
-  if (cls[t] == kTarget) {
-    const int p = src[t];
-    if (p >= 0 && p < P) row[p >> 1] = (p & 1) ? (1u << 31) : (1u << 15);
+  if (t >= words) return;
+  const int64_t node = t / half;
+  const int q = (int)(t - node * half);
+  uint32_t v = 0u;
+  if (cls[node] == kTarget) {
+    const int p = src[node];
+    if ((p >> 1) == q) v = (p & 1) ? (1u << 31) : (1u << 15);
   }
+  phi32[t] = v;
 }
 
 constexpr int kLabTile = 16;  // 16 x 16 nodes per tile
@@ -176,6 +177,10 @@ __global__ void labctl_select_kernel(uint8_t* __restrict__ flag, const float* __
 // flag the neighbours (and the tile itself if it did not settle) when anything changed. Only the
 // words (patch pairs) that are nonzero somewhere in the staged region can become nonzero, so the
 // iteration walks those words only. P <= 64, even.
+// LDS holds one plane per word, tile[qw * kLabPlane + node]: the 64 lanes of a wavefront update 64
+// neighbouring nodes of one word and read neighbouring addresses. The odd plane stride spreads the
+// banks when the staging loop writes the words of one node.
+constexpr int kLabPlane = kLabSpan * kLabSpan + 1;
 __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__ phi32, const uint8_t* __restrict__ cls,
                                                           const int16_t* __restrict__ ctrl,
                                                           const float* __restrict__ speed, float speed_const,
@@ -207,9 +212,10 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     c->kmin[q ^ 1] = 0x7f800000u;
   }
   const int half = P >> 1;
-  uint32_t* tile = lds;                                               // kLabSpan^2 * half words
-  int* fbase = (int*)(lds + kLabSpan * kLabSpan * half);              // 256 ints
-  uint32_t* fw = (uint32_t*)(fbase + kLabTile * kLabTile);            // 256 packed (fx | fy << 16)
+  uint32_t* tile = lds;  // half planes of kLabPlane words
+  // the node of this thread (256 threads = 256 tile nodes)
+  const int lx = threadIdx.x & (kLabTile - 1), ly = threadIdx.x >> 4;
+  const int self = (ly + kLabHalo) * kLabSpan + lx + kLabHalo;
   for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
     const int tid = list[slot];
     const int tx = tid % tiles_x, ty = tid / tiles_x;
@@ -220,39 +226,36 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     unsigned mymask = 0u;
     for (int w = threadIdx.x; w < kLabSpan * kLabSpan * half; w += blockDim.x) {
       const int node = w / half, qw = w - node * half;
-      const int ly = node / kLabSpan, lx = node - ly * kLabSpan;
-      const int gx = x0 + lx, gy = y0 + ly;
+      const int sy = node / kLabSpan, sx = node - sy * kLabSpan;
+      const int gx = x0 + sx, gy = y0 + sy;
       uint32_t val = 0u;
       if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[((size_t)gy * n + gx) * half + qw];
-      tile[w] = val;
+      tile[qw * kLabPlane + node] = val;
       mymask |= (val != 0u ? 1u : 0u) << qw;
     }
     if (mymask) atomicOr(&smask, mymask);
-    // feet of the tile's FREE nodes
-    {
-      const int ln = threadIdx.x;  // 256 threads = 256 tile nodes
-      const int lx = ln & (kLabTile - 1), ly = ln >> 4;
-      const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
-      int base = -1;
-      uint32_t packed = 0u;
-      if (gx < n && gy < n) {
-        const size_t idx = (size_t)gy * n + gx;
-        const int m = ctrl[idx];
-        if (cls[idx] == kFree && m >= 0) {
-          const float k = r * (speed ? speed[idx] : speed_const);
-          const float2 a = ctab[m];
-          const float px = k * a.x, py = k * a.y;
-          // |D| <= 256 for every first-ring foot (the host rejects larger reaches); the clamp only
-          // keeps the LDS reads inside the tile if that contract is broken
-          const int Dx = min(256, max(-256, (int)rintf(256.0f * px)));
-          const int Dy = min(256, max(-256, (int)rintf(256.0f * py)));
-          const int cx = lx + kLabHalo + (Dx >> 8), cy = ly + kLabHalo + (Dy >> 8);
-          base = cy * kLabSpan + cx;
-          packed = (uint32_t)(Dx & 255) | ((uint32_t)(Dy & 255) << 16);
-        }
+    // foot of this thread's node, if FREE: corner cell and Q.8 fractions
+    const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
+    int base = -1;
+    uint32_t w00 = 0u, w10 = 0u, w01 = 0u, w11 = 0u;
+    if (gx < n && gy < n) {
+      const size_t idx = (size_t)gy * n + gx;
+      const int m = ctrl[idx];
+      if (cls[idx] == kFree && m >= 0) {
+        const float k = r * (speed ? speed[idx] : speed_const);
+        const float2 a = ctab[m];
+        const float px = k * a.x, py = k * a.y;
+        // |D| <= 256 for every first-ring foot (the host rejects larger reaches); the clamp only
+        // keeps the LDS reads inside the tile if that contract is broken
+        const int Dx = min(256, max(-256, (int)rintf(256.0f * px)));
+        const int Dy = min(256, max(-256, (int)rintf(256.0f * py)));
+        base = (ly + kLabHalo + (Dy >> 8)) * kLabSpan + lx + kLabHalo + (Dx >> 8);
+        const uint32_t fx = (uint32_t)(Dx & 255), fy = (uint32_t)(Dy & 255);
+        w00 = (256u - fx) * (256u - fy);
+        w10 = fx * (256u - fy);
+        w01 = (256u - fx) * fy;
+        w11 = fx * fy;
       }
-      fbase[ln] = base;
-      fw[ln] = packed;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -267,27 +270,21 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     if (A > 0) {
       for (;;) {
         int ch = 0;
-        for (int item = threadIdx.x; item < kLabTile * kLabTile * A; item += blockDim.x) {
-          const int ln = item / A;
-          const int qw = act[item - ln * A];
-          const int base = fbase[ln];
-          if (base < 0) continue;
-          const uint32_t pk = fw[ln];
-          const uint32_t fx = pk & 0xffffu, fy = pk >> 16;
-          const uint32_t w00 = (256u - fx) * (256u - fy), w10 = fx * (256u - fy);
-          const uint32_t w01 = (256u - fx) * fy, w11 = fx * fy;
-          const uint32_t c00 = tile[base * half + qw], c10 = tile[(base + 1) * half + qw];
-          const uint32_t c01 = tile[(base + kLabSpan) * half + qw], c11 = tile[(base + kLabSpan + 1) * half + qw];
-          const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
-                                w11 * (c11 & 0xffffu) + 32768u) >> 16);
-          const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
-                                32768u) >> 16);
-          const uint32_t nv = lo | (hi << 16);
-          const int ly = ln >> 4, lx = ln & (kLabTile - 1);
-          const int self = ((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + qw;
-          if (nv != tile[self]) {
-            tile[self] = nv;
-            ch = 1;
+        if (base >= 0) {
+          for (int qi = 0; qi < A; ++qi) {
+            const uint32_t* pl = tile + act[qi] * kLabPlane;
+            const uint32_t c00 = pl[base], c10 = pl[base + 1];
+            const uint32_t c01 = pl[base + kLabSpan], c11 = pl[base + kLabSpan + 1];
+            const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
+                                  w11 * (c11 & 0xffffu) + 32768u) >> 16);
+            const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
+                                  32768u) >> 16);
+            const uint32_t nv = lo | (hi << 16);
+            uint32_t* me = tile + act[qi] * kLabPlane + self;
+            if (nv != *me) {
+              *me = nv;
+              ch = 1;
+            }
           }
         }
         last = __syncthreads_or(ch);  // barrier + block-wide OR
@@ -298,13 +295,10 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     }
     const bool converged_here = (last == 0);
     // write back the words that can have changed (interior nodes only)
-    if (ever) {
-      for (int item = threadIdx.x; item < kLabTile * kLabTile * A; item += blockDim.x) {
-        const int node = item / A, qw = act[item - node * A];
-        const int ly = node / kLabTile, lx = node - ly * kLabTile;
-        const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
-        if (gx < n && gy < n)
-          phi32[((size_t)gy * n + gx) * half + qw] = tile[((ly + kLabHalo) * kLabSpan + lx + kLabHalo) * half + qw];
+    if (ever && gx < n && gy < n) {
+      for (int qi = 0; qi < A; ++qi) {
+        const int qw = act[qi];
+        phi32[((size_t)gy * n + gx) * half + qw] = tile[qw * kLabPlane + self];
       }
     }
     if (threadIdx.x == 0 && ever) {
@@ -367,39 +361,60 @@ hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t
   return hipGetLastError();
 }
 
-__global__ void label_argmax_kernel(const uint16_t* __restrict__ phi, int64_t count, int P, int16_t* __restrict__ label,
-                                    uint64_t* __restrict__ overlap, uint16_t tau) {
+// L lanes per node (L a power of two >= P/2), each reading one uint32 word (two patches), so a
+// wavefront reads 64/L whole rows of phi contiguously. The pair (value, p) is reduced across the L
+// lanes keeping the larger value and, on ties, the lower p; the overlap bits are OR-reduced.
+__global__ __launch_bounds__(256) void label_argmax_kernel(const uint32_t* __restrict__ phi32, int64_t count, int P,
+                                                           int L, int16_t* __restrict__ label,
+                                                           uint64_t* __restrict__ overlap, uint16_t tau) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const uint16_t* row = phi + t * P;
-  int best = -1;
-  uint32_t bv = 0;
-  uint64_t ov = 0;
-  for (int p = 0; p < P; ++p) {
-    const uint32_t v = row[p];
-    if (v > bv) {
-      bv = v;
-      best = p;
-    }
-    if (tau > 0 && v >= tau) ov |= 1ull << p;
+  const int64_t node = t / L;
+  const int q = (int)(t - node * L);
+  const int half = P >> 1;
+  const bool live = node < count;
+  uint32_t word = 0u;
+  if (live && q < half) word = phi32[node * half + q];
+  const uint32_t v0 = word & 0xffffu, v1 = word >> 16;
+  uint32_t bv = v1 > v0 ? v1 : v0;
+  int bp = v1 > v0 ? 2 * q + 1 : 2 * q;
+  uint32_t ovlo = 0u, ovhi = 0u;
+  if (tau > 0) {
+    const uint32_t bits = (v0 >= tau ? 1u : 0u) | (v1 >= tau ? 2u : 0u);
+    if (2 * q < 32) ovlo = bits << (2 * q);
+    else ovhi = bits << (2 * q - 32);
   }
-  label[t] = (int16_t)best;
-  if (overlap) overlap[t] = ov;
+  for (int off = 1; off < L; off <<= 1) {
+    const uint32_t ov = __shfl_xor(bv, off, 64);
+    const int op = __shfl_xor(bp, off, 64);
+    if (ov > bv || (ov == bv && op < bp)) {
+      bv = ov;
+      bp = op;
+    }
+    ovlo |= __shfl_xor(ovlo, off, 64);
+    ovhi |= __shfl_xor(ovhi, off, 64);
+  }
+  if (live && q == 0) {
+    label[node] = (int16_t)(bv > 0u ? bp : -1);
+    if (overlap) overlap[node] = ((uint64_t)ovhi << 32) | ovlo;
+  }
 }
 
 hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t count, int P, uint32_t* phi32,
                              hipStream_t s) {
-  label_init_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(cls, src, count, P, phi32);
+  const int64_t words = count * (P >> 1);
+  label_init_kernel<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(cls, src, words, P >> 1, phi32);
   return hipGetLastError();
 }
 
-size_t label_pass_lds_bytes(int P) {
-  return sizeof(uint32_t) * (size_t)kLabSpan * kLabSpan * (P / 2) + sizeof(int) * 256 + sizeof(uint32_t) * 256;
-}
+size_t label_pass_lds_bytes(int P) { return sizeof(uint32_t) * (size_t)kLabPlane * (P / 2); }
 
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
                                uint16_t tau, hipStream_t s) {
-  label_argmax_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(phi, count, P, label, overlap, tau);
+  int L = 1;
+  while (L < (P >> 1)) L <<= 1;
+  const int64_t threads = count * L;
+  label_argmax_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>((const uint32_t*)phi, count, P, L, label,
+                                                                        overlap, tau);
   return hipGetLastError();
 }
 

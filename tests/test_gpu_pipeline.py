@@ -92,7 +92,9 @@ def _label_case(ctx, inst, ctrl, src, P, tau=0):
     dp = capi.DeviceProblem(inst, capi.SL3)
     lab = torch.empty(n * n, dtype=torch.int16, device="cuda")
     phi = torch.empty(n * n * P, dtype=torch.int16, device="cuda")
-    passes = ctx.label(dp, _dev(ctrl, np.int16), _dev(src, np.int16), P, lab, tau_q15=tau, phi_out=phi)
+    ov = torch.empty(n * n, dtype=torch.int64, device="cuda") if tau > 0 else None
+    passes = ctx.label(dp, _dev(ctrl, np.int16), _dev(src, np.int16), P, lab, tau_q15=tau, phi_out=phi,
+                       overlap_out=ov)
     # the tile order (here by a synthetic u_hat: distance to the nearest target node) changes the work,
     # never the least fixed point
     X1, X2 = I.node_coords(n)
@@ -111,10 +113,15 @@ def _label_case(ctx, inst, ctrl, src, P, tau=0):
     got_phi = phi.cpu().numpy().view(np.uint16).reshape(n * n, P)
     assert np.array_equal(got_phi, ref_phi)
     assert np.array_equal(lab.cpu().numpy(), ref_lab)
+    if tau > 0:
+        # bit p where phi_p >= tau (the fuzzy patches' overlap, Section 4.3)
+        bits = (ref_phi >= tau).astype(np.uint64) << np.arange(P, dtype=np.uint64)[None, :]
+        want = np.bitwise_or.reduce(bits, axis=1)
+        assert np.array_equal(ov.cpu().numpy().view(np.uint64), want)
     return passes, ref_passes
 
 
-@pytest.mark.parametrize("n,P", [(97, 8), (130, 6), (257, 64)])
+@pytest.mark.parametrize("n,P", [(97, 8), (130, 6), (257, 64), (200, 63)])
 def test_label_radial_bit_exact(ctx, n, P):
     from paper_1502_01629_amd import capi
 
@@ -124,8 +131,8 @@ def test_label_radial_bit_exact(ctx, n, P):
     _label_case(ctx, fine, ctrl, src, P)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_label_random_field_bit_exact(ctx, seed):
+@pytest.mark.parametrize("seed,tau", [(0, 0), (1, 9000)])
+def test_label_random_field_bit_exact(ctx, seed, tau):
     """A random control field (every direction, edges, obstacles): the exact least fixed point."""
     from paper_1502_01629_amd import capi
 
@@ -140,7 +147,7 @@ def test_label_random_field_bit_exact(ctx, seed):
     inst.speed = (0.5 + 0.6 * rng.random((n, n))).astype(np.float32)
     src, _ = capi.partition_sources(cls, P)
     ctrl = rng.integers(0, 32, size=(n, n))
-    _label_case(ctx, inst, ctrl, src, P)
+    _label_case(ctx, inst, ctrl, src, P, tau)
 
 
 def test_label_rejects_far_feet(ctx):

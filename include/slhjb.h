@@ -162,6 +162,45 @@ typedef struct {
 int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
                       const slhjb_tile_opts* opts, slhjb_stats* stats);
 
+/* ---- batched solve of many independent instances ------------------------------------------ */
+enum { SLHJB_BATCH_TILE_64x16 = 0, SLHJB_BATCH_TILE_64x8 = 1, SLHJB_BATCH_TILE_32x16 = 2, SLHJB_BATCH_TILE_32x8 = 3 };
+typedef struct {
+    int32_t check_every;        /* sweeps between residual checks, 1..256; 0 = 16. (slhjb_solve's
+                                   automatic value depends on the grid size: give both calls the
+                                   same explicit value to compare them.)                           */
+    int32_t batches_per_graph;  /* check batches captured in one graph replay, 1..64; 0 = 4         */
+    const int8_t* tile_shapes;  /* host int8[count] of SLHJB_BATCH_TILE_* per instance, nullable
+                                   (= SLHJB_BATCH_TILE_64x16 for all)                             */
+    int32_t max_workgroups;     /* grid of the sweep launches; 0 = 4096                             */
+    int32_t pad;
+} slhjb_batch_opts;
+typedef struct {
+    int64_t sweeps;             /* sweep launches (each covers every instance still iterating)      */
+    int64_t node_updates;       /* FREE-node Bellman updates over all instances                      */
+    int64_t tiles_swept;        /* tile visits over all sweeps                                       */
+    int64_t replays;            /* graph replays                                                     */
+    double seconds;             /* device time of the call (HIP events), conversions included        */
+    int32_t converged;          /* instances that met tol                                            */
+    int32_t status;             /* worst status over the instances                                    */
+} slhjb_batch_stats;
+/* Jacobi value iteration (as slhjb_solve) of `count` independent problems at once (1 <= count
+ * <= 4096, all with the same scheme). v[i]: device float[n_i*n_i], the start, overwritten with the
+ * result. Every instance gets exactly the arithmetic, the check cadence (residual of the last sweep
+ * of each batch of check_every sweeps) and the stopping rule of slhjb_solve(problems[i], v[i], tol,
+ * max_sweeps, check_every): the results, stats[i].sweeps and stats[i].converged_sweep are
+ * bit-for-bit those of the single-instance calls. The sweeps of all instances still iterating run
+ * in the same launches, over one device work list of (instance, tile) items rebuilt after every
+ * check; an instance leaves it when it converges, fails (non-finite value) or reaches max_sweeps.
+ * The launches of batches_per_graph checks are captured in one HIP graph and replayed until no
+ * instance is left. The tile shape of an instance changes the schedule, never the values.
+ * stats (nullable): slhjb_stats[count] (seconds = the whole call); total (nullable).
+ * Returns SLHJB_OK if every instance converged, SLHJB_NOT_CONVERGED if some reached max_sweeps, a
+ * negative status on an error (for SLHJB_E_NONFINITE, stats[i].status names the instance).
+ * Needs device memory for two FP32 copies of all the grids. Synchronises. */
+int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v, double tol,
+                      int64_t max_sweeps, const slhjb_batch_opts* opts, slhjb_stats* stats,
+                      slhjb_batch_stats* total);
+
 /* ---- the patchy method end to end (Section 4.3) ------------------------------------------- */
 enum { SLHJB_PATCHY_TRANSMISSION = 0,  /* patchy decomposition, one shared iterate             */
        SLHJB_PATCHY_INDEPENDENT = 1,   /* patchy decomposition, state constraints at interfaces */

@@ -123,6 +123,36 @@ class PatchyStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 MODE_TRANSMISSION, MODE_INDEPENDENT = 0, 1
 
+# tile shapes of the batched solve (slhjb_batch_opts.tile_shapes)
+BATCH_TILE_64x16, BATCH_TILE_64x8, BATCH_TILE_32x16, BATCH_TILE_32x8 = 0, 1, 2, 3
+BATCH_TILE_SHAPES = {BATCH_TILE_64x16: (64, 16), BATCH_TILE_64x8: (64, 8), BATCH_TILE_32x16: (32, 16),
+                     BATCH_TILE_32x8: (32, 8)}
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("check_every", ctypes.c_int32),
+        ("batches_per_graph", ctypes.c_int32),
+        ("tile_shapes", ctypes.c_void_p),
+        ("max_workgroups", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int64),
+        ("node_updates", ctypes.c_int64),
+        ("tiles_swept", ctypes.c_int64),
+        ("replays", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("converged", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
 
 class Regime(ctypes.Structure):
     _fields_ = [
@@ -157,6 +187,8 @@ SIGNATURES = {
     "slhjb_solve_tiles": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, ctypes.POINTER(TileOpts), ctypes.POINTER(Stats)]),
     "slhjb_solve_patchy": (ctypes.c_int, [_vp, _PP, _PP, ctypes.POINTER(PatchyOpts), _vp, _vp,
                                           ctypes.POINTER(PatchyStats)]),
+    "slhjb_solve_batch": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), _f64, _i64, ctypes.POINTER(BatchOpts),
+                                         ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
@@ -317,6 +349,29 @@ class Context:
                                       _ptr(overlap_out) if overlap_out is not None else None,
                                       _ptr(phi_out) if phi_out is not None else None, ctypes.byref(passes)))
         return passes.value
+
+    def solve_batch(self, probs, vs, tol: float = 1e-6, max_sweeps: int = 1_000_000, check_every: int = 16,
+                    batches_per_graph: int = 0, tile_shapes=None, max_workgroups: int = 0):
+        """Jacobi value iteration of independent instances in shared launches (slhjb_solve_batch).
+        Returns (per-instance stats dicts, totals dict)."""
+        count = len(probs)
+        if len(vs) != count:
+            raise ValueError("one iterate per problem")
+        arr = (Problem * count)(*[p.struct for p in probs])
+        ptrs = (_vp * count)(*[_ptr(v) for v in vs])
+        shapes = None
+        if tile_shapes is not None:
+            shapes = np.ascontiguousarray(tile_shapes, dtype=np.int8)
+            if shapes.size != count:
+                raise ValueError("one tile shape per problem")
+        opts = BatchOpts(check_every, batches_per_graph, shapes.ctypes.data if shapes is not None else None,
+                         max_workgroups, 0)
+        stats = (Stats * count)()
+        tot = BatchStats()
+        st = lib().slhjb_solve_batch(self.handle, arr, count, ptrs, tol, max_sweeps, ctypes.byref(opts), stats,
+                                     ctypes.byref(tot))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return [s.as_dict() for s in stats], tot.as_dict()
 
     def solve(self, prob: DeviceProblem, v, tol: float = 1e-6, max_sweeps: int = 1_000_000, check_every: int = 0):
         stats = Stats()

@@ -916,6 +916,204 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   return status;
 }
 
+int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v, double tol,
+                      int64_t max_sweeps, const slhjb_batch_opts* opts, slhjb_stats* stats,
+                      slhjb_batch_stats* total) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!problems || !v || count < 1 || count > 4096)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "need problems, v and 1 <= count <= 4096");
+  if (!(tol >= 0.0) || max_sweeps < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol >= 0 and max_sweeps >= 1");
+  slhjb_batch_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (o.check_every < 0 || o.check_every > 256 || o.batches_per_graph < 0 || o.batches_per_graph > 64 ||
+      o.max_workgroups < 0)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "invalid batch options");
+  const int check_every = o.check_every > 0 ? o.check_every : 16;
+  const int per_graph = o.batches_per_graph > 0 ? o.batches_per_graph : 4;
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(ctx, SLHJB_E_INVALID_ARG, "v[" + std::to_string(i) + "] is NULL");
+    if (o.tile_shapes && (o.tile_shapes[i] < 0 || o.tile_shapes[i] > 3))
+      return fail(ctx, SLHJB_E_INVALID_ARG, "tile_shapes[" + std::to_string(i) + "] out of range");
+    if (problems[i].scheme != problems[0].scheme)
+      return fail(ctx, SLHJB_E_INVALID_ARG, "all instances of a batch must use the same scheme");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // device scratch of this call
+  BatchInst* d_inst = nullptr;
+  float4* d_ctrl = nullptr;
+  float *pool0 = nullptr, *pool1 = nullptr, *d_last = nullptr;
+  unsigned *d_resid = nullptr, *d_flags = nullptr;
+  int *d_state = nullptr, *d_first = nullptr;
+  long long* d_done = nullptr;
+  int2* d_work = nullptr;
+  void* d_ctl = nullptr;
+  unsigned* h_ctl = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int status = SLHJB_OK;
+  auto cleanup = [&]() {
+    hipStreamSynchronize(ctx->stream);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    for (void* q : {(void*)d_inst, (void*)d_ctrl, (void*)pool0, (void*)pool1, (void*)d_last, (void*)d_resid,
+                    (void*)d_flags, (void*)d_state, (void*)d_first, (void*)d_done, (void*)d_work, d_ctl})
+      if (q) hipFree(q);
+    if (h_ctl) hipHostFree(h_ctl);
+  };
+  auto bail = [&](hipError_t e, const char* what) {
+    cleanup();
+    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, std::string(what) + ": out of device memory");
+    return hip_fail(ctx, e, what);
+  };
+#define BATCH_TRY(expr)                       \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return bail(_e, #expr); \
+  } while (0)
+  BATCH_TRY(hipMalloc(&d_ctrl, sizeof(float4) * kCtrlCap * count));
+  // per-instance parameters, exactly as the single-instance solve derives them
+  std::vector<BatchInst> inst(count);
+  std::vector<int> first_item(count);
+  std::vector<float> vstar(count);
+  long long nodes = 0;
+  int ctrl_total = 0, items = 0;
+  size_t lds = 0;
+  for (int i = 0; i < count; ++i) {
+    Prepared P;
+    int st = prepare(ctx, &problems[i], &P);
+    if (st != SLHJB_OK) {
+      cleanup();
+      ctx->last_msg = "instance " + std::to_string(i) + ": " + ctx->last_msg;
+      return st;
+    }
+    // prepare() leaves the instance's padded control table in ctx->ctrl (stream-ordered copy)
+    BATCH_TRY(hipMemcpyAsync(d_ctrl + ctrl_total, ctx->ctrl, sizeof(float4) * P.args.n_controls,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+    BatchInst& b = inst[i];
+    memset(&b, 0, sizeof(b));
+    b.a = P.args;
+    b.a.w_in = nullptr;
+    b.a.w_out = nullptr;
+    b.a.resid = nullptr;
+    b.a.flags = nullptr;
+    b.a.ctrl = nullptr;
+    const int shape = o.tile_shapes ? o.tile_shapes[i] : SLHJB_BATCH_TILE_64x16;
+    b.tw_log2 = (shape == SLHJB_BATCH_TILE_32x16 || shape == SLHJB_BATCH_TILE_32x8) ? 5 : 6;
+    b.th = (shape == SLHJB_BATCH_TILE_64x8 || shape == SLHJB_BATCH_TILE_32x8) ? 8 : 16;
+    const int n = problems[i].n, TW = 1 << b.tw_log2;
+    b.tiles_x = (n + TW - 1) / TW;
+    b.tiles = b.tiles_x * ((n + b.th - 1) / b.th);
+    b.offset = nodes;
+    nodes += ((long long)n * n + 63) / 64 * 64;
+    b.free_nodes = P.free_nodes;
+    b.path = P.path;
+    b.diffusion = P.diffusion;
+    b.ctrl_offset = ctrl_total;
+    first_item[i] = items;
+    items += b.tiles;
+    vstar[i] = P.vstar;
+    lds = std::max(lds, sizeof(float) * (size_t)(TW + 2 * P.args.halo) * (size_t)(b.th + 2 * P.args.halo));
+    ctrl_total += P.args.n_controls;
+  }
+  BATCH_TRY(hipMalloc(&d_inst, sizeof(BatchInst) * count));
+  BATCH_TRY(hipMalloc(&pool0, sizeof(float) * nodes));
+  BATCH_TRY(hipMalloc(&pool1, sizeof(float) * nodes));
+  BATCH_TRY(hipMalloc(&d_last, sizeof(float) * count));
+  BATCH_TRY(hipMalloc(&d_resid, sizeof(unsigned) * count));
+  BATCH_TRY(hipMalloc(&d_flags, sizeof(unsigned) * count));
+  BATCH_TRY(hipMalloc(&d_state, sizeof(int) * count));
+  BATCH_TRY(hipMalloc(&d_first, sizeof(int) * count));
+  BATCH_TRY(hipMalloc(&d_done, sizeof(long long) * count));
+  BATCH_TRY(hipMalloc(&d_work, sizeof(int2) * items));
+  BATCH_TRY(hipMalloc(&d_ctl, batchctl_bytes()));
+  BATCH_TRY(hipHostMalloc(&h_ctl, 128, hipHostMallocDefault));
+  BATCH_TRY(hipMemcpyAsync(d_inst, inst.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice, ctx->stream));
+  BATCH_TRY(hipMemcpyAsync(d_first, first_item.data(), sizeof(int) * count, hipMemcpyHostToDevice, ctx->stream));
+  BATCH_TRY(hipStreamSynchronize(ctx->stream));  // the host vectors are pageable
+  BATCH_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+  for (int i = 0; i < count; ++i) {
+    const int64_t N = (int64_t)problems[i].n * problems[i].n;
+    BATCH_TRY(launch_v_to_w(v[i], pool0 + inst[i].offset, problems[i].node_class, N, vstar[i], inst[i].a.w_target,
+                            inst[i].a.w_obstacle, ctx->stream));
+  }
+  BATCH_TRY(launch_batch_init(d_inst, count, d_state, d_done, d_last, d_resid, d_flags, d_work, d_first, d_ctl,
+                              (long long)max_sweeps, check_every, tol, (unsigned)items, ctx->stream));
+  const int grid = std::min(items, o.max_workgroups > 0 ? o.max_workgroups : 4096);
+  if (!ctx->cap_stream) BATCH_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  BATCH_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t ce = hipSuccess;
+  for (int r = 0; r < per_graph && ce == hipSuccess; ++r)
+    ce = launch_batch_round(d_inst, count, d_ctrl, pool0, pool1, d_resid, d_flags, d_state, d_done, d_last, d_work,
+                            d_ctl, problems[0].scheme, check_every, grid, lds, ctx->cap_stream);
+  hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (ce != hipSuccess) return bail(ce, "capture of the batched sweeps");
+  if (ee != hipSuccess) return bail(ee, "hipStreamEndCapture");
+  BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  int64_t replays = 0;
+  while (true) {
+    BATCH_TRY(hipGraphLaunch(exec, ctx->stream));
+    ++replays;
+    BATCH_TRY(hipMemcpyAsync(h_ctl, d_ctl, batchctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
+    BATCH_TRY(hipStreamSynchronize(ctx->stream));
+    if (h_ctl[kBatchCtlActive] == 0u) break;
+  }
+  // results: the iterate of an instance that stopped after S sweeps is in pool (S & 1)
+  std::vector<int> state(count);
+  std::vector<long long> done(count);
+  std::vector<float> last(count);
+  BATCH_TRY(hipMemcpy(state.data(), d_state, sizeof(int) * count, hipMemcpyDeviceToHost));
+  BATCH_TRY(hipMemcpy(done.data(), d_done, sizeof(long long) * count, hipMemcpyDeviceToHost));
+  BATCH_TRY(hipMemcpy(last.data(), d_last, sizeof(float) * count, hipMemcpyDeviceToHost));
+  for (int i = 0; i < count; ++i) {
+    const int64_t N = (int64_t)problems[i].n * problems[i].n;
+    const float* src = ((done[i] & 1) ? pool1 : pool0) + inst[i].offset;
+    BATCH_TRY(launch_w_to_v(src, v[i], N, vstar[i], ctx->stream));
+  }
+  BATCH_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+  BATCH_TRY(hipEventSynchronize(ctx->ev1));
+  float ms = 0.0f;
+  BATCH_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  int converged = 0;
+  for (int i = 0; i < count; ++i) {
+    const int si = state[i] == 1 ? SLHJB_OK : (state[i] == 3 ? SLHJB_E_NONFINITE : SLHJB_NOT_CONVERGED);
+    converged += state[i] == 1 ? 1 : 0;
+    if (si == SLHJB_E_NONFINITE) status = SLHJB_E_NONFINITE;
+    else if (si == SLHJB_NOT_CONVERGED && status == SLHJB_OK) status = SLHJB_NOT_CONVERGED;
+    if (stats) {
+      slhjb_stats& t = stats[i];
+      memset(&t, 0, sizeof(t));
+      t.sweeps = done[i];
+      t.converged_sweep = state[i] == 1 ? done[i] : -1;
+      t.node_updates = done[i] * inst[i].free_nodes;
+      t.residual = last[i];
+      t.seconds = ms * 1e-3;
+      t.status = si;
+      t.kernel_path = inst[i].path;
+      t.halo = inst[i].a.halo;
+    }
+  }
+  if (total) {
+    memset(total, 0, sizeof(*total));
+    long long sw;
+    unsigned long long u, tv;
+    memcpy(&sw, &h_ctl[kBatchCtlSweeps], sizeof(sw));
+    memcpy(&u, &h_ctl[kBatchCtlUpdates], sizeof(u));
+    memcpy(&tv, &h_ctl[kBatchCtlTiles], sizeof(tv));
+    total->sweeps = sw;
+    total->node_updates = (int64_t)u;
+    total->tiles_swept = (int64_t)tv;
+    total->replays = replays;
+    total->seconds = ms * 1e-3;
+    total->converged = converged;
+    total->status = status;
+  }
+  cleanup();
+#undef BATCH_TRY
+  if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "an instance produced a non-finite value");
+  return status;
+}
+
 int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
                             int32_t* n_targets_out) {
   if (n < 3 || n > 32769 || !node_class || !source_patch || n_patches < 1 || n_patches > 32767)

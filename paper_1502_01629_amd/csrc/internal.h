@@ -101,4 +101,32 @@ hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, 
                                   float act, float window, float tol, int max_passes, void* state, int max_grid,
                                   int* grid_used, hipStream_t s);
 
+// Batched solve (batch.hip). One entry per instance; `a` carries the instance's parameters as for
+// the single-instance sweep (its pointers w_in/w_out/resid/flags are not used: the iterates live in
+// two pools at `offset`, the control table in one array at `ctrl_offset`).
+struct BatchInst {
+  SweepArgs a;
+  long long offset;        // first node of the instance in the pools
+  long long free_nodes;
+  int ctrl_offset;
+  int tiles_x;
+  int tiles;
+  int tw_log2;             // tile width 1 << tw_log2 (32 or 64)
+  int th;                  // tile height (8 or 16)
+  int path;                // 1 first-ring kernel path, 0 general
+  int diffusion;
+  int pad;
+};
+size_t batchctl_bytes();
+hipError_t launch_batch_init(const BatchInst* inst, int count, int* state, long long* done_at, float* last_resid,
+                             unsigned* resid, unsigned* flags, int2* work, const int* first_item, void* ctl,
+                             long long max_sweeps, int check_every, double tol, unsigned items, hipStream_t s);
+hipError_t launch_batch_round(const BatchInst* inst, int count, const float4* ctrl_all, float* pool0, float* pool1,
+                              unsigned* resid, unsigned* flags, int* state, long long* done_at, float* last_resid,
+                              int2* work, void* ctl, int scheme, int check_every, int grid, size_t lds,
+                              hipStream_t s);
+// Host-readable words of the batch control block: [1] active, [4..5] sweeps, [10..11] node
+// updates, [12..13] tile visits.
+constexpr int kBatchCtlActive = 1, kBatchCtlSweeps = 4, kBatchCtlUpdates = 10, kBatchCtlTiles = 12;
+
 }  // namespace slhjb

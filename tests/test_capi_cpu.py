@@ -33,6 +33,49 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(capi.SIGNATURES), "binding and header disagree"
 
 
+# every struct of the header and its ctypes mirror in the binding
+_STRUCTS = {
+    "slhjb_problem": "Problem", "slhjb_stats": "Stats", "slhjb_tile_opts": "TileOpts",
+    "slhjb_patchy_opts": "PatchyOpts", "slhjb_patchy_stats": "PatchyStats", "slhjb_regime": "Regime",
+    "slhjb_batch_opts": "BatchOpts", "slhjb_batch_stats": "BatchStats",
+}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Compile a probe against include/slhjb.h with the host C compiler and compare the size and
+    every field offset of each struct with the binding's ctypes mirror."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "slhjb.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(capi, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            cfield = "lambda" if field == "lam" else field
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {cfield}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(capi, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
 def test_status_strings_and_version():
     for st in (0, 1, -1, -2, -3, -4, -5):
         assert capi.status_string(st)

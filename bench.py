@@ -10,9 +10,15 @@ One step = the patchy method of Section 4.3 end to end with inputs resident in H
 solve from u_hat with tiles taken by increasing u_hat, until one full Jacobi sweep changes no
 node by more than 1e-6. `value` is the mean wall time of a step (lower is better).
 
-Beside the timed steps, each comparison arm runs once: the plain cold-start global Jacobi value
-iteration (the SL sweep kernel at full rate), the same from u_hat, and the static decomposition
-(active tiles, fixed order, cold start). Prints one JSON line.
+Beside the timed steps, each comparison arm runs once (progress on stderr):
+  c2     the plain cold-start global Jacobi value iteration (the SL sweep kernel at full rate), the
+         same from u_hat, and the static decomposition (active tiles, fixed order, cold start);
+  c2eps  the same 2049^2 workload with isotropic diffusion eps = 1e-3 and 1e-2: patchy pipeline
+         against the cold global Jacobi iteration;
+  batch  256 independent instances (65^2..1025^2, eps > 0) in one batched solve against the same
+         instances solved one by one (bit-exact agreement counted);
+  bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -78,6 +84,161 @@ def cpu_baseline(inst, scheme: int, jacobi_sweeps: int, budget_s: float = 12.0) 
                       f"global Jacobi iteration needs to reach residual 1e-6"}
 
 
+def log(msg: str) -> None:
+    """Progress of the long arms, on stderr (stdout carries the one JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def arm_batch(ctx, seed: int, tol: float) -> dict:
+    """256 independent instances (grid sizes 65..1025, 1-4 disc targets, 8 speed bumps, eps
+    log-uniform in [1e-4, 1e-2], 32-64 controls, isotropic diffusion, h = dx): one batched solve
+    (tile shapes from the autotuner) against the same instances solved one after the other with
+    the single-instance Jacobi solve; the two must agree bit for bit."""
+    import torch
+
+    from paper_1502_01629_amd import autotune, capi
+    from paper_1502_01629_amd import instances as I
+
+    xs = I.batch_problems(seed, count=256)
+    probs = [capi.DeviceProblem(x, capi.SL3) for x in xs]
+    starts = [torch.from_numpy(x.initial().reshape(-1)).cuda() for x in xs]
+    t = time.perf_counter()
+    shapes = autotune.tune(ctx, xs, cache=os.path.join(ROOT, "_build", "batch_tiles.json"))
+    t_tune = time.perf_counter() - t
+    log(f"batch: autotuned {len(set(autotune.bucket_key(x) for x in xs))} buckets in {t_tune:.1f} s")
+    vb = [s0.clone() for s0 in starts]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stats, tot = ctx.solve_batch(probs, vb, tol=tol, max_sweeps=1_000_000, check_every=16, tile_shapes=shapes)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    log(f"batch: batched solve {t_batch:.2f} s, {tot['sweeps']} sweeps")
+    t = time.perf_counter()
+    equal = 0
+    upd = 0
+    for k, p in enumerate(probs):
+        v1 = starts[k].clone()
+        st1 = ctx.solve(p, v1, tol=tol, max_sweeps=1_000_000, check_every=16)
+        upd += st1["node_updates"]
+        equal += int(bool(torch.equal(v1, vb[k])) and st1["sweeps"] == stats[k]["sweeps"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    log(f"batch: sequential single-instance solves {t_seq:.2f} s")
+    sizes = sorted({x.n for x in xs})
+    return {
+        "instances": len(xs), "nodes": int(sum(x.n * x.n for x in xs)),
+        "grid_sizes": {str(n): sum(1 for x in xs if x.n == n) for n in sizes},
+        "time_s_batched": t_batch, "device_s_batched": tot["seconds"], "time_s_sequential": t_seq,
+        "speedup": t_seq / t_batch, "node_updates": tot["node_updates"],
+        "node_updates_per_s_batched": tot["node_updates"] / t_batch, "node_updates_per_s_sequential": upd / t_seq,
+        "sweeps_max": tot["sweeps"], "graph_replays": tot["replays"], "converged": tot["converged"],
+        "bit_exact_vs_single": f"{equal}/{len(xs)}", "autotune_s": t_tune,
+        "tile_shapes": {capi.BATCH_TILE_SHAPES[k][0] * 1000 + capi.BATCH_TILE_SHAPES[k][1]: shapes.count(k)
+                        for k in set(shapes)},
+    }
+
+
+def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
+    """Degenerate (rank-1) diffusion on 4097^2: full Jacobi sweeps against the active-tile work list
+    with per-tile convergence flags, both from the cold start, plus the active tiles ordered by the
+    u_hat of a coarse sigma = 0 solve."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    x = I.bumps_problem(seed, n=n)
+    free = int((x.node_class == 0).sum())
+    dp = capi.DeviceProblem(x, capi.SL3)
+    v0 = torch.from_numpy(x.initial().reshape(-1)).cuda()
+    out = {"n": n, "eps": float(x.eps), "free_nodes": free, "diffusion": "rank-1 sqrt(2 eps) a"}
+    vf = v0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sf = ctx.solve(dp, vf, tol=tol, max_sweeps=200_000)
+    torch.cuda.synchronize()
+    out["full_sweeps"] = {"time_s": time.perf_counter() - t, "sweeps": sf["sweeps"],
+                          "node_updates_per_free_node": sf["node_updates"] / free,
+                          "sweep_kernel_us": 1e6 * sf["sweep_seconds"] / sf["sweep_launches"], "halo": sf["halo"]}
+    log(f"bumps: full sweeps {out['full_sweeps']['time_s']:.2f} s")
+    vt = v0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = ctx.solve_tiles(dp, vt, tol=tol, order=capi.ORDER_NONE, max_passes=200_000)
+    torch.cuda.synchronize()
+    out["active_tiles_cold"] = {"time_s": time.perf_counter() - t, "passes": st["sweeps"],
+                                "node_updates_per_free_node": st["node_updates"] / free,
+                                "max_abs_diff_vs_full": float((vt - vf).abs().max())}
+    log(f"bumps: active tiles {out['active_tiles_cold']['time_s']:.2f} s")
+    # u_hat from a coarse sigma = 0 solve, tiles by increasing u_hat
+    xc = I.bumps_problem(seed, n=257, eps=0.0)
+    xc.diffusion = I.DIFF_NONE
+    dpc = capi.DeviceProblem(xc, capi.SL3)
+    vc = torch.from_numpy(xc.initial().reshape(-1)).cuda()
+    vk = torch.empty_like(v0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sc = ctx.solve_tiles(dpc, vc, tol=tol, order=capi.ORDER_NONE, tile_shape=capi.TILE_8x8_SPLIT4, max_passes=20000)
+    ctx.upsample(vc, xc.n, vk, n)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t
+    sk = ctx.solve_tiles(dp, vk, tol=tol, order=capi.ORDER_KEYS, max_passes=200_000)
+    torch.cuda.synchronize()
+    out["active_tiles_uhat"] = {"time_s": time.perf_counter() - t, "coarse_and_upsample_s": t_pre,
+                                "coarse_passes": sc["sweeps"], "passes": sk["sweeps"],
+                                "node_updates_per_free_node": sk["node_updates"] / free,
+                                "max_abs_diff_vs_full": float((vk - vf).abs().max())}
+    log(f"bumps: active tiles from u_hat {out['active_tiles_uhat']['time_s']:.2f} s")
+    out["speedup_active_tiles_cold"] = out["full_sweeps"]["time_s"] / out["active_tiles_cold"]["time_s"]
+    out["speedup_active_tiles_uhat"] = out["full_sweeps"]["time_s"] / out["active_tiles_uhat"]["time_s"]
+    return out
+
+
+def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) -> dict:
+    """The same 2049^2 workload with isotropic diffusion: the patchy pipeline (coarse sigma = 0
+    solve, u_hat, synthesis, labels, u_hat-ordered active tiles) against the cold global Jacobi
+    iteration."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    out = {}
+    for eps in eps_list:
+        fine, coarse = I.scattered_problem(seed, eps=eps)
+        free = int((fine.node_class == 0).sum())
+        dp = capi.DeviceProblem(fine, capi.SL3)
+        dpc = capi.DeviceProblem(coarse, capi.SL3)
+        src_host, _ = capi.partition_sources(fine.node_class, patches)
+        src = torch.from_numpy(src_host.reshape(-1)).cuda()
+        v = torch.empty(fine.n * fine.n, dtype=torch.float32, device="cuda")
+        lab = torch.empty(fine.n * fine.n, dtype=torch.int16, device="cuda")
+        times = []
+        for _ in range(2):  # warm-up, then timed
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sp = ctx.solve_patchy(dp, dpc, v, mode=capi.PATCHY_TRANSMISSION, tol=tol, tol_coarse=1e-7,
+                                  source_patch=src, n_patches=patches, label_out=lab)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        vj = torch.from_numpy(fine.initial().reshape(-1)).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sj = ctx.solve(dp, vj, tol=tol, max_sweeps=200_000)
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - t
+        out[f"eps={eps:g}"] = {
+            "patchy_time_s": times[-1], "patchy_stages_s": {k: sp[k] for k in ("t_coarse", "t_synthesize", "t_label",
+                                                                                "t_solve")},
+            "patchy_passes": sp["passes"], "patchy_node_updates_per_free_node": sp["node_updates"] / free,
+            "global_jacobi_cold_s": tj, "global_jacobi_sweeps": sj["sweeps"], "halo": sj["halo"],
+            "sweep_kernel_us": 1e6 * sj["sweep_seconds"] / sj["sweep_launches"],
+            "speedup": tj / times[-1], "max_abs_diff": float((v - vj).abs().max()),
+        }
+        log(f"c2 eps={eps:g}: patchy {times[-1]:.3f} s, global Jacobi {tj:.3f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +251,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="skip the comparison arms")
+    ap.add_argument("--arms", default="c2,c2eps,batch,bumps",
+                    help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
+                         "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion)")
+    ap.add_argument("--bumps-n", type=int, default=4097)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -191,8 +356,9 @@ def main():
     }
 
     jacobi_sweeps = None
-    if not args.no_arms:
-        arms = {}
+    which = set() if args.no_arms else {a.strip() for a in args.arms.split(",") if a.strip()}
+    arms = {}
+    if "c2" in which:
         v0 = torch.from_numpy(fine.initial().reshape(-1)).cuda()
         # plain global Jacobi from v = 1: the SL sweep kernel at full rate
         vj = v0.clone()
@@ -231,8 +397,16 @@ def main():
         arms["static_decomposition_cold"] = {"time_s": t, "passes": ss["passes"],
                                              "node_updates_per_free_node": ss["node_updates"] / free,
                                              "max_abs_diff_vs_patchy": float((vs - v_pdd).abs().max())}
-        out["arms"] = arms
         out["speedup_vs_global_jacobi_cold"] = arms["global_jacobi_cold"]["time_s"] / out["value"]
+        log("c2 arms done")
+    if "c2eps" in which:
+        arms["c2_diffusion"] = arm_c2_eps(ctx, args.seed, args.tol, args.patches)
+    if "batch" in which:
+        arms["batch_256_instances"] = arm_batch(ctx, args.seed, args.tol)
+    if "bumps" in which:
+        arms["rank1_bumps"] = arm_bumps(ctx, args.seed, args.tol, args.bumps_n)
+    if arms:
+        out["arms"] = arms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fine, scheme, jacobi_sweeps or 1672)
     ctx.close()

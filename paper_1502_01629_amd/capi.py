@@ -256,6 +256,19 @@ class DeviceProblem:
         self.scheme = scheme
         self.struct = self._make()
 
+    @staticmethod
+    def host_struct(inst, scheme: int = SL3) -> Problem:
+        """The problem struct with no device arrays (for the host-only calls such as
+        slhjb_foot_reach); the controls array is kept alive on the struct."""
+        controls = np.ascontiguousarray(inst.controls, dtype=np.float32).reshape(-1)
+        p = Problem(n=inst.n, x_lo=float(inst.x_lo), x_hi=float(inst.x_hi), h=float(inst.h), lam=float(inst.lam),
+                    eps=float(inst.eps), diffusion=int(inst.diffusion), scheme=int(scheme),
+                    n_controls=int(controls.size // 2), controls=controls.ctypes.data, speed=None, speed_const=1.0,
+                    running_cost=float(inst.running_cost), node_class=None, target_value=float(inst.target_value),
+                    v_out=float(inst.v_out))
+        p._keep = controls
+        return p
+
     def _make(self) -> Problem:
         inst = self.inst
         return Problem(

@@ -762,7 +762,11 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!ctx->tupdates) HIP_TRY(ctx, hipMalloc(&ctx->tupdates, sizeof(unsigned long long)));
   const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;
   const bool keyed = opts->order == SLHJB_ORDER_KEYS;
-  const int max_inner = opts->max_inner > 0 ? opts->max_inner : 2 * (tw + th);
+  // Without diffusion a tile is a transport problem: iterating it to its own fixed point against
+  // the frozen halo carries the values across it in one visit. With diffusion every node depends
+  // on the halo through the noise feet and a settled tile is settled only once its neighbours are:
+  // a few iterations per visit waste the least work.
+  const int max_inner = opts->max_inner > 0 ? opts->max_inner : (P.diffusion == SLHJB_DIFF_NONE ? 2 * (tw + th) : 2);
   const float tol_inner = (float)(0.5 * tol), act = (float)(0.5 * tol);
   // band width of arrival times: the time to cross 1/16 of the box (at least 16 cells) at the
   // fastest speed

@@ -38,11 +38,15 @@ sys.path.insert(0, ROOT)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+# the files that define the dominant kernel (the tile visit) and everything it inlines
+KERNEL_SOURCES = ("tiles.hip", "sweep_device.h", "internal.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_1502_01629_amd", "csrc", "*"))):
-        with open(fn, "rb") as f:
-            h.update(os.path.basename(fn).encode() + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1502_01629_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 

@@ -16,6 +16,8 @@
 //    of the four cells around a node is a bilinear form A + B s + C t + D s t; with the
 //    node's 3x3 neighbourhood in registers and the controls grouped by quadrant, a control
 //    costs three FMAs (SL2) instead of a gather.
+#include <algorithm>
+
 #include "sweep_device.h"
 
 namespace slhjb {
@@ -190,15 +192,34 @@ __global__ void problem_stats_kernel(const float* __restrict__ speed, const uint
     hi = fmaxf(hi, __shfl_xor(hi, off, 64));
     nfree += __shfl_xor(nfree, off, 64);
   }
+  // one set of atomics per workgroup: same-address atomics from every wavefront serialise in L2
+  __shared__ float slo[kThreads / 64], shi[kThreads / 64];
+  __shared__ unsigned sfree[kThreads / 64];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
   if ((threadIdx.x & 63) == 0) {
+    slo[threadIdx.x >> 6] = lo;
+    shi[threadIdx.x >> 6] = hi;
+    sfree[threadIdx.x >> 6] = nfree;
+  }
+  if (bad_speed) atomicOr(&sbad, 1);
+  if (bad_cls) atomicOr(&sbad, 2);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kThreads / 64; ++k) {
+      lo = fminf(lo, slo[k]);
+      hi = fmaxf(hi, shi[k]);
+      nfree += sfree[k];
+    }
     if (speed) {
       if (lo < INFINITY) atomicMin(&out[0], __float_as_uint(lo));
       atomicMax(&out[1], __float_as_uint(hi));
     }
     atomicAdd(&out[3], nfree);
+    if (sbad & 1) atomicOr(&out[2], 1u);
+    if (sbad & 2) atomicOr(&out[4], 1u);
   }
-  if (bad_speed) atomicOr(&out[2], 1u);
-  if (bad_cls) atomicOr(&out[4], 1u);
 }
 
 __global__ void fill_u32_kernel(unsigned* p, unsigned value, int count) {
@@ -226,7 +247,7 @@ hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, h
 
 hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t count, unsigned* out,
                                 hipStream_t s) {
-  problem_stats_kernel<<<grid_for(count), 256, 0, s>>>(speed, cls, count, out);
+  problem_stats_kernel<<<std::min(grid_for(count), 512), kThreads, 0, s>>>(speed, cls, count, out);
   return hipGetLastError();
 }
 

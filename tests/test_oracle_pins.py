@@ -267,3 +267,41 @@ def test_upsample_reproduces_bilinear_and_coarse_nodes():
     vr = rng.random((9, 9))
     vf = oracle.upsample_bilinear(vr, 33).reshape(33, 33)
     assert np.array_equal(vf[::4, ::4], vr)
+
+
+# ---------------------------------------------------------------- independent (state-constraint) sweep
+@pytest.mark.parametrize("scheme", [SL2, SL3])
+@pytest.mark.parametrize("eps", [0.0, 0.02])
+def test_independent_sweep_reduces_to_the_global_sweep_with_one_patch(scheme, eps):
+    """With every node in one patch there is no interface: the per-patch sweep is the global one."""
+    inst = I.disc_problem(33, eps)
+    p = _prob(inst, scheme)
+    rng = np.random.default_rng(7)
+    v = p.initial()
+    v[inst.node_class.reshape(-1) == I.FREE] = rng.uniform(0.2, 1.0, size=int((inst.node_class == I.FREE).sum()))
+    a, ra = p.sweep(v)
+    b, rb = p.sweep_independent(np.zeros(33 * 33, dtype=np.int16), v)
+    assert np.array_equal(a, b) and ra == rb
+
+
+@pytest.mark.parametrize("scheme", [SL2, SL3])
+def test_independent_sweep_is_a_state_constraint(scheme):
+    """Reading v_out (the largest value) at other-patch corners can only raise a monotone update, and
+    a node whose feet never leave its patch's cells gets exactly the global update."""
+    inst = I.disc_problem(33, 0.02)
+    p = _prob(inst, scheme)
+    n = 33
+    v = p.initial()
+    rng = np.random.default_rng(3)
+    free = inst.node_class.reshape(-1) == I.FREE
+    v[free] = rng.uniform(0.2, 0.9, size=int(free.sum()))
+    lab = (np.arange(n)[None, :] // 11 + np.zeros((n, 1), dtype=np.int64)).astype(np.int16).reshape(-1)
+    g, _ = p.sweep(v)
+    s, _ = p.sweep_independent(lab, v)
+    assert (s >= g - 1e-15).all()
+    # the reach of every foot is below 2 cells here: nodes at least 3 columns from an interface
+    col = np.arange(n * n) % n
+    far = np.minimum(np.abs(col - 10.5), np.abs(col - 21.5)) >= 3
+    assert np.array_equal(s[far & free], g[far & free])
+    near = (~far) & free
+    assert (s[near] > g[near]).any()

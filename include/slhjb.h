@@ -288,6 +288,64 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
                 const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15, int16_t* label_out,
                 uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out);
 
+/* ---- learned warm start ------------------------------------------------------------------ */
+/* A small dilated convolutional network that maps [u_hat, c, target mask, log10(eps) + 3] on the
+ * fine grid to a correction delta of u_hat; the start of the SL iteration is then
+ * clamp(u_hat + delta, 0, 1) on FREE nodes (the boundary data elsewhere). The iteration
+ * converges to the same fixed point from any start, so the network can only change the work,
+ * never the result. (A serving addition beside the u_hat start of Section 4.3; the paper has no
+ * network.)
+ * Architecture: `layers` 3 x 3 convolutions with ReLU, the first from 16 input channels (4 used,
+ * 12 zero) to `channels`, the others channels -> channels, with per-layer dilation, then a 1 x 1
+ * head channels -> 1. Zero padding at image borders. Activations and conv weights in bfloat16
+ * on the matrix cores with FP32 accumulation; head, loss, gradients and Adam in FP32.
+ * Parameters (FP32, flat): per layer l, W_l[9][channels][cin_l] (tap-major, taps row-major over
+ * dy, dx in {-1,0,1} x dilation) then b_l[channels]; then the head w[channels], b[1]. */
+typedef struct slhjb_net slhjb_net;
+typedef struct {
+    int32_t layers;             /* 1..12                                                           */
+    int32_t channels;           /* 32                                                              */
+    int32_t dilation[12];       /* per layer, 1..64                                                */
+} slhjb_net_config;
+/* One training or evaluation frame: the crop [x0, x0+crop) x [y0, y0+crop) of an n x n problem. */
+typedef struct {
+    const float* v_hat;         /* device float[n*n]: u_hat, the upsampled coarse solution         */
+    const float* v_star;        /* device float[n*n]: the converged solution (target), nullable for
+                                   inference                                                       */
+    const float* speed;         /* device float[n*n], NULL = speed_const                           */
+    const uint8_t* node_class;  /* device uint8[n*n]                                               */
+    float speed_const;
+    float eps;                  /* diffusion coefficient of the problem (> 0; feature log10(eps)+3) */
+    int32_t n;
+    int32_t x0, y0;
+} slhjb_net_sample;
+/* Create a network with zero parameters (set them with slhjb_net_set_params). The network owns
+ * its device memory (parameters, gradients, Adam moments, activations) and uses ctx's stream. */
+int slhjb_net_create(slhjb_ctx* ctx, const slhjb_net_config* cfg, slhjb_net** out);
+int slhjb_net_destroy(slhjb_net* net);
+/* Number of FP32 parameters (the length of the flat vectors below). */
+int64_t slhjb_net_param_count(const slhjb_net* net);
+/* Copy parameters from / to host float[param_count]; set also resets the Adam moments and step. */
+int slhjb_net_set_params(slhjb_net* net, const float* host);
+int slhjb_net_get_params(slhjb_net* net, float* host);
+/* Gradients of the last slhjb_net_loss_grad call, host float[param_count]. */
+int slhjb_net_get_grads(slhjb_net* net, float* host);
+/* Forward pass on `count` crops of side `crop` (1 <= count <= 256, 1 <= crop <= 4096, crop
+ * inside each frame): delta_out device float[count*crop*crop] (row-major per crop). */
+int slhjb_net_forward(slhjb_net* net, const slhjb_net_sample* samples, int32_t count, int32_t crop,
+                      float* delta_out);
+/* Loss and gradients on `count` crops: L = mean over the FREE nodes of (u_hat + delta - v*)^2,
+ * accumulated into the network's gradient buffer (zeroed first). loss_out: host, nullable. */
+int slhjb_net_loss_grad(slhjb_net* net, const slhjb_net_sample* samples, int32_t count, int32_t crop,
+                        double* loss_out);
+/* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8, bias-corrected) with learning rate lr on
+ * the current gradients. */
+int slhjb_net_adam_step(slhjb_net* net, float lr);
+/* Start of the SL iteration for `problem` from u_hat: v_out = clamp(v_hat + delta, 0, 1) on FREE
+ * nodes, target_value on TARGET, v_out on OBSTACLE (device float[n*n]; v_hat and v_out may be the
+ * same array). Needs problem->eps > 0 for the feature. */
+int slhjb_net_warm_start(slhjb_net* net, const slhjb_problem* problem, const float* v_hat, float* v_out);
+
 /* ---- parameter theory (host only, no GPU needed) --------------------------------------- */
 /* The upwind diffusion ball analysis of Section 4.1 for dynamics bounded by f_min <= |f| <= f_max
  * and diffusion rows of length at most sigma_inf (eq. upper-bound, lower-bound, upper-alpha,

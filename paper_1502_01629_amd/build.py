@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslhjb.so")
 ARCH = "gfx950"
 
-SOURCES = ["sweep.hip", "pipeline.hip", "tiles.hip", "batch.hip", "capi.hip"]
+SOURCES = ["sweep.hip", "pipeline.hip", "tiles.hip", "batch.hip", "cnn.hip", "net.hip", "capi.hip"]
 
 # -packed-fp32-ops: never emit packed FP32 VALU instructions (some of their forms have been
 # seen to give wrong results on this hardware); hipcc's host pass warns that it does not

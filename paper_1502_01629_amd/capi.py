@@ -154,6 +154,28 @@ class BatchStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NetConfig(ctypes.Structure):
+    _fields_ = [
+        ("layers", ctypes.c_int32),
+        ("channels", ctypes.c_int32),
+        ("dilation", ctypes.c_int32 * 12),
+    ]
+
+
+class NetSample(ctypes.Structure):
+    _fields_ = [
+        ("v_hat", ctypes.c_void_p),
+        ("v_star", ctypes.c_void_p),
+        ("speed", ctypes.c_void_p),
+        ("node_class", ctypes.c_void_p),
+        ("speed_const", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("n", ctypes.c_int32),
+        ("x0", ctypes.c_int32),
+        ("y0", ctypes.c_int32),
+    ]
+
+
 class Regime(ctypes.Structure):
     _fields_ = [
         ("omega", ctypes.c_double),
@@ -189,6 +211,16 @@ SIGNATURES = {
                                           ctypes.POINTER(PatchyStats)]),
     "slhjb_solve_batch": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), _f64, _i64, ctypes.POINTER(BatchOpts),
                                          ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
+    "slhjb_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(NetConfig), ctypes.POINTER(_vp)]),
+    "slhjb_net_destroy": (ctypes.c_int, [_vp]),
+    "slhjb_net_param_count": (_i64, [_vp]),
+    "slhjb_net_set_params": (ctypes.c_int, [_vp, _vp]),
+    "slhjb_net_get_params": (ctypes.c_int, [_vp, _vp]),
+    "slhjb_net_get_grads": (ctypes.c_int, [_vp, _vp]),
+    "slhjb_net_forward": (ctypes.c_int, [_vp, ctypes.POINTER(NetSample), _i32, _i32, _vp]),
+    "slhjb_net_loss_grad": (ctypes.c_int, [_vp, ctypes.POINTER(NetSample), _i32, _i32, ctypes.POINTER(_f64)]),
+    "slhjb_net_adam_step": (ctypes.c_int, [_vp, _f32]),
+    "slhjb_net_warm_start": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
@@ -392,3 +424,76 @@ class Context:
                                ctypes.byref(stats))
         self._check(st, allow=(OK, NOT_CONVERGED))
         return stats.as_dict()
+
+
+class Net:
+    """The learned warm-start network of a context (slhjb_net_*): parameters live on the device."""
+
+    def __init__(self, ctx: "Context", layers: int = 6, channels: int = 32, dilations=(1, 2, 4, 8, 16, 1)):
+        if len(dilations) != layers:
+            raise ValueError("one dilation per layer")
+        self.ctx = ctx
+        self.layers, self.channels, self.dilations = layers, channels, tuple(int(d) for d in dilations)
+        cfg = NetConfig(layers, channels, (ctypes.c_int32 * 12)(*self.dilations))
+        h = ctypes.c_void_p()
+        ctx._check(lib().slhjb_net_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().slhjb_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return int(lib().slhjb_net_param_count(self.handle))
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.param_count:
+            raise ValueError("wrong parameter count")
+        self.ctx._check(lib().slhjb_net_set_params(self.handle, p.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.param_count, dtype=np.float32)
+        self.ctx._check(lib().slhjb_net_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.param_count, dtype=np.float32)
+        self.ctx._check(lib().slhjb_net_get_grads(self.handle, out.ctypes.data))
+        return out
+
+    @staticmethod
+    def samples(items) -> "ctypes.Array":
+        """items: (v_hat, v_star or None, DeviceProblem, x0, y0) tuples."""
+        arr = (NetSample * len(items))()
+        for k, (vh, vs, dp, x0, y0) in enumerate(items):
+            st = dp.struct
+            arr[k] = NetSample(_ptr(vh), _ptr(vs) if vs is not None else None, st.speed, st.node_class,
+                               st.speed_const, st.eps, st.n, x0, y0)
+        return arr
+
+    def forward(self, items, crop: int, out):
+        arr = self.samples(items)
+        self.ctx._check(lib().slhjb_net_forward(self.handle, arr, len(items), crop, _ptr(out)))
+        return out
+
+    def loss_grad(self, items, crop: int) -> float:
+        arr = self.samples(items)
+        loss = ctypes.c_double()
+        self.ctx._check(lib().slhjb_net_loss_grad(self.handle, arr, len(items), crop, ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr: float):
+        self.ctx._check(lib().slhjb_net_adam_step(self.handle, lr))
+
+    def warm_start(self, dp: DeviceProblem, v_hat, v_out):
+        self.ctx._check(lib().slhjb_net_warm_start(self.handle, ctypes.byref(dp.struct), _ptr(v_hat), _ptr(v_out)))
+        return v_out

@@ -281,6 +281,15 @@ int ensure_tiles(slhjb_ctx* ctx, size_t tiles) {
 
 }  // namespace
 
+namespace slhjb {
+// accessors for the other translation units of the library (network entry points)
+hipStream_t ctx_stream(slhjb_ctx* ctx) { return ctx->stream; }
+int ctx_device(slhjb_ctx* ctx) { return ctx->device; }
+int ctx_fail(slhjb_ctx* ctx, int status, const std::string& msg) { return fail(ctx, status, msg); }
+int ctx_hip_fail(slhjb_ctx* ctx, hipError_t e, const char* what) { return hip_fail(ctx, e, what); }
+int ctx_validate(slhjb_ctx* ctx, const slhjb_problem* p) { return validate(ctx, p); }
+}  // namespace slhjb
+
 extern "C" {
 
 const char* slhjb_status_string(int status) {

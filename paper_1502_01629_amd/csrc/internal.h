@@ -129,4 +129,45 @@ hipError_t launch_batch_round(const BatchInst* inst, int count, const float4* ct
 // updates, [12..13] tile visits.
 constexpr int kBatchCtlActive = 1, kBatchCtlSweeps = 4, kBatchCtlUpdates = 10, kBatchCtlTiles = 12;
 
+// Context accessors (capi.hip) for the network entry points (net.hip).
+}  // namespace slhjb
+struct slhjb_ctx;
+#include <string>
+namespace slhjb {
+hipStream_t ctx_stream(slhjb_ctx* ctx);
+int ctx_device(slhjb_ctx* ctx);
+int ctx_fail(slhjb_ctx* ctx, int status, const std::string& msg);
+int ctx_hip_fail(slhjb_ctx* ctx, hipError_t e, const char* what);
+
+// Learned warm start (cnn.hip): NHWC bfloat16 activations, FP32 master parameters.
+hipError_t launch_conv3x3(int cin, int cout, int mode, const uint16_t* in, const uint16_t* w, const float* bias,
+                          const uint16_t* gate, int images, int H, int W, int dil, int relu, uint16_t* out,
+                          hipStream_t s);
+hipError_t launch_conv3x3_wgrad(int cin, int cout, const uint16_t* x, const uint16_t* dy, int images, int H, int W,
+                                int dil, float* dw, float* db, hipStream_t s);
+hipError_t launch_head_fwd(int c, const uint16_t* h, const float* hw, const float* hb, long long total, float* delta,
+                           hipStream_t s);
+hipError_t launch_loss_head_bwd(int c, const float* delta, const float* uhat, const float* vstar, const uint8_t* mask,
+                                long long total, float inv_n, const uint16_t* h, const float* hw, uint16_t* dh,
+                                float* dhw, float* dhb, float* loss_acc, hipStream_t s);
+struct CropSrc {
+  const float* uhat;
+  const float* vstar;
+  const float* speed;
+  const uint8_t* cls;
+  float speed_const;
+  float leps;
+  int n, x0, y0;
+};
+hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, uint16_t* feat, float* uhat, float* vstar,
+                        uint8_t* mask, hipStream_t s);
+hipError_t launch_project(const float* uhat, const float* delta, const uint8_t* cls, long long total,
+                          float target_value, float v_out, float* v, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long count, float lr_t, float b1, float b2,
+                       float eps_t, hipStream_t s);
+hipError_t launch_pack_weights(const float* w, int cout, int cin, uint16_t* wt, uint16_t* wtt, hipStream_t s);
+hipError_t launch_zero_f32(float* p, long long count, hipStream_t s);
+hipError_t launch_scale_f32(float* p, long long count, float a, hipStream_t s);
+hipError_t launch_count_nonzero_u8(const uint8_t* m, long long count, unsigned* out, hipStream_t s);
+
 }  // namespace slhjb

@@ -227,6 +227,28 @@ def batch_problems(seed: int = 0, count: int = 256, sizes=(65, 129, 257, 513, 10
     return out
 
 
+def warmstart_problems(seed: int = 0, count: int = 64, n: int = 1025, n_coarse: int = 129,
+                       sizes_controls=(32, 65)) -> list[tuple[Instance, Instance]]:
+    """Learned-warm-start data: the batch law (1-4 discs, 8 bumps, eps log-uniform in
+    [1e-4, 1e-2], 32-64 controls, isotropic diffusion, h = dx) at a fixed fine size n, each with
+    its coarse sigma = 0 companion on n_coarse^2 (h = dx_c). Returns (fine, coarse) pairs."""
+    ss = np.random.SeedSequence([1502, 1629, 5, seed])
+    out = []
+    for k, child in enumerate(ss.spawn(count)):
+        rng = np.random.default_rng(child)
+        nt = int(rng.integers(1, 5))
+        targets = [(float(rng.uniform(-0.8, 0.8)), float(rng.uniform(-0.8, 0.8)), float(rng.uniform(0.02, 0.1)))
+                   for _ in range(nt)]
+        eps = float(10.0 ** rng.uniform(-4, -2))
+        na = int(rng.integers(*sizes_controls))
+        g = Geometry(targets=targets, speed_law="bumps", bumps=bump_geometry(rng, 8))
+        fine = g.instance(n, na, eps, DIFF_ISO, 2.0 / (n - 1), workload="warmstart", seed=seed, index=k)
+        coarse = g.instance(n_coarse, na, 0.0, DIFF_NONE, 2.0 / (n_coarse - 1), workload="warmstart-coarse",
+                            seed=seed, index=k)
+        out.append((fine, coarse))
+    return out
+
+
 # ---------------------------------------------------------------------------------------
 # Small problems with closed-form discrete solutions (used to pin the oracle).
 

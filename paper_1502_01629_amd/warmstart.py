@@ -1,0 +1,128 @@
+"""Learned warm start: training data from the method's own solves, training with the library's
+network kernels (slhjb_net_*), and the comparison of starts.
+
+A frame is one fine problem with u_hat (the bilinear upsampling of its coarse sigma = 0 solve,
+Section 4.3) and v* (its converged fine solution). The network learns delta = v* - u_hat from
+[u_hat, c, target mask, log10(eps)] on random crops; the start of the fine iteration is then
+clamp(u_hat + delta, 0, 1). The iteration converges to the same fixed point from any start, so
+the comparison measures work only: the error of the start and the sweeps to the tolerance.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import capi
+
+
+def init_params(net: "capi.Net", seed: int = 0) -> np.ndarray:
+    """He-normal 3 x 3 weights over the used input channels, zero biases, a small head."""
+    rng = np.random.default_rng(seed)
+    C = net.channels
+    parts = []
+    for l in range(net.layers):
+        cin = 16 if l == 0 else C
+        used = 4 if l == 0 else C
+        w = rng.normal(0.0, math.sqrt(2.0 / (9 * used)), size=(9, C, cin))
+        if l == 0:
+            w[:, :, 4:] = 0.0
+        parts += [w.reshape(-1), np.zeros(C)]
+    parts += [rng.normal(0.0, 1e-2, size=C), np.zeros(1)]
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == net.param_count
+    return p
+
+
+@dataclass
+class Frame:
+    dp: "capi.DeviceProblem"
+    vhat: object   # device float[n*n]
+    vstar: object  # device float[n*n]
+    n: int
+    eps: float
+    seconds_coarse: float
+    seconds_fine: float
+
+
+def make_frames(ctx: "capi.Context", pairs, tol: float = 1e-6) -> list[Frame]:
+    """Solve each (fine, coarse) pair with the library: coarse sigma = 0 active-tile solve, u_hat,
+    then the fine solve from u_hat in u_hat order to tol."""
+    import torch
+
+    frames = []
+    for fine, coarse in pairs:
+        dpc = capi.DeviceProblem(coarse, capi.SL3)
+        vc = torch.from_numpy(coarse.initial().reshape(-1)).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.solve_tiles(dpc, vc, tol=tol, order=capi.ORDER_NONE, tile_shape=capi.TILE_8x8_SPLIT4, max_passes=50000)
+        vhat = torch.empty(fine.n * fine.n, dtype=torch.float32, device="cuda")
+        ctx.upsample(vc, coarse.n, vhat, fine.n)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t
+        dp = capi.DeviceProblem(fine, capi.SL3)
+        vstar = vhat.clone()
+        t = time.perf_counter()
+        st = ctx.solve_tiles(dp, vstar, tol=tol, order=capi.ORDER_KEYS, max_passes=1_000_000)
+        torch.cuda.synchronize()
+        if st["status"] != 0:
+            raise RuntimeError(f"fine solve did not converge: {st}")
+        frames.append(Frame(dp, vhat, vstar, fine.n, float(fine.eps), tc, time.perf_counter() - t))
+    return frames
+
+
+def train(net: "capi.Net", frames, steps: int, batch: int = 8, crop: int = 256, lr: float = 2e-3,
+          seed: int = 0, lr_final: float = 0.05) -> list[float]:
+    """Adam on random crops; cosine decay of the learning rate to lr * lr_final."""
+    rng = np.random.default_rng(seed)
+    losses = []
+    c = min(crop, min(f.n for f in frames))
+    for s in range(steps):
+        items = []
+        for _ in range(batch):
+            f = frames[int(rng.integers(len(frames)))]
+            items.append((f.vhat, f.vstar, f.dp, int(rng.integers(0, f.n - c + 1)), int(rng.integers(0, f.n - c + 1))))
+        losses.append(net.loss_grad(items, c))
+        rate = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps - 1))))
+        net.adam_step(rate)
+    return losses
+
+
+def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6) -> list[dict]:
+    """For every frame: error of u_hat and of the network's start against v*, and the plain Jacobi
+    solve and the u_hat-ordered active-tile solve from each start."""
+    import torch
+
+    out = []
+    for f in frames:
+        free = torch.from_numpy((f.dp.inst.node_class.reshape(-1) == 0)).cuda()
+        g = torch.empty_like(f.vhat)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        net.warm_start(f.dp, f.vhat, g)
+        torch.cuda.synchronize()
+        t_net = time.perf_counter() - t
+        row = {"n": f.n, "eps": f.eps, "t_network_s": t_net}
+        for name, start in (("uhat", f.vhat), ("network", g)):
+            e = (start - f.vstar).abs()[free]
+            row[f"err_max_{name}"] = float(e.max())
+            row[f"err_mean_{name}"] = float(e.mean())
+            v = start.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = ctx.solve(f.dp, v, tol=tol, max_sweeps=1_000_000)
+            torch.cuda.synchronize()
+            row[f"jacobi_sweeps_{name}"] = st["sweeps"]
+            row[f"jacobi_s_{name}"] = time.perf_counter() - t
+            v = start.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = ctx.solve_tiles(f.dp, v, tol=tol, order=capi.ORDER_KEYS, max_passes=1_000_000)
+            torch.cuda.synchronize()
+            row[f"tiles_s_{name}"] = time.perf_counter() - t
+            row[f"tiles_updates_per_node_{name}"] = st["node_updates"] / max(1, int(free.sum()))
+        out.append(row)
+    return out

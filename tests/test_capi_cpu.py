@@ -38,6 +38,7 @@ _STRUCTS = {
     "slhjb_problem": "Problem", "slhjb_stats": "Stats", "slhjb_tile_opts": "TileOpts",
     "slhjb_patchy_opts": "PatchyOpts", "slhjb_patchy_stats": "PatchyStats", "slhjb_regime": "Regime",
     "slhjb_batch_opts": "BatchOpts", "slhjb_batch_stats": "BatchStats",
+    "slhjb_net_config": "NetConfig", "slhjb_net_sample": "NetSample",
 }
 
 

@@ -17,7 +17,9 @@ Beside the timed steps, each comparison arm runs once (progress on stderr):
          against the cold global Jacobi iteration;
   batch  256 independent instances (65^2..1025^2, eps > 0) in one batched solve against the same
          instances solved one by one (bit-exact agreement counted);
-  bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered).
+  bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered);
+  learned  a CNN warm start trained on the method's own 1025^2 solves against u_hat and the cold
+         start on held-out problems.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -243,6 +245,57 @@ def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) 
     return out
 
 
+def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, train_count: int = 48,
+                test_count: int = 8, steps: int = 1500) -> dict:
+    """Learned warm start: a dilated CNN (BF16 matrix-core kernels of the library) trained on the
+    method's own solves of the batch law at n^2 (coarse n_coarse^2), then on held-out problems the
+    cold start (v = 1), u_hat and the network's start, each solved to tol."""
+    import torch
+
+    from paper_1502_01629_amd import capi, warmstart
+    from paper_1502_01629_amd import instances as I
+
+    pairs = I.warmstart_problems(seed, count=train_count + test_count, n=n, n_coarse=n_coarse)
+    t = time.perf_counter()
+    frames = warmstart.make_frames(ctx, pairs, tol=tol)
+    t_data = time.perf_counter() - t
+    log(f"learned: {len(frames)} training/evaluation solves in {t_data:.1f} s")
+    train, test = frames[:train_count], frames[train_count:]
+    net = capi.Net(ctx, 6, 32, (1, 2, 4, 8, 16, 1))
+    net.set_params(warmstart.init_params(net, seed))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = warmstart.train(net, train, steps=steps, batch=8, crop=256, lr=2e-3, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    log(f"learned: {steps} training steps in {t_train:.1f} s, loss {np.mean(losses[:20]):.2e} -> "
+        f"{np.mean(losses[-20:]):.2e}")
+    rows = warmstart.evaluate(ctx, net, test, tol=tol)
+    for f, r in zip(test, rows):
+        v = torch.from_numpy(f.dp.inst.initial().reshape(-1)).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = ctx.solve(f.dp, v, tol=tol, max_sweeps=1_000_000)
+        torch.cuda.synchronize()
+        r["jacobi_sweeps_cold"] = st["sweeps"]
+        r["jacobi_s_cold"] = time.perf_counter() - t
+    mean = lambda k: float(np.mean([r[k] for r in rows]))
+    net.close()
+    return {
+        "n": n, "coarse": n_coarse, "train_problems": train_count, "test_problems": test_count,
+        "data_generation_s": t_data, "training_steps": steps, "training_s": t_train,
+        "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
+        "inference_s": mean("t_network_s"),
+        "start_error_mean": {"uhat": mean("err_mean_uhat"), "network": mean("err_mean_network")},
+        "start_error_max": {"uhat": mean("err_max_uhat"), "network": mean("err_max_network")},
+        "jacobi_sweeps": {"cold": mean("jacobi_sweeps_cold"), "uhat": mean("jacobi_sweeps_uhat"),
+                          "network": mean("jacobi_sweeps_network")},
+        "jacobi_time_s": {"cold": mean("jacobi_s_cold"), "uhat": mean("jacobi_s_uhat"),
+                          "network": mean("jacobi_s_network")},
+        "active_tiles_time_s": {"uhat": mean("tiles_s_uhat"), "network": mean("tiles_s_network")},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,9 +308,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="skip the comparison arms")
-    ap.add_argument("--arms", default="c2,c2eps,batch,bumps",
+    ap.add_argument("--arms", default="c2,c2eps,batch,bumps,learned",
                     help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
-                         "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion)")
+                         "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
+                         "learned (CNN warm start at 1025^2)")
     ap.add_argument("--bumps-n", type=int, default=4097)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -409,6 +463,8 @@ def main():
         arms["batch_256_instances"] = arm_batch(ctx, args.seed, args.tol)
     if "bumps" in which:
         arms["rank1_bumps"] = arm_bumps(ctx, args.seed, args.tol, args.bumps_n)
+    if "learned" in which:
+        arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol)
     if arms:
         out["arms"] = arms
     if not args.no_cpu_baseline:

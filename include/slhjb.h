@@ -289,14 +289,15 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
                 uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out);
 
 /* ---- learned warm start ------------------------------------------------------------------ */
-/* A small dilated convolutional network that maps [u_hat, c, target mask, log10(eps) + 3] on the
- * fine grid to a correction delta of u_hat; the start of the SL iteration is then
+/* A small dilated convolutional network that maps [u_hat, c, target mask, log10(eps) + 3,
+ * 1 / (1 + d / 4)] (d: distance in cells to the nearest side of the box) on the fine grid to a
+ * correction delta of u_hat; the start of the SL iteration is then
  * clamp(u_hat + delta, 0, 1) on FREE nodes (the boundary data elsewhere). The iteration
  * converges to the same fixed point from any start, so the network can only change the work,
  * never the result. (A serving addition beside the u_hat start of Section 4.3; the paper has no
  * network.)
- * Architecture: `layers` 3 x 3 convolutions with ReLU, the first from 16 input channels (4 used,
- * 12 zero) to `channels`, the others channels -> channels, with per-layer dilation, then a 1 x 1
+ * Architecture: `layers` 3 x 3 convolutions with ReLU, the first from 16 input channels (5 used,
+ * 11 zero) to `channels`, the others channels -> channels, with per-layer dilation, then a 1 x 1
  * head channels -> 1. Zero padding at image borders. Activations and conv weights in bfloat16
  * on the matrix cores with FP32 accumulation; head, loss, gradients and Adam in FP32.
  * Parameters (FP32, flat): per layer l, W_l[9][channels][cin_l] (tap-major, taps row-major over
@@ -334,8 +335,10 @@ int slhjb_net_get_grads(slhjb_net* net, float* host);
  * inside each frame): delta_out device float[count*crop*crop] (row-major per crop). */
 int slhjb_net_forward(slhjb_net* net, const slhjb_net_sample* samples, int32_t count, int32_t crop,
                       float* delta_out);
-/* Loss and gradients on `count` crops: L = mean over the FREE nodes of (u_hat + delta - v*)^2,
- * accumulated into the network's gradient buffer (zeroed first). loss_out: host, nullable. */
+/* Loss and gradients on `count` crops: L = mean of (u_hat + delta - v*)^2 over the FREE nodes at
+ * least R = sum of the dilations (the receptive-field radius) away from every crop edge that lies
+ * inside the frame (there the zero padding is not the box boundary), into the network's gradient
+ * buffer (zeroed first). loss_out: host, nullable. */
 int slhjb_net_loss_grad(slhjb_net* net, const slhjb_net_sample* samples, int32_t count, int32_t crop,
                         double* loss_out);
 /* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8, bias-corrected) with learning rate lr on

@@ -4,11 +4,13 @@ TEST INFRASTRUCTURE ONLY: the GPU network kernels are checked against it; nothin
 path imports it. It shares no code with the GPU package.
 
 The network (the definition of the library's slhjb_net):
-  features  x0[p] = [u_hat, c, target mask, log10(eps) + 3, 0 x 12]            (16 channels)
+  features  x0[p] = [u_hat, c, target mask, log10(eps) + 3, 1 / (1 + d / 4), 0 x 11]  (16 channels)
+            d = distance in cells from p to the nearest side of the box
   layer l   x_{l+1}[p][co] = relu(b_l[co] + sum_t sum_ci x_l[p + d_l off_t][ci] W_l[t][co][ci])
             off_t = (t // 3 - 1, t % 3 - 1) in (dy, dx), zero outside the image
   head      delta[p] = hb + sum_c x_L[p][c] hw[c]
-  loss      L = mean over FREE p of (u_hat + delta - v*)^2
+  loss      L = mean over the masked p of (u_hat + delta - v*)^2: FREE nodes at least R = sum of
+            the dilations away from every crop edge inside the frame (crop_mask)
 Parameters, flat FP32: per layer W_l[9][C][cin_l] then b_l[C]; then hw[C], hb.
 
 With emulate=True the reference rounds to bfloat16 where the GPU stores bfloat16 (features, conv
@@ -55,16 +57,35 @@ def unpack(params: np.ndarray, layers: int, channels: int) -> dict:
 
 
 def features(uhat, speed, cls, eps, emulate=True):
-    """[H, W, 16] input features of one frame (cls: 1 = TARGET)."""
+    """[H, W, 16] input features of a whole frame (cls: 1 = TARGET)."""
     H, W = uhat.shape
     f = np.zeros((H, W, CIN0))
     f[..., 0] = uhat
     f[..., 1] = speed
     f[..., 2] = (cls == 1).astype(np.float64)
     f[..., 3] = np.log10(np.float64(np.float32(eps))) + 3.0
+    j, i = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    d = np.minimum(np.minimum(i, j), np.minimum(W - 1 - i, H - 1 - j)).astype(np.float32)
+    # in float32, as the device computes it (IEEE division: the same value)
+    f[..., 4] = np.float32(1.0) / (np.float32(1.0) + np.float32(0.25) * d)
     if emulate:
-        f[..., :4] = bf16(f[..., :4].astype(np.float32))
+        f[..., :5] = bf16(f[..., :5].astype(np.float32))
     return f
+
+
+def crop_mask(cls, x0, y0, S, n, margin):
+    """Loss mask of the S x S crop at (x0, y0) of an n x n frame: FREE nodes (cls 0) at least margin
+    cells from every crop edge that lies inside the frame."""
+    m = (cls[y0:y0 + S, x0:x0 + S] == 0).copy()
+    if x0 > 0:
+        m[:, :margin] = False
+    if y0 > 0:
+        m[:margin, :] = False
+    if x0 + S < n:
+        m[:, S - margin:] = False
+    if y0 + S < n:
+        m[S - margin:, :] = False
+    return m.astype(np.float64)
 
 
 def shift(x: np.ndarray, oy: int, ox: int) -> np.ndarray:

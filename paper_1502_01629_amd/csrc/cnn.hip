@@ -272,27 +272,38 @@ __global__ __launch_bounds__(256) void loss_head_bwd_kernel(const float* __restr
 
 // Training crops (and whole frames for inference): image k of the batch is the S x S window at
 // (x0, y0) of its source frame (side n). Features NHWC, CIN channels:
-// [u_hat, c, target mask, log10(eps) + 3, 0, ...]; also u_hat, v* and the FREE mask of the window.
+// [u_hat, c, target mask, log10(eps) + 3, 1 / (1 + d / 4), 0, ...] with d the distance in cells to
+// the nearest side of the box (where the diffusion feet start to leave it); also u_hat, v* and the
+// loss mask: FREE nodes at least `margin` cells (the receptive-field radius) from every window edge
+// that lies inside the frame, where the zero padding of the window is not the box boundary.
 template <int CIN>
-__global__ void crop_kernel(const CropSrc* __restrict__ src, int S, uint16_t* __restrict__ out,
+__global__ void crop_kernel(const CropSrc* __restrict__ src, int S, int margin, uint16_t* __restrict__ out,
                             float* __restrict__ uhat, float* __restrict__ vstar, uint8_t* __restrict__ mask) {
   const int k = blockIdx.z;
   const int y = blockIdx.y, x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= S) return;
   const CropSrc c = src[k];
-  const size_t q = (size_t)(c.y0 + y) * c.n + c.x0 + x;
+  const int gx = c.x0 + x, gy = c.y0 + y;
+  const size_t q = (size_t)gy * c.n + gx;
   const size_t dst = ((size_t)k * S + y) * S + x;
   uint16_t* o = out + dst * CIN;
   const float u = c.uhat[q];
+  const int d = min(min(gx, gy), min(c.n - 1 - gx, c.n - 1 - gy));
   o[0] = f2bf(u);
   o[1] = f2bf(c.speed ? c.speed[q] : c.speed_const);
   o[2] = f2bf(c.cls[q] == kTarget ? 1.0f : 0.0f);
   o[3] = f2bf(c.leps);
+  o[4] = f2bf(1.0f / (1.0f + 0.25f * (float)d));
 #pragma unroll
-  for (int ch = 4; ch < CIN; ++ch) o[ch] = 0;
+  for (int ch = 5; ch < CIN; ++ch) o[ch] = 0;
   uhat[dst] = u;
   vstar[dst] = c.vstar ? c.vstar[q] : 0.0f;
-  mask[dst] = c.cls[q] == kFree ? 1 : 0;
+  bool inner = true;
+  if (c.x0 > 0) inner &= x >= margin;
+  if (c.y0 > 0) inner &= y >= margin;
+  if (c.x0 + S < c.n) inner &= x < S - margin;
+  if (c.y0 + S < c.n) inner &= y < S - margin;
+  mask[dst] = (c.cls[q] == kFree && inner) ? 1 : 0;
 }
 
 // Start of the SL iteration from the network: clamp(u_hat + delta, 0, 1) on FREE nodes, the
@@ -399,11 +410,11 @@ hipError_t launch_loss_head_bwd(int c, const float* delta, const float* uhat, co
   return hipGetLastError();
 }
 
-hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, uint16_t* feat, float* uhat, float* vstar,
-                        uint8_t* mask, hipStream_t s) {
+hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, int margin, uint16_t* feat, float* uhat,
+                        float* vstar, uint8_t* mask, hipStream_t s) {
   if (cin != 16) return hipErrorInvalidValue;
   dim3 grid((S + 63) / 64, S, images);
-  crop_kernel<16><<<grid, 64, 0, s>>>(src, S, feat, uhat, vstar, mask);
+  crop_kernel<16><<<grid, 64, 0, s>>>(src, S, margin, feat, uhat, vstar, mask);
   return hipGetLastError();
 }
 

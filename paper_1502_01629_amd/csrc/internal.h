@@ -159,8 +159,8 @@ struct CropSrc {
   float leps;
   int n, x0, y0;
 };
-hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, uint16_t* feat, float* uhat, float* vstar,
-                        uint8_t* mask, hipStream_t s);
+hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, int margin, uint16_t* feat, float* uhat,
+                        float* vstar, uint8_t* mask, hipStream_t s);
 hipError_t launch_project(const float* uhat, const float* delta, const uint8_t* cls, long long total,
                           float target_value, float v_out, float* v, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long count, float lr_t, float b1, float b2,

@@ -14,7 +14,7 @@
 using namespace slhjb;
 
 namespace {
-constexpr int kCin0 = 16;      // input feature channels (4 used)
+constexpr int kCin0 = 16;      // input feature channels (5 used)
 constexpr int kMaxImages = 256;
 }  // namespace
 
@@ -139,7 +139,9 @@ int forward_core(slhjb_net* net, const slhjb_net_sample* smp, int count, int cro
     c.y0 = q.y0;
   }
   NET_TRY(hipMemcpyAsync(net->d_src, net->h_src, sizeof(CropSrc) * count, hipMemcpyHostToDevice, s));
-  NET_TRY(launch_crops(kCin0, net->d_src, count, crop, net->feat, net->uhat, net->vstar, net->mask, s));
+  int margin = 0;  // receptive-field radius: the sum of the dilations
+  for (int l = 0; l < net->L; ++l) margin += net->dil[l];
+  NET_TRY(launch_crops(kCin0, net->d_src, count, crop, margin, net->feat, net->uhat, net->vstar, net->mask, s));
   for (int l = 0; l < net->L; ++l)
     NET_TRY(launch_conv3x3(net->cin[l], net->C, 0, l == 0 ? net->feat : net->act[l - 1], net->wt[l],
                            net->params + net->b_off[l], nullptr, count, crop, crop, net->dil[l], 1, net->act[l], s));

@@ -3,7 +3,7 @@ network kernels (slhjb_net_*), and the comparison of starts.
 
 A frame is one fine problem with u_hat (the bilinear upsampling of its coarse sigma = 0 solve,
 Section 4.3) and v* (its converged fine solution). The network learns delta = v* - u_hat from
-[u_hat, c, target mask, log10(eps)] on random crops; the start of the fine iteration is then
+[u_hat, c, target mask, log10(eps), distance to the box] on random crops; the start of the fine iteration is then
 clamp(u_hat + delta, 0, 1). The iteration converges to the same fixed point from any start, so
 the comparison measures work only: the error of the start and the sweeps to the tolerance.
 """
@@ -25,10 +25,10 @@ def init_params(net: "capi.Net", seed: int = 0) -> np.ndarray:
     parts = []
     for l in range(net.layers):
         cin = 16 if l == 0 else C
-        used = 4 if l == 0 else C
+        used = 5 if l == 0 else C
         w = rng.normal(0.0, math.sqrt(2.0 / (9 * used)), size=(9, C, cin))
         if l == 0:
-            w[:, :, 4:] = 0.0
+            w[:, :, 5:] = 0.0
         parts += [w.reshape(-1), np.zeros(C)]
     parts += [rng.normal(0.0, 1e-2, size=C), np.zeros(1)]
     p = np.concatenate(parts).astype(np.float32)
@@ -76,15 +76,24 @@ def make_frames(ctx: "capi.Context", pairs, tol: float = 1e-6) -> list[Frame]:
 
 def train(net: "capi.Net", frames, steps: int, batch: int = 8, crop: int = 256, lr: float = 2e-3,
           seed: int = 0, lr_final: float = 0.05) -> list[float]:
-    """Adam on random crops; cosine decay of the learning rate to lr * lr_final."""
+    """Adam on random crops; cosine decay of the learning rate to lr * lr_final. Each crop coordinate
+    is snapped to a side of the box half of the time: the boundary layer (diffusion feet leaving the
+    box read v_out) is where u_hat, a sigma = 0 solution, is furthest from v*, and a uniform origin
+    would almost never show it."""
     rng = np.random.default_rng(seed)
     losses = []
     c = min(crop, min(f.n for f in frames))
+
+    def origin(n):
+        if rng.random() < 0.5:
+            return 0 if rng.random() < 0.5 else n - c
+        return int(rng.integers(0, n - c + 1))
+
     for s in range(steps):
         items = []
         for _ in range(batch):
             f = frames[int(rng.integers(len(frames)))]
-            items.append((f.vhat, f.vstar, f.dp, int(rng.integers(0, f.n - c + 1)), int(rng.integers(0, f.n - c + 1))))
+            items.append((f.vhat, f.vstar, f.dp, origin(f.n), origin(f.n)))
         losses.append(net.loss_grad(items, c))
         rate = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps - 1))))
         net.adam_step(rate)

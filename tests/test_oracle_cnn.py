@@ -33,7 +33,7 @@ def _tiny(seed, layers=3, channels=32, dil=(1, 2, 1), H=9, W=11):
     _, total = cnn.layout(layers, channels)
     params = rng.normal(0.0, 0.15, size=total)
     feats = np.zeros((2, H, W, cnn.CIN0))
-    feats[..., :4] = rng.uniform(0.0, 1.0, size=(2, H, W, 4))
+    feats[..., :5] = rng.uniform(0.0, 1.0, size=(2, H, W, 5))
     uhat = feats[..., 0].copy()
     vstar = uhat + rng.normal(0.0, 0.05, size=uhat.shape)
     mask = (rng.random(uhat.shape) < 0.8).astype(np.float64)
@@ -50,7 +50,7 @@ def test_gradients_match_finite_differences():
     for name, o, shape in lay:
         size = int(np.prod(shape))
         if name == "W0":
-            cand = [o + (t * C + co) * cnn.CIN0 + ci for t in range(9) for co in range(C) for ci in range(4)]
+            cand = [o + (t * C + co) * cnn.CIN0 + ci for t in range(9) for co in range(C) for ci in range(5)]
         else:
             cand = list(range(o, o + size))
         idx += list(rng.choice(cand, size=min(6, len(cand)), replace=False))
@@ -68,7 +68,7 @@ def test_unused_input_channels_have_zero_gradient():
     params, feats, uhat, vstar, mask, L, C, dil = _tiny(2)
     _, g = cnn.loss_and_grads(params, L, C, dil, feats, uhat, vstar, mask, emulate=False)
     W0 = g[:9 * C * cnn.CIN0].reshape(9, C, cnn.CIN0)
-    assert np.all(W0[:, :, 4:] == 0.0)
+    assert np.all(W0[:, :, 5:] == 0.0)
 
 
 def test_bf16_rounding_is_round_to_nearest_even():
@@ -83,3 +83,17 @@ def test_adam_first_step_is_sign_times_lr():
     # the first bias-corrected step is -lr g / (|g| + eps): the sign, up to eps / |g|
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     assert np.allclose(p, -0.01 * np.sign(g), rtol=2e-5)
+
+
+def test_crop_mask_keeps_the_margin_from_inner_edges_only():
+    cls = np.zeros((20, 20), dtype=np.uint8)
+    m = cnn.crop_mask(cls, 0, 6, 10, 20, 3)  # left edge is the box side, the others are inside
+    want = np.zeros((10, 10))
+    want[3:7, 0:7] = 1.0
+    assert np.array_equal(m, want)
+
+
+def test_boundary_feature_is_one_on_the_box_sides():
+    f = cnn.features(np.zeros((9, 9)), np.ones((9, 9)), np.zeros((9, 9), dtype=np.uint8), 1e-3, emulate=False)
+    assert np.all(f[0, :, 4] == 1.0) and np.all(f[:, -1, 4] == 1.0)
+    assert f[4, 4, 4] == np.float32(1.0) / np.float32(2.0)

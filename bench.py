@@ -7,8 +7,9 @@ discount lambda = 1, h = dx/1.5, sigma = 0, scheme SL3 (eq. SLscheme3); coarse g
 
 One step = the patchy method of Section 4.3 end to end with inputs resident in HBM: coarse solve
 (sigma = 0) -> u_hat -> synthesis of the control -> integer patch labels (64 patches) -> the fine
-solve from u_hat with tiles taken by increasing u_hat, until one full Jacobi sweep changes no
-node by more than 1e-6. `value` is the mean wall time of a step (lower is better).
+solve from u_hat with tiles taken by increasing u_hat (each tile visit alternating full Bellman
+iterations with policy-evaluation iterations, modified policy iteration), until one full Jacobi
+sweep changes no node by more than 1e-6. `value` is the mean wall time of a step (lower is better).
 
 Beside the timed steps, each comparison arm runs once (progress on stderr):
   c2     the plain cold-start global Jacobi value iteration (the SL sweep kernel at full rate), the
@@ -38,6 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# modified policy iteration inside the tile visits of the active-tile solves (0 = off)
+POLICY_SWEEPS = 7
 
 
 # the files that define the dominant kernel (the tile visit) and everything it inlines
@@ -170,10 +173,11 @@ def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
     vt = v0.clone()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    st = ctx.solve_tiles(dp, vt, tol=tol, order=capi.ORDER_NONE, max_passes=200_000)
+    st = ctx.solve_tiles(dp, vt, tol=tol, order=capi.ORDER_NONE, max_passes=200_000, policy_sweeps=POLICY_SWEEPS)
     torch.cuda.synchronize()
     out["active_tiles_cold"] = {"time_s": time.perf_counter() - t, "passes": st["sweeps"],
                                 "node_updates_per_free_node": st["node_updates"] / free,
+                                "policy_updates_per_free_node": st["policy_updates"] / free,
                                 "max_abs_diff_vs_full": float((vt - vf).abs().max())}
     log(f"bumps: active tiles {out['active_tiles_cold']['time_s']:.2f} s")
     # u_hat from a coarse sigma = 0 solve, tiles by increasing u_hat
@@ -188,11 +192,12 @@ def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
     ctx.upsample(vc, xc.n, vk, n)
     torch.cuda.synchronize()
     t_pre = time.perf_counter() - t
-    sk = ctx.solve_tiles(dp, vk, tol=tol, order=capi.ORDER_KEYS, max_passes=200_000)
+    sk = ctx.solve_tiles(dp, vk, tol=tol, order=capi.ORDER_KEYS, max_passes=200_000, policy_sweeps=POLICY_SWEEPS)
     torch.cuda.synchronize()
     out["active_tiles_uhat"] = {"time_s": time.perf_counter() - t, "coarse_and_upsample_s": t_pre,
                                 "coarse_passes": sc["sweeps"], "passes": sk["sweeps"],
                                 "node_updates_per_free_node": sk["node_updates"] / free,
+                                "policy_updates_per_free_node": sk["policy_updates"] / free,
                                 "max_abs_diff_vs_full": float((vk - vf).abs().max())}
     log(f"bumps: active tiles from u_hat {out['active_tiles_uhat']['time_s']:.2f} s")
     out["speedup_active_tiles_cold"] = out["full_sweeps"]["time_s"] / out["active_tiles_cold"]["time_s"]
@@ -224,7 +229,7 @@ def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) 
             torch.cuda.synchronize()
             t = time.perf_counter()
             sp = ctx.solve_patchy(dp, dpc, v, mode=capi.PATCHY_TRANSMISSION, tol=tol, tol_coarse=1e-7,
-                                  source_patch=src, n_patches=patches, label_out=lab)
+                                  source_patch=src, n_patches=patches, label_out=lab, policy_sweeps=POLICY_SWEEPS)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         vj = torch.from_numpy(fine.initial().reshape(-1)).cuda()
@@ -237,6 +242,7 @@ def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) 
             "patchy_time_s": times[-1], "patchy_stages_s": {k: sp[k] for k in ("t_coarse", "t_synthesize", "t_label",
                                                                                 "t_solve")},
             "patchy_passes": sp["passes"], "patchy_node_updates_per_free_node": sp["node_updates"] / free,
+            "patchy_policy_updates_per_free_node": sp["policy_updates"] / free,
             "global_jacobi_cold_s": tj, "global_jacobi_sweeps": sj["sweeps"], "halo": sj["halo"],
             "sweep_kernel_us": 1e6 * sj["sweep_seconds"] / sj["sweep_launches"],
             "speedup": tj / times[-1], "max_abs_diff": float((v - vj).abs().max()),
@@ -313,6 +319,8 @@ def main():
                          "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
                          "learned (CNN warm start at 1025^2)")
     ap.add_argument("--bumps-n", type=int, default=4097)
+    ap.add_argument("--policy-sweeps", type=int, default=POLICY_SWEEPS,
+                    help="policy-evaluation iterations after each full iteration of a tile visit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -354,7 +362,8 @@ def main():
 
     def step():
         return ctx.solve_patchy(dp, dpc, v, mode=capi.PATCHY_TRANSMISSION, tol=args.tol, tol_coarse=1e-7,
-                                source_patch=src, n_patches=args.patches, label_out=lab, collect_kernel_time=1)
+                                source_patch=src, n_patches=args.patches, label_out=lab, collect_kernel_time=1,
+                                policy_sweeps=args.policy_sweeps)
 
     for _ in range(args.warmup):
         step()
@@ -370,9 +379,12 @@ def main():
     visit_s = sum(s["t_visit"] for s in stats)
     visit_launches = sum(s["passes"] for s in stats)
     fine_updates = sum(s["node_updates"] for s in stats)
+    policy_updates = sum(s["policy_updates"] for s in stats)
     flop_per_update = RL.sweep_flops_per_node_update(fine.diffusion, scheme, fine.n_controls)
+    # a policy-evaluation update is the same update with one control
+    flop_per_policy_update = RL.sweep_flops_per_node_update(fine.diffusion, scheme, 1)
     avg_launch = visit_s / visit_launches
-    achieved = fine_updates * flop_per_update / visit_s / 1e12
+    achieved = (fine_updates * flop_per_update + policy_updates * flop_per_policy_update) / visit_s / 1e12
     kernel = "tilectl_visit_kernel<16,16,split 2,NONE,SL3,first-ring>"
     traffic = measured_traffic(kernel)
 
@@ -400,6 +412,8 @@ def main():
         "source_partition_host_s": t_part,
         "passes": int(med("passes")),
         "node_updates_per_free_node": fine_updates / len(stats) / free,
+        "policy_updates_per_free_node": policy_updates / len(stats) / free,
+        "policy_sweeps": args.policy_sweeps,
         "roofline": {
             "kernel": kernel,
             "bound": "alu",
@@ -410,6 +424,7 @@ def main():
             "traffic": traffic,
             "avg_launch_us": avg_launch * 1e6,
             "flops_per_node_update": flop_per_update,
+            "flops_per_policy_update": flop_per_policy_update,
         },
     }
 
@@ -449,7 +464,7 @@ def main():
         vs = torch.empty_like(v0)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        ss = ctx.solve_patchy(dp, None, vs, mode=capi.PATCHY_STATIC, tol=args.tol)
+        ss = ctx.solve_patchy(dp, None, vs, mode=capi.PATCHY_STATIC, tol=args.tol, policy_sweeps=args.policy_sweeps)
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         arms["static_decomposition_cold"] = {"time_s": t, "passes": ss["passes"],

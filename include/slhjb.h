@@ -104,6 +104,8 @@ typedef struct {
     int32_t kernel_path;        /* 0 general halo-tile kernel, 1 first-ring register kernel       */
     int32_t halo;               /* interpolation halo of the LDS tile, in cells                   */
     int32_t pad;
+    int64_t policy_updates;     /* node updates of policy-evaluation iterations (one control each;
+                                   active-tile solver with policy_sweeps > 0), not in node_updates */
 } slhjb_stats;
 
 /* One Jacobi sweep of the scheme (eq. SLscheme2 or SLscheme3 per problem->scheme):
@@ -136,7 +138,8 @@ typedef struct {
     float key_slack;            /* band width of arrival times (ORDER_KEYS); < 0 = the time to
                                    cross max(16, (n-1)/16) cells at the fastest speed             */
     int32_t max_inner;          /* Jacobi iterations per tile visit at most; 0 = 2 (tile width +
-                                   height) without diffusion, 2 with diffusion (eps > 0)          */
+                                   height) without diffusion, 2 with diffusion (eps > 0), or
+                                   policy_sweeps + 1 with diffusion and policy_sweeps > 0          */
     int32_t tile_shape;         /* 0: 32x16 nodes, 1: 16x16 nodes (one node per thread, 256
                                    threads); 2: 8x8 nodes with the control set split over four
                                    groups of wavefronts (256 threads); 3: 16x16 split over four
@@ -146,6 +149,10 @@ typedef struct {
     int32_t max_workgroups;     /* persistent launch: cap on co-resident workgroups; 0 = 1024     */
     int32_t collect_kernel_time;/* 1: time every visit launch with events (stats->sweep_seconds,
                                    sweep_launches = passes); graph driver only                    */
+    int32_t policy_sweeps;      /* 0..64 (tile shapes 2-4): after each full iteration of a visit,
+                                   this many iterations that apply every node's maximising control
+                                   of that iteration only (modified policy iteration; the fixed point
+                                   is the same, only full iterations decide that a tile settled)  */
 } slhjb_tile_opts;
 
 /* Solve from the guess in v (device float[n*n], overwritten) with the active-tile method: the
@@ -217,12 +224,14 @@ typedef struct {
     float key_window;             /* band width of the u_hat order, < 0 = automatic               */
     int32_t tile_shape;           /* as slhjb_tile_opts.tile_shape                                */
     int32_t collect_kernel_time;  /* as slhjb_tile_opts.collect_kernel_time (fine solve)          */
+    int32_t policy_sweeps;        /* as slhjb_tile_opts.policy_sweeps (fine solve)                */
 } slhjb_patchy_opts;
 
 typedef struct {
     double t_coarse, t_upsample, t_synthesize, t_label, t_solve, t_total;  /* seconds (events)    */
     double t_visit;               /* fine solve: time inside the tile-visit kernels (if collected)*/
     int64_t coarse_passes, node_updates_coarse, label_passes, passes, node_updates;
+    int64_t policy_updates;       /* fine solve: policy-evaluation node updates                    */
     double residual;              /* of the final check sweep on the fine grid                    */
     int32_t status;
     int32_t pad;

@@ -60,6 +60,7 @@ class Stats(ctypes.Structure):
         ("kernel_path", ctypes.c_int32),
         ("halo", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("policy_updates", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -77,6 +78,7 @@ class TileOpts(ctypes.Structure):
         ("persistent", ctypes.c_int32),
         ("max_workgroups", ctypes.c_int32),
         ("collect_kernel_time", ctypes.c_int32),
+        ("policy_sweeps", ctypes.c_int32),
     ]
 
 
@@ -97,6 +99,7 @@ class PatchyOpts(ctypes.Structure):
         ("key_window", ctypes.c_float),
         ("tile_shape", ctypes.c_int32),
         ("collect_kernel_time", ctypes.c_int32),
+        ("policy_sweeps", ctypes.c_int32),
     ]
 
 
@@ -114,6 +117,7 @@ class PatchyStats(ctypes.Structure):
         ("label_passes", ctypes.c_int64),
         ("passes", ctypes.c_int64),
         ("node_updates", ctypes.c_int64),
+        ("policy_updates", ctypes.c_int64),
         ("residual", ctypes.c_double),
         ("status", ctypes.c_int32),
         ("pad", ctypes.c_int32),
@@ -356,9 +360,9 @@ class Context:
     def solve_tiles(self, prob: DeviceProblem, v, tol: float = 1e-6, max_passes: int = 1_000_000,
                     order: int = ORDER_NONE, mode: int = MODE_TRANSMISSION, label=None, key_slack: float = -1.0,
                     max_inner: int = 0, tile_shape: int = TILE_16x16_SPLIT2, persistent: int = 0, max_workgroups: int = 0,
-                    collect_kernel_time: int = 0):
+                    collect_kernel_time: int = 0, policy_sweeps: int = 0):
         opts = TileOpts(order, mode, _ptr(label) if label is not None else None, key_slack, max_inner, tile_shape,
-                        persistent, max_workgroups, collect_kernel_time)
+                        persistent, max_workgroups, collect_kernel_time, policy_sweeps)
         stats = Stats()
         st = lib().slhjb_solve_tiles(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_passes,
                                      ctypes.byref(opts), ctypes.byref(stats))
@@ -368,9 +372,9 @@ class Context:
     def solve_patchy(self, fine: DeviceProblem, coarse: DeviceProblem | None, v, mode: int = PATCHY_TRANSMISSION,
                      tol: float = 1e-6, tol_coarse: float = 1e-7, source_patch=None, n_patches: int = 0,
                      label_out=None, max_passes: int = 1_000_000, key_window: float = -1.0, tile_shape: int = TILE_16x16_SPLIT2,
-                     collect_kernel_time: int = 0):
+                     collect_kernel_time: int = 0, policy_sweeps: int = 0):
         opts = PatchyOpts(mode, n_patches, _ptr(source_patch) if source_patch is not None else None, tol, tol_coarse,
-                          max_passes, key_window, tile_shape, collect_kernel_time)
+                          max_passes, key_window, tile_shape, collect_kernel_time, policy_sweeps)
         stats = PatchyStats()
         st = lib().slhjb_solve_patchy(self.handle, ctypes.byref(fine.struct),
                                       ctypes.byref(coarse.struct) if coarse is not None else None,

@@ -40,7 +40,6 @@ struct slhjb_ctx {
   // active-tile solver scratch
   float* tkey = nullptr;
   float* tchange = nullptr;
-  unsigned long long* tupdates = nullptr;
   size_t stiles_cap = 0;
   void* coop = nullptr;           // persistent-solver state (device)
   unsigned* coop_host = nullptr;  // pinned mirror
@@ -345,7 +344,6 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tcount_host) hipHostFree(ctx->tcount_host);
   if (ctx->tkey) hipFree(ctx->tkey);
   if (ctx->tchange) hipFree(ctx->tchange);
-  if (ctx->tupdates) hipFree(ctx->tupdates);
   if (ctx->coop) hipFree(ctx->coop);
   if (ctx->tctl) hipFree(ctx->tctl);
   if (ctx->lctl) hipFree(ctx->lctl);
@@ -477,6 +475,7 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
     stats->kernel_path = P.path;
     stats->halo = P.args.halo;
     stats->pad = 0;
+    stats->policy_updates = 0;
   }
   if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
   return status;
@@ -488,6 +487,8 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   if (!fine || !opts || !v) return fail(ctx, SLHJB_E_INVALID_ARG, "fine, opts and v must be non-NULL");
   if (opts->mode < 0 || opts->mode > 2) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown patchy mode");
   if (!(opts->tol > 0.0) || opts->max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0, max_passes >= 1");
+  if (opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "policy_sweeps must be in [0, 64]");
   const bool pdd = opts->mode != SLHJB_PATCHY_STATIC;
   const bool need_labels = opts->mode == SLHJB_PATCHY_INDEPENDENT || label_out;
   if (pdd) {
@@ -527,6 +528,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   to.tile_shape = opts->tile_shape;
   to.key_slack = opts->key_window;
   to.collect_kernel_time = opts->collect_kernel_time;
+  to.policy_sweeps = opts->policy_sweeps;
   slhjb_stats ts;
   int16_t* ctrl = nullptr;
   float* vc = nullptr;
@@ -599,6 +601,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   if (st == SLHJB_OK || st == SLHJB_NOT_CONVERGED) {
     S.passes = ts.sweeps;
     S.node_updates = ts.node_updates;
+    S.policy_updates = ts.policy_updates;
     S.residual = ts.residual;
     S.t_solve = ts.seconds;
     S.t_visit = ts.sweep_seconds;
@@ -738,7 +741,8 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
   if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
       opts->tile_shape < 0 || opts->tile_shape >= kTileShapes || opts->persistent < 0 || opts->persistent > 1 ||
-      opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1)
+      opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1 ||
+      opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
     return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
   if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
     return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
@@ -768,14 +772,17 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
     ctx->stiles_cap = tiles;
   }
-  if (!ctx->tupdates) HIP_TRY(ctx, hipMalloc(&ctx->tupdates, sizeof(unsigned long long)));
   const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;
   const bool keyed = opts->order == SLHJB_ORDER_KEYS;
   // Without diffusion a tile is a transport problem: iterating it to its own fixed point against
   // the frozen halo carries the values across it in one visit. With diffusion every node depends
   // on the halo through the noise feet and a settled tile is settled only once its neighbours are:
   // a few iterations per visit waste the least work.
-  const int max_inner = opts->max_inner > 0 ? opts->max_inner : (P.diffusion == SLHJB_DIFF_NONE ? 2 * (tw + th) : 2);
+  // (with policy-evaluation iterations: one full iteration and the policy sweeps per visit)
+  const int max_inner = opts->max_inner > 0
+                            ? opts->max_inner
+                            : (P.diffusion == SLHJB_DIFF_NONE ? 2 * (tw + th)
+                                                               : (opts->policy_sweeps > 0 ? opts->policy_sweeps + 1 : 2));
   const float tol_inner = (float)(0.5 * tol), act = (float)(0.5 * tol);
   // band width of arrival times: the time to cross 1/16 of the box (at least 16 cells) at the
   // fastest speed
@@ -793,7 +800,6 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     HIP_TRY(ctx, launch_tile_keys(v, problem->node_class, tw, th, n, tiles_x, tiles_y, P.vstar, problem->lambda,
                                   ctx->tkey, ctx->stream));
   HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tupdates, 0u, 2, ctx->stream));
   HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount + 2, 0xff800000u, 1, ctx->stream));  // band bound -inf
   HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tcount + 3, 0u, 1, ctx->stream));           // passes with work
   SweepArgs a = P.args;
@@ -801,7 +807,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   int64_t passes = 0, converged = -1;
   double resid = INFINITY;
   int status = SLHJB_NOT_CONVERGED;
-  int64_t coop_updates = -1;
+  int64_t updates = 0, pe_updates = 0;
   double visit_sec = 0.0;
   if (opts->persistent) {
     if (!ctx->coop) {
@@ -815,7 +821,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
                                         keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf,
                                         ctx->tchange, ctx->tflag, max_inner, tol_inner, act, window, (float)tol, mp,
                                         ctx->coop, opts->max_workgroups > 0 ? opts->max_workgroups : 1024, &grid_used,
-                                        ctx->stream));
+                                        opts->policy_sweeps, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->coop_host, ctx->coop, coop_state_bytes(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const unsigned* cs = ctx->coop_host;
@@ -827,9 +833,11 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
       status = SLHJB_OK;
       converged = passes;
     }
-    unsigned long long u;
+    unsigned long long u, pu;
     memcpy(&u, &cs[6], sizeof(u));
-    coop_updates = (int64_t)u;
+    memcpy(&pu, &cs[8], sizeof(pu));
+    updates = (int64_t)u;
+    pe_updates = (int64_t)pu;
   }
   if (!opts->persistent) {
     // device-driven passes, captured once into a graph of kBatch passes and replayed
@@ -853,7 +861,8 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
         e = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label,
                                 keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange,
                                 ctx->tflag, max_inner, tol_inner, act, window, (float)tol, b & 1, ctx->tctl, grid,
-                                ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr, s);
+                                ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr,
+                                opts->policy_sweeps, s);
       return e;
     };
     if (!timing) {
@@ -900,24 +909,22 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
       converged = passes;
       resid = r;
     }
-    unsigned long long u;
+    unsigned long long u, pu;
     memcpy(&u, &ctx->tctl_host[12], sizeof(u));
-    coop_updates = (int64_t)u;
+    memcpy(&pu, &ctx->tctl_host[14], sizeof(pu));
+    updates = (int64_t)u;
+    pe_updates = (int64_t)pu;
   }
   HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-  unsigned long long upd = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&ctx->small_host[8], ctx->tupdates, sizeof(upd), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  memcpy(&upd, &ctx->small_host[8], sizeof(upd));
-  if (coop_updates >= 0) upd = (unsigned long long)coop_updates;
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
   float ms = 0.0f;
   HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   if (stats) {
     memset(stats, 0, sizeof(*stats));
     stats->sweeps = passes;
     stats->converged_sweep = converged;
-    stats->node_updates = (int64_t)upd;
+    stats->node_updates = updates;
     stats->residual = resid;
     stats->seconds = ms * 1e-3;
     stats->status = status;
@@ -925,6 +932,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     stats->halo = P.args.halo;
     stats->sweep_seconds = visit_sec;
     stats->sweep_launches = visit_sec > 0.0 ? passes : 0;
+    stats->policy_updates = pe_updates;
   }
   return status;
 }

@@ -87,19 +87,21 @@ hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int tw, int th, 
 size_t coop_state_bytes();
 hipError_t launch_coop_state_init(void* state, hipStream_t s);
 // Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes(). Layout of
-// the words the host reads: [9] done, [10] passes, [7] resid bits, [12..13] updates.
+// the words the host reads: [9] done, [10] passes, [7] resid bits, [12..13] updates,
+// [14..15] policy-evaluation updates. `pe`: policy-evaluation iterations after each full one
+// (split tile shapes only). The cooperative state: [6..7] updates, [8..9] policy updates.
 size_t tilectl_bytes();
 hipError_t launch_tilectl_init(void* ctl, hipStream_t s);
 hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
-                               hipEvent_t ev_after, hipStream_t s);
+                               hipEvent_t ev_after, int pe, hipStream_t s);
 hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                   float act, float window, float tol, int max_passes, void* state, int max_grid,
-                                  int* grid_used, hipStream_t s);
+                                  int* grid_used, int pe, hipStream_t s);
 
 // Batched solve (batch.hip). One entry per instance; `a` carries the instance's parameters as for
 // the single-instance sweep (its pointers w_in/w_out/resid/flags are not used: the iterates live in

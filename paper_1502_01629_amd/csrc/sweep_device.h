@@ -225,11 +225,11 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
 // control list, so every wavefront still walks a uniform control range with scalar loads.
 // Partial of SL2 (first ring): max over the range of I - w00; of SL2 (general): max of the feet
 // sum; of SL3: the best quotient as (num, den).
-template <int SCHEME, bool EDGE, bool INDEP>
+template <int SCHEME, bool EDGE, bool INDEP, bool TRACK = false>
 __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int LW, float k,
                                               const float4* __restrict__ ctrl, const SweepArgs& a, bool lft, bool rgt,
                                               bool bot, bool top, const int16_t* __restrict__ L, int q_lo,
-                                              int q_hi, float& pnum, float& pden) {
+                                              int q_hi, float& pnum, float& pden, int* pidx = nullptr) {
   const float w00 = T[0];
   float wE = T[1], wW = T[-1], wN = T[LW], wS = T[-LW];
   float wNE = T[LW + 1], wNW = T[LW - 1], wSE = T[-LW + 1], wSW = T[-LW - 1];
@@ -253,6 +253,7 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
   const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
   float best2 = -INFINITY;
   float bnum = -1.0f, bden = 1.0f;
+  int bidx = 0;
   const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll
@@ -277,7 +278,14 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
         if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
         if (SCHEME == kSL2) {
           if (EDGE) val = out ? a.w_outside - w00 : val;
-          best2 = fmaxf(best2, val);
+          if (TRACK) {
+            if (val > best2) {
+              best2 = val;
+              bidx = m0 + u;
+            }
+          } else {
+            best2 = fmaxf(best2, val);
+          }
         } else {
           float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
           if (EDGE) {
@@ -287,6 +295,7 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
           if (val * bden > bnum * den) {
             bnum = val;
             bden = den;
+            if (TRACK) bidx = m0 + u;
           }
         }
       }
@@ -299,13 +308,58 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
     pnum = bnum;
     pden = bden;
   }
+  if (TRACK) *pidx = bidx;
 }
 
-template <int DIFF, int SCHEME, bool INDEP>
+// First-ring update of one node for one control cm (policy evaluation of modified policy
+// iteration): the expressions of ring1_partial for that control, with its quadrant taken from
+// the signs of (a_x, a_y) as the host groups the table. Returns (num, den) as a partial does.
+template <int SCHEME, bool INDEP>
+__device__ __forceinline__ void ring1_policy(const float* __restrict__ T, int LW, float k, float4 cm,
+                                             const SweepArgs& a, bool lft, bool rgt, bool bot, bool top,
+                                             const int16_t* __restrict__ L, float& pnum, float& pden) {
+  // the host's quadrant of a control is (+x,+y), (-x,+y), (-x,-y) or (+x,-y) by the signs a_x >= 0,
+  // a_y >= 0: the cell east/west and north/south of the node
+  const int ox = cm.x >= 0.0f ? 1 : -1;
+  const int oy = cm.y >= 0.0f ? LW : -LW;
+  const float w00 = T[0];
+  float wX = T[ox], wY = T[oy], wXY = T[ox + oy];
+  if (INDEP) {
+    const int me = L[0];
+    wX = L[ox] == me ? wX : a.w_outside;
+    wY = L[oy] == me ? wY : a.w_outside;
+    wXY = L[ox + oy] == me ? wXY : a.w_outside;
+  }
+  const float sx = ox > 0 ? 1.0f : -1.0f, sy = oy > 0 ? 1.0f : -1.0f;
+  const float k2 = k * k;
+  float B, C, D;
+  if (SCHEME == kSL2) {
+    B = k * sx * (wX - w00);
+    C = k * sy * (wY - w00);
+    D = k2 * (sx * sy) * ((wXY - wX) - (wY - w00));
+  } else {
+    B = k * sx * wX;
+    C = k * sy * wY;
+    D = k2 * (sx * sy) * (wXY - wX - wY);
+  }
+  float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
+  const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+  if (SCHEME == kSL2) {
+    pnum = out ? a.w_outside - w00 : val;
+    pden = 1.0f;
+  } else {
+    const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
+    const float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
+    pnum = out ? a.w_outside : val;
+    pden = out ? 1.0f : den;
+  }
+}
+
+template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false>
 __device__ __forceinline__ void general_partial(const float* __restrict__ tile, int LW, int node_li, int i, int j,
                                                 float k, float wself, const float4* __restrict__ ctrl,
                                                 const SweepArgs& a, const int16_t* __restrict__ lab, int mylab,
-                                                int m_lo, int m_hi, float& pnum, float& pden) {
+                                                int m_lo, int m_hi, float& pnum, float& pden, int* pidx = nullptr) {
   using F = Feet<DIFF>;
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
@@ -315,6 +369,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
   const float LWf = (float)LW;
   float best2 = -INFINITY;
   float bnum = -1.0f, bden = 1.0f;
+  int bidx = m_lo;
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll 4
   for (int m = m_lo; m < m_hi; ++m) {
@@ -353,13 +408,21 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
       }
     }
     if (SCHEME == kSL2) {
-      best2 = fmaxf(best2, acc);
+      if (TRACK) {
+        if (acc > best2) {
+          best2 = acc;
+          bidx = m;
+        }
+      } else {
+        best2 = fmaxf(best2, acc);
+      }
     } else {
       const float num = __builtin_fmaf(-lam0, wself, acc);
       const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
       if (num * bden > bnum * den) {
         bnum = num;
         bden = den;
+        if (TRACK) bidx = m;
       }
     }
   }
@@ -370,5 +433,6 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
     pnum = bnum;
     pden = bden;
   }
+  if (TRACK) *pidx = bidx;
 }
 }  // namespace slhjb

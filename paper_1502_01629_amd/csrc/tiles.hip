@@ -24,6 +24,11 @@ namespace slhjb {
 // and the first group combines them in a fixed order, so the result does not depend on timing.
 // Splitting the controls shortens one inner iteration S times, which is what bounds a pass when
 // few tiles are selected.
+//
+// Modified policy iteration (pe > 0): after every full iteration, pe policy-evaluation
+// iterations apply each node's maximising control of that full iteration only (one candidate,
+// no search); the fixed point is the same, and only full iterations decide that a tile settled.
+// Their node updates are counted apart in pe_updates.
 template <int T, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
 __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float* __restrict__ w,
                                                  const float* __restrict__ speed, const uint8_t* __restrict__ cls,
@@ -31,7 +36,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
                                                  int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                                  float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                                  float tol_inner, unsigned long long* __restrict__ updates, float* lds,
-                                                 float* red) {
+                                                 float* red, int pe, unsigned long long* __restrict__ pe_updates) {
   constexpr int TT = T * T, NT = TT * S;
   static_assert(TT % 64 == 0 && (S == 2 || S == 4), "split tile shape");
   const int R = a.halo;
@@ -40,7 +45,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   float* bufB = lds + span;
   float* pn = lds + 2 * span;
   float* pd = pn + NT;
-  int16_t* labs = (int16_t*)(pd + NT);
+  int* pix = (int*)(pd + NT);
+  int16_t* labs = (int16_t*)(pix + NT);
   const int n = a.n;
   const int node = threadIdx.x % TT, part = threadIdx.x / TT;
   const int tx = tid % tiles_x, ty = tid / tiles_x;
@@ -71,34 +77,58 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   __syncthreads();
   float* cur = bufA;
   float* nxt = bufB;
-  int it = 0;
+  int it = 0, evals = 0;
+  int pol = 0;  // maximising control of the last full iteration (part 0)
   for (;;) {
     if (fr) {
       float num, den;
+      int mi = 0;
       if (PATH == 1) {
         const float* Tp = cur + li;
         const int16_t* L = INDEP ? labs + li : nullptr;
-        if (interior)
-          ring1_partial<SCHEME, false, INDEP>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
-                                              part * QP + QP, num, den);
-        else
-          ring1_partial<SCHEME, true, INDEP>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1, L,
-                                             part * QP, part * QP + QP, num, den);
+        if (pe > 0) {
+          if (interior)
+            ring1_partial<SCHEME, false, INDEP, true>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
+                                                      part * QP + QP, num, den, &mi);
+          else
+            ring1_partial<SCHEME, true, INDEP, true>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1,
+                                                     L, part * QP, part * QP + QP, num, den, &mi);
+        } else {
+          if (interior)
+            ring1_partial<SCHEME, false, INDEP>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
+                                                part * QP + QP, num, den);
+          else
+            ring1_partial<SCHEME, true, INDEP>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1, L,
+                                               part * QP, part * QP + QP, num, den);
+        }
       } else {
-        general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                             INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den);
+        if (pe > 0)
+          general_partial<DIFF, SCHEME, INDEP, true>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
+                                                     INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den,
+                                                     &mi);
+        else
+          general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
+                                               INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den);
       }
       pn[part * TT + node] = num;
       pd[part * TT + node] = den;
+      pix[part * TT + node] = mi;
     }
     __syncthreads();
     float lmax = 0.0f;
     if (part == 0 && fr) {
       float v;
+      int bi = pix[node];
       if (SCHEME == kSL2) {
         float m = pn[node];
 #pragma unroll
-        for (int q = 1; q < S; ++q) m = fmaxf(m, pn[q * TT + node]);
+        for (int q = 1; q < S; ++q) {
+          const float qm = pn[q * TT + node];
+          if (qm > m) {
+            m = qm;
+            bi = pix[q * TT + node];
+          }
+        }
         constexpr int K = Feet<DIFF>::K;
         v = PATH == 1 ? a.beta * (cur[li] + m) : a.beta * m * (1.0f / (float)K);
       } else {
@@ -109,10 +139,12 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
           if (qn * bd > bn * qd) {
             bn = qn;
             bd = qd;
+            bi = pix[q * TT + node];
           }
         }
         v = a.beta * bn / bd;
       }
+      pol = bi;
       nxt[li] = v;
       lmax = fabsf(v - cur[li]);
     }
@@ -122,6 +154,32 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     nxt = tmp;
     ++it;
     if (!moving || it >= max_inner) break;
+    // policy evaluation: the last full iteration's maximising control of every node, one
+    // candidate each; leaves room for the full iteration that must end the visit
+    if (pe > 0) {
+      const float4 cm = ctrl[pol];
+      for (int e = 0; e < pe && it < max_inner - 1; ++e) {
+        if (part == 0 && fr) {
+          float num, den;
+          if (PATH == 1) {
+            ring1_policy<SCHEME, INDEP>(cur + li, LW, kk, cm, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1,
+                                        INDEP ? labs + li : nullptr, num, den);
+            nxt[li] = SCHEME == kSL2 ? a.beta * (cur[li] + num) : a.beta * num / den;
+          } else {
+            general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
+                                                 INDEP ? labs[li] : 0, pol, pol + 1, num, den);
+            constexpr int K = Feet<DIFF>::K;
+            nxt[li] = SCHEME == kSL2 ? a.beta * num * (1.0f / (float)K) : a.beta * num / den;
+          }
+        }
+        __syncthreads();
+        float* t2 = cur;
+        cur = nxt;
+        nxt = t2;
+        ++it;
+        ++evals;
+      }
+    }
   }
   float moved = 0.0f;
   if (part == 0) {
@@ -137,7 +195,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     for (int k = 1; k < TT / 64; ++k) m = fmaxf(m, red[k]);
     const bool unsettled = it >= max_inner && max_inner > 1;
     tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
-    atomicAdd(updates, (unsigned long long)it * (unsigned long long)free_total);
+    atomicAdd(updates, (unsigned long long)(it - evals) * (unsigned long long)free_total);
+    if (evals) atomicAdd(pe_updates, (unsigned long long)evals * (unsigned long long)free_total);
   }
   __syncthreads();
 }
@@ -151,13 +210,16 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                            int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                            float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                            float tol_inner, unsigned long long* __restrict__ updates, float* lds,
-                                           float* red) {
+                                           float* red, int pe, unsigned long long* __restrict__ pe_updates) {
   if constexpr (S > 1) {
     static_assert(TW == TH, "split tiles are square");
     visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf,
-                                                       tchange, flag, max_inner, tol_inner, updates, lds, red);
+                                                       tchange, flag, max_inner, tol_inner, updates, lds, red, pe,
+                                                       pe_updates);
     return;
   } else {
+  (void)pe;
+  (void)pe_updates;
   constexpr int kTW = TW, kTH = TH, kTN = TW * TH, NPT = kTN / kThreads;  // NPT nodes per thread
   static_assert(kTN % kThreads == 0 && 64 % TW == 0, "tile shape");
   const int R = a.halo;
@@ -325,7 +387,8 @@ __global__ __launch_bounds__(kThreads) void tile_keys_kernel(const float* __rest
 
 size_t tile_pass_lds_bytes(const TileShape& sh, int halo, bool indep) {
   const size_t span = (size_t)(sh.tw + 2 * halo) * (sh.th + 2 * halo);
-  const size_t partials = sh.split > 1 ? 2 * (size_t)sh.threads * sizeof(float) : 0;
+  // split shapes: per thread a partial numerator, denominator and control index
+  const size_t partials = sh.split > 1 ? 3 * (size_t)sh.threads * sizeof(float) : 0;
   return 2 * span * sizeof(float) + partials + (indep ? span * sizeof(int16_t) : 0);
 }
 
@@ -360,7 +423,11 @@ struct CoopState {
   unsigned passes;    // passes done (written by workgroup 0 at the end)
   unsigned status;    // 1 converged, 2 pass budget exhausted
   unsigned long long updates;
+  unsigned long long pe_updates;
 };
+static_assert(offsetof(CoopState, updates) == 6 * 4 && offsetof(CoopState, pe_updates) == 8 * 4 &&
+                  sizeof(CoopState) <= 64,
+              "host reads these words");
 
 __device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -382,7 +449,7 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const float* __restrict__ key,
     int* __restrict__ list, int tiles_x, int tiles_y, float* __restrict__ outbuf, float* __restrict__ tchange,
     uint8_t* __restrict__ flag, int max_inner, float tol_inner, float act, float window, float tol, int max_passes,
-    CoopState* __restrict__ st) {
+    CoopState* __restrict__ st, int pe) {
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
   cooperative_groups::grid_group g = cooperative_groups::this_grid();
@@ -428,7 +495,8 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
       // (3) visits
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
         visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                      tchange, flag, max_inner, tol_inner, &st->updates, lds, red);
+                                                      tchange, flag, max_inner, tol_inner, &st->updates, lds, red, pe,
+                                                      &st->pe_updates);
       grid_barrier(g);
       // (4) commits; workgroup 0 resets the selection state for the next pass
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
@@ -444,7 +512,7 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
     // nothing flagged: check sweep of every tile, one Jacobi iteration each
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, &st->updates, lds, red);
+                                                    flag, 1, 0.0f, &st->updates, lds, red, 0, &st->pe_updates);
     grid_barrier(g);
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, &st->resid);
@@ -472,7 +540,7 @@ template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP>
 static hipError_t launch_coop_one(const SweepArgs& a, const int16_t* label, const float* key, int* list, int tiles_x,
                                   int tiles_y, float* outbuf, float* tchange, uint8_t* flag, int max_inner,
                                   float tol_inner, float act, float window, float tol, int max_passes, CoopState* st,
-                                  int max_grid, int* grid_used, hipStream_t s) {
+                                  int max_grid, int* grid_used, int pe, hipStream_t s) {
   auto kern = tile_solve_coop_kernel<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>;
   const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
   const size_t lds = tile_pass_lds_bytes(sh, a.halo, INDEP);
@@ -493,7 +561,7 @@ static hipError_t launch_coop_one(const SweepArgs& a, const int16_t* label, cons
   const uint8_t* cp = a.cls;
   const float4* ct = a.ctrl;
   void* args[] = {&aa, &wp, &sp, &cp, &ct, (void*)&label, (void*)&key, &list, &tiles_x, &tiles_y, &outbuf,
-                  &tchange, &flag, &max_inner, &tol_inner, &act, &window, &tol, &max_passes, &st};
+                  &tchange, &flag, &max_inner, &tol_inner, &act, &window, &tol, &max_passes, &st, &pe};
   return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(sh.threads), args, (unsigned)lds, s);
 }
 
@@ -502,11 +570,11 @@ static hipError_t launch_coop_shape(const SweepArgs& a, int diffusion, int schem
                                     const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                     float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                     float act, float window, float tol, int max_passes, CoopState* st, int max_grid,
-                                    int* grid_used, hipStream_t s) {
+                                    int* grid_used, int pe, hipStream_t s) {
 #define SLHJB_CO(D, S, PA, IN)                                                                                        \
   return launch_coop_one<TW, TH, SPL, D, S, PA, IN>(a, label, key, list, tiles_x, tiles_y, outbuf, tchange, flag,     \
                                                     max_inner, tol_inner, act, window, tol, max_passes, st, max_grid, \
-                                                    grid_used, s)
+                                                    grid_used, pe, s)
 #define SLHJB_CO_S(D, PA, IN)                      \
   do {                                             \
     if (scheme == kSL2) SLHJB_CO(D, kSL2, PA, IN); \
@@ -539,12 +607,12 @@ hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, 
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                   float act, float window, float tol, int max_passes, void* state, int max_grid,
-                                  int* grid_used, hipStream_t s) {
+                                  int* grid_used, int pe, hipStream_t s) {
   CoopState* st = (CoopState*)state;
 #define SLHJB_COOP_CALL(TW, TH, SPL)                                                                                  \
   return launch_coop_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, outbuf, \
                                         tchange, flag, max_inner, tol_inner, act, window, tol, max_passes, st,       \
-                                        max_grid, grid_used, s)
+                                        max_grid, grid_used, pe, s)
   SLHJB_FOR_SHAPE(shape, SLHJB_COOP_CALL)
 #undef SLHJB_COOP_CALL
 }
@@ -559,6 +627,7 @@ __global__ void coop_state_init_kernel(CoopState* st) {
   st->passes = 0u;
   st->status = 0u;
   st->updates = 0ull;
+  st->pe_updates = 0ull;
 }
 
 hipError_t launch_coop_state_init(void* state, hipStream_t s) {
@@ -583,6 +652,7 @@ struct TileCtl {
   unsigned passes;     // passes that did work (check sweeps included)
   unsigned pad;
   unsigned long long updates;
+  unsigned long long pe_updates;  // policy-evaluation node updates
 };
 
 __global__ void tilectl_init_kernel(TileCtl* c) {
@@ -596,6 +666,7 @@ __global__ void tilectl_init_kernel(TileCtl* c) {
   c->passes = 0u;
   c->pad = 0u;
   c->updates = 0ull;
+  c->pe_updates = 0ull;
 }
 
 // Also clears the outcome of the last check sweep once read: a workgroup that reads it after
@@ -646,7 +717,7 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x,
     int tiles, float* __restrict__ outbuf, float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-    float tol_inner, float window, int q, TileCtl* __restrict__ c) {
+    float tol_inner, float window, int q, TileCtl* __restrict__ c, int pe) {
   if (c->done) return;
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
@@ -655,7 +726,8 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
   if (cnt > 0) {
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                    tchange, flag, max_inner, tol_inner, &c->updates, lds, red);
+                                                    tchange, flag, max_inner, tol_inner, &c->updates, lds, red, pe,
+                                                    &c->pe_updates);
   } else if (nf > 0) {
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
     if (blockIdx.x == 0 && threadIdx.x == 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
@@ -663,7 +735,7 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     // nothing flagged: check sweep, one Jacobi iteration of every tile
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, &c->updates, lds, red);
+                                                    flag, 1, 0.0f, &c->updates, lds, red, 0, &c->pe_updates);
   }
 }
 
@@ -696,7 +768,8 @@ __global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __r
 }
 
 static_assert(offsetof(TileCtl, resid) == 7 * 4 && offsetof(TileCtl, done) == 9 * 4 &&
-                  offsetof(TileCtl, passes) == 10 * 4 && offsetof(TileCtl, updates) == 12 * 4,
+                  offsetof(TileCtl, passes) == 10 * 4 && offsetof(TileCtl, updates) == 12 * 4 &&
+                  offsetof(TileCtl, pe_updates) == 14 * 4 && sizeof(TileCtl) <= 64,
               "host reads these words");
 size_t tilectl_bytes() { return sizeof(TileCtl); }
 
@@ -710,7 +783,7 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                       const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                       float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                       float act, float window, float tol, int q, TileCtl* c, int grid,
-                                      hipEvent_t ev_before, hipEvent_t ev_after, hipStream_t s) {
+                                      hipEvent_t ev_before, hipEvent_t ev_after, int pe, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   tilectl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, tol, q, list, c);
   const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
@@ -719,7 +792,7 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
 #define SLHJB_TV(D, S, PA, IN)                                                                              \
   tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                            \
       a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,     \
-      tol_inner, window, q, c)
+      tol_inner, window, q, c, pe)
 #define SLHJB_TV_S(D, PA, IN)                      \
   do {                                             \
     if (scheme == kSL2) SLHJB_TV(D, kSL2, PA, IN); \
@@ -746,11 +819,11 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
-                               hipEvent_t ev_after, hipStream_t s) {
+                               hipEvent_t ev_after, int pe, hipStream_t s) {
 #define SLHJB_CTL_CALL(TW, TH, SPL)                                                                                  \
   launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y,      \
                                          outbuf, tchange, flag, max_inner, tol_inner, act, window, tol, q,           \
-                                         (TileCtl*)ctl, grid, ev_before, ev_after, s);                               \
+                                         (TileCtl*)ctl, grid, ev_before, ev_after, pe, s);                           \
   break
   SLHJB_FOR_SHAPE(shape, SLHJB_CTL_CALL)
 #undef SLHJB_CTL_CALL

@@ -138,3 +138,37 @@ def test_persistent_and_host_driven_agree_bit_for_bit(ctx, order, shape):
         out.append((v.cpu().numpy(), st["sweeps"], st["node_updates"]))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("shape", [2, 4])
+@pytest.mark.parametrize("pe", [2, 8])
+@pytest.mark.parametrize("eps,scheme", [(0.0, 1), (0.0, 0), (0.01, 1)])
+def test_policy_evaluation_iterations_reach_the_same_fixed_point(ctx, shape, pe, eps, scheme):
+    """Modified policy iteration inside the visits: cheap iterations with each node's maximising
+    control between full ones; the fixed point, and so the oracle's solution, is unchanged."""
+    from paper_1502_01629_amd import capi
+
+    inst = I.disc_problem(129, eps)
+    dp = capi.DeviceProblem(inst, scheme)
+    v = _dev(inst.initial())
+    st = ctx.solve_tiles(dp, v, tol=5e-7, order=0, max_passes=20000, tile_shape=shape, policy_sweeps=pe,
+                         max_inner=16 if eps > 0 else 0)
+    print(st, flush=True)
+    assert st["status"] == 0 and st["residual"] <= 5e-7
+    assert st["policy_updates"] > 0
+    ref, _, _, _ = oracle.Problem.from_instance(inst, scheme).solve(tol=1e-10, threads=8)
+    err = np.abs(v.cpu().numpy().astype(np.float64) - ref).max()
+    print("max abs err", err, flush=True)
+    assert err < 1e-5
+
+
+def test_policy_evaluation_on_scattered_obstacles_uhat_order(ctx):
+    from paper_1502_01629_amd import capi
+
+    fine, coarse = I.scattered_problem(1, n=257, n_coarse=65)
+    dp = capi.DeviceProblem(fine, 1)
+    v = _dev(_uhat(fine, coarse))
+    st = ctx.solve_tiles(dp, v, tol=5e-7, order=1, max_passes=20000, policy_sweeps=4)
+    assert st["status"] == 0 and st["policy_updates"] > 0
+    ref, _, _, _ = oracle.Problem.from_instance(fine, 1).solve(tol=1e-10, threads=8)
+    assert np.abs(v.cpu().numpy().astype(np.float64) - ref).max() < 1e-5

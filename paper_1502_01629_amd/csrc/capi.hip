@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/slhjb.h"
@@ -48,6 +49,13 @@ struct slhjb_ctx {
   unsigned* lctl_host = nullptr;
   unsigned* tctl_host = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  // labeler buffers of its own, so that it can run beside the tile solver (patchy pipeline)
+  hipStream_t aux_stream = nullptr;
+  uint8_t* lflag = nullptr;
+  int* llist = nullptr;
+  float* lkey = nullptr;
+  size_t ltiles_cap = 0;
+  float2* lctab = nullptr;        // controls in the caller's order, for the labeler's feet
   hipEvent_t tev[32] = {};           // visit-kernel timing events of one captured batch
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
@@ -350,6 +358,11 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->lctl_host) hipHostFree(ctx->lctl_host);
   if (ctx->tctl_host) hipHostFree(ctx->tctl_host);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
+  if (ctx->lflag) hipFree(ctx->lflag);
+  if (ctx->llist) hipFree(ctx->llist);
+  if (ctx->lkey) hipFree(ctx->lkey);
+  if (ctx->lctab) hipFree(ctx->lctab);
   for (auto& e : ctx->tev)
     if (e) hipEventDestroy(e);
   if (ctx->coop_host) hipHostFree(ctx->coop_host);
@@ -481,6 +494,139 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
   return status;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Everything one run of the labeler needs, decided and validated beforehand; the run itself only
+// enqueues on its stream and reads the pass state back.
+struct LabelJob {
+  int n = 0, Ppad = 2, n_patches = 1, tiles_x = 0;
+  const int16_t* ctrl = nullptr;
+  const float* v_hat = nullptr;
+  const int16_t* source_patch = nullptr;
+  const uint8_t* cls = nullptr;
+  const float* speed = nullptr;
+  float speed_const = 1.0f, r = 0.0f, vstar = 1.0f, lambda = 1.0f, window = INFINITY;
+  uint16_t tau = 0;
+  int16_t* label_out = nullptr;
+  uint64_t* overlap_out = nullptr;
+  uint16_t* phi_out = nullptr;
+  // scratch
+  uint32_t* phi = nullptr;
+  uint8_t* flag = nullptr;
+  int* list = nullptr;
+  float* key = nullptr;
+  void* lctl = nullptr;
+  unsigned* lctl_host = nullptr;
+  const float2* ctab = nullptr;
+  bool keys_ready = false;  // the caller already computed the u_hat keys into `key`
+};
+
+// Validation and parameters of a labeling of `problem` (after prepare(): speed bounds in
+// small_host), the phi scratch and the pass state; the tile buffers are the caller's choice.
+int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P, const int16_t* ctrl,
+                const float* v_hat, const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15,
+                int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out, LabelJob* J) {
+  if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
+  if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
+  if (tau_q15 > (1u << 15)) return fail(ctx, SLHJB_E_INVALID_ARG, "tau_q15 must be <= 2^15");
+  // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
+  slhjb_problem p0 = *problem;
+  p0.diffusion = SLHJB_DIFF_NONE;
+  const float speed_max = (float)speed_max_of(ctx, problem);
+  if (reach_for(&p0, speed_max) > 1.0 + 1e-6)
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labeling needs h c |a| <= dx (feet in the first ring of cells)");
+  const int n = problem->n;
+  const int64_t N = (int64_t)n * n;
+  int Ppad = 2;
+  while (Ppad < n_patches) Ppad *= 2;
+  const size_t words = (size_t)N * (Ppad / 2);
+  if (ctx->phi_words < words) {
+    if (ctx->phi) hipFree(ctx->phi);
+    ctx->phi = nullptr;
+    ctx->phi_words = 0;
+    hipError_t e = hipMalloc(&ctx->phi, sizeof(uint32_t) * words);
+    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, "labeler scratch allocation failed");
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
+    ctx->phi_words = words;
+  }
+  if (!ctx->lctl) {
+    HIP_TRY(ctx, hipMalloc(&ctx->lctl, labctl_bytes()));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host, 64, hipHostMallocDefault));
+  }
+  J->n = n;
+  J->Ppad = Ppad;
+  J->n_patches = n_patches;
+  J->tiles_x = (n + kLabelTile - 1) / kLabelTile;
+  J->ctrl = ctrl;
+  J->v_hat = v_hat;
+  J->source_patch = source_patch;
+  J->cls = problem->node_class;
+  J->speed = problem->speed;
+  J->speed_const = problem->speed_const;
+  J->r = P.args.r;
+  J->vstar = P.vstar;
+  J->lambda = problem->lambda;
+  J->window = v_hat ? (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max) : INFINITY;
+  J->tau = tau_q15;
+  J->label_out = label_out;
+  J->overlap_out = overlap_out;
+  J->phi_out = phi_out;
+  J->phi = ctx->phi;
+  J->lctl = ctx->lctl;
+  J->lctl_host = ctx->lctl_host;
+  return SLHJB_OK;
+}
+
+// Enqueue the labeling on stream s and run its pass loop (host reads of the pass state every 16
+// passes) to the end. Touches only the job's buffers. Returns hipSuccess or the first error, and
+// a status for a labeler that did not settle.
+hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int* status) {
+  *status = SLHJB_OK;
+  const int n = J.n;
+  const int64_t N = (int64_t)n * n;
+  const int tiles = J.tiles_x * J.tiles_x;
+  hipError_t e = launch_label_init(J.cls, J.source_patch, N, J.Ppad, J.phi, s);
+  if (e == hipSuccess) e = launch_fill_u8(J.flag, 1, tiles, s);
+  if (e == hipSuccess) e = launch_labctl_init(J.lctl, s);
+  if (e == hipSuccess && J.v_hat && !J.keys_ready)
+    e = launch_label_keys(J.v_hat, J.cls, n, J.tiles_x, J.tiles_x, J.vstar, J.lambda, J.key, s);
+  if (e != hipSuccess) return e;
+  const int grid = std::min(tiles, 1024);
+  const int max_inner = 4 * kLabelTile;
+  // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
+  // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
+  const int64_t max_passes = 4000000;
+  int64_t launched = 0;
+  for (;;) {
+    for (int b = 0; b < 16 && e == hipSuccess; ++b)
+      e = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad,
+                             J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, max_inner, J.window,
+                             b & 1, J.lctl, grid, s);
+    launched += 16;
+    if (e == hipSuccess) e = hipMemcpyAsync(J.lctl_host, J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (J.lctl_host[7]) break;  // done
+    if (launched > max_passes) {
+      *status = SLHJB_E_HIP;
+      return hipSuccess;
+    }
+  }
+  *passes_out = J.lctl_host[8];
+  e = launch_label_argmax((const uint16_t*)J.phi, N, J.Ppad, J.label_out, J.overlap_out, J.tau, s);
+  if (e == hipSuccess && J.phi_out)
+    e = hipMemcpy2DAsync(J.phi_out, sizeof(uint16_t) * J.n_patches, J.phi, sizeof(uint16_t) * J.Ppad,
+                         sizeof(uint16_t) * J.n_patches, (size_t)N, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_problem* coarse,
                        const slhjb_patchy_opts* opts, float* v, int16_t* label_out, slhjb_patchy_stats* stats) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
@@ -533,6 +679,71 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   int16_t* ctrl = nullptr;
   float* vc = nullptr;
   int16_t* lab = label_out;
+  // In the transmission mode the fine solve does not read the labels: the labeler then runs on a
+  // stream of its own, in a host thread of its own, beside the fine solve (buffers of its own:
+  // phi, tile flags / list / keys, pass state and control table).
+  const bool overlap_labels = pdd && need_labels && opts->mode == SLHJB_PATCHY_TRANSMISSION;
+  std::thread labeler;
+  int64_t lab_passes = 0;
+  int lab_status = SLHJB_OK;
+  hipError_t lab_err = hipSuccess;
+  double lab_seconds = 0.0;
+  LabelJob J;
+  auto start_labels = [&]() -> int {
+    Prepared Pf;
+    int r = prepare(ctx, fine, &Pf);
+    if (r != SLHJB_OK) return r;
+    r = label_setup(ctx, fine, Pf, ctrl, v, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &J);
+    if (r != SLHJB_OK) return r;
+    const size_t tiles = (size_t)J.tiles_x * J.tiles_x;
+    if (ctx->ltiles_cap < tiles) {
+      if (ctx->lflag) hipFree(ctx->lflag);
+      if (ctx->llist) hipFree(ctx->llist);
+      if (ctx->lkey) hipFree(ctx->lkey);
+      ctx->lflag = nullptr;
+      ctx->llist = nullptr;
+      ctx->lkey = nullptr;
+      ctx->ltiles_cap = 0;
+      HIP_TRY(ctx, hipMalloc(&ctx->lflag, tiles));
+      HIP_TRY(ctx, hipMalloc(&ctx->llist, sizeof(int) * tiles));
+      HIP_TRY(ctx, hipMalloc(&ctx->lkey, sizeof(float) * tiles));
+      ctx->ltiles_cap = tiles;
+    }
+    if (!ctx->lctab) HIP_TRY(ctx, hipMalloc(&ctx->lctab, sizeof(float2) * 256));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->lctab, fine->controls, sizeof(float2) * fine->n_controls, hipMemcpyHostToDevice,
+                                ctx->stream));
+    J.flag = ctx->lflag;
+    J.list = ctx->llist;
+    J.key = ctx->lkey;
+    J.ctab = ctx->lctab;
+    // the keys read u_hat, which the fine solve overwrites: compute them before the fork
+    HIP_TRY(ctx, launch_label_keys(v, fine->node_class, J.n, J.tiles_x, J.tiles_x, J.vstar, J.lambda, J.key,
+                                   ctx->stream));
+    J.keys_ready = true;
+    if (!ctx->aux_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux_stream, e1, 0));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host control array is pageable
+    const int dev = ctx->device;
+    hipStream_t aux = ctx->aux_stream;
+    labeler = std::thread([&J, aux, dev, &lab_passes, &lab_status, &lab_err, &lab_seconds]() {
+      hipError_t e = hipSetDevice(dev);
+      hipEvent_t a = nullptr, b = nullptr;
+      if (e == hipSuccess) e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&b);
+      if (e == hipSuccess) e = hipEventRecord(a, aux);
+      if (e == hipSuccess) e = label_run(J, aux, &lab_passes, &lab_status);
+      if (e == hipSuccess) e = hipEventRecord(b, aux);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      lab_seconds = ms * 1e-3;
+      if (a) hipEventDestroy(a);
+      if (b) hipEventDestroy(b);
+      lab_err = e;
+    });
+    return SLHJB_OK;
+  };
   if (he != hipSuccess) {
     st = hip_fail(ctx, he, "event");
   } else if (pdd) {
@@ -570,12 +781,13 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     if (st == SLHJB_OK && need_labels) {
       st = slhjb_synthesize(ctx, fine, v, ctrl);
       if (st == SLHJB_OK && (he = lap(&S.t_synthesize)) != hipSuccess) st = hip_fail(ctx, he, "event");
-      if (st == SLHJB_OK) {
+      if (st == SLHJB_OK && !overlap_labels) {
         int64_t lp = 0;
         st = slhjb_label(ctx, fine, ctrl, v, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &lp);
         S.label_passes = lp;
+        if (st == SLHJB_OK && (he = lap(&S.t_label)) != hipSuccess) st = hip_fail(ctx, he, "event");
       }
-      if (st == SLHJB_OK && (he = lap(&S.t_label)) != hipSuccess) st = hip_fail(ctx, he, "event");
+      if (st == SLHJB_OK && overlap_labels) st = start_labels();
     }
     // (5) computation: tiles by increasing u_hat, from u_hat
     if (st == SLHJB_OK) {
@@ -583,6 +795,13 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
       to.mode = opts->mode == SLHJB_PATCHY_INDEPENDENT ? SLHJB_MODE_INDEPENDENT : SLHJB_MODE_TRANSMISSION;
       to.label = opts->mode == SLHJB_PATCHY_INDEPENDENT ? lab : nullptr;
       st = slhjb_solve_tiles(ctx, fine, v, opts->tol, opts->max_passes, &to, &ts);
+    }
+    if (labeler.joinable()) {
+      labeler.join();
+      S.label_passes = lab_passes;
+      S.t_label = lab_seconds;
+      if (lab_err != hipSuccess && st == SLHJB_OK) st = hip_fail(ctx, lab_err, "patch labels");
+      else if (lab_status != SLHJB_OK && st == SLHJB_OK) st = fail(ctx, lab_status, "labeler did not settle (internal error)");
     }
   } else {
     // static decomposition: no pre-computation, tiles in their fixed order, from v = 1
@@ -647,89 +866,33 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
                 const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15, int16_t* label_out,
                 uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
-  if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
-  if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
-  if (tau_q15 > (1u << 15)) return fail(ctx, SLHJB_E_INVALID_ARG, "tau_q15 must be <= 2^15");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   Prepared P;
   int st = prepare(ctx, problem, &P);
   if (st != SLHJB_OK) return st;
-  // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
-  slhjb_problem p0 = *problem;
-  p0.diffusion = SLHJB_DIFF_NONE;
-  float speed_max = 0.0f;
-  memcpy(&speed_max, &ctx->small_host[3], sizeof(float));
-  if (!problem->speed) speed_max = problem->speed_const;
-  if (reach_for(&p0, speed_max) > 1.0 + 1e-6)
-    return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labeling needs h c |a| <= dx (feet in the first ring of cells)");
-  const int n = problem->n;
-  const int64_t N = (int64_t)n * n;
-  int Ppad = 2;
-  while (Ppad < n_patches) Ppad *= 2;
-  const int half = Ppad / 2;
-  const size_t words = (size_t)N * half;
-  if (ctx->phi_words < words) {
-    if (ctx->phi) hipFree(ctx->phi);
-    ctx->phi = nullptr;
-    ctx->phi_words = 0;
-    hipError_t e = hipMalloc(&ctx->phi, sizeof(uint32_t) * words);
-    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, "labeler scratch allocation failed");
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
-    ctx->phi_words = words;
-  }
-  const int tiles_x = (n + kLabelTile - 1) / kLabelTile;
-  const int tiles = tiles_x * tiles_x;
+  LabelJob J;
+  st = label_setup(ctx, problem, P, ctrl, v_hat, source_patch, n_patches, tau_q15, label_out, overlap_out, phi_out, &J);
+  if (st != SLHJB_OK) return st;
+  const int tiles = J.tiles_x * J.tiles_x;
   st = ensure_tiles(ctx, (size_t)tiles);
   if (st != SLHJB_OK) return st;
-  HIP_TRY(ctx, launch_label_init(problem->node_class, source_patch, N, Ppad, ctx->phi, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u8(ctx->tflag, 1, tiles, ctx->stream));
-  if (!ctx->lctl) {
-    HIP_TRY(ctx, hipMalloc(&ctx->lctl, labctl_bytes()));
-    HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host, 64, hipHostMallocDefault));
+  if (v_hat && ctx->stiles_cap < (size_t)tiles) {
+    if (ctx->tkey) hipFree(ctx->tkey);
+    if (ctx->tchange) hipFree(ctx->tchange);
+    ctx->tkey = ctx->tchange = nullptr;
+    ctx->stiles_cap = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
+    HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
+    ctx->stiles_cap = tiles;
   }
-  HIP_TRY(ctx, launch_labctl_init(ctx->lctl, ctx->stream));
-  // optional u_hat order: tiles by increasing arrival time of v_hat, in bands
-  const float* key = nullptr;
-  float window = INFINITY;
-  if (v_hat) {
-    if (ctx->stiles_cap < (size_t)tiles) {
-      if (ctx->tkey) hipFree(ctx->tkey);
-      if (ctx->tchange) hipFree(ctx->tchange);
-      ctx->tkey = ctx->tchange = nullptr;
-      ctx->stiles_cap = 0;
-      HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
-      HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
-      ctx->stiles_cap = tiles;
-    }
-    const float vstar = (float)((double)problem->running_cost / (double)problem->lambda);
-    HIP_TRY(ctx, launch_label_keys(v_hat, problem->node_class, n, tiles_x, tiles_x, vstar, problem->lambda, ctx->tkey,
-                                   ctx->stream));
-    key = ctx->tkey;
-    window = (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max);
-  }
-  const int grid = std::min(tiles, 1024);
-  const int max_inner = 4 * kLabelTile;
-  // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
-  // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
-  const int64_t max_passes = 4000000;
-  int64_t launched = 0;
-  for (;;) {
-    for (int b = 0; b < 16; ++b)
-      HIP_TRY(ctx, launch_label_pass2(ctx->phi, problem->node_class, ctrl, problem->speed, problem->speed_const,
-                                      ctx->ctrl2, P.args.r, n, Ppad, key, ctx->tlist, tiles_x, tiles_x, ctx->tflag,
-                                      max_inner, window, b & 1, ctx->lctl, grid, ctx->stream));
-    launched += 16;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->lctl_host, ctx->lctl, labctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->lctl_host[7]) break;  // done
-    if (launched > max_passes) return fail(ctx, SLHJB_E_HIP, "labeler did not settle (internal error)");
-  }
-  const int64_t passes = ctx->lctl_host[8];
-  HIP_TRY(ctx, launch_label_argmax((const uint16_t*)ctx->phi, N, Ppad, label_out, overlap_out, tau_q15, ctx->stream));
-  if (phi_out)
-    HIP_TRY(ctx, hipMemcpy2DAsync(phi_out, sizeof(uint16_t) * n_patches, ctx->phi, sizeof(uint16_t) * Ppad,
-                                  sizeof(uint16_t) * n_patches, (size_t)N, hipMemcpyDeviceToDevice, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  J.flag = ctx->tflag;
+  J.list = ctx->tlist;
+  J.key = ctx->tkey;
+  J.ctab = ctx->ctrl2;
+  int64_t passes = 0;
+  int lst = SLHJB_OK;
+  HIP_TRY(ctx, label_run(J, ctx->stream, &passes, &lst));
+  if (lst != SLHJB_OK) return fail(ctx, lst, "labeler did not settle (internal error)");
   if (passes_out) *passes_out = passes;
   return SLHJB_OK;
 }

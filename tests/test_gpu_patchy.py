@@ -102,3 +102,30 @@ def test_patchy_independent_mode_error_is_measured(ctx, case):
     print("decomposition error max", err[free].max(), "interface mean", e_if.mean(), "interior mean", e_in.mean(),
           flush=True)
     assert e_if.mean() > e_in.mean()
+
+
+def test_labels_beside_the_solve_equal_the_sequential_labels(ctx, case):
+    """In the transmission mode the labeler runs on its own stream beside the fine solve; its labels
+    are bit-identical to those computed before the solve (independent mode), and the solution to the
+    one computed without labels."""
+    from paper_1502_01629_amd import capi
+
+    fine, coarse, _ = case
+    P = 16
+    src, _ = capi.partition_sources(fine.node_class, P)
+    dp, dpc = capi.DeviceProblem(fine, 1), capi.DeviceProblem(coarse, 1)
+    n2 = fine.n * fine.n
+    v1 = torch.empty(n2, dtype=torch.float32, device="cuda")
+    v2 = torch.empty_like(v1)
+    v3 = torch.empty_like(v1)
+    lab1 = torch.empty(n2, dtype=torch.int16, device="cuda")
+    lab2 = torch.empty_like(lab1)
+    s1 = ctx.solve_patchy(dp, dpc, v1, mode=0, tol=5e-7, source_patch=_dev(src, np.int16), n_patches=P,
+                          label_out=lab1, policy_sweeps=4)
+    s2 = ctx.solve_patchy(dp, dpc, v2, mode=1, tol=5e-7, source_patch=_dev(src, np.int16), n_patches=P,
+                          label_out=lab2)
+    s3 = ctx.solve_patchy(dp, dpc, v3, mode=0, tol=5e-7, policy_sweeps=4)
+    assert s1["status"] == 0 and s2["status"] == 0 and s3["status"] == 0
+    assert s1["label_passes"] == s2["label_passes"] > 0
+    assert torch.equal(lab1, lab2)
+    assert torch.equal(v1, v3)

@@ -56,6 +56,8 @@ struct slhjb_ctx {
   float* lkey = nullptr;
   size_t ltiles_cap = 0;
   float2* lctab = nullptr;        // controls in the caller's order, for the labeler's feet
+  unsigned* lmask = nullptr;      // word masks of the labeler tiles
+  size_t lmask_cap = 0;
   hipEvent_t tev[32] = {};           // visit-kernel timing events of one captured batch
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
@@ -363,6 +365,7 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->llist) hipFree(ctx->llist);
   if (ctx->lkey) hipFree(ctx->lkey);
   if (ctx->lctab) hipFree(ctx->lctab);
+  if (ctx->lmask) hipFree(ctx->lmask);
   for (auto& e : ctx->tev)
     if (e) hipEventDestroy(e);
   if (ctx->coop_host) hipHostFree(ctx->coop_host);
@@ -520,6 +523,7 @@ struct LabelJob {
   void* lctl = nullptr;
   unsigned* lctl_host = nullptr;
   const float2* ctab = nullptr;
+  unsigned* wmask = nullptr;
   bool keys_ready = false;  // the caller already computed the u_hat keys into `key`
 };
 
@@ -555,6 +559,15 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
     HIP_TRY(ctx, hipMalloc(&ctx->lctl, labctl_bytes()));
     HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host, 64, hipHostMallocDefault));
   }
+  const int ltx = (n + kLabelTile - 1) / kLabelTile;
+  if (ctx->lmask_cap < (size_t)ltx * ltx) {
+    if (ctx->lmask) hipFree(ctx->lmask);
+    ctx->lmask = nullptr;
+    ctx->lmask_cap = 0;
+    HIP_TRY(ctx, hipMalloc(&ctx->lmask, sizeof(unsigned) * ltx * ltx));
+    ctx->lmask_cap = (size_t)ltx * ltx;
+  }
+  J->wmask = ctx->lmask;
   J->n = n;
   J->Ppad = Ppad;
   J->n_patches = n_patches;
@@ -588,6 +601,7 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   const int64_t N = (int64_t)n * n;
   const int tiles = J.tiles_x * J.tiles_x;
   hipError_t e = launch_label_init(J.cls, J.source_patch, N, J.Ppad, J.phi, s);
+  if (e == hipSuccess) e = launch_label_mask_init(J.cls, J.source_patch, n, J.tiles_x, J.wmask, s);
   if (e == hipSuccess) e = launch_fill_u8(J.flag, 1, tiles, s);
   if (e == hipSuccess) e = launch_labctl_init(J.lctl, s);
   if (e == hipSuccess && J.v_hat && !J.keys_ready)
@@ -602,8 +616,8 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   for (;;) {
     for (int b = 0; b < 16 && e == hipSuccess; ++b)
       e = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad,
-                             J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, max_inner, J.window,
-                             b & 1, J.lctl, grid, s);
+                             J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, J.wmask, max_inner,
+                             J.window, b & 1, J.lctl, grid, s);
     launched += 16;
     if (e == hipSuccess) e = hipMemcpyAsync(J.lctl_host, J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -616,9 +630,7 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   }
   *passes_out = J.lctl_host[8];
   e = launch_label_argmax((const uint16_t*)J.phi, N, J.Ppad, J.label_out, J.overlap_out, J.tau, s);
-  if (e == hipSuccess && J.phi_out)
-    e = hipMemcpy2DAsync(J.phi_out, sizeof(uint16_t) * J.n_patches, J.phi, sizeof(uint16_t) * J.Ppad,
-                         sizeof(uint16_t) * J.n_patches, (size_t)N, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && J.phi_out) e = launch_label_phi_out(J.phi, N, J.n_patches, J.phi_out, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e;
 }

@@ -64,8 +64,12 @@ hipError_t launch_label_keys(const float* vhat, const uint8_t* cls, int n, int t
                              float lambda, float* key, hipStream_t s);
 hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
                               float speed_const, const float2* ctab, float r, int n, int P, const float* key, int* list,
-                              int tiles_x, int tiles_y, uint8_t* flag, int max_inner, float window, int q, void* ctl,
-                              int grid, hipStream_t s);
+                              int tiles_x, int tiles_y, uint8_t* flag, unsigned* wmask, int max_inner, float window,
+                              int q, void* ctl, int grid, hipStream_t s);
+// word masks of the labeler tiles (uint32 each); phi in the caller's node-major layout
+hipError_t launch_label_mask_init(const uint8_t* cls, const int16_t* src, int n, int tiles_x, unsigned* mask,
+                                  hipStream_t s);
+hipError_t launch_label_phi_out(const uint32_t* phi32, int64_t count, int n_patches, uint16_t* out, hipStream_t s);
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
                                uint16_t tau, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int count, hipStream_t s);

@@ -88,7 +88,10 @@ hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_
 }
 
 // ---- integer patch labeling --------------------------------------------------------------
-// phi_p(x) in [0, 2^15] per node and patch, stored node-major: phi[node * P + p], uint16.
+// phi_p(x) in [0, 2^15] per node and patch, two patches per uint32 word, stored word-planar:
+// phi32[q * N + node] holds patches 2q (low half) and 2q + 1 (high half), so a plane of one word
+// is contiguous over the nodes. Each labeler tile keeps a mask of the words that are nonzero
+// somewhere in it (it only grows, as the values do).
 // A FREE node takes the Q.8 bilinear value of phi_p at its synthesized foot,
 //   D = round_half_even(256 fl(fl(r c) a))  per axis (r = fl(h/dx)),
 //   corner (i + (D_x >> 8), j + (D_y >> 8)), weights (256 - f or f) per axis, f = D & 255,
@@ -97,13 +100,13 @@ hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_
 // and concurrently, climb to the same least fixed point: the kernels below update in place
 // and iterate until nothing changes.
 
-// One thread per uint32 word (two patches) of phi, so the stores of a wavefront are contiguous.
-__global__ void label_init_kernel(const uint8_t* __restrict__ cls, const int16_t* __restrict__ src, int64_t words,
+// One thread per uint32 word (two patches) of phi, plane by plane, so the stores are contiguous.
+__global__ void label_init_kernel(const uint8_t* __restrict__ cls, const int16_t* __restrict__ src, int64_t count,
                                   int half, uint32_t* __restrict__ phi32) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= words) return;
-  const int64_t node = t / half;
-  const int q = (int)(t - node * half);
+  if (t >= count * half) return;
+  const int q = (int)(t / count);
+  const int64_t node = t - (int64_t)q * count;
   uint32_t v = 0u;
   if (cls[node] == kTarget) {
     const int p = src[node];
@@ -112,7 +115,20 @@ __global__ void label_init_kernel(const uint8_t* __restrict__ cls, const int16_t
   phi32[t] = v;
 }
 
+// The word masks of the labeler tiles at the start: the words of the sources (zeroed before).
+__global__ void label_mask_init_kernel(const uint8_t* __restrict__ cls, const int16_t* __restrict__ src, int n,
+                                       int tiles_x, int tile, unsigned* __restrict__ mask) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  if (cls[t] != kTarget) return;
+  const int p = src[t];
+  if (p < 0) return;
+  const int x = (int)(t % n), y = (int)(t / n);
+  atomicOr(&mask[(y / tile) * tiles_x + x / tile], 1u << (p >> 1));
+}
+
 constexpr int kLabTile = 16;  // 16 x 16 nodes per tile
+constexpr int kLabSub = 4;    // in-place sweeps of a tile per barrier
 constexpr int kLabHalo = 2;
 constexpr int kLabSpan = kLabTile + 2 * kLabHalo;
 
@@ -186,11 +202,11 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
                                                           const float* __restrict__ speed, float speed_const,
                                                           const float2* __restrict__ ctab, float r, int n, int P,
                                                           const int* __restrict__ list, int tiles_x, int tiles_y,
-                                                          uint8_t* __restrict__ flag, int max_inner, float window, int q,
-                                                          LabCtl* __restrict__ c) {
+                                                          uint8_t* __restrict__ flag, unsigned* __restrict__ wmask,
+                                                          int max_inner, float window, int q, LabCtl* __restrict__ c) {
   if (c->done) return;
   extern __shared__ uint32_t lds[];
-  __shared__ unsigned smask;
+  __shared__ unsigned smask, omask;
   __shared__ int act[32];
   __shared__ int nact;
   const int cnt = (int)c->count[q];
@@ -212,6 +228,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     c->kmin[q ^ 1] = 0x7f800000u;
   }
   const int half = P >> 1;
+  const size_t N = (size_t)n * n;
   uint32_t* tile = lds;  // half planes of kLabPlane words
   // the node of this thread (256 threads = 256 tile nodes)
   const int lx = threadIdx.x & (kLabTile - 1), ly = threadIdx.x >> 4;
@@ -220,20 +237,35 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     const int tid = list[slot];
     const int tx = tid % tiles_x, ty = tid / tiles_x;
     const int x0 = tx * kLabTile - kLabHalo, y0 = ty * kLabTile - kLabHalo;
-    if (threadIdx.x == 0) smask = 0u;
+    if (threadIdx.x == 0) {
+      smask = 0u;
+      omask = 0u;
+    }
     __syncthreads();
-    // stage phi of the tile and its halo (nodes outside the grid read 0), noting nonzero words
-    unsigned mymask = 0u;
-    for (int w = threadIdx.x; w < kLabSpan * kLabSpan * half; w += blockDim.x) {
-      const int node = w / half, qw = w - node * half;
+    // words that can be nonzero in the staged region: the masks of the tile and its 8 neighbours
+    // (the halo of 2 nodes lies in them)
+    if (threadIdx.x < 9) {
+      const int nx = tx + threadIdx.x % 3 - 1, ny = ty + threadIdx.x / 3 - 1;
+      if (nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) atomicOr(&smask, wmask[ny * tiles_x + nx]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int k = 0;
+      for (int b = 0; b < half; ++b)
+        if (smask & (1u << b)) act[k++] = b;
+      nact = k;
+    }
+    __syncthreads();
+    const int A = nact;
+    // stage those words of the tile and its halo (nodes outside the grid read 0)
+    for (int e = threadIdx.x; e < kLabSpan * kLabSpan * A; e += blockDim.x) {
+      const int qi = e / (kLabSpan * kLabSpan), node = e - qi * (kLabSpan * kLabSpan);
       const int sy = node / kLabSpan, sx = node - sy * kLabSpan;
       const int gx = x0 + sx, gy = y0 + sy;
       uint32_t val = 0u;
-      if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[((size_t)gy * n + gx) * half + qw];
-      tile[qw * kLabPlane + node] = val;
-      mymask |= (val != 0u ? 1u : 0u) << qw;
+      if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[(size_t)act[qi] * N + (size_t)gy * n + gx];
+      tile[act[qi] * kLabPlane + node] = val;
     }
-    if (mymask) atomicOr(&smask, mymask);
     // foot of this thread's node, if FREE: corner cell and Q.8 fractions
     const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
     int base = -1;
@@ -258,18 +290,14 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int k = 0;
-      for (int b = 0; b < half; ++b)
-        if (smask & (1u << b)) act[k++] = b;
-      nact = k;
-    }
-    __syncthreads();
-    const int A = nact;
     int it = 0, last = 0, ever = 0;
     if (A > 0) {
       for (;;) {
+        // a round of kLabSub in-place sweeps of the tile under one barrier: values only grow, so
+        // any interleaving of the wavefronts climbs to the same least fixed point, and a round in
+        // which no thread changed anything read final values everywhere (the tile is settled)
         int ch = 0;
+        for (int sub = 0; sub < kLabSub; ++sub) {
         if (base >= 0) {
           for (int qi = 0; qi < A; ++qi) {
             const uint32_t* pl = tile + act[qi] * kLabPlane;
@@ -287,21 +315,28 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
             }
           }
         }
+        }
         last = __syncthreads_or(ch);  // barrier + block-wide OR
         ever |= last;
-        ++it;
+        it += kLabSub;
         if (!last || it >= max_inner) break;
       }
     }
     const bool converged_here = (last == 0);
-    // write back the words that can have changed (interior nodes only)
+    // write back the words that can have changed (interior nodes only) and note the nonzero ones
     if (ever && gx < n && gy < n) {
+      unsigned mine = 0u;
       for (int qi = 0; qi < A; ++qi) {
         const int qw = act[qi];
-        phi32[((size_t)gy * n + gx) * half + qw] = tile[qw * kLabPlane + self];
+        const uint32_t val = tile[qw * kLabPlane + self];
+        phi32[(size_t)qw * N + (size_t)gy * n + gx] = val;
+        mine |= (val != 0u ? 1u : 0u) << qw;
       }
+      if (mine) atomicOr(&omask, mine);
     }
+    if (ever) __syncthreads();  // uniform: `ever` is a block-wide OR
     if (threadIdx.x == 0 && ever) {
+      if (omask) atomicOr(&wmask[tid], omask);
       // neighbours read this tile as their halo; the tile itself continues if it did not settle
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
@@ -351,58 +386,74 @@ hipError_t launch_label_keys(const float* vhat, const uint8_t* cls, int n, int t
 
 hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t* ctrl, const float* speed,
                               float speed_const, const float2* ctab, float r, int n, int P, const float* key, int* list,
-                              int tiles_x, int tiles_y, uint8_t* flag, int max_inner, float window, int q, void* ctl,
-                              int grid, hipStream_t s) {
+                              int tiles_x, int tiles_y, uint8_t* flag, unsigned* wmask, int max_inner, float window,
+                              int q, void* ctl, int grid, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   labctl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, q, list, (LabCtl*)ctl);
   label_visit_kernel<<<grid, 256, label_pass_lds_bytes(P), s>>>(phi32, cls, ctrl, speed, speed_const, ctab, r, n, P,
-                                                                list, tiles_x, tiles_y, flag, max_inner, window, q,
-                                                                (LabCtl*)ctl);
+                                                                list, tiles_x, tiles_y, flag, wmask, max_inner, window,
+                                                                q, (LabCtl*)ctl);
   return hipGetLastError();
 }
 
-// L lanes per node (L a power of two >= P/2), each reading one uint32 word (two patches), so a
-// wavefront reads 64/L whole rows of phi contiguously. The pair (value, p) is reduced across the L
-// lanes keeping the larger value and, on ties, the lower p; the overlap bits are OR-reduced.
+// One thread per node: the planes of phi in order, keeping the larger value and, on ties, the
+// lower p (reads of a plane are contiguous over the threads); the overlap bits where phi_p >= tau.
 __global__ __launch_bounds__(256) void label_argmax_kernel(const uint32_t* __restrict__ phi32, int64_t count, int P,
-                                                           int L, int16_t* __restrict__ label,
-                                                           uint64_t* __restrict__ overlap, uint16_t tau) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t node = t / L;
-  const int q = (int)(t - node * L);
+                                                           int16_t* __restrict__ label, uint64_t* __restrict__ overlap,
+                                                           uint16_t tau) {
+  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (node >= count) return;
   const int half = P >> 1;
-  const bool live = node < count;
-  uint32_t word = 0u;
-  if (live && q < half) word = phi32[node * half + q];
-  const uint32_t v0 = word & 0xffffu, v1 = word >> 16;
-  uint32_t bv = v1 > v0 ? v1 : v0;
-  int bp = v1 > v0 ? 2 * q + 1 : 2 * q;
-  uint32_t ovlo = 0u, ovhi = 0u;
-  if (tau > 0) {
-    const uint32_t bits = (v0 >= tau ? 1u : 0u) | (v1 >= tau ? 2u : 0u);
-    if (2 * q < 32) ovlo = bits << (2 * q);
-    else ovhi = bits << (2 * q - 32);
-  }
-  for (int off = 1; off < L; off <<= 1) {
-    const uint32_t ov = __shfl_xor(bv, off, 64);
-    const int op = __shfl_xor(bp, off, 64);
-    if (ov > bv || (ov == bv && op < bp)) {
-      bv = ov;
-      bp = op;
+  uint32_t bv = 0u;
+  int bp = -1;
+  uint64_t ov = 0ull;
+  for (int q = 0; q < half; ++q) {
+    const uint32_t word = phi32[(size_t)q * count + node];
+    const uint32_t v0 = word & 0xffffu, v1 = word >> 16;
+    if (v0 > bv) {
+      bv = v0;
+      bp = 2 * q;
     }
-    ovlo |= __shfl_xor(ovlo, off, 64);
-    ovhi |= __shfl_xor(ovhi, off, 64);
+    if (v1 > bv) {
+      bv = v1;
+      bp = 2 * q + 1;
+    }
+    if (tau > 0) ov |= (uint64_t)((v0 >= tau ? 1u : 0u) | (v1 >= tau ? 2u : 0u)) << (2 * q);
   }
-  if (live && q == 0) {
-    label[node] = (int16_t)(bv > 0u ? bp : -1);
-    if (overlap) overlap[node] = ((uint64_t)ovhi << 32) | ovlo;
-  }
+  label[node] = (int16_t)bp;
+  if (overlap) overlap[node] = ov;
+}
+
+// phi in the caller's layout: out[node * n_patches + p], uint16
+__global__ void label_phi_out_kernel(const uint32_t* __restrict__ phi32, int64_t count, int n_patches,
+                                     uint16_t* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= count * n_patches) return;
+  const int64_t node = t / n_patches;
+  const int p = (int)(t - node * n_patches);
+  const uint32_t word = phi32[(size_t)(p >> 1) * count + node];
+  out[t] = (uint16_t)((p & 1) ? (word >> 16) : (word & 0xffffu));
 }
 
 hipError_t launch_label_init(const uint8_t* cls, const int16_t* src, int64_t count, int P, uint32_t* phi32,
                              hipStream_t s) {
   const int64_t words = count * (P >> 1);
-  label_init_kernel<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(cls, src, words, P >> 1, phi32);
+  label_init_kernel<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(cls, src, count, P >> 1, phi32);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_mask_init(const uint8_t* cls, const int16_t* src, int n, int tiles_x, unsigned* mask,
+                                  hipStream_t s) {
+  hipError_t e = launch_fill_u32(mask, 0u, tiles_x * tiles_x, s);
+  if (e != hipSuccess) return e;
+  const int64_t count = (int64_t)n * n;
+  label_mask_init_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(cls, src, n, tiles_x, kLabTile, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_label_phi_out(const uint32_t* phi32, int64_t count, int n_patches, uint16_t* out, hipStream_t s) {
+  const int64_t total = count * n_patches;
+  label_phi_out_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(phi32, count, n_patches, out);
   return hipGetLastError();
 }
 
@@ -410,11 +461,8 @@ size_t label_pass_lds_bytes(int P) { return sizeof(uint32_t) * (size_t)kLabPlane
 
 hipError_t launch_label_argmax(const uint16_t* phi, int64_t count, int P, int16_t* label, uint64_t* overlap,
                                uint16_t tau, hipStream_t s) {
-  int L = 1;
-  while (L < (P >> 1)) L <<= 1;
-  const int64_t threads = count * L;
-  label_argmax_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>((const uint32_t*)phi, count, P, L, label,
-                                                                        overlap, tau);
+  label_argmax_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>((const uint32_t*)phi, count, P, label, overlap,
+                                                                      tau);
   return hipGetLastError();
 }
 

@@ -39,8 +39,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-# modified policy iteration inside the tile visits of the active-tile solves (0 = off)
-POLICY_SWEEPS = 7
+# modified policy iteration inside the tile visits of the active-tile solves (0 = off): policy
+# iterations after each full one, for sigma = 0 (the main step) and with diffusion (the arms, where
+# a visit is one full iteration and these)
+POLICY_SWEEPS = 16
+POLICY_SWEEPS_DIFFUSION = 7
 
 
 # the files that define the dominant kernel (the tile visit) and everything it inlines
@@ -173,7 +176,7 @@ def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
     vt = v0.clone()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    st = ctx.solve_tiles(dp, vt, tol=tol, order=capi.ORDER_NONE, max_passes=200_000, policy_sweeps=POLICY_SWEEPS)
+    st = ctx.solve_tiles(dp, vt, tol=tol, order=capi.ORDER_NONE, max_passes=200_000, policy_sweeps=POLICY_SWEEPS_DIFFUSION)
     torch.cuda.synchronize()
     out["active_tiles_cold"] = {"time_s": time.perf_counter() - t, "passes": st["sweeps"],
                                 "node_updates_per_free_node": st["node_updates"] / free,
@@ -192,7 +195,7 @@ def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
     ctx.upsample(vc, xc.n, vk, n)
     torch.cuda.synchronize()
     t_pre = time.perf_counter() - t
-    sk = ctx.solve_tiles(dp, vk, tol=tol, order=capi.ORDER_KEYS, max_passes=200_000, policy_sweeps=POLICY_SWEEPS)
+    sk = ctx.solve_tiles(dp, vk, tol=tol, order=capi.ORDER_KEYS, max_passes=200_000, policy_sweeps=POLICY_SWEEPS_DIFFUSION)
     torch.cuda.synchronize()
     out["active_tiles_uhat"] = {"time_s": time.perf_counter() - t, "coarse_and_upsample_s": t_pre,
                                 "coarse_passes": sc["sweeps"], "passes": sk["sweeps"],
@@ -229,7 +232,7 @@ def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) 
             torch.cuda.synchronize()
             t = time.perf_counter()
             sp = ctx.solve_patchy(dp, dpc, v, mode=capi.PATCHY_TRANSMISSION, tol=tol, tol_coarse=1e-7,
-                                  source_patch=src, n_patches=patches, label_out=lab, policy_sweeps=POLICY_SWEEPS)
+                                  source_patch=src, n_patches=patches, label_out=lab, policy_sweeps=POLICY_SWEEPS_DIFFUSION)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         vj = torch.from_numpy(fine.initial().reshape(-1)).cuda()

@@ -224,7 +224,7 @@ typedef struct {
     float key_window;             /* band width of the u_hat order, < 0 = automatic               */
     int32_t tile_shape;           /* as slhjb_tile_opts.tile_shape                                */
     int32_t collect_kernel_time;  /* as slhjb_tile_opts.collect_kernel_time (fine solve)          */
-    int32_t policy_sweeps;        /* as slhjb_tile_opts.policy_sweeps (fine solve)                */
+    int32_t policy_sweeps;        /* as slhjb_tile_opts.policy_sweeps (coarse and fine solves)    */
 } slhjb_patchy_opts;
 
 typedef struct {

@@ -780,6 +780,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
       slhjb_tile_opts co;
       memset(&co, 0, sizeof(co));
       co.tile_shape = 2;
+      co.policy_sweeps = opts->policy_sweeps;
       st = slhjb_solve_tiles(ctx, &pc, vc, opts->tol_coarse, opts->max_passes, &co, &ts);
       if (st == SLHJB_NOT_CONVERGED) st = SLHJB_OK;  // a rough coarse solution is still a valid start
       S.coarse_passes = ts.sweeps;

@@ -47,7 +47,10 @@ struct slhjb_ctx {
   void* tctl = nullptr;           // device-driven pass state
   void* lctl = nullptr;           // labeler pass state
   unsigned* lctl_host = nullptr;
+  unsigned* lctl_host2 = nullptr;
   unsigned* tctl_host = nullptr;
+  unsigned* tctl_host2 = nullptr;    // second pinned copy (two graph replays in flight)
+  hipEvent_t tdone[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   // labeler buffers of its own, so that it can run beside the tile solver (patchy pipeline)
   hipStream_t aux_stream = nullptr;
@@ -358,7 +361,11 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tctl) hipFree(ctx->tctl);
   if (ctx->lctl) hipFree(ctx->lctl);
   if (ctx->lctl_host) hipHostFree(ctx->lctl_host);
+  if (ctx->lctl_host2) hipHostFree(ctx->lctl_host2);
   if (ctx->tctl_host) hipHostFree(ctx->tctl_host);
+  if (ctx->tctl_host2) hipHostFree(ctx->tctl_host2);
+  for (auto& e : ctx->tdone)
+    if (e) hipEventDestroy(e);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
   if (ctx->lflag) hipFree(ctx->lflag);
@@ -522,6 +529,7 @@ struct LabelJob {
   float* key = nullptr;
   void* lctl = nullptr;
   unsigned* lctl_host = nullptr;
+  unsigned* lctl_host2 = nullptr;
   const float2* ctab = nullptr;
   unsigned* wmask = nullptr;
   bool keys_ready = false;  // the caller already computed the u_hat keys into `key`
@@ -558,6 +566,7 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
   if (!ctx->lctl) {
     HIP_TRY(ctx, hipMalloc(&ctx->lctl, labctl_bytes()));
     HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host, 64, hipHostMallocDefault));
+    HIP_TRY(ctx, hipHostMalloc(&ctx->lctl_host2, 64, hipHostMallocDefault));
   }
   const int ltx = (n + kLabelTile - 1) / kLabelTile;
   if (ctx->lmask_cap < (size_t)ltx * ltx) {
@@ -589,6 +598,7 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
   J->phi = ctx->phi;
   J->lctl = ctx->lctl;
   J->lctl_host = ctx->lctl_host;
+  J->lctl_host2 = ctx->lctl_host2;
   return SLHJB_OK;
 }
 
@@ -612,22 +622,52 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
   // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
   const int64_t max_passes = 4000000;
-  int64_t launched = 0;
-  for (;;) {
-    for (int b = 0; b < 16 && e == hipSuccess; ++b)
-      e = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad,
-                             J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, J.wmask, max_inner,
-                             J.window, b & 1, J.lctl, grid, s);
-    launched += 16;
-    if (e == hipSuccess) e = hipMemcpyAsync(J.lctl_host, J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    if (J.lctl_host[7]) break;  // done
-    if (launched > max_passes) {
+  // 16 passes captured in a graph; two replays in flight, so the GPU never waits for the host's
+  // check of the pass state (a replay after the end is all no-ops)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t ce = hipSuccess;
+    for (int b = 0; b < 16 && ce == hipSuccess; ++b)
+      ce = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad,
+                              J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, J.wmask, max_inner,
+                              J.window, b & 1, J.lctl, grid, cap);
+    e = hipStreamEndCapture(cap, &graph);
+    if (ce != hipSuccess) e = ce;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+  unsigned* hb[2] = {J.lctl_host, J.lctl_host2};
+  auto replay = [&](int k) -> hipError_t {
+    hipError_t r = hipGraphLaunch(exec, s);
+    if (r == hipSuccess) r = hipMemcpyAsync(hb[k & 1], J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
+    if (r == hipSuccess) r = hipEventRecord(ev[k & 1], s);
+    return r;
+  };
+  if (e == hipSuccess) e = replay(0);
+  for (int k = 0; e == hipSuccess; ++k) {
+    e = replay(k + 1);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[k & 1]);
+    if (e != hipSuccess) break;
+    if (hb[k & 1][7]) break;  // done
+    if ((int64_t)(k + 1) * 16 > max_passes) {
       *status = SLHJB_E_HIP;
-      return hipSuccess;
+      break;
     }
   }
+  if (e == hipSuccess) e = hipMemcpyAsync(J.lctl_host, J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (cap) hipStreamDestroy(cap);
+  for (auto& x : ev)
+    if (x) hipEventDestroy(x);
+  if (e != hipSuccess || *status != SLHJB_OK) return e;
   *passes_out = J.lctl_host[8];
   e = launch_label_argmax((const uint16_t*)J.phi, N, J.Ppad, J.label_out, J.overlap_out, J.tau, s);
   if (e == hipSuccess && J.phi_out) e = launch_label_phi_out(J.phi, N, J.n_patches, J.phi_out, s);
@@ -1055,24 +1095,50 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     }
     hipError_t le = hipSuccess;
     unsigned done = 0, dev_passes = 0;
-    while (true) {
-      le = timing ? enqueue_batch(ctx->stream, true) : hipGraphLaunch(exec, ctx->stream);
-      if (le != hipSuccess) break;
-      le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
-      if (le != hipSuccess) break;
-      le = hipStreamSynchronize(ctx->stream);
-      if (le != hipSuccess) break;
-      if (timing) {
+    if (timing) {
+      while (true) {
+        le = enqueue_batch(ctx->stream, true);
+        if (le == hipSuccess)
+          le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
+        if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
         for (int b = 0; b < kBatch && le == hipSuccess; ++b) {
           float ms = 0.0f;
           le = hipEventElapsedTime(&ms, ctx->tev[2 * b], ctx->tev[2 * b + 1]);
           visit_sec += ms * 1e-3;
         }
         if (le != hipSuccess) break;
+        done = ctx->tctl_host[9];
+        dev_passes = ctx->tctl_host[10];
+        if (done || (int64_t)dev_passes >= max_passes) break;
       }
+    } else {
+      // Two replays in flight: the host reads the state copied after replay k while replay k + 1
+      // runs, so the GPU never waits for the host; a replay after convergence is all no-ops.
+      if (!ctx->tctl_host2) HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host2, 64, hipHostMallocDefault));
+      if (!ctx->tdone[0]) {
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->tdone[0], hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->tdone[1], hipEventDisableTiming));
+      }
+      unsigned* hb[2] = {ctx->tctl_host, ctx->tctl_host2};
+      auto replay = [&](int k) -> hipError_t {
+        hipError_t e = hipGraphLaunch(exec, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hb[k & 1], ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->tdone[k & 1], ctx->stream);
+        return e;
+      };
+      le = replay(0);
+      for (int k = 0; le == hipSuccess; ++k) {
+        le = replay(k + 1);
+        if (le == hipSuccess) le = hipEventSynchronize(ctx->tdone[k & 1]);
+        if (le != hipSuccess) break;
+        if (hb[k & 1][9] || (int64_t)hb[k & 1][10] >= max_passes) break;
+      }
+      // the state after everything that ran (the replay in flight included)
+      if (le == hipSuccess)
+        le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
+      if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
       done = ctx->tctl_host[9];
       dev_passes = ctx->tctl_host[10];
-      if (done || (int64_t)dev_passes >= max_passes) break;
     }
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);

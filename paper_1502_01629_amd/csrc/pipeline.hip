@@ -3,6 +3,7 @@
 // patch construction (eq. discrete-advection followed by the argmax that turns the fuzzy
 // indicators into patches).
 #include "internal.h"
+#include "select_device.h"
 
 namespace slhjb {
 
@@ -157,8 +158,9 @@ __global__ void labctl_init_kernel(LabCtl* c) {
 
 // A selected tile's flag is cleared here, not in the visit kernel: visits set the flags of
 // their neighbours, and a clear in the same launch could erase a neighbour's request.
-__global__ void labctl_select_kernel(uint8_t* __restrict__ flag, const float* __restrict__ key, int tiles, int q,
-                                     int* __restrict__ list, LabCtl* __restrict__ c) {
+__global__ __launch_bounds__(kSelectThreads) void labctl_select_kernel(uint8_t* __restrict__ flag,
+                                                                       const float* __restrict__ key, int tiles, int q,
+                                                                       int* __restrict__ list, LabCtl* __restrict__ c) {
   if (c->done) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float B = key ? __uint_as_float(c->bound) : INFINITY;
@@ -169,23 +171,8 @@ __global__ void labctl_select_kernel(uint8_t* __restrict__ flag, const float* __
     if (key) k = key[t];
     on = !key || k <= B;
   }
-  const unsigned long long fmask = __ballot(fl), mask = __ballot(on);
-  const int lane = threadIdx.x & 63;
-  if (key) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
-  }
-  int base = 0;
-  if (lane == 0) {
-    if (fmask) atomicAdd(&c->nflag[q], (unsigned)__popcll(fmask));
-    if (key && k < INFINITY) atomicMin(&c->kmin[q], __float_as_uint(k));
-    if (mask) base = atomicAdd(&c->count[q], (unsigned)__popcll(mask));
-  }
-  base = __shfl(base, 0, 64);
-  if (on) {
-    list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
-    flag[t] = 0;
-  }
+  block_select(t, fl, on, k, key != nullptr, &c->count[q], &c->nflag[q], &c->kmin[q], list);
+  if (on) flag[t] = 0;
 }
 
 // One visit per selected tile: stage phi of the tile and a halo in LDS, iterate the in-place
@@ -389,7 +376,8 @@ hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t
                               int tiles_x, int tiles_y, uint8_t* flag, unsigned* wmask, int max_inner, float window,
                               int q, void* ctl, int grid, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
-  labctl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, q, list, (LabCtl*)ctl);
+  labctl_select_kernel<<<(tiles + kSelectThreads - 1) / kSelectThreads, kSelectThreads, 0, s>>>(flag, key, tiles, q,
+                                                                                            list, (LabCtl*)ctl);
   label_visit_kernel<<<grid, 256, label_pass_lds_bytes(P), s>>>(phi32, cls, ctrl, speed, speed_const, ctab, r, n, P,
                                                                 list, tiles_x, tiles_y, flag, wmask, max_inner, window,
                                                                 q, (LabCtl*)ctl);

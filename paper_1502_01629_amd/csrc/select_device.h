@@ -1,0 +1,53 @@
+// Band selection of flagged tiles, shared by the tile solver and the labeler.
+#pragma once
+
+#include "internal.h"
+
+namespace slhjb {
+
+constexpr int kSelectThreads = 1024;
+
+// One tile per thread of a kSelectThreads workgroup: `fl` says the tile is flagged, `on` that it is
+// selected, `k` is its key (+inf when not flagged or unkeyed). The workgroup adds its flagged and
+// selected counts to *nflag and *count and lowers *kmin with one atomic each (device-scope atomics
+// on one word from every workgroup of the grid are what made a per-wavefront version slow), then
+// writes its selected tiles to list at the offset the count atomic returned. Every thread of the
+// workgroup must call it. The order of the list depends on timing, its contents do not.
+__device__ __forceinline__ void block_select(int t, bool fl, bool on, float k, bool keyed, unsigned* count,
+                                             unsigned* nflag, unsigned* kmin, int* list) {
+  constexpr int W = kSelectThreads / 64;
+  __shared__ unsigned s_on[W], s_fl[W];
+  __shared__ float s_k[W];
+  __shared__ unsigned s_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long fmask = __ballot(fl), mask = __ballot(on);
+  if (keyed) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
+  }
+  if (lane == 0) {
+    s_on[wave] = (unsigned)__popcll(mask);
+    s_fl[wave] = (unsigned)__popcll(fmask);
+    s_k[wave] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned total = 0u, nf = 0u;
+    float km = INFINITY;
+    const int waves = (int)(blockDim.x >> 6);
+    for (int w = 0; w < waves; ++w) {
+      const unsigned c = s_on[w];
+      s_on[w] = total;  // exclusive prefix over the wavefronts
+      total += c;
+      nf += s_fl[w];
+      km = fminf(km, s_k[w]);
+    }
+    if (nf) atomicAdd(nflag, nf);
+    if (keyed && km < INFINITY) atomicMin(kmin, __float_as_uint(km));
+    s_base = total ? atomicAdd(count, total) : 0u;
+  }
+  __syncthreads();
+  if (on) list[s_base + s_on[wave] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))] = t;
+}
+
+}  // namespace slhjb

@@ -14,6 +14,7 @@
 // whose upwind values are still moving from being iterated to convergence against stale halos.
 #include <hip/hip_cooperative_groups.h>
 
+#include "select_device.h"
 #include "sweep_device.h"
 
 namespace slhjb {
@@ -669,22 +670,17 @@ __global__ void tilectl_init_kernel(TileCtl* c) {
   c->pe_updates = 0ull;
 }
 
-// Also clears the outcome of the last check sweep once read: a workgroup that reads it after
-// workgroup 0 cleared it sees "no check" and selects, which is what every workgroup does when the
-// check failed; when it met tol nothing is cleared and every workgroup stops.
-__global__ void tilectl_select_kernel(const uint8_t* __restrict__ flag, const float* __restrict__ key, int tiles,
-                                      float tol, int q, int* __restrict__ list, TileCtl* __restrict__ c) {
+// The outcome of the last check sweep (checked, resid) is written by the visit and commit
+// launches only, so every thread of this launch reads the same values and a workgroup takes one
+// branch as a whole.
+__global__ __launch_bounds__(kSelectThreads) void tilectl_select_kernel(const uint8_t* __restrict__ flag,
+                                                                        const float* __restrict__ key, int tiles,
+                                                                        float tol, int q, int* __restrict__ list,
+                                                                        TileCtl* __restrict__ c) {
   if (c->done) return;
-  if (c->checked) {
-    const bool ok = __uint_as_float(c->resid) <= tol;
-    if (ok) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) c->done = 1u;
-      return;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    c->checked = 0u;
-    c->resid = 0u;
+  if (c->checked && __uint_as_float(c->resid) <= tol) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->done = 1u;
+    return;
   }
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float B = key ? __uint_as_float(c->bound) : INFINITY;
@@ -695,20 +691,7 @@ __global__ void tilectl_select_kernel(const uint8_t* __restrict__ flag, const fl
     if (key) k = key[t];
     on = !key || k <= B;
   }
-  const unsigned long long fmask = __ballot(fl), mask = __ballot(on);
-  const int lane = threadIdx.x & 63;
-  if (key) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
-  }
-  int base = 0;
-  if (lane == 0) {
-    if (fmask) atomicAdd(&c->nflag[q], (unsigned)__popcll(fmask));
-    if (key && k < INFINITY) atomicMin(&c->kmin[q], __float_as_uint(k));
-    if (mask) base = atomicAdd(&c->count[q], (unsigned)__popcll(mask));
-  }
-  base = __shfl(base, 0, 64);
-  if (on) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
+  block_select(t, fl, on, k, key != nullptr, &c->count[q], &c->nflag[q], &c->kmin[q], list);
 }
 
 template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP,
@@ -732,7 +715,8 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
     if (blockIdx.x == 0 && threadIdx.x == 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
   } else {
-    // nothing flagged: check sweep, one Jacobi iteration of every tile
+    // nothing flagged: check sweep, one Jacobi iteration of every tile; its commit raises resid
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->resid = 0u;
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
                                                     flag, 1, 0.0f, &c->updates, lds, red, 0, &c->pe_updates);
@@ -785,7 +769,8 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                       float act, float window, float tol, int q, TileCtl* c, int grid,
                                       hipEvent_t ev_before, hipEvent_t ev_after, int pe, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
-  tilectl_select_kernel<<<(tiles + 255) / 256, 256, 0, s>>>(flag, key, tiles, tol, q, list, c);
+  tilectl_select_kernel<<<(tiles + kSelectThreads - 1) / kSelectThreads, kSelectThreads, 0, s>>>(flag, key, tiles,
+                                                                                             tol, q, list, c);
   const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
   const size_t lds = tile_pass_lds_bytes(sh, a.halo, indep);
   if (ev_before) hipEventRecord(ev_before, s);

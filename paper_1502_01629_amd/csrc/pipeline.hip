@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
                                                           int max_inner, float window, int q, LabCtl* __restrict__ c) {
   if (c->done) return;
   extern __shared__ uint32_t lds[];
-  __shared__ unsigned smask, omask;
+  __shared__ unsigned omask;
   __shared__ int act[32];
   __shared__ int nact;
   const int cnt = (int)c->count[q];
@@ -224,36 +224,26 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     const int tid = list[slot];
     const int tx = tid % tiles_x, ty = tid / tiles_x;
     const int x0 = tx * kLabTile - kLabHalo, y0 = ty * kLabTile - kLabHalo;
-    if (threadIdx.x == 0) {
-      smask = 0u;
-      omask = 0u;
+    // wavefront 0: the words that can be nonzero in the staged region, the union of the masks of
+    // the tile and its 8 neighbours (the halo of 2 nodes lies in them), as a list of planes
+    if (threadIdx.x < 64) {
+      unsigned m = 0u;
+      if (threadIdx.x < 9) {
+        const int nx = tx + threadIdx.x % 3 - 1, ny = ty + threadIdx.x / 3 - 1;
+        if (nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) m = wmask[ny * tiles_x + nx];
+      }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) m |= __shfl_xor(m, off, 64);
+      if (threadIdx.x == 0) {
+        int k = 0;
+        for (int b = 0; b < half; ++b)
+          if (m & (1u << b)) act[k++] = b;
+        nact = k;
+        omask = 0u;
+      }
     }
-    __syncthreads();
-    // words that can be nonzero in the staged region: the masks of the tile and its 8 neighbours
-    // (the halo of 2 nodes lies in them)
-    if (threadIdx.x < 9) {
-      const int nx = tx + threadIdx.x % 3 - 1, ny = ty + threadIdx.x / 3 - 1;
-      if (nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) atomicOr(&smask, wmask[ny * tiles_x + nx]);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int k = 0;
-      for (int b = 0; b < half; ++b)
-        if (smask & (1u << b)) act[k++] = b;
-      nact = k;
-    }
-    __syncthreads();
-    const int A = nact;
-    // stage those words of the tile and its halo (nodes outside the grid read 0)
-    for (int e = threadIdx.x; e < kLabSpan * kLabSpan * A; e += blockDim.x) {
-      const int qi = e / (kLabSpan * kLabSpan), node = e - qi * (kLabSpan * kLabSpan);
-      const int sy = node / kLabSpan, sx = node - sy * kLabSpan;
-      const int gx = x0 + sx, gy = y0 + sy;
-      uint32_t val = 0u;
-      if (gx >= 0 && gx < n && gy >= 0 && gy < n) val = phi32[(size_t)act[qi] * N + (size_t)gy * n + gx];
-      tile[act[qi] * kLabPlane + node] = val;
-    }
-    // foot of this thread's node, if FREE: corner cell and Q.8 fractions
+    // foot of this thread's node, if FREE: corner cell and Q.8 fractions (its loads overlap the
+    // mask reads above)
     const int gx = tx * kLabTile + lx, gy = ty * kLabTile + ly;
     int base = -1;
     uint32_t w00 = 0u, w10 = 0u, w01 = 0u, w11 = 0u;
@@ -275,6 +265,17 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
         w01 = (256u - fx) * fy;
         w11 = fx * fy;
       }
+    }
+    __syncthreads();
+    const int A = nact;
+    // stage those words of the tile and its halo (nodes outside the grid read 0)
+    for (int e = threadIdx.x; e < kLabSpan * kLabSpan * A; e += blockDim.x) {
+      const int qi = e / (kLabSpan * kLabSpan), node = e - qi * (kLabSpan * kLabSpan);
+      const int sy = node / kLabSpan, sx = node - sy * kLabSpan;
+      const int ggx = x0 + sx, ggy = y0 + sy;
+      uint32_t val = 0u;
+      if (ggx >= 0 && ggx < n && ggy >= 0 && ggy < n) val = phi32[(size_t)act[qi] * N + (size_t)ggy * n + ggx];
+      tile[act[qi] * kLabPlane + node] = val;
     }
     __syncthreads();
     int it = 0, last = 0, ever = 0;

@@ -311,48 +311,73 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
   if (TRACK) *pidx = bidx;
 }
 
-// First-ring update of one node for one control cm (policy evaluation of modified policy
-// iteration): the expressions of ring1_partial for that control, with its quadrant taken from
-// the signs of (a_x, a_y) as the host groups the table. Returns (num, den) as a partial does.
+// Policy evaluation on the first ring (modified policy iteration): the update of a node for one
+// fixed control cm, with the quadrant taken from the signs of (a_x, a_y) as the host groups the
+// table. Everything that does not depend on the iterate is computed once per node after each full
+// iteration (policy_prepare); policy_apply then evaluates the expressions of ring1_partial for
+// that control operation for operation, so that a node whose control is still the maximiser gets
+// bit for bit the value a full iteration would give it. (Otherwise the two maps would have fixed
+// points a few ulp apart, and a tolerance near the FP32 resolution could never be met.) SL3
+// divides by the denominator through its reciprocal, as the full iteration of the split visit does.
+struct PolicyEval {
+  int ox, oy;            // LDS offsets of the east/west and north/south corners
+  float ksx, ksy, k2s;   // k sx, k sy, k^2 sx sy (exact: sx, sy = +-1)
+  float cx, cy, cz;      // a_x, a_y, a_x a_y
+  float rden;            // SL3: 1 / (1 - beta w00) as the full iteration computes it
+  bool out;              // the foot leaves the box: w_outside
+};
+
+template <int SCHEME>
+__device__ __forceinline__ PolicyEval policy_prepare(int LW, float k, float4 cm, const SweepArgs& a, bool lft,
+                                                     bool rgt, bool bot, bool top) {
+  PolicyEval p;
+  const float sx = cm.x >= 0.0f ? 1.0f : -1.0f, sy = cm.y >= 0.0f ? 1.0f : -1.0f;
+  p.ox = cm.x >= 0.0f ? 1 : -1;
+  p.oy = cm.y >= 0.0f ? LW : -LW;
+  const float k2 = k * k;
+  p.ksx = k * sx;
+  p.ksy = k * sy;
+  p.k2s = k2 * (sx * sy);
+  p.cx = cm.x;
+  p.cy = cm.y;
+  p.cz = cm.z;
+  p.out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+  p.rden = 1.0f;
+  if (SCHEME == kSL3 && !p.out) {
+    const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
+    p.rden = 1.0f / __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
+  }
+  return p;
+}
+
 template <int SCHEME, bool INDEP>
-__device__ __forceinline__ void ring1_policy(const float* __restrict__ T, int LW, float k, float4 cm,
-                                             const SweepArgs& a, bool lft, bool rgt, bool bot, bool top,
-                                             const int16_t* __restrict__ L, float& pnum, float& pden) {
-  // the host's quadrant of a control is (+x,+y), (-x,+y), (-x,-y) or (+x,-y) by the signs a_x >= 0,
-  // a_y >= 0: the cell east/west and north/south of the node
-  const int ox = cm.x >= 0.0f ? 1 : -1;
-  const int oy = cm.y >= 0.0f ? LW : -LW;
+__device__ __forceinline__ float policy_apply(const float* __restrict__ T, const PolicyEval& p, const SweepArgs& a,
+                                              const int16_t* __restrict__ L) {
   const float w00 = T[0];
-  float wX = T[ox], wY = T[oy], wXY = T[ox + oy];
+  float wX = T[p.ox], wY = T[p.oy], wXY = T[p.ox + p.oy];
   if (INDEP) {
     const int me = L[0];
-    wX = L[ox] == me ? wX : a.w_outside;
-    wY = L[oy] == me ? wY : a.w_outside;
-    wXY = L[ox + oy] == me ? wXY : a.w_outside;
+    wX = L[p.ox] == me ? wX : a.w_outside;
+    wY = L[p.oy] == me ? wY : a.w_outside;
+    wXY = L[p.ox + p.oy] == me ? wXY : a.w_outside;
   }
-  const float sx = ox > 0 ? 1.0f : -1.0f, sy = oy > 0 ? 1.0f : -1.0f;
-  const float k2 = k * k;
   float B, C, D;
   if (SCHEME == kSL2) {
-    B = k * sx * (wX - w00);
-    C = k * sy * (wY - w00);
-    D = k2 * (sx * sy) * ((wXY - wX) - (wY - w00));
+    B = p.ksx * (wX - w00);
+    C = p.ksy * (wY - w00);
+    D = p.k2s * ((wXY - wX) - (wY - w00));
   } else {
-    B = k * sx * wX;
-    C = k * sy * wY;
-    D = k2 * (sx * sy) * (wXY - wX - wY);
+    B = p.ksx * wX;
+    C = p.ksy * wY;
+    D = p.k2s * (wXY - wX - wY);
   }
-  float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
-  const bool out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+  float val = __builtin_fmaf(p.cz, D, __builtin_fmaf(p.cy, C, p.cx * B));
   if (SCHEME == kSL2) {
-    pnum = out ? a.w_outside - w00 : val;
-    pden = 1.0f;
-  } else {
-    const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
-    const float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
-    pnum = out ? a.w_outside : val;
-    pden = out ? 1.0f : den;
+    if (p.out) val = a.w_outside - w00;
+    return a.beta * (w00 + val);
   }
+  if (p.out) val = a.w_outside;
+  return (a.beta * val) * p.rden;
 }
 
 template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false>

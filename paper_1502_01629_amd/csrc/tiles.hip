@@ -143,7 +143,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
             bi = pix[q * TT + node];
           }
         }
-        v = a.beta * bn / bd;
+        // through the reciprocal, as the policy evaluation of the first-ring path divides
+        v = (a.beta * bn) * (1.0f / bd);
       }
       pol = bi;
       nxt[li] = v;
@@ -159,18 +160,19 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     // candidate each; leaves room for the full iteration that must end the visit
     if (pe > 0) {
       const float4 cm = ctrl[pol];
+      PolicyEval pv{};
+      if (PATH == 1 && part == 0 && fr)
+        pv = policy_prepare<SCHEME>(LW, kk, cm, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1);
       for (int e = 0; e < pe && it < max_inner - 1; ++e) {
         if (part == 0 && fr) {
-          float num, den;
           if (PATH == 1) {
-            ring1_policy<SCHEME, INDEP>(cur + li, LW, kk, cm, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1,
-                                        INDEP ? labs + li : nullptr, num, den);
-            nxt[li] = SCHEME == kSL2 ? a.beta * (cur[li] + num) : a.beta * num / den;
+            nxt[li] = policy_apply<SCHEME, INDEP>(cur + li, pv, a, INDEP ? labs + li : nullptr);
           } else {
+            float num, den;
             general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
                                                  INDEP ? labs[li] : 0, pol, pol + 1, num, den);
             constexpr int K = Feet<DIFF>::K;
-            nxt[li] = SCHEME == kSL2 ? a.beta * num * (1.0f / (float)K) : a.beta * num / den;
+            nxt[li] = SCHEME == kSL2 ? a.beta * num * (1.0f / (float)K) : (a.beta * num) * (1.0f / den);
           }
         }
         __syncthreads();

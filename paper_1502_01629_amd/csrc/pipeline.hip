@@ -239,6 +239,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
         for (int b = 0; b < half; ++b)
           if (m & (1u << b)) act[k++] = b;
         nact = k;
+        if (k & 1) act[k] = act[k - 1];  // the sweeps take the words in pairs (k <= 31 here)
         omask = 0u;
       }
     }
@@ -268,14 +269,30 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     }
     __syncthreads();
     const int A = nact;
-    // stage those words of the tile and its halo (nodes outside the grid read 0)
-    for (int e = threadIdx.x; e < kLabSpan * kLabSpan * A; e += blockDim.x) {
-      const int qi = e / (kLabSpan * kLabSpan), node = e - qi * (kLabSpan * kLabSpan);
-      const int sy = node / kLabSpan, sx = node - sy * kLabSpan;
-      const int ggx = x0 + sx, ggy = y0 + sy;
-      uint32_t val = 0u;
-      if (ggx >= 0 && ggx < n && ggy >= 0 && ggy < n) val = phi32[(size_t)act[qi] * N + (size_t)ggy * n + ggx];
-      tile[act[qi] * kLabPlane + node] = val;
+    // stage those words of the tile and its halo (nodes outside the grid read 0): this thread's
+    // two staged nodes (the region has kLabSpan^2 <= 2 * 256), two planes at a time so that four
+    // loads are in flight
+    static_assert(kLabSpan * kLabSpan <= 2 * 256, "two staged nodes per thread");
+    {
+      const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+      const int sy0 = e0 / kLabSpan, sx0 = e0 - sy0 * kLabSpan;
+      const int sy1 = e1 / kLabSpan, sx1 = e1 - sy1 * kLabSpan;
+      const int gx0 = x0 + sx0, gy0 = y0 + sy0, gx1 = x0 + sx1, gy1 = y0 + sy1;
+      const bool in0 = gx0 >= 0 && gx0 < n && gy0 >= 0 && gy0 < n;
+      const bool in1 = e1 < kLabSpan * kLabSpan && gx1 >= 0 && gx1 < n && gy1 >= 0 && gy1 < n;
+      const bool st1 = e1 < kLabSpan * kLabSpan;
+      const size_t o0 = in0 ? (size_t)gy0 * n + gx0 : 0, o1 = in1 ? (size_t)gy1 * n + gx1 : 0;
+      for (int qi = 0; qi < A; qi += 2) {
+        const int qa = act[qi], qb = act[qi + 1];  // qb == qa for the padding of an odd count
+        const uint32_t va0 = in0 ? phi32[(size_t)qa * N + o0] : 0u, va1 = in1 ? phi32[(size_t)qa * N + o1] : 0u;
+        const uint32_t vb0 = in0 ? phi32[(size_t)qb * N + o0] : 0u, vb1 = in1 ? phi32[(size_t)qb * N + o1] : 0u;
+        tile[qa * kLabPlane + e0] = va0;
+        tile[qb * kLabPlane + e0] = vb0;
+        if (st1) {
+          tile[qa * kLabPlane + e1] = va1;
+          tile[qb * kLabPlane + e1] = vb1;
+        }
+      }
     }
     __syncthreads();
     int it = 0, last = 0, ever = 0;
@@ -284,25 +301,37 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
         // a round of kLabSub in-place sweeps of the tile under one barrier: values only grow, so
         // any interleaving of the wavefronts climbs to the same least fixed point, and a round in
         // which no thread changed anything read final values everywhere (the tile is settled)
+        // A word's update reads only its own plane, so the words are independent: they go in
+        // pairs with all ten reads issued before either write (the padding of an odd count
+        // repeats the last word, which then gets the same value written twice).
         int ch = 0;
+        auto interp = [&](uint32_t c00, uint32_t c10, uint32_t c01, uint32_t c11) -> uint32_t {
+          const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
+                                w11 * (c11 & 0xffffu) + 32768u) >> 16);
+          const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
+                                32768u) >> 16);
+          return lo | (hi << 16);
+        };
         for (int sub = 0; sub < kLabSub; ++sub) {
-        if (base >= 0) {
-          for (int qi = 0; qi < A; ++qi) {
-            const uint32_t* pl = tile + act[qi] * kLabPlane;
-            const uint32_t c00 = pl[base], c10 = pl[base + 1];
-            const uint32_t c01 = pl[base + kLabSpan], c11 = pl[base + kLabSpan + 1];
-            const uint32_t lo = ((w00 * (c00 & 0xffffu) + w10 * (c10 & 0xffffu) + w01 * (c01 & 0xffffu) +
-                                  w11 * (c11 & 0xffffu) + 32768u) >> 16);
-            const uint32_t hi = ((w00 * (c00 >> 16) + w10 * (c10 >> 16) + w01 * (c01 >> 16) + w11 * (c11 >> 16) +
-                                  32768u) >> 16);
-            const uint32_t nv = lo | (hi << 16);
-            uint32_t* me = tile + act[qi] * kLabPlane + self;
-            if (nv != *me) {
-              *me = nv;
-              ch = 1;
+          if (base >= 0) {
+            for (int qi = 0; qi < A; qi += 2) {
+              uint32_t* pa = tile + act[qi] * kLabPlane;
+              uint32_t* pb = tile + act[qi + 1] * kLabPlane;
+              const uint32_t a00 = pa[base], a10 = pa[base + 1], a01 = pa[base + kLabSpan],
+                             a11 = pa[base + kLabSpan + 1], am = pa[self];
+              const uint32_t b00 = pb[base], b10 = pb[base + 1], b01 = pb[base + kLabSpan],
+                             b11 = pb[base + kLabSpan + 1], bm = pb[self];
+              const uint32_t na = interp(a00, a10, a01, a11), nb = interp(b00, b10, b01, b11);
+              if (na != am) {
+                pa[self] = na;
+                ch = 1;
+              }
+              if (nb != bm) {
+                pb[self] = nb;
+                ch = 1;
+              }
             }
           }
-        }
         }
         last = __syncthreads_or(ch);  // barrier + block-wide OR
         ever |= last;

@@ -23,6 +23,8 @@ struct slhjb_ctx {
   // scratch
   float* buf = nullptr;          // second iterate buffer
   size_t buf_elems = 0;
+  float* uhat = nullptr;         // pipeline: copy of u_hat read by the synthesis and the labeler
+  size_t uhat_elems = 0;
   float* vbuf[2] = {nullptr, nullptr};  // single-sweep staging buffers
   size_t vbuf_elems = 0;
   unsigned* small = nullptr;     // [0] residual bits, [1] flags, [2..4] speed stats
@@ -96,6 +98,7 @@ struct Prepared {
   float vstar = 1.0f;
   double reach = 0.0;
   int64_t free_nodes = 0;
+  float speed_min = 0.0f, speed_max = 0.0f;  // over the nodes (speed_const without a field)
 };
 
 int validate(slhjb_ctx* ctx, const slhjb_problem* p) {
@@ -171,6 +174,9 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   const int64_t free_nodes = ctx->small_host[5];
   const double reach = reach_for(p, speed_max);
   Prepared P;
+  P.speed_max = (float)speed_max;
+  P.speed_min = p->speed_const;
+  if (p->speed) memcpy(&P.speed_min, &ctx->small_host[2], sizeof(float));
   P.diffusion = p->eps > 0.0f ? p->diffusion : SLHJB_DIFF_NONE;
   P.scheme = p->scheme;
   P.reach = reach;
@@ -266,14 +272,6 @@ int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
   return SLHJB_OK;
 }
 
-double speed_max_of(slhjb_ctx* ctx, const slhjb_problem* p) {
-  // valid right after prepare(): small_host[3] holds the bits of the largest speed
-  if (!p->speed) return p->speed_const;
-  float hi;
-  memcpy(&hi, &ctx->small_host[3], sizeof(float));
-  return hi;
-}
-
 int ensure_tiles(slhjb_ctx* ctx, size_t tiles) {
   if (!ctx->tcount) {
     HIP_TRY(ctx, hipMalloc(&ctx->tcount, sizeof(int) * 4));
@@ -344,6 +342,7 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   else hipDeviceSynchronize();
   if (ctx->buf) hipFree(ctx->buf);
+  if (ctx->uhat) hipFree(ctx->uhat);
   for (auto* b : ctx->vbuf)
     if (b) hipFree(b);
   if (ctx->small) hipFree(ctx->small);
@@ -546,7 +545,7 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
   // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
   slhjb_problem p0 = *problem;
   p0.diffusion = SLHJB_DIFF_NONE;
-  const float speed_max = (float)speed_max_of(ctx, problem);
+  const float speed_max = P.speed_max;
   if (reach_for(&p0, speed_max) > 1.0 + 1e-6)
     return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labeling needs h c |a| <= dx (feet in the first ring of cells)");
   const int n = problem->n;
@@ -675,6 +674,9 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   return e;
 }
 
+int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P, float* v, double tol,
+                     int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats);
+
 }  // namespace
 
 extern "C" {
@@ -739,13 +741,15 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   int64_t lab_passes = 0;
   int lab_status = SLHJB_OK;
   hipError_t lab_err = hipSuccess;
-  double lab_seconds = 0.0;
+  double lab_seconds = 0.0, syn_seconds = 0.0;
   LabelJob J;
-  auto start_labels = [&]() -> int {
-    Prepared Pf;
-    int r = prepare(ctx, fine, &Pf);
+  // Overlapped labels: u_hat is copied, the fine problem prepared once, and the labeler stream
+  // gets the synthesis, the keys and the labeling of the copy while the fine solve overwrites v.
+  auto start_labels = [&](const Prepared& Pf) -> int {
+    int r = ensure_buf(ctx, &ctx->uhat, &ctx->uhat_elems, (size_t)N);
     if (r != SLHJB_OK) return r;
-    r = label_setup(ctx, fine, Pf, ctrl, v, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &J);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->uhat, v, sizeof(float) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    r = label_setup(ctx, fine, Pf, ctrl, ctx->uhat, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &J);
     if (r != SLHJB_OK) return r;
     const size_t tiles = (size_t)J.tiles_x * J.tiles_x;
     if (ctx->ltiles_cap < tiles) {
@@ -768,29 +772,36 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     J.list = ctx->llist;
     J.key = ctx->lkey;
     J.ctab = ctx->lctab;
-    // the keys read u_hat, which the fine solve overwrites: compute them before the fork
-    HIP_TRY(ctx, launch_label_keys(v, fine->node_class, J.n, J.tiles_x, J.tiles_x, J.vstar, J.lambda, J.key,
-                                   ctx->stream));
-    J.keys_ready = true;
+    J.keys_ready = false;  // computed on the labeler stream, from the copy
     if (!ctx->aux_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux_stream, e1, 0));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host control array is pageable
     const int dev = ctx->device;
     hipStream_t aux = ctx->aux_stream;
-    labeler = std::thread([&J, aux, dev, &lab_passes, &lab_status, &lab_err, &lab_seconds]() {
+    const float r_h = Pf.args.r;
+    labeler = std::thread([&J, aux, dev, fine, ctrl, r_h, &lab_passes, &lab_status, &lab_err, &lab_seconds,
+                           &syn_seconds]() {
       hipError_t e = hipSetDevice(dev);
-      hipEvent_t a = nullptr, b = nullptr;
+      hipEvent_t a = nullptr, m = nullptr, b = nullptr;
       if (e == hipSuccess) e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&m);
       if (e == hipSuccess) e = hipEventCreate(&b);
       if (e == hipSuccess) e = hipEventRecord(a, aux);
+      if (e == hipSuccess)
+        e = launch_synthesize(J.v_hat, fine->speed, fine->node_class, J.ctab, fine->n_controls, fine->n, r_h,
+                              fine->speed_const, fine->v_out, ctrl, aux);
+      if (e == hipSuccess) e = hipEventRecord(m, aux);
       if (e == hipSuccess) e = label_run(J, aux, &lab_passes, &lab_status);
       if (e == hipSuccess) e = hipEventRecord(b, aux);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, m);
+      syn_seconds = ms * 1e-3;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, m, b);
       lab_seconds = ms * 1e-3;
       if (a) hipEventDestroy(a);
+      if (m) hipEventDestroy(m);
       if (b) hipEventDestroy(b);
       lab_err = e;
     });
@@ -830,29 +841,37 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     // (2) u_hat on the fine grid
     if (st == SLHJB_OK) st = slhjb_upsample(ctx, coarse->n, vc, n, v);
     if (st == SLHJB_OK && (he = lap(&S.t_upsample)) != hipSuccess) st = hip_fail(ctx, he, "event");
+    // the fine problem, prepared once for the synthesis, the labels and the solve (after the
+    // coarse solve, which loaded the coarse problem's control table)
+    Prepared Pf;
+    if (st == SLHJB_OK) st = prepare(ctx, fine, &Pf);
     // (3) synthesis of the control and (4) patch labels
-    if (st == SLHJB_OK && need_labels) {
-      st = slhjb_synthesize(ctx, fine, v, ctrl);
+    if (st == SLHJB_OK && need_labels && !overlap_labels) {
+      he = launch_synthesize(v, fine->speed, fine->node_class, ctx->ctrl2, fine->n_controls, n, Pf.args.r,
+                             fine->speed_const, fine->v_out, ctrl, ctx->stream);
+      if (he != hipSuccess) st = hip_fail(ctx, he, "synthesis");
       if (st == SLHJB_OK && (he = lap(&S.t_synthesize)) != hipSuccess) st = hip_fail(ctx, he, "event");
-      if (st == SLHJB_OK && !overlap_labels) {
+      if (st == SLHJB_OK) {
         int64_t lp = 0;
         st = slhjb_label(ctx, fine, ctrl, v, opts->source_patch, opts->n_patches, 0, lab, nullptr, nullptr, &lp);
         S.label_passes = lp;
         if (st == SLHJB_OK && (he = lap(&S.t_label)) != hipSuccess) st = hip_fail(ctx, he, "event");
       }
-      if (st == SLHJB_OK && overlap_labels) st = start_labels();
+      // slhjb_label prepared the problem again: same tables, same statistics
     }
+    if (st == SLHJB_OK && overlap_labels) st = start_labels(Pf);
     // (5) computation: tiles by increasing u_hat, from u_hat
     if (st == SLHJB_OK) {
       to.order = SLHJB_ORDER_KEYS;
       to.mode = opts->mode == SLHJB_PATCHY_INDEPENDENT ? SLHJB_MODE_INDEPENDENT : SLHJB_MODE_TRANSMISSION;
       to.label = opts->mode == SLHJB_PATCHY_INDEPENDENT ? lab : nullptr;
-      st = slhjb_solve_tiles(ctx, fine, v, opts->tol, opts->max_passes, &to, &ts);
+      st = solve_tiles_impl(ctx, fine, Pf, v, opts->tol, opts->max_passes, &to, &ts);
     }
     if (labeler.joinable()) {
       labeler.join();
       S.label_passes = lab_passes;
       S.t_label = lab_seconds;
+      S.t_synthesize = syn_seconds;
       if (lab_err != hipSuccess && st == SLHJB_OK) st = hip_fail(ctx, lab_err, "patch labels");
       else if (lab_status != SLHJB_OK && st == SLHJB_OK) st = fail(ctx, lab_status, "labeler did not settle (internal error)");
     }
@@ -950,24 +969,15 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
   return SLHJB_OK;
 }
 
-int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
-                      const slhjb_tile_opts* opts, slhjb_stats* stats) {
-  if (!ctx) return SLHJB_E_INVALID_ARG;
-  if (!v || !opts) return fail(ctx, SLHJB_E_INVALID_ARG, "v and opts must be non-NULL");
-  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
-  if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
-      opts->tile_shape < 0 || opts->tile_shape >= kTileShapes || opts->persistent < 0 || opts->persistent > 1 ||
-      opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1 ||
-      opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
-    return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
-  if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
-    return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  Prepared P;
-  int st = prepare(ctx, problem, &P);
-  if (st != SLHJB_OK) return st;
-  float speed_min = problem->speed_const;
-  if (problem->speed) memcpy(&speed_min, &ctx->small_host[2], sizeof(float));
+}  // extern "C"
+
+namespace {
+
+// The tile solver on a problem already prepared (validated, its statistics read back and its
+// control table on the device): the pipeline prepares each problem once.
+int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P, float* v, double tol,
+                     int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats) {
+  int st = SLHJB_OK;
   const int n = problem->n;
   const int64_t N = (int64_t)n * n;
   const int shape = opts->tile_shape;
@@ -1004,8 +1014,7 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   // fastest speed
   const float window = opts->key_slack >= 0.0f
                            ? opts->key_slack
-                           : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / speed_max_of(ctx, problem));
-  (void)speed_min;
+                           : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(problem) / P.speed_max);
   const int grid = std::min(tiles, 2048);
   const size_t lds = tile_pass_lds_bytes(sh, P.args.halo, indep);
   if (lds > 64 * 1024) return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
@@ -1177,6 +1186,29 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
     stats->policy_updates = pe_updates;
   }
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
+                      const slhjb_tile_opts* opts, slhjb_stats* stats) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v || !opts) return fail(ctx, SLHJB_E_INVALID_ARG, "v and opts must be non-NULL");
+  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
+  if (opts->order < 0 || opts->order > 1 || opts->mode < 0 || opts->mode > 1 || opts->max_inner < 0 ||
+      opts->tile_shape < 0 || opts->tile_shape >= kTileShapes || opts->persistent < 0 || opts->persistent > 1 ||
+      opts->max_workgroups < 0 || opts->collect_kernel_time < 0 || opts->collect_kernel_time > 1 ||
+      opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
+  if (opts->mode == SLHJB_MODE_INDEPENDENT && !opts->label)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "independent mode needs patch labels");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Prepared P;
+  const int st = prepare(ctx, problem, &P);
+  if (st != SLHJB_OK) return st;
+  return solve_tiles_impl(ctx, problem, P, v, tol, max_passes, opts, stats);
 }
 
 int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v, double tol,

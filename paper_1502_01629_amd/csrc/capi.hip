@@ -15,6 +15,65 @@
 
 using namespace slhjb;
 
+namespace {
+
+// Instantiated graphs of device-driven pass batches, kept by the bytes of every launch argument
+// they were captured with: a later solve with the same arguments (same problem, buffers,
+// tolerances) replays the graph without capturing and instantiating it again. Least recently used
+// entries are dropped. One cache per user (the tile solver, the labeler), each used from one
+// host thread at a time.
+struct GraphKey {
+  std::vector<unsigned char> b;
+  template <class T>
+  GraphKey& add(const T& v) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+    b.insert(b.end(), p, p + sizeof(T));
+    return *this;
+  }
+};
+
+struct GraphCache {
+  struct Entry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  static constexpr int kEntries = 4;
+  Entry e[kEntries];
+  uint64_t clock = 0;
+  hipGraphExec_t find(const GraphKey& k) {
+    for (auto& x : e)
+      if (x.exec && x.key == k.b) {
+        x.used = ++clock;
+        return x.exec;
+      }
+    return nullptr;
+  }
+  void insert(GraphKey&& k, hipGraphExec_t exec) {
+    Entry* v = &e[0];
+    for (auto& x : e) {
+      if (!x.exec) {
+        v = &x;
+        break;
+      }
+      if (x.used < v->used) v = &x;
+    }
+    if (v->exec) hipGraphExecDestroy(v->exec);
+    v->key = std::move(k.b);
+    v->exec = exec;
+    v->used = ++clock;
+  }
+  void clear() {
+    for (auto& x : e) {
+      if (x.exec) hipGraphExecDestroy(x.exec);
+      x.exec = nullptr;
+      x.key.clear();
+    }
+  }
+};
+
+}  // namespace
+
 struct slhjb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -54,6 +113,10 @@ struct slhjb_ctx {
   unsigned* tctl_host2 = nullptr;    // second pinned copy (two graph replays in flight)
   hipEvent_t tdone[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  GraphCache tile_graphs;            // tile-solver pass batches
+  GraphCache label_graphs;           // labeler pass batches
+  hipStream_t lcap_stream = nullptr; // capture stream of the labeler
+  hipEvent_t ldone[2] = {nullptr, nullptr};
   // labeler buffers of its own, so that it can run beside the tile solver (patchy pipeline)
   hipStream_t aux_stream = nullptr;
   uint8_t* lflag = nullptr;
@@ -365,7 +428,12 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tctl_host2) hipHostFree(ctx->tctl_host2);
   for (auto& e : ctx->tdone)
     if (e) hipEventDestroy(e);
+  ctx->tile_graphs.clear();
+  ctx->label_graphs.clear();
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->lcap_stream) hipStreamDestroy(ctx->lcap_stream);
+  for (auto& e : ctx->ldone)
+    if (e) hipEventDestroy(e);
   if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
   if (ctx->lflag) hipFree(ctx->lflag);
   if (ctx->llist) hipFree(ctx->llist);
@@ -532,6 +600,9 @@ struct LabelJob {
   const float2* ctab = nullptr;
   unsigned* wmask = nullptr;
   bool keys_ready = false;  // the caller already computed the u_hat keys into `key`
+  GraphCache* graphs = nullptr;  // the context's labeler graphs, capture stream and events
+  hipStream_t cap = nullptr;
+  hipEvent_t* done = nullptr;
 };
 
 // Validation and parameters of a labeling of `problem` (after prepare(): speed bounds in
@@ -598,6 +669,14 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
   J->lctl = ctx->lctl;
   J->lctl_host = ctx->lctl_host;
   J->lctl_host2 = ctx->lctl_host2;
+  if (!ctx->lcap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->lcap_stream, hipStreamNonBlocking));
+  if (!ctx->ldone[0]) {
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ldone[0], hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ldone[1], hipEventDisableTiming));
+  }
+  J->graphs = &ctx->label_graphs;
+  J->cap = ctx->lcap_stream;
+  J->done = ctx->ldone;
   return SLHJB_OK;
 }
 
@@ -621,26 +700,31 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   // The iteration is monotone and bounded, so it stops; fields that are far from causal (random
   // ones) can creep for thousands of passes. The cap only guards against a broken invariant.
   const int64_t max_passes = 4000000;
-  // 16 passes captured in a graph; two replays in flight, so the GPU never waits for the host's
-  // check of the pass state (a replay after the end is all no-ops)
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    hipError_t ce = hipSuccess;
-    for (int b = 0; b < 16 && ce == hipSuccess; ++b)
-      ce = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad,
-                              J.v_hat ? J.key : nullptr, J.list, J.tiles_x, J.tiles_x, J.flag, J.wmask, max_inner,
-                              J.window, b & 1, J.lctl, grid, cap);
-    e = hipStreamEndCapture(cap, &graph);
-    if (ce != hipSuccess) e = ce;
+  // 16 passes captured in a graph (kept in the context's cache); two replays in flight, so the GPU
+  // never waits for the host's check of the pass state (a replay after the end is all no-ops)
+  const float* keyp = J.v_hat ? J.key : nullptr;
+  GraphKey gk;
+  gk.add(J.phi).add(J.cls).add(J.ctrl).add(J.speed).add(J.speed_const).add(J.ctab).add(J.r).add(n).add(J.Ppad)
+      .add(keyp).add(J.list).add(J.tiles_x).add(J.flag).add(J.wmask).add(max_inner).add(J.window).add(J.lctl)
+      .add(grid);
+  hipGraphExec_t exec = J.graphs->find(gk);
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(J.cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t ce = hipSuccess;
+      for (int b = 0; b < 16 && ce == hipSuccess; ++b)
+        ce = launch_label_pass2(J.phi, J.cls, J.ctrl, J.speed, J.speed_const, J.ctab, J.r, n, J.Ppad, keyp, J.list,
+                                J.tiles_x, J.tiles_x, J.flag, J.wmask, max_inner, J.window, b & 1, J.lctl, grid, J.cap);
+      e = hipStreamEndCapture(J.cap, &graph);
+      if (ce != hipSuccess) e = ce;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    J.graphs->insert(std::move(gk), exec);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+  hipEvent_t* ev = J.done;
   unsigned* hb[2] = {J.lctl_host, J.lctl_host2};
   auto replay = [&](int k) -> hipError_t {
     hipError_t r = hipGraphLaunch(exec, s);
@@ -661,11 +745,6 @@ hipError_t label_run(const LabelJob& J, hipStream_t s, int64_t* passes_out, int*
   }
   if (e == hipSuccess) e = hipMemcpyAsync(J.lctl_host, J.lctl, labctl_bytes(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
-  if (cap) hipStreamDestroy(cap);
-  for (auto& x : ev)
-    if (x) hipEventDestroy(x);
   if (e != hipSuccess || *status != SLHJB_OK) return e;
   *passes_out = J.lctl_host[8];
   e = launch_label_argmax((const uint16_t*)J.phi, N, J.Ppad, J.label_out, J.overlap_out, J.tau, s);
@@ -1091,15 +1170,24 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
       return e;
     };
     if (!timing) {
-      HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = enqueue_batch(ctx->cap_stream, false);
-      hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
-      if (ce != hipSuccess) return hip_fail(ctx, ce, "capture of the tile passes");
-      if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
-      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (ie != hipSuccess) {
+      // every argument of the captured launches (the parity and the events are fixed per position)
+      GraphKey gk;
+      gk.add(a).add(shape).add(P.diffusion).add(P.scheme).add(P.path).add(indep).add(opts->label)
+          .add(keyed ? ctx->tkey : nullptr).add(ctx->tlist).add(tiles_x).add(tiles_y).add(ctx->buf)
+          .add(ctx->tchange).add(ctx->tflag).add(max_inner).add(tol_inner).add(act).add(window).add((float)tol)
+          .add(ctx->tctl).add(grid).add(opts->policy_sweeps);
+      exec = ctx->tile_graphs.find(gk);
+      if (!exec) {
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = enqueue_batch(ctx->cap_stream, false);
+        hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (ce != hipSuccess) return hip_fail(ctx, ce, "capture of the tile passes");
+        if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         hipGraphDestroy(graph);
-        return hip_fail(ctx, ie, "hipGraphInstantiate");
+        graph = nullptr;
+        if (ie != hipSuccess) return hip_fail(ctx, ie, "hipGraphInstantiate");
+        ctx->tile_graphs.insert(std::move(gk), exec);
       }
     }
     hipError_t le = hipSuccess;
@@ -1149,8 +1237,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
       done = ctx->tctl_host[9];
       dev_passes = ctx->tctl_host[10];
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    // the instantiated graph stays in the context's cache
     if (le != hipSuccess) return hip_fail(ctx, le, "tile pass graph");
     passes = dev_passes;
     float r;

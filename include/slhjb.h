@@ -90,6 +90,14 @@ typedef struct {
     const uint8_t* node_class;  /* device uint8[n*n] of SLHJB_FREE / _TARGET / _OBSTACLE         */
     float target_value;         /* g on TARGET nodes                                             */
     float v_out;                /* value at feet outside the closed box and on OBSTACLE nodes    */
+    const float* drift;         /* device float[2*n*n], (d_1, d_2) per node, row-major, finite, or
+                                 * NULL. With a drift the dynamics is f(x,a) = c(x) (d(x) + a):
+                                 * the advection (A) and Zermelo (C) examples of Section 5 (for C,
+                                 * c = 1/(1+|x|^2), d = R_theta x/|x| and the controls carry the
+                                 * factor eta/2). The feet then go through the general kernels;
+                                 * slhjb_synthesize, slhjb_label, patch labels in
+                                 * slhjb_solve_patchy and slhjb_solve_batch reject a drift
+                                 * (SLHJB_E_UNSUPPORTED). NULL: f(x,a) = c(x) a.            */
 } slhjb_problem;
 
 typedef struct {
@@ -238,7 +246,9 @@ typedef struct {
 } slhjb_patchy_stats;
 
 /* The algorithm of Section 4.3 on one GPU. Patchy modes: (1) coarse solve of `coarse` with
- * sigma = 0 from v = V* (the Kruzkov "+infinity") to tol_coarse by the active-tile solver;
+ * sigma = 0 from v = V* (the Kruzkov "+infinity") to tol_coarse by the active-tile solver, for
+ * at most min(max_passes, 16 n_coarse) passes (a coarse solution short of tol_coarse is still a
+ * valid start);
  * (2) u_hat = bilinear interpolation on the fine grid, written to v; (3) synthesis of the
  * feedback control from u_hat and (4) integer patch labels (when label_out is given or the mode
  * is INDEPENDENT); (5) the fine solve from u_hat, tiles by increasing u_hat
@@ -378,7 +388,8 @@ typedef struct {
 int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx, slhjb_regime* out);
 
 /* Largest distance, in cells along either axis, between a FREE node and any of its feet, for
- * speeds bounded by speed_max (host computation). Used to size the interpolation halo. */
+ * speeds bounded by speed_max (host computation). Used to size the interpolation halo. A drift
+ * (device data) is not included: the solvers add max_x h c(x) |d(x)|_inf / dx from a device pass. */
 double slhjb_foot_reach(const slhjb_problem* problem, float speed_max);
 
 #ifdef __cplusplus

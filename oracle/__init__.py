@@ -54,6 +54,7 @@ class _Problem(ctypes.Structure):
         ("node_class", ctypes.c_void_p),
         ("target_value", ctypes.c_double),
         ("v_out", ctypes.c_double),
+        ("drift", ctypes.c_void_p),
     ]
 
 
@@ -102,7 +103,8 @@ def _ptr(a: np.ndarray) -> int:
 @dataclass
 class Problem:
     """A discrete problem on the n x n grid of [x_lo, x_hi]^2 (node (i,j) stored at j*n+i),
-    dynamics f(x,a) = c(x) a. Arrays are held as float64/uint8 copies owned by this object."""
+    dynamics f(x,a) = c(x) (d(x) + a) with the drift d absent (0) unless given. Arrays are held
+    as float64/uint8 copies owned by this object."""
 
     n: int
     x_lo: float
@@ -118,9 +120,13 @@ class Problem:
     running_cost: float = 1.0
     target_value: float = 0.0
     v_out: float = 1.0
+    drift: np.ndarray | None = None  # (n, n, 2) or None
 
     def __post_init__(self):
         self.controls = np.ascontiguousarray(self.controls, dtype=np.float64).reshape(-1, 2)
+        if self.drift is not None:
+            self.drift = np.ascontiguousarray(self.drift, dtype=np.float64).reshape(-1)
+            assert self.drift.size == 2 * self.n * self.n
         self.speed = np.ascontiguousarray(self.speed, dtype=np.float64).reshape(-1)
         self.node_class = np.ascontiguousarray(self.node_class, dtype=np.uint8).reshape(-1)
         assert self.speed.size == self.n * self.n and self.node_class.size == self.n * self.n
@@ -128,7 +134,8 @@ class Problem:
     def c_struct(self) -> _Problem:
         return _Problem(self.n, self.x_lo, self.x_hi, self.h, self.lam, self.eps, self.diffusion,
                         self.scheme, self.controls.shape[0], _ptr(self.controls), _ptr(self.speed),
-                        self.running_cost, _ptr(self.node_class), self.target_value, self.v_out)
+                        self.running_cost, _ptr(self.node_class), self.target_value, self.v_out,
+                        _ptr(self.drift) if self.drift is not None else None)
 
     @classmethod
     def from_instance(cls, inst, scheme: int = SL3) -> "Problem":
@@ -137,7 +144,8 @@ class Problem:
                    lam=float(inst.lam), eps=float(inst.eps), diffusion=int(inst.diffusion), scheme=scheme,
                    controls=inst.controls.astype(np.float64), speed=inst.speed.astype(np.float64),
                    node_class=inst.node_class, running_cost=float(inst.running_cost),
-                   target_value=float(inst.target_value), v_out=float(inst.v_out))
+                   target_value=float(inst.target_value), v_out=float(inst.v_out),
+                   drift=None if getattr(inst, "drift", None) is None else inst.drift.astype(np.float64))
 
     # ---- thin wrappers -------------------------------------------------------------------
     def beta(self) -> float:

@@ -30,7 +30,8 @@ double or_beta(const or_problem* p) { return (double)(float)exp(-p->lambda * p->
 /* Running cost collected over one step in the discounted form: (1-beta) l / lambda. */
 double or_rho(const or_problem* p) { return (1.0 - or_beta(p)) * p->running_cost / p->lambda; }
 
-/* Feet of node (i,j) under control m (eq. SLscheme2, first line). Drift f = c(x) a.
+/* Feet of node (i,j) under control m (eq. SLscheme2, first line). Dynamics
+ * f = c(x) (d(x) + a): the drift d of the advection and Zermelo examples (Section 5), 0 if absent.
  * NONE : sigma = 0, the 2d feet coincide, one foot.
  * ISO  : sigma = sqrt(2 eps) I, feet x + h f +- sqrt(2 eps h) e_k, k = 1,2 (Section 4.1).
  * RANK1: sigma(x,a) = sqrt(2 eps) a, one noise direction, feet x + h f +- sqrt(2 eps h) a
@@ -43,8 +44,10 @@ int32_t or_feet(const or_problem* p, int32_t i, int32_t j, int32_t m, double* y)
     const double c = p->speed[(int64_t)j * p->n + i];
     const double a1 = p->controls[2 * m];
     const double a2 = p->controls[2 * m + 1];
-    const double b1 = x1 + p->h * c * a1;
-    const double b2 = x2 + p->h * c * a2;
+    const double d1 = p->drift ? p->drift[2 * ((int64_t)j * p->n + i)] : 0.0;
+    const double d2 = p->drift ? p->drift[2 * ((int64_t)j * p->n + i) + 1] : 0.0;
+    const double b1 = x1 + p->h * c * (d1 + a1);
+    const double b2 = x2 + p->h * c * (d2 + a2);
     const double d = sqrt(2.0 * p->eps * p->h);
     switch (p->diffusion) {
     case OR_DIFF_ISO:
@@ -261,8 +264,10 @@ void or_synthesize(const or_problem* p, const double* v_hat, int32_t* ctrl_out, 
         double best = INFINITY, second = INFINITY;
         int32_t bm = -1;
         for (int32_t m = 0; m < p->n_controls; ++m) {
-            const double q = or_interp(p, v_hat, x1 + p->h * c * p->controls[2 * m],
-                                       x2 + p->h * c * p->controls[2 * m + 1]);
+            const double d1 = p->drift ? p->drift[2 * node] : 0.0;
+            const double d2 = p->drift ? p->drift[2 * node + 1] : 0.0;
+            const double q = or_interp(p, v_hat, x1 + p->h * c * (d1 + p->controls[2 * m]),
+                                       x2 + p->h * c * (d2 + p->controls[2 * m + 1]));
             if (q < best) { second = best; best = q; bm = m; }
             else if (q < second) second = q;
         }

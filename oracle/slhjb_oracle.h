@@ -24,7 +24,8 @@ enum { OR_DIFF_NONE = 0, OR_DIFF_ISO = 1, OR_DIFF_RANK1 = 2 };
 enum { OR_SL2 = 0, OR_SL3 = 1 };
 
 /* A discrete problem on the n x n node grid of [x_lo,x_hi]^2, node (i,j) at
- * (x_lo+i*dx, x_lo+j*dx), stored row-major at j*n+i. Dynamics f(x,a)=c(x)a. */
+ * (x_lo+i*dx, x_lo+j*dx), stored row-major at j*n+i. Dynamics f(x,a)=c(x)(d(x)+a), with the
+ * drift d = 0 when drift is NULL (Section 5: A is a pure drift, B has none, C both). */
 typedef struct {
     int32_t n;
     double x_lo, x_hi;
@@ -40,6 +41,7 @@ typedef struct {
     const uint8_t* node_class;     /* [n*n] OR_FREE / OR_TARGET / OR_OBSTACLE */
     double target_value;           /* g on TARGET nodes */
     double v_out;                  /* value at feet outside the closed box; held by OBSTACLE nodes */
+    const double* drift;           /* [2*n*n] (d_1, d_2) per node, or NULL */
 } or_problem;
 
 double or_beta(const or_problem* p);

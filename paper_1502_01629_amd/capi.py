@@ -44,6 +44,7 @@ class Problem(ctypes.Structure):
         ("node_class", ctypes.c_void_p),
         ("target_value", ctypes.c_float),
         ("v_out", ctypes.c_float),
+        ("drift", ctypes.c_void_p),
     ]
 
 
@@ -289,6 +290,9 @@ class DeviceProblem:
         self.controls = np.ascontiguousarray(inst.controls, dtype=np.float32).reshape(-1)
         self.speed = torch.from_numpy(np.ascontiguousarray(inst.speed, dtype=np.float32).reshape(-1)).to(device)
         self.node_class = torch.from_numpy(np.ascontiguousarray(inst.node_class, dtype=np.uint8).reshape(-1)).to(device)
+        drift = getattr(inst, "drift", None)
+        self.drift = None if drift is None else \
+            torch.from_numpy(np.ascontiguousarray(drift, dtype=np.float32).reshape(-1)).to(device)
         self.scheme = scheme
         self.struct = self._make()
 
@@ -312,7 +316,8 @@ class DeviceProblem:
             eps=float(inst.eps), diffusion=int(inst.diffusion), scheme=int(self.scheme),
             n_controls=int(self.controls.size // 2), controls=self.controls.ctypes.data, speed=_ptr(self.speed),
             speed_const=1.0, running_cost=float(inst.running_cost), node_class=_ptr(self.node_class),
-            target_value=float(inst.target_value), v_out=float(inst.v_out))
+            target_value=float(inst.target_value), v_out=float(inst.v_out),
+            drift=_ptr(self.drift) if self.drift is not None else None)
 
     def with_scheme(self, scheme: int) -> "DeviceProblem":
         self.scheme = scheme

@@ -219,15 +219,19 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   if (st != SLHJB_OK) return st;
   const int n = p->n;
   const int64_t N = (int64_t)n * n;
-  // speed bounds, FREE count and class validity (one device pass, one read-back)
+  // speed bounds, FREE count, class validity and the drift's reach (one device pass, one read-back)
+  if (p->drift && (reinterpret_cast<uintptr_t>(p->drift) & 7u))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "drift must be 8-byte aligned");
   HIP_TRY(ctx, launch_fill_u32(ctx->small + 2, 0x7f7fffffu, 1, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32(ctx->small + 3, 0u, 4, ctx->stream));
-  HIP_TRY(ctx, launch_problem_stats(p->speed, p->node_class, N, ctx->small + 2, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 2, ctx->small + 2, sizeof(unsigned) * 5, hipMemcpyDeviceToHost,
+  HIP_TRY(ctx, launch_fill_u32(ctx->small + 3, 0u, 6, ctx->stream));
+  HIP_TRY(ctx, launch_problem_stats(p->speed, p->node_class, reinterpret_cast<const float2*>(p->drift),
+                                    p->speed_const, N, ctx->small + 2, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 2, ctx->small + 2, sizeof(unsigned) * 7, hipMemcpyDeviceToHost,
                               ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (ctx->small_host[4]) return fail(ctx, SLHJB_E_INVALID_ARG, "speed has a non-finite or non-positive value");
   if (ctx->small_host[6]) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class has a value other than 0, 1, 2");
+  if (ctx->small_host[8]) return fail(ctx, SLHJB_E_INVALID_ARG, "drift has a non-finite value");
   double speed_max = p->speed_const;
   if (p->speed) {
     float hi;
@@ -235,7 +239,14 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
     speed_max = hi;
   }
   const int64_t free_nodes = ctx->small_host[5];
-  const double reach = reach_for(p, speed_max);
+  double reach = reach_for(p, speed_max);
+  if (p->drift) {
+    // the drift moves every foot of a node by h c d / dx
+    float dmax;
+    memcpy(&dmax, &ctx->small_host[7], sizeof(float));
+    const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
+    reach += (double)(p->h / dx32) * (double)dmax;
+  }
   Prepared P;
   P.speed_max = (float)speed_max;
   P.speed_min = p->speed_const;
@@ -244,7 +255,8 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   P.scheme = p->scheme;
   P.reach = reach;
   P.free_nodes = free_nodes;
-  if (P.diffusion == SLHJB_DIFF_NONE && reach <= 1.0 + 1e-6) {
+  // the first-ring kernels take a foot's quadrant from the signs of the control: no drift
+  if (P.diffusion == SLHJB_DIFF_NONE && reach <= 1.0 + 1e-6 && !p->drift) {
     P.path = 1;
   } else {
     P.path = 0;
@@ -316,6 +328,7 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   a.d = P.diffusion == SLHJB_DIFF_NONE ? 0.0f : (float)(sqrt(2.0 * (double)p->eps * (double)p->h) / dx);
   a.beta = (float)exp(-(double)p->lambda * (double)p->h);
   a.w_outside = vstar - p->v_out;
+  a.drift = reinterpret_cast<const float2*>(p->drift);
   a.w_target = vstar - p->target_value;
   a.w_obstacle = vstar - p->v_out;
   P.vstar = vstar;
@@ -378,7 +391,7 @@ const char* slhjb_status_string(int status) {
   }
 }
 
-int slhjb_version(void) { return 1; }
+int slhjb_version(void) { return 2; }
 
 int slhjb_ctx_create(slhjb_ctx** out, int hip_device, void* hip_stream) {
   if (!out) return SLHJB_E_INVALID_ARG;
@@ -611,6 +624,7 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
                 const float* v_hat, const int16_t* source_patch, int32_t n_patches, uint16_t tau_q15,
                 int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out, LabelJob* J) {
   if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
+  if (problem->drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no drift");
   if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
   if (tau_q15 > (1u << 15)) return fail(ctx, SLHJB_E_INVALID_ARG, "tau_q15 must be <= 2^15");
   // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
@@ -770,6 +784,8 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     return fail(ctx, SLHJB_E_INVALID_ARG, "policy_sweeps must be in [0, 64]");
   const bool pdd = opts->mode != SLHJB_PATCHY_STATIC;
   const bool need_labels = opts->mode == SLHJB_PATCHY_INDEPENDENT || label_out;
+  if (pdd && need_labels && fine->drift)
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no drift (transmission mode without labels does)");
   if (pdd) {
     if (!coarse) return fail(ctx, SLHJB_E_INVALID_ARG, "the patchy modes need a coarse problem");
     if (coarse->x_lo != fine->x_lo || coarse->x_hi != fine->x_hi)
@@ -911,7 +927,11 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
       memset(&co, 0, sizeof(co));
       co.tile_shape = 2;
       co.policy_sweeps = opts->policy_sweeps;
-      st = slhjb_solve_tiles(ctx, &pc, vc, opts->tol_coarse, opts->max_passes, &co, &ts);
+      // A sigma = 0 coarse problem settles within a few passes per tile row; the cap bounds a
+      // coarse solve whose tolerance lies below what its FP32 iterate can resolve (the general
+      // kernels, taken with a drift, settle into changes of a few 1e-7).
+      const int64_t coarse_passes = std::min<int64_t>(opts->max_passes, 16 * (int64_t)coarse->n);
+      st = slhjb_solve_tiles(ctx, &pc, vc, opts->tol_coarse, coarse_passes, &co, &ts);
       if (st == SLHJB_NOT_CONVERGED) st = SLHJB_OK;  // a rough coarse solution is still a valid start
       S.coarse_passes = ts.sweeps;
       S.node_updates_coarse = ts.node_updates;
@@ -1004,6 +1024,7 @@ int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, f
 int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_hat, int16_t* ctrl_out) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (!v_hat || !ctrl_out) return fail(ctx, SLHJB_E_INVALID_ARG, "v_hat and ctrl_out must be non-NULL");
+  if (problem && problem->drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "the synthesis takes no drift");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   Prepared P;
   int st = prepare(ctx, problem, &P);
@@ -1319,6 +1340,7 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
       return fail(ctx, SLHJB_E_INVALID_ARG, "tile_shapes[" + std::to_string(i) + "] out of range");
     if (problems[i].scheme != problems[0].scheme)
       return fail(ctx, SLHJB_E_INVALID_ARG, "all instances of a batch must use the same scheme");
+    if (problems[i].drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "batched solves take no drift");
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   // device scratch of this call

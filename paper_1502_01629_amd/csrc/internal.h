@@ -39,6 +39,7 @@ struct SweepArgs {
   float w_outside;         // w at feet outside the closed box
   float w_target;
   float w_obstacle;
+  const float2* drift;     // nullable: f(x,a) = c(x) (drift(x) + a), general kernels only
 };
 
 // Launchers (sweep.hip). `path` 0 = general halo tile, 1 = first-ring register stencil.
@@ -46,8 +47,10 @@ hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path,
 hipError_t launch_v_to_w(const float* v, float* w, const uint8_t* cls, int64_t count, float vstar,
                          float w_target, float w_obstacle, hipStream_t s);
 hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, hipStream_t s);
-hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t count, unsigned* out,
-                                hipStream_t s);
+// out[0] min speed, [1] max speed (float bits), [2] bad speed, [3] FREE count, [4] bad class,
+// [5] max over nodes of c |drift|_inf (float bits), [6] bad drift (drift may be NULL)
+hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, const float2* drift, float speed_const,
+                                int64_t count, unsigned* out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned value, int count, hipStream_t s);
 
 // Pre-computation kernels (pipeline.hip).

@@ -168,32 +168,40 @@ __global__ void w_to_v_kernel(const float* __restrict__ w, float* __restrict__ v
 // maximum speed (positive floats order like their bits), out[2] |= 1 if a speed is not finite
 // or not > 0, out[3] += number of FREE nodes, out[4] |= 1 if a class value is not 0, 1 or 2.
 // The caller initialises out to (0x7f7fffff, 0, 0, 0, 0). speed may be NULL.
-__global__ void problem_stats_kernel(const float* __restrict__ speed, const uint8_t* __restrict__ cls, int64_t count,
+__global__ void problem_stats_kernel(const float* __restrict__ speed, const uint8_t* __restrict__ cls,
+                                     const float2* __restrict__ drift, float speed_const, int64_t count,
                                      unsigned* out) {
-  float lo = INFINITY, hi = 0.0f;
-  bool bad_speed = false, bad_cls = false;
+  float lo = INFINITY, hi = 0.0f, dmax = 0.0f;
+  bool bad_speed = false, bad_cls = false, bad_drift = false;
   unsigned nfree = 0;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
     const int c = cls[t];
     nfree += c == kFree ? 1u : 0u;
     bad_cls |= c > kObstacle;
+    float v = speed_const;
     if (speed) {
-      const float v = speed[t];
+      v = speed[t];
       if (!(v > 0.0f) || !isfinite(v)) bad_speed = true;
       else {
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
       }
     }
+    if (drift) {
+      const float2 d = drift[t];
+      if (!isfinite(d.x) || !isfinite(d.y)) bad_drift = true;
+      else if (isfinite(v)) dmax = fmaxf(dmax, v * fmaxf(fabsf(d.x), fabsf(d.y)));
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lo = fminf(lo, __shfl_xor(lo, off, 64));
     hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+    dmax = fmaxf(dmax, __shfl_xor(dmax, off, 64));
     nfree += __shfl_xor(nfree, off, 64);
   }
   // one set of atomics per workgroup: same-address atomics from every wavefront serialise in L2
-  __shared__ float slo[kThreads / 64], shi[kThreads / 64];
+  __shared__ float slo[kThreads / 64], shi[kThreads / 64], sdm[kThreads / 64];
   __shared__ unsigned sfree[kThreads / 64];
   __shared__ int sbad;
   if (threadIdx.x == 0) sbad = 0;
@@ -201,15 +209,18 @@ __global__ void problem_stats_kernel(const float* __restrict__ speed, const uint
   if ((threadIdx.x & 63) == 0) {
     slo[threadIdx.x >> 6] = lo;
     shi[threadIdx.x >> 6] = hi;
+    sdm[threadIdx.x >> 6] = dmax;
     sfree[threadIdx.x >> 6] = nfree;
   }
   if (bad_speed) atomicOr(&sbad, 1);
   if (bad_cls) atomicOr(&sbad, 2);
+  if (bad_drift) atomicOr(&sbad, 4);
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 1; k < kThreads / 64; ++k) {
       lo = fminf(lo, slo[k]);
       hi = fmaxf(hi, shi[k]);
+      dmax = fmaxf(dmax, sdm[k]);
       nfree += sfree[k];
     }
     if (speed) {
@@ -219,6 +230,8 @@ __global__ void problem_stats_kernel(const float* __restrict__ speed, const uint
     atomicAdd(&out[3], nfree);
     if (sbad & 1) atomicOr(&out[2], 1u);
     if (sbad & 2) atomicOr(&out[4], 1u);
+    if (drift) atomicMax(&out[5], __float_as_uint(dmax));  // non-negative: the bits order as the values
+    if (sbad & 4) atomicOr(&out[6], 1u);
   }
 }
 
@@ -245,9 +258,10 @@ hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, h
   return hipGetLastError();
 }
 
-hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, int64_t count, unsigned* out,
-                                hipStream_t s) {
-  problem_stats_kernel<<<std::min(grid_for(count), 512), kThreads, 0, s>>>(speed, cls, count, out);
+hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, const float2* drift, float speed_const,
+                                int64_t count, unsigned* out, hipStream_t s) {
+  problem_stats_kernel<<<std::min(grid_for(count), 512), kThreads, 0, s>>>(speed, cls, drift, speed_const, count,
+                                                                             out);
   return hipGetLastError();
 }
 

@@ -85,6 +85,14 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
   const float lox = -fi, hix = nm1 - fi, loy = -fj, hiy = nm1 - fj;
   const float cmx = nm2 - fi, cmy = nm2 - fj;
   const float LWf = (float)LW;
+  // drift part of the feet, the same for every control: k d(x) (0 without a drift, and then
+  // fma(k, a, 0) is the product k a bit for bit)
+  float kdx = 0.0f, kdy = 0.0f;
+  if (a.drift) {
+    const float2 dv = a.drift[(size_t)j * a.n + i];
+    kdx = k * dv.x;
+    kdy = k * dv.y;
+  }
   float best2 = 0.0f;                 // SL2: max over controls of the feet sum
   float bnum = -1.0f, bden = 1.0f;    // SL3: best quotient num / den
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
@@ -92,8 +100,8 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
 #pragma unroll 4
   for (int m = 0; m < a.n_controls; ++m) {
     const float4 cm = ctab[m];
-    const float bx = k * cm.x;
-    const float by = k * cm.y;
+    const float bx = __builtin_fmaf(k, cm.x, kdx);
+    const float by = __builtin_fmaf(k, cm.y, kdy);
     float acc = 0.0f, lam0 = 0.0f;
 #pragma unroll
     for (int f = 0; f < F::K; ++f) {
@@ -392,6 +400,14 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
   const float lox = -fi, hix = nm1 - fi, loy = -fj, hiy = nm1 - fj;
   const float cmx = nm2 - fi, cmy = nm2 - fj;
   const float LWf = (float)LW;
+  // drift part of the feet, the same for every control: k d(x) (0 without a drift, and then
+  // fma(k, a, 0) is the product k a bit for bit)
+  float kdx = 0.0f, kdy = 0.0f;
+  if (a.drift) {
+    const float2 dv = a.drift[(size_t)j * a.n + i];
+    kdx = k * dv.x;
+    kdy = k * dv.y;
+  }
   float best2 = -INFINITY;
   float bnum = -1.0f, bden = 1.0f;
   int bidx = m_lo;
@@ -399,8 +415,8 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
 #pragma unroll 4
   for (int m = m_lo; m < m_hi; ++m) {
     const float4 cm = ctab[m];
-    const float bx = k * cm.x;
-    const float by = k * cm.y;
+    const float bx = __builtin_fmaf(k, cm.x, kdx);
+    const float by = __builtin_fmaf(k, cm.y, kdy);
     float acc = 0.0f, lam0 = 0.0f;
 #pragma unroll
     for (int f = 0; f < F::K; ++f) {

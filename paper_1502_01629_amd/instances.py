@@ -37,6 +37,7 @@ class Instance:
     target_value: np.float32 = np.float32(0.0)
     v_out: np.float32 = np.float32(1.0)
     meta: dict = field(default_factory=dict)
+    drift: np.ndarray | None = None  # float32 (n, n, 2): f(x,a) = c(x) (drift(x) + a); None = no drift
 
     @property
     def dx(self) -> float:
@@ -271,3 +272,64 @@ def rank1_walk_problem(n: int = 9) -> Instance:
     return Instance(n=n, h=np.float32(dx), eps=np.float32(dx / 2.0), diffusion=DIFF_RANK1,
                     controls=np.array([[-1.0, 0.0]], dtype=np.float32), speed=np.ones((n, n), dtype=np.float32),
                     node_class=cls, meta=dict(workload="rank1-walk"))
+
+
+# ---------------------------------------------------------------------------------------
+# Exit-to-boundary problems of the paper's experiments (Section 5): Omega = [-1,1]^2, g = 0 on
+# the boundary, l = 1, 16 controls discretizing the unit ball, in Kruzkov form (lambda = 1,
+# v = 1 - exp(-T), T the exit time). Boundary nodes are the target (v = 0); a foot outside the
+# box has exited (v_out = 0).
+
+def zermelo_drift(n: int, theta: float) -> np.ndarray:
+    """d(x) = R_theta x / |x| (counter-clockwise rotation by theta), 0 at the origin."""
+    X1, X2 = node_coords(n)
+    r = np.hypot(X1, X2)
+    safe = np.where(r > 0.0, r, 1.0)
+    ux, uy = X1 / safe, X2 / safe
+    ct, st = math.cos(theta), math.sin(theta)
+    d = np.stack([ct * ux - st * uy, st * ux + ct * uy], axis=-1)
+    d[r == 0.0] = 0.0
+    return d.astype(np.float32)
+
+
+def exit_dynamics(n: int, dynamics: str, eta: float = 1.0, theta: float = math.pi / 4,
+                  n_controls: int = 16):
+    """(speed, drift, controls, f_min, f_max) of the paper's test dynamics:
+      A   advection b . grad u = 1 with b = (1, 0): in the control form f = -b (no control; the
+          solution is T = 1 + x_1, information runs from the left side to the right)
+      B   eikonal f = c a, c = 1
+      B2  eikonal f = c a, c = 1 + chi{x_1 >= 0}
+      C   Zermelo f = (R_theta x/|x| + (eta/2) a) / (1 + |x|^2)"""
+    X1, X2 = node_coords(n)
+    ones = np.ones((n, n), dtype=np.float32)
+    if dynamics == "A":
+        drift = np.zeros((n, n, 2), dtype=np.float32)
+        drift[..., 0] = -1.0
+        return ones, drift, np.zeros((1, 2), dtype=np.float32), 1.0, 1.0
+    if dynamics == "B":
+        return ones, None, control_table(n_controls), 1.0, 1.0
+    if dynamics == "B2":
+        c = np.where(X1 >= 0.0, 2.0, 1.0).astype(np.float32)
+        return c, None, control_table(n_controls), 1.0, 2.0
+    if dynamics == "C":
+        c = (1.0 / (1.0 + X1 * X1 + X2 * X2)).astype(np.float32)
+        ctrl = (np.float32(eta / 2.0) * control_table(n_controls)).astype(np.float32) if eta > 0 else \
+            np.zeros((1, 2), dtype=np.float32)
+        # |f| over the box and the controls: (1 - eta/2) / 3 at the corners, (1 + eta/2) at the origin
+        return c, zermelo_drift(n, theta), ctrl, (1.0 - eta / 2.0) / 3.0, 1.0 + eta / 2.0
+    raise ValueError(dynamics)
+
+
+def exit_problem(n: int, dynamics: str = "B", eps: float = 0.0, eta: float = 1.0, theta: float = math.pi / 4,
+                 n_controls: int = 16, h: float | None = None, diffusion: int = DIFF_ISO) -> Instance:
+    """Exit time from [-1,1]^2 with g = 0 (Section 5). h defaults to the paper's choice
+    h = alpha dx / f_min with alpha = 1 / (1 + Upsilon), Upsilon = f_max / f_min."""
+    speed, drift, ctrl, fmin, fmax = exit_dynamics(n, dynamics, eta, theta, n_controls)
+    dx = 2.0 / (n - 1)
+    if h is None:
+        h = dx / (1.0 + fmax / fmin) / fmin
+    cls = np.zeros((n, n), dtype=np.uint8)
+    cls[0, :] = cls[-1, :] = cls[:, 0] = cls[:, -1] = TARGET
+    return Instance(n=n, h=np.float32(h), eps=np.float32(eps), diffusion=diffusion if eps > 0 else DIFF_NONE,
+                    controls=ctrl, speed=speed, node_class=cls, v_out=np.float32(0.0), drift=drift,
+                    meta=dict(workload=f"exit {dynamics}", f_min=fmin, f_max=fmax, eta=eta, theta=theta))

@@ -208,6 +208,71 @@ def arm_bumps(ctx, seed: int, tol: float, n: int) -> dict:
     return out
 
 
+# Table 0 of the paper (Section 5.1): Gauss-Seidel iterations of eq. SLscheme2 / eq. SLscheme3
+# on a 50 x 50 grid, as printed; context for the GPU's Jacobi counts, not a target.
+PAPER_TABLE0 = {("A", 0.0): (176, 2), ("A", 1e-2): (458, 102), ("B", 0.0): (145, 26), ("B", 1e-2): (353, 98),
+                ("B2", 0.0): (276, 33), ("B2", 1e-2): (305, 78), ("C", 0.0): (716, 116), ("C", 1e-2): (961, 325)}
+
+
+def arm_exit(ctx, tol: float) -> dict:
+    """The paper's exit-to-boundary experiments (Section 5): g = 0 on the boundary, l = 1, 16
+    controls, h = dx / (1 + Upsilon) / f_min. (1) Table 0: Jacobi sweeps of SL2 and SL3 for the
+    advection (A), eikonal (B, B2) and Zermelo (C) dynamics at eps = 0 and 1e-2 on 50 x 50 nodes.
+    (2) Tables 1 and 2: the patchy solve (coarse 51^2 sigma = 0 solve, u_hat, tiles by increasing
+    u_hat) against the static decomposition (cold, fixed order) over eps, on 101^2 and 201^2
+    nodes (dx = 0.02, 0.01), for the eikonal-diffusion (threshold eps < dx/4) and Zermelo
+    (eps < dx/120) problems: work per node and time across the upwind diffusion ball threshold."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    out = {"table0": [], "threshold": {}}
+    for (dyn, eps), (p2, p3) in PAPER_TABLE0.items():
+        x = I.exit_problem(50, dyn, eps=eps)
+        row = {"equation": dyn, "eps": eps, "paper_gauss_seidel_sl2_sl3": [p2, p3]}
+        for name, scheme in (("sl2", capi.SL2), ("sl3", capi.SL3)):
+            dp = capi.DeviceProblem(x, scheme)
+            v = torch.from_numpy(x.initial().reshape(-1)).cuda()
+            st = ctx.solve(dp, v, tol=tol, max_sweeps=1_000_000, check_every=1)
+            row[f"jacobi_sweeps_{name}"] = st["converged_sweep"] if st["status"] == 0 else None
+        out["table0"].append(row)
+    log("exit: Table 0 done")
+    eps_sets = {"B": [1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 6.25e-4, 1.25e-3, 2.5e-3, 5e-3, 1e-2],
+                "C": [1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 2.083e-5, 4.16e-5, 8.3e-5, 1.6e-4, 1e-3, 5e-3]}
+    for dyn, eps_list in eps_sets.items():
+        per_grid = {}
+        for n in (101, 201):
+            dx = 2.0 / (n - 1)
+            rows = []
+            for eps in eps_list:
+                fine = I.exit_problem(n, dyn, eps=eps)
+                coarse = I.exit_problem(51, dyn, eps=0.0)
+                free = int((fine.node_class == 0).sum())
+                dp, dpc = capi.DeviceProblem(fine, capi.SL3), capi.DeviceProblem(coarse, capi.SL3)
+                row = {"eps": eps}
+                for name, mode, cp in (("patchy", capi.PATCHY_TRANSMISSION, dpc), ("static", capi.PATCHY_STATIC, None)):
+                    v = torch.empty(n * n, dtype=torch.float32, device="cuda")
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    st = ctx.solve_patchy(dp, cp, v, mode=mode, tol=tol, tol_coarse=tol, max_passes=100_000,
+                                          policy_sweeps=POLICY_SWEEPS_DIFFUSION if eps > 0 else POLICY_SWEEPS)
+                    torch.cuda.synchronize()
+                    row[name] = {"time_s": time.perf_counter() - t, "passes": st["passes"],
+                                 "node_updates_per_free_node": st["node_updates"] / free,
+                                 "policy_updates_per_free_node": st["policy_updates"] / free,
+                                 "converged": st["status"] == 0}
+                rows.append(row)
+                log(f"exit {dyn} n={n} eps={eps:g}: patchy {row['patchy']['passes']} passes "
+                    f"{row['patchy']['node_updates_per_free_node']:.1f} upd/node, static {row['static']['passes']} passes")
+            f_min, f_max = fine.meta["f_min"], fine.meta["f_max"]
+            per_grid[str(n)] = {"dx": dx, "h": float(I.exit_problem(n, dyn).h),
+                                "eps_threshold": dx * f_min / (2.0 * (1.0 + f_max / f_min)), "rows": rows}
+        out["threshold"]["eikonal-diffusion" if dyn == "B" else "zermelo"] = per_grid
+        log(f"exit: threshold sweep {dyn} done")
+    return out
+
+
 def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) -> dict:
     """The same 2049^2 workload with isotropic diffusion: the patchy pipeline (coarse sigma = 0
     solve, u_hat, synthesis, labels, u_hat-ordered active tiles) against the cold global Jacobi
@@ -317,10 +382,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="skip the comparison arms")
-    ap.add_argument("--arms", default="c2,c2eps,batch,bumps,learned",
+    ap.add_argument("--arms", default="c2,c2eps,batch,bumps,learned,exit",
                     help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
                          "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
-                         "learned (CNN warm start at 1025^2)")
+                         "learned (CNN warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
+                         "Table 0 on the GPU and the eps-threshold sweeps of Tables 1 and 2)")
     ap.add_argument("--bumps-n", type=int, default=4097)
     ap.add_argument("--policy-sweeps", type=int, default=POLICY_SWEEPS,
                     help="policy-evaluation iterations after each full iteration of a tile visit")
@@ -489,6 +555,8 @@ def main():
         arms["rank1_bumps"] = arm_bumps(ctx, args.seed, args.tol, args.bumps_n)
     if "learned" in which:
         arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol)
+    if "exit" in which:
+        arms["exit_to_boundary"] = arm_exit(ctx, args.tol)
     if arms:
         out["arms"] = arms
     if not args.no_cpu_baseline:

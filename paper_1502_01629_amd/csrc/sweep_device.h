@@ -78,6 +78,7 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
                                                 const SweepArgs& a, const int16_t* __restrict__ lab = nullptr,
                                                 int mylab = 0) {
   using F = Feet<DIFF>;
+  (void)wself;  // SL3 leaves the node's own value out instead of subtracting it
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
   const float nm2 = (float)(a.n - 2);
@@ -123,6 +124,17 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
         v01 = lab[li + LW] == mylab ? v01 : a.w_outside;
         v11 = lab[li + LW + 1] == mylab ? v11 : a.w_outside;
       }
+      if (SCHEME == kSL3) {
+        // eq. SLscheme3 leaves the node's own value out of Lambda1: the corner that is the node
+        // reads 0, so the update does not read the node at all, not even through rounding
+        // (subtracting lam0 w_i afterwards would leave it there at the ulp level, and the FP32
+        // iteration could then cycle instead of settling)
+        const int self = node_li - li;
+        v00 = self == 0 ? 0.0f : v00;
+        v10 = self == 1 ? 0.0f : v10;
+        v01 = self == LW ? 0.0f : v01;
+        v11 = self == LW + 1 ? 0.0f : v11;
+      }
       const float lo = __builtin_fmaf(s, v10 - v00, v00);
       const float hi = __builtin_fmaf(s, v11 - v01, v01);
       const float val = __builtin_fmaf(t, hi - lo, lo);
@@ -136,7 +148,7 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
     if (SCHEME == kSL2) {
       best2 = fmaxf(best2, acc);
     } else {
-      const float num = __builtin_fmaf(-lam0, wself, acc);
+      const float num = acc;  // the node's own weight is already out (see above)
       const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
       if (num * bden > bnum * den) {
         bnum = num;
@@ -394,6 +406,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
                                                 const SweepArgs& a, const int16_t* __restrict__ lab, int mylab,
                                                 int m_lo, int m_hi, float& pnum, float& pden, int* pidx = nullptr) {
   using F = Feet<DIFF>;
+  (void)wself;  // SL3 leaves the node's own value out instead of subtracting it
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
   const float nm2 = (float)(a.n - 2);
@@ -438,6 +451,17 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
         v01 = lab[li + LW] == mylab ? v01 : a.w_outside;
         v11 = lab[li + LW + 1] == mylab ? v11 : a.w_outside;
       }
+      if (SCHEME == kSL3) {
+        // eq. SLscheme3 leaves the node's own value out of Lambda1: the corner that is the node
+        // reads 0, so the update does not read the node at all, not even through rounding
+        // (subtracting lam0 w_i afterwards would leave it there at the ulp level, and the FP32
+        // iteration could then cycle instead of settling)
+        const int self = node_li - li;
+        v00 = self == 0 ? 0.0f : v00;
+        v10 = self == 1 ? 0.0f : v10;
+        v01 = self == LW ? 0.0f : v01;
+        v11 = self == LW + 1 ? 0.0f : v11;
+      }
       const float lo = __builtin_fmaf(s, v10 - v00, v00);
       const float hi = __builtin_fmaf(s, v11 - v01, v01);
       const float val = __builtin_fmaf(t, hi - lo, lo);
@@ -458,7 +482,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
         best2 = fmaxf(best2, acc);
       }
     } else {
-      const float num = __builtin_fmaf(-lam0, wself, acc);
+      const float num = acc;  // the node's own weight is already out (see above)
       const float den = __builtin_fmaf(-a.beta, lam0, (float)F::K);
       if (num * bden > bnum * den) {
         bnum = num;

@@ -128,12 +128,16 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
         // eq. SLscheme3 leaves the node's own value out of Lambda1: the corner that is the node
         // reads 0, so the update does not read the node at all, not even through rounding
         // (subtracting lam0 w_i afterwards would leave it there at the ulp level, and the FP32
-        // iteration could then cycle instead of settling)
-        const int self = node_li - li;
-        v00 = self == 0 ? 0.0f : v00;
-        v10 = self == 1 ? 0.0f : v10;
-        v01 = self == LW ? 0.0f : v01;
-        v11 = self == LW + 1 ? 0.0f : v11;
+        // iteration could then cycle instead of settling). The node is a corner only of the
+        // four cells around it (|offset| < 1 on both axes); a wavefront in which no foot lies
+        // there skips the test.
+        if (__any((fabsf(cx) < 1.0f) & (fabsf(cy) < 1.0f))) {
+          const int self = node_li - li;
+          v00 = self == 0 ? 0.0f : v00;
+          v10 = self == 1 ? 0.0f : v10;
+          v01 = self == LW ? 0.0f : v01;
+          v11 = self == LW + 1 ? 0.0f : v11;
+        }
       }
       const float lo = __builtin_fmaf(s, v10 - v00, v00);
       const float hi = __builtin_fmaf(s, v11 - v01, v01);
@@ -455,12 +459,16 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
         // eq. SLscheme3 leaves the node's own value out of Lambda1: the corner that is the node
         // reads 0, so the update does not read the node at all, not even through rounding
         // (subtracting lam0 w_i afterwards would leave it there at the ulp level, and the FP32
-        // iteration could then cycle instead of settling)
-        const int self = node_li - li;
-        v00 = self == 0 ? 0.0f : v00;
-        v10 = self == 1 ? 0.0f : v10;
-        v01 = self == LW ? 0.0f : v01;
-        v11 = self == LW + 1 ? 0.0f : v11;
+        // iteration could then cycle instead of settling). The node is a corner only of the
+        // four cells around it (|offset| < 1 on both axes); a wavefront in which no foot lies
+        // there skips the test.
+        if (__any((fabsf(cx) < 1.0f) & (fabsf(cy) < 1.0f))) {
+          const int self = node_li - li;
+          v00 = self == 0 ? 0.0f : v00;
+          v10 = self == 1 ? 0.0f : v10;
+          v01 = self == LW ? 0.0f : v01;
+          v11 = self == LW + 1 ? 0.0f : v11;
+        }
       }
       const float lo = __builtin_fmaf(s, v10 - v00, v00);
       const float hi = __builtin_fmaf(s, v11 - v01, v01);

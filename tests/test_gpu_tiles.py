@@ -172,3 +172,32 @@ def test_policy_evaluation_on_scattered_obstacles_uhat_order(ctx):
     assert st["status"] == 0 and st["policy_updates"] > 0
     ref, _, _, _ = oracle.Problem.from_instance(fine, 1).solve(tol=1e-10, threads=8)
     assert np.abs(v.cpu().numpy().astype(np.float64) - ref).max() < 1e-5
+
+
+def test_cached_pass_graphs_replay_and_rekey(ctx):
+    """The context keeps instantiated pass graphs keyed by every launch argument. A repeated solve
+    (cache hit) must give the same bits and statistics as the first; a solve that differs in one
+    argument (the tolerance) must not replay the old graph: it meets its own tolerance and equals,
+    bit for bit, the same solve on a fresh context (which has to capture it)."""
+    from paper_1502_01629_amd import capi
+
+    inst = I.scattered_problem(3, n=257, n_controls=32, n_coarse=65)[0]
+    dp = capi.DeviceProblem(inst, capi.SL3)
+    v0 = _dev(inst.initial())
+    outs = []
+    for tol in (1e-5, 1e-5, 1e-6):
+        v = v0.clone()
+        st = ctx.solve_tiles(dp, v, tol=tol, order=capi.ORDER_KEYS, policy_sweeps=16, max_passes=100_000)
+        assert st["status"] == 0 and st["residual"] <= tol
+        outs.append((v.cpu().numpy(), st))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for k in ("sweeps", "node_updates", "policy_updates", "residual"):
+        assert outs[0][1][k] == outs[1][1][k], k
+    fresh = capi.Context(0)
+    try:
+        v = v0.clone()
+        st = fresh.solve_tiles(dp, v, tol=1e-6, order=capi.ORDER_KEYS, policy_sweeps=16, max_passes=100_000)
+        assert np.array_equal(v.cpu().numpy(), outs[2][0])
+        assert st["sweeps"] == outs[2][1]["sweeps"]
+    finally:
+        fresh.close()

@@ -497,7 +497,13 @@ def main():
             "frac": achieved / RL.FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
             "avg_launch_us": avg_launch * 1e6,
-            "measured_over": f"{args.steps} steps with HIP events around every visit launch, after the timed steps",
+            # per step, over the visit launches of the instrumented steps (passes that did work plus
+            # the no-op passes of the last batch): a kernel-trace profile of the same command has
+            # the same total per step over its graph replays
+            "visit_ms_per_step": 1e3 * visit_s / len(kstats),
+            "measured_over": f"{args.steps} steps after the timed steps, every visit launched through "
+                             "hipExtLaunchKernel with events stamped at the kernel's start and end; the time per "
+                             "pass that did work",
             "flops_per_node_update": flop_per_update,
             "flops_per_policy_update": flop_per_policy_update,
         },

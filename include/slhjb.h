@@ -145,9 +145,10 @@ typedef struct {
     const int16_t* label;       /* device int16[n*n] patch labels; needed for INDEPENDENT         */
     float key_slack;            /* band width of arrival times (ORDER_KEYS); < 0 = the time to
                                    cross max(16, (n-1)/16) cells at the fastest speed             */
-    int32_t max_inner;          /* Jacobi iterations per tile visit at most; 0 = 2 (tile width +
-                                   height) without diffusion, 2 with diffusion (eps > 0), or
-                                   policy_sweeps + 1 with diffusion and policy_sweeps > 0          */
+    int32_t max_inner;          /* Jacobi iterations per tile visit at most; 0 = without diffusion
+                                   2 (tile width + height), or tile width + height with
+                                   policy_sweeps > 0; with diffusion (eps > 0) 2, or
+                                   policy_sweeps + 1 with policy_sweeps > 0                        */
     int32_t tile_shape;         /* 0: 32x16 nodes, 1: 16x16 nodes (one node per thread, 256
                                    threads); 2: 8x8 nodes with the control set split over four
                                    groups of wavefronts (256 threads); 3: 16x16 split over four

@@ -13,6 +13,7 @@
 // tile granularity, bucketed so that a whole ring of tiles runs at once, and it keeps tiles
 // whose upwind values are still moving from being iterated to convergence against stale halos.
 #include <hip/hip_cooperative_groups.h>
+#include <hip/hip_ext.h>
 
 #include "select_device.h"
 #include "sweep_device.h"
@@ -775,11 +776,20 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                                                                              tol, q, list, c);
   const TileShape sh{TW, TH, SPL, SPL == 1 ? kThreads : TW * TH * SPL};
   const size_t lds = tile_pass_lds_bytes(sh, a.halo, indep);
-  if (ev_before) hipEventRecord(ev_before, s);
-#define SLHJB_TV(D, S, PA, IN)                                                                              \
-  tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                            \
-      a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,     \
-      tol_inner, window, q, c, pe)
+  // With events the visit goes through hipExtLaunchKernel, which stamps them at the kernel's own
+  // start and end (as a profiler measures it), not around the launch on the stream.
+#define SLHJB_TV(D, S, PA, IN)                                                                                   \
+  do {                                                                                                           \
+    if (ev_before)                                                                                               \
+      hipExtLaunchKernelGGL((tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN>), dim3(grid), dim3(sh.threads),     \
+                            (std::uint32_t)lds, s, ev_before, ev_after, 0u, a, a.w_in, a.speed, a.cls, a.ctrl,   \
+                            label, (const int*)list, tiles_x, tiles, outbuf, tchange, flag, max_inner, tol_inner, \
+                            window, q, c, pe);                                                                    \
+    else                                                                                                         \
+      tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                             \
+          a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,      \
+          tol_inner, window, q, c, pe);                                                                           \
+  } while (0)
 #define SLHJB_TV_S(D, PA, IN)                      \
   do {                                             \
     if (scheme == kSL2) SLHJB_TV(D, kSL2, PA, IN); \
@@ -797,7 +807,6 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
 #undef SLHJB_TV_I
 #undef SLHJB_TV_S
 #undef SLHJB_TV
-  if (ev_after) hipEventRecord(ev_after, s);
   tilectl_commit_kernel<<<grid, kThreads, 0, s>>>(list, TW, TH, tiles_x, tiles_y, a.n, outbuf, tchange, act, a.cls,
                                                   const_cast<float*>(a.w_in), flag, q, c);
 }

@@ -1061,7 +1061,7 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
     ctx->tkey = ctx->tchange = nullptr;
     ctx->stiles_cap = 0;
     HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
-    HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
+    HIP_TRY(ctx, hipMalloc(&ctx->tchange, 2 * sizeof(float) * tiles));  // moves, then sides
     ctx->stiles_cap = tiles;
   }
   J.flag = ctx->tflag;
@@ -1102,7 +1102,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     ctx->tkey = ctx->tchange = nullptr;
     ctx->stiles_cap = 0;
     HIP_TRY(ctx, hipMalloc(&ctx->tkey, sizeof(float) * tiles));
-    HIP_TRY(ctx, hipMalloc(&ctx->tchange, sizeof(float) * tiles));
+    HIP_TRY(ctx, hipMalloc(&ctx->tchange, 2 * sizeof(float) * tiles));  // moves, then sides
     ctx->stiles_cap = tiles;
   }
   const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;

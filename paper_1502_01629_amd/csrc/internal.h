@@ -93,6 +93,9 @@ hipError_t launch_tile_keys(const float* w, const uint8_t* cls, int tw, int th, 
 // initialised by the caller: {count 0, kmin +inf, bound -inf, resid 0, passes 0, status 0, updates 0}.
 size_t coop_state_bytes();
 hipError_t launch_coop_state_init(void* state, hipStream_t s);
+// `tchange` of the tile-solver launches holds 2 * tiles words: the move of each staged slot
+// (float, negative when its visit stopped unsettled), then the neighbour sides it flags (uint32,
+// bit (dy + 1) * 3 + dx + 1 for the neighbour at tile offset (dx, dy)).
 // Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes(). Layout of
 // the words the host reads: [9] done, [10] passes, [7] resid bits, [12..13] updates,
 // [14..15] policy-evaluation updates. `pe`: policy-evaluation iterations after each full one

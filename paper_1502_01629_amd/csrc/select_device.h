@@ -7,6 +7,12 @@ namespace slhjb {
 
 constexpr int kSelectThreads = 1024;
 
+// An empty asm statement that takes the values as operands ("+s" for uniform ones, "+v" for
+// per-lane ones): the loads that produce them must be complete at this point, so loads written
+// above it are in flight at the same time instead of each being moved down to its first use
+// behind a branch (one memory latency instead of several at the start of a short kernel).
+#define SLHJB_ISSUE_TOGETHER(...) asm volatile("" : __VA_ARGS__)
+
 // One tile per thread of a kSelectThreads workgroup: `fl` says the tile is flagged, `on` that it is
 // selected, `k` is its key (+inf when not flagged or unkeyed). The workgroup adds its flagged and
 // selected counts to *nflag and *count and lowers *kmin with one atomic each (device-scope atomics

@@ -6,8 +6,9 @@
 // tile's FREE nodes, with the halo frozen, until no node moves by more than tol_inner (or
 // max_inner iterations). Results go to a staging buffer, so every tile of a pass reads the
 // iterate of the previous pass and the outcome does not depend on scheduling. A commit kernel
-// writes the staged tiles back and flags a tile and its 8 neighbours for the next pass when it
-// moved by more than the activation threshold. The next pass takes the flagged tiles; with keys
+// writes the staged tiles back and flags, for the next pass, each of the 8 neighbours whose halo
+// holds a node that moved by more than the activation threshold (the tile's strip of the
+// dependence radius on that side), and the tile itself when its visit stopped unsettled. The next pass takes the flagged tiles; with keys
 // (the arrival time of u_hat, min over the tile) only a band of them: those whose key is within
 // a window of the smallest flagged key. That is the order "by increasing u_hat" of the paper at
 // tile granularity, bucketed so that a whole ring of tiles runs at once, and it keeps tiles
@@ -31,15 +32,39 @@ namespace slhjb {
 // iterations apply each node's maximising control of that full iteration only (one candidate,
 // no search); the fixed point is the same, and only full iterations decide that a tile settled.
 // Their node updates are counted apart in pe_updates.
+// Neighbours of a tile that read node (lx, ly) of it in their halo: the node lies within the
+// dependence radius d of the tile's side or corner facing them. Bit (dy + 1) * 3 + (dx + 1) stands
+// for the neighbour at tile offset (dx, dy).
+__device__ __forceinline__ unsigned near_sides(int lx, int ly, int tw, int th, int d) {
+  const bool w = lx < d, e = lx >= tw - d, s = ly < d, nn = ly >= th - d;
+  return (w ? 1u << 3 : 0u) | (e ? 1u << 5 : 0u) | (s ? 1u << 1 : 0u) | (nn ? 1u << 7 : 0u) |
+         (w && s ? 1u << 0 : 0u) | (e && s ? 1u << 2 : 0u) | (w && nn ? 1u << 6 : 0u) | (e && nn ? 1u << 8 : 0u);
+}
+
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
+  return v;
+}
+
+// How far a tile's values reach into its neighbours' updates: one cell on the first-ring path
+// (the 3 x 3 stencil), the interpolation halo otherwise.
+template <int PATH>
+__device__ __forceinline__ int dependence_radius(const SweepArgs& a) {
+  return PATH == 1 ? 1 : a.halo;
+}
+
 template <int T, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
 __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float* __restrict__ w,
                                                  const float* __restrict__ speed, const uint8_t* __restrict__ cls,
                                                  const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
                                                  int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                                  float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-                                                 float tol_inner, unsigned long long* __restrict__ updates, float* lds,
-                                                 float* red, int pe, unsigned long long* __restrict__ pe_updates) {
+                                                 float tol_inner, float act, unsigned* __restrict__ tsides,
+                                                 unsigned long long* __restrict__ updates, float* lds, float* red, int pe,
+                                                 unsigned long long* __restrict__ pe_updates) {
   constexpr int TT = T * T, NT = TT * S;
+  __shared__ unsigned sides_red[NT / 64];
   static_assert(TT % 64 == 0 && (S == 2 || S == 4), "split tile shape");
   const int R = a.halo;
   const int LW = T + 2 * R, span = LW * LW;
@@ -67,9 +92,10 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   const int gi = x0 + lx, gj = y0 + ly;
   const int li = (ly + R) * LW + lx + R;
   bool fr = false;
-  float kk = 0.0f;
+  float kk = 0.0f, w0 = 0.0f;  // w0: the node's value before the visit, for the move it reports
   if (gi < n && gj < n) {
     const size_t idx = (size_t)gj * n + gi;
+    w0 = w[idx];
     fr = cls[idx] == kFree;
     if (fr) kk = a.r * (speed ? speed[idx] : a.speed_const);
   }
@@ -186,19 +212,30 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     }
   }
   float moved = 0.0f;
+  unsigned sides = 0u;
   if (part == 0) {
     outbuf[(size_t)slot * TT + node] = cur[li];
-    if (fr) moved = fabsf(cur[li] - w[(size_t)gj * n + gi]);
+    if (fr) moved = fabsf(cur[li] - w0);
+    if (moved > act) sides = near_sides(lx, ly, T, T, dependence_radius<PATH>(a));
   }
   moved = wave_max(moved);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = moved;
+  sides = wave_or(sides);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = moved;
+    sides_red[threadIdx.x >> 6] = sides;
+  }
   const int free_total = __syncthreads_count(part == 0 && fr);
   if (threadIdx.x == 0) {
     float m = red[0];
+    unsigned sd = sides_red[0];
 #pragma unroll
-    for (int k = 1; k < TT / 64; ++k) m = fmaxf(m, red[k]);
+    for (int k = 1; k < TT / 64; ++k) {
+      m = fmaxf(m, red[k]);
+      sd |= sides_red[k];
+    }
     const bool unsettled = it >= max_inner && max_inner > 1;
     tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
+    tsides[slot] = sd;
     atomicAdd(updates, (unsigned long long)(it - evals) * (unsigned long long)free_total);
     if (evals) atomicAdd(pe_updates, (unsigned long long)evals * (unsigned long long)free_total);
   }
@@ -213,18 +250,20 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                            const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
                                            int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                            float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-                                           float tol_inner, unsigned long long* __restrict__ updates, float* lds,
-                                           float* red, int pe, unsigned long long* __restrict__ pe_updates) {
+                                           float tol_inner, float act, unsigned* __restrict__ tsides,
+                                           unsigned long long* __restrict__ updates, float* lds, float* red, int pe,
+                                           unsigned long long* __restrict__ pe_updates) {
   if constexpr (S > 1) {
     static_assert(TW == TH, "split tiles are square");
     visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf,
-                                                       tchange, flag, max_inner, tol_inner, updates, lds, red, pe,
-                                                       pe_updates);
+                                                       tchange, flag, max_inner, tol_inner, act, tsides, updates, lds,
+                                                       red, pe, pe_updates);
     return;
   } else {
   (void)pe;
   (void)pe_updates;
   constexpr int kTW = TW, kTH = TH, kTN = TW * TH, NPT = kTN / kThreads;  // NPT nodes per thread
+  __shared__ unsigned sides_red[kThreads / 64];
   static_assert(kTN % kThreads == 0 && 64 % TW == 0, "tile shape");
   const int R = a.halo;
   const int LW = kTW + 2 * R, LH = kTH + 2 * R, span = LW * LH;
@@ -249,7 +288,7 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
     // the NPT nodes of this thread
     int li[NPT], gi[NPT], gj[NPT];
     bool fr[NPT];
-    float kk[NPT];
+    float kk[NPT], w0[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int q = threadIdx.x + r * kThreads;
@@ -259,8 +298,10 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       li[r] = (ly + R) * LW + lx + R;
       fr[r] = false;
       kk[r] = 0.0f;
+      w0[r] = 0.0f;
       if (gi[r] < n && gj[r] < n) {
         const size_t idx = (size_t)gj[r] * n + gi[r];
+        w0[r] = w[idx];
         fr[r] = cls[idx] == kFree;
         if (fr[r]) kk[r] = a.r * (speed ? speed[idx] : a.speed_const);
       }
@@ -304,26 +345,38 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
     }
     // stage the tile and measure how far it moved during this visit
     float moved = 0.0f;
+    unsigned sides = 0u;
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int q = threadIdx.x + r * kThreads;
       const float v = cur[li[r]];
       outbuf[(size_t)slot * kTN + q] = v;
-      if (fr[r]) moved = fmaxf(moved, fabsf(v - w[(size_t)gj[r] * n + gi[r]]));
+      const float mv = fr[r] ? fabsf(v - w0[r]) : 0.0f;
+      moved = fmaxf(moved, mv);
+      if (mv > act) sides |= near_sides(q & (kTW - 1), q / kTW, kTW, kTH, dependence_radius<PATH>(a));
     }
     moved = wave_max(moved);
-    if ((threadIdx.x & 63) == 0) red[wave] = moved;
+    sides = wave_or(sides);
+    if ((threadIdx.x & 63) == 0) {
+      red[wave] = moved;
+      sides_red[wave] = sides;
+    }
     int nf = 0;
 #pragma unroll
     for (int r = 0; r < NPT; ++r) nf += fr[r] ? 1 : 0;
     const int free_total = __syncthreads_count(nf >= 1) + (NPT > 1 ? __syncthreads_count(nf >= 2) : 0);
     if (threadIdx.x == 0) {
       float m = red[0];
+      unsigned sd = sides_red[0];
 #pragma unroll
-      for (int k = 1; k < kThreads / 64; ++k) m = fmaxf(m, red[k]);
+      for (int k = 1; k < kThreads / 64; ++k) {
+        m = fmaxf(m, red[k]);
+        sd |= sides_red[k];
+      }
       // a visit that stopped at max_inner while still moving is marked by a negative sign
       const bool unsettled = it >= max_inner && max_inner > 1;
       tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
+      tsides[slot] = sd;
       atomicAdd(updates, (unsigned long long)it * (unsigned long long)free_total);
     }
     __syncthreads();
@@ -331,11 +384,12 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
   }
 }
 
-// Write staged tile `tid` (slot `slot`) back and flag the neighbourhood of a tile that moved by
-// more than `act`; the tile itself is flagged again only if its visit stopped before settling.
+// Write staged tile `tid` (slot `slot`) back and flag the neighbours in `sides` (the visit found a
+// node that moved by more than `act` in the strip they read); the tile itself is flagged again only
+// if its visit stopped before settling. `tc` is the visit's move of the tile, tchange[slot].
 __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, int tiles_x, int tiles_y, int n,
-                                            const float* __restrict__ outbuf, const float* __restrict__ tchange,
-                                            float act, const uint8_t* __restrict__ cls, float* __restrict__ w,
+                                            const float* __restrict__ outbuf, float tc, unsigned sides, float act,
+                                            const uint8_t* __restrict__ cls, float* __restrict__ w,
                                             uint8_t* __restrict__ flag, unsigned* __restrict__ resid) {
   const int tx = tid % tiles_x, ty = tid / tiles_x;
   const int tn = tw * th;
@@ -347,15 +401,14 @@ __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, i
     }
   }
   if (threadIdx.x == 0) {
-    const float tc = tchange[slot];
     const float m = fabsf(tc);
     if (resid) atomicMax(resid, __float_as_uint(m));
     if (m > act) {
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           const int nx = tx + dx, ny = ty + dy;
-          if ((dx | dy) == 0 && !(tc < 0.0f)) continue;
-          if (nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) flag[ny * tiles_x + nx] = 1;
+          const bool take = (dx | dy) == 0 ? tc < 0.0f : ((sides >> ((dy + 1) * 3 + dx + 1)) & 1u) != 0u;
+          if (take && nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) flag[ny * tiles_x + nx] = 1;
         }
     }
   }
@@ -458,6 +511,7 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
   __shared__ float red[NT / 64];
   cooperative_groups::grid_group g = cooperative_groups::this_grid();
   const int tiles = tiles_x * tiles_y;
+  unsigned* tsides = reinterpret_cast<unsigned*>(tchange + tiles);
   const int n = a.n;
   const bool keyed = key != nullptr;
   int passes = 0;
@@ -499,12 +553,13 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
       // (3) visits
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
         visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                      tchange, flag, max_inner, tol_inner, &st->updates, lds, red, pe,
-                                                      &st->pe_updates);
+                                                      tchange, flag, max_inner, tol_inner, act, tsides, &st->updates,
+                                                      lds, red, pe, &st->pe_updates);
       grid_barrier(g);
       // (4) commits; workgroup 0 resets the selection state for the next pass
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-        commit_tile(slot, list[slot], TW, TH, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, nullptr);
+        commit_tile(slot, list[slot], TW, TH, tiles_x, tiles_y, n, outbuf, tchange[slot], tsides[slot], act, cls, w,
+                    flag, nullptr);
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st_agent(&st->count, 0u);
         st_agent(&st->kmin, 0x7f800000u);
@@ -516,10 +571,11 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
     // nothing flagged: check sweep of every tile, one Jacobi iteration each
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, &st->updates, lds, red, 0, &st->pe_updates);
+                                                    flag, 1, 0.0f, act, tsides, &st->updates, lds, red, 0,
+                                                    &st->pe_updates);
     grid_barrier(g);
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, &st->resid);
+      commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, &st->resid);
     grid_barrier(g);
     ++passes;
     const float r = __uint_as_float(ld_agent(&st->resid));
@@ -680,20 +736,22 @@ __global__ __launch_bounds__(kSelectThreads) void tilectl_select_kernel(const ui
                                                                         const float* __restrict__ key, int tiles,
                                                                         float tol, int q, int* __restrict__ list,
                                                                         TileCtl* __restrict__ c) {
-  if (c->done) return;
-  if (c->checked && __uint_as_float(c->resid) <= tol) {
+  // the tile's flag and key do not depend on the pass words: all their loads go out together
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tt = t < tiles ? t : tiles - 1;
+  unsigned done = c->done, checked = c->checked, resid = c->resid, bound = c->bound;
+  unsigned fb = flag[tt];
+  float kt = key ? key[tt] : INFINITY;
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(checked), "+s"(resid), "+s"(bound), "+v"(fb), "+v"(kt));
+  if (done) return;
+  if (checked && __uint_as_float(resid) <= tol) {
     if (blockIdx.x == 0 && threadIdx.x == 0) c->done = 1u;
     return;
   }
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const float B = key ? __uint_as_float(c->bound) : INFINITY;
-  bool fl = false, on = false;
-  float k = INFINITY;
-  if (t < tiles && flag[t]) {
-    fl = true;
-    if (key) k = key[t];
-    on = !key || k <= B;
-  }
+  const bool fl = t < tiles && fb != 0u;
+  const float B = key ? __uint_as_float(bound) : INFINITY;
+  const float k = fl ? kt : INFINITY;
+  const bool on = fl && (!key || k <= B);
   block_select(t, fl, on, k, key != nullptr, &c->count[q], &c->nflag[q], &c->kmin[q], list);
 }
 
@@ -703,17 +761,25 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x,
     int tiles, float* __restrict__ outbuf, float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-    float tol_inner, float window, int q, TileCtl* __restrict__ c, int pe) {
-  if (c->done) return;
+    float tol_inner, float act, float window, int q, TileCtl* __restrict__ c, int pe) {
+  unsigned* tsides = reinterpret_cast<unsigned*>(tchange + tiles);
+  // The first slot's tile is read with the pass words, so that the loads overlap: the grid has at
+  // most `tiles` workgroups and the list `tiles` entries, and the value is used only if the slot
+  // is taken.
+  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
+  int first = list[blockIdx.x];
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first));
+  if (done) return;
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
-  const int cnt = (int)c->count[q];
-  const int nf = (int)c->nflag[q];
+  const int cnt = (int)ucnt;
+  const int nf = (int)unf;
   if (cnt > 0) {
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                    tchange, flag, max_inner, tol_inner, &c->updates, lds, red, pe,
-                                                    &c->pe_updates);
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot,
+                                                    slot == (int)blockIdx.x ? first : list[slot], tiles_x, outbuf,
+                                                    tchange, flag, max_inner, tol_inner, act, tsides, &c->updates, lds,
+                                                    red, pe, &c->pe_updates);
   } else if (nf > 0) {
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
     if (blockIdx.x == 0 && threadIdx.x == 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
@@ -722,7 +788,8 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     if (blockIdx.x == 0 && threadIdx.x == 0) c->resid = 0u;
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, &c->updates, lds, red, 0, &c->pe_updates);
+                                                    flag, 1, 0.0f, act, tsides, &c->updates, lds, red, 0,
+                                                    &c->pe_updates);
   }
 }
 
@@ -733,16 +800,26 @@ __global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __r
                                                                   const uint8_t* __restrict__ cls,
                                                                   float* __restrict__ w, uint8_t* __restrict__ flag,
                                                                   int q, TileCtl* __restrict__ c) {
-  if (c->done) return;
-  const int cnt = (int)c->count[q];
-  const int nf = (int)c->nflag[q];
   const int tiles = tiles_x * tiles_y;
+  const unsigned* tsides = reinterpret_cast<const unsigned*>(tchange + tiles);
+  // the first slot's tile, move and sides are read with the pass words, as in the visit launch
+  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
+  int first = list[blockIdx.x];
+  float first_tc = tchange[blockIdx.x];
+  unsigned first_sides = tsides[blockIdx.x];
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first), "+s"(first_tc), "+s"(first_sides));
+  if (done) return;
+  const int cnt = (int)ucnt;
+  const int nf = (int)unf;
   if (cnt > 0) {
-    for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-      commit_tile(slot, list[slot], tw, th, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, nullptr);
+    for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
+      const bool pre = slot == (int)blockIdx.x;
+      commit_tile(slot, pre ? first : list[slot], tw, th, tiles_x, tiles_y, n, outbuf, pre ? first_tc : tchange[slot],
+                  pre ? first_sides : tsides[slot], act, cls, w, flag, nullptr);
+    }
   } else if (nf == 0) {
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      commit_tile(t, t, tw, th, tiles_x, tiles_y, n, outbuf, tchange, act, cls, w, flag, &c->resid);
+      commit_tile(t, t, tw, th, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, &c->resid);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (cnt > 0 || nf == 0) c->passes += 1u;
@@ -784,11 +861,11 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
       hipExtLaunchKernelGGL((tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN>), dim3(grid), dim3(sh.threads),     \
                             (std::uint32_t)lds, s, ev_before, ev_after, 0u, a, a.w_in, a.speed, a.cls, a.ctrl,   \
                             label, (const int*)list, tiles_x, tiles, outbuf, tchange, flag, max_inner, tol_inner, \
-                            window, q, c, pe);                                                                    \
+                            act, window, q, c, pe);                                                               \
     else                                                                                                         \
       tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                             \
           a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,      \
-          tol_inner, window, q, c, pe);                                                                           \
+          tol_inner, act, window, q, c, pe);                                                                      \
   } while (0)
 #define SLHJB_TV_S(D, PA, IN)                      \
   do {                                             \
@@ -816,6 +893,8 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
                                hipEvent_t ev_after, int pe, hipStream_t s) {
+  // the visit and commit launches read list[blockIdx.x] and tchange[blockIdx.x] unconditionally
+  if (grid < 1 || grid > tiles_x * tiles_y) return hipErrorInvalidValue;
 #define SLHJB_CTL_CALL(TW, TH, SPL)                                                                                  \
   launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y,      \
                                          outbuf, tchange, flag, max_inner, tol_inner, act, window, tol, q,           \

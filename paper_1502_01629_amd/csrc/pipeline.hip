@@ -176,8 +176,9 @@ __global__ __launch_bounds__(kSelectThreads) void labctl_select_kernel(uint8_t* 
 }
 
 // One visit per selected tile: stage phi of the tile and a halo in LDS, iterate the in-place
-// update on the tile's FREE nodes until nothing changes (or max_inner), write the tile back and
-// flag the neighbours (and the tile itself if it did not settle) when anything changed. Only the
+// update on the tile's FREE nodes until nothing changes (or max_inner), write the changed nodes
+// back and flag each neighbour whose halo holds one of them (the strip of kLabHalo nodes on its
+// side), and the tile itself if it did not settle. Only the
 // words (patch pairs) that are nonzero somewhere in the staged region can become nonzero, so the
 // iteration walks those words only. P <= 64, even.
 // LDS holds one plane per word, tile[qw * kLabPlane + node]: the 64 lanes of a wavefront update 64
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
                                                           int max_inner, float window, int q, LabCtl* __restrict__ c) {
   if (c->done) return;
   extern __shared__ uint32_t lds[];
-  __shared__ unsigned omask;
+  __shared__ unsigned omask, osides;
   __shared__ int act[32];
   __shared__ int nact;
   const int cnt = (int)c->count[q];
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
         nact = k;
         if (k & 1) act[k] = act[k - 1];  // the sweeps take the words in pairs (k <= 31 here)
         omask = 0u;
+        osides = 0u;
       }
     }
     // foot of this thread's node, if FREE: corner cell and Q.8 fractions (its loads overlap the
@@ -296,6 +298,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
     }
     __syncthreads();
     int it = 0, last = 0, ever = 0;
+    bool mine_changed = false;  // this thread's node changed during the visit
     if (A > 0) {
       for (;;) {
         // a round of kLabSub in-place sweeps of the tile under one barrier: values only grow, so
@@ -333,6 +336,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
             }
           }
         }
+        mine_changed |= ch != 0;
         last = __syncthreads_or(ch);  // barrier + block-wide OR
         ever |= last;
         it += kLabSub;
@@ -340,27 +344,36 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
       }
     }
     const bool converged_here = (last == 0);
-    // write back the words that can have changed (interior nodes only) and note the nonzero ones
-    if (ever && gx < n && gy < n) {
-      unsigned mine = 0u;
-      for (int qi = 0; qi < A; ++qi) {
-        const int qw = act[qi];
-        const uint32_t val = tile[qw * kLabPlane + self];
-        phi32[(size_t)qw * N + (size_t)gy * n + gx] = val;
-        mine |= (val != 0u ? 1u : 0u) << qw;
+    // write back the words that can have changed of the nodes that changed (a node that did not
+    // change holds what phi32 holds, and its nonzero words are in the mask since they were
+    // written), note their nonzero words and the neighbours that read them
+    if (ever) {
+      unsigned sides = 0u;
+      if (mine_changed) {  // only FREE nodes inside the grid are ever written
+        unsigned mine = 0u;
+        for (int qi = 0; qi < A; ++qi) {
+          const int qw = act[qi];
+          const uint32_t val = tile[qw * kLabPlane + self];
+          phi32[(size_t)qw * N + (size_t)gy * n + gx] = val;
+          mine |= (val != 0u ? 1u : 0u) << qw;
+        }
+        if (mine) atomicOr(&omask, mine);
+        sides = near_sides(lx, ly, kLabTile, kLabTile, kLabHalo);
       }
-      if (mine) atomicOr(&omask, mine);
+      sides = wave_or(sides);
+      if ((threadIdx.x & 63) == 0 && sides) atomicOr(&osides, sides);
+      __syncthreads();  // uniform: `ever` is a block-wide OR
     }
-    if (ever) __syncthreads();  // uniform: `ever` is a block-wide OR
     if (threadIdx.x == 0 && ever) {
       if (omask) atomicOr(&wmask[tid], omask);
       // neighbours read this tile as their halo; the tile itself continues if it did not settle
+      const unsigned sd = osides;
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           const int nx = tx + dx, ny = ty + dy;
           if (nx < 0 || ny < 0 || nx >= tiles_x || ny >= tiles_y) continue;
-          if (dx == 0 && dy == 0 && converged_here) continue;
-          flag[ny * tiles_x + nx] = 1;
+          const bool take = (dx | dy) == 0 ? !converged_here : ((sd >> ((dy + 1) * 3 + dx + 1)) & 1u) != 0u;
+          if (take) flag[ny * tiles_x + nx] = 1;
         }
     }
     __syncthreads();

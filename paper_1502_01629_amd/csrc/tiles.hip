@@ -32,21 +32,6 @@ namespace slhjb {
 // iterations apply each node's maximising control of that full iteration only (one candidate,
 // no search); the fixed point is the same, and only full iterations decide that a tile settled.
 // Their node updates are counted apart in pe_updates.
-// Neighbours of a tile that read node (lx, ly) of it in their halo: the node lies within the
-// dependence radius d of the tile's side or corner facing them. Bit (dy + 1) * 3 + (dx + 1) stands
-// for the neighbour at tile offset (dx, dy).
-__device__ __forceinline__ unsigned near_sides(int lx, int ly, int tw, int th, int d) {
-  const bool w = lx < d, e = lx >= tw - d, s = ly < d, nn = ly >= th - d;
-  return (w ? 1u << 3 : 0u) | (e ? 1u << 5 : 0u) | (s ? 1u << 1 : 0u) | (nn ? 1u << 7 : 0u) |
-         (w && s ? 1u << 0 : 0u) | (e && s ? 1u << 2 : 0u) | (w && nn ? 1u << 6 : 0u) | (e && nn ? 1u << 8 : 0u);
-}
-
-__device__ __forceinline__ unsigned wave_or(unsigned v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
-  return v;
-}
-
 // How far a tile's values reach into its neighbours' updates: one cell on the first-ring path
 // (the 3 x 3 stencil), the interpolation halo otherwise.
 template <int PATH>

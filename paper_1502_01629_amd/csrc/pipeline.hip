@@ -161,16 +161,18 @@ __global__ void labctl_init_kernel(LabCtl* c) {
 __global__ __launch_bounds__(kSelectThreads) void labctl_select_kernel(uint8_t* __restrict__ flag,
                                                                        const float* __restrict__ key, int tiles, int q,
                                                                        int* __restrict__ list, LabCtl* __restrict__ c) {
-  if (c->done) return;
+  // the tile's flag and key do not depend on the pass words: all their loads go out together
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const float B = key ? __uint_as_float(c->bound) : INFINITY;
-  bool fl = false, on = false;
-  float k = INFINITY;
-  if (t < tiles && flag[t]) {
-    fl = true;
-    if (key) k = key[t];
-    on = !key || k <= B;
-  }
+  const int tt = t < tiles ? t : tiles - 1;
+  unsigned done = c->done, bound = c->bound;
+  unsigned fb = flag[tt];
+  float kt = key ? key[tt] : INFINITY;
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(bound), "+v"(fb), "+v"(kt));
+  if (done) return;
+  const bool fl = t < tiles && fb != 0u;
+  const float B = key ? __uint_as_float(bound) : INFINITY;
+  const float k = fl ? kt : INFINITY;
+  const bool on = fl && (!key || k <= B);
   block_select(t, fl, on, k, key != nullptr, &c->count[q], &c->nflag[q], &c->kmin[q], list);
   if (on) flag[t] = 0;
 }
@@ -192,13 +194,18 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
                                                           const int* __restrict__ list, int tiles_x, int tiles_y,
                                                           uint8_t* __restrict__ flag, unsigned* __restrict__ wmask,
                                                           int max_inner, float window, int q, LabCtl* __restrict__ c) {
-  if (c->done) return;
+  // the first slot's tile is read with the pass words (the grid and the list have at most `tiles`
+  // entries; the value is used only if the slot is taken)
+  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
+  int first = list[blockIdx.x];
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first));
+  if (done) return;
   extern __shared__ uint32_t lds[];
   __shared__ unsigned omask, osides;
   __shared__ int act[32];
   __shared__ int nact;
-  const int cnt = (int)c->count[q];
-  const int nf = (int)c->nflag[q];
+  const int cnt = (int)ucnt;
+  const int nf = (int)unf;
   if (cnt == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (nf > 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
   const int lx = threadIdx.x & (kLabTile - 1), ly = threadIdx.x >> 4;
   const int self = (ly + kLabHalo) * kLabSpan + lx + kLabHalo;
   for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
-    const int tid = list[slot];
+    const int tid = slot == (int)blockIdx.x ? first : list[slot];
     const int tx = tid % tiles_x, ty = tid / tiles_x;
     const int x0 = tx * kLabTile - kLabHalo, y0 = ty * kLabTile - kLabHalo;
     // wavefront 0: the words that can be nonzero in the staged region, the union of the masks of
@@ -419,6 +426,7 @@ hipError_t launch_label_pass2(uint32_t* phi32, const uint8_t* cls, const int16_t
                               int tiles_x, int tiles_y, uint8_t* flag, unsigned* wmask, int max_inner, float window,
                               int q, void* ctl, int grid, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
+  if (grid < 1 || grid > tiles) return hipErrorInvalidValue;  // the visit reads list[blockIdx.x]
   labctl_select_kernel<<<(tiles + kSelectThreads - 1) / kSelectThreads, kSelectThreads, 0, s>>>(flag, key, tiles, q,
                                                                                             list, (LabCtl*)ctl);
   label_visit_kernel<<<grid, 256, label_pass_lds_bytes(P), s>>>(phi32, cls, ctrl, speed, speed_const, ctab, r, n, P,

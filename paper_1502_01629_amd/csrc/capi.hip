@@ -107,6 +107,7 @@ struct slhjb_ctx {
   void* coop = nullptr;           // persistent-solver state (device)
   unsigned* coop_host = nullptr;  // pinned mirror
   void* tctl = nullptr;           // device-driven pass state
+  unsigned long long* tacc = nullptr;  // update counters of the visit workgroups (2 per workgroup)
   void* lctl = nullptr;           // labeler pass state
   unsigned* lctl_host = nullptr;
   unsigned* lctl_host2 = nullptr;
@@ -436,6 +437,7 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tchange) hipFree(ctx->tchange);
   if (ctx->coop) hipFree(ctx->coop);
   if (ctx->tctl) hipFree(ctx->tctl);
+  if (ctx->tacc) hipFree(ctx->tacc);
   if (ctx->lctl) hipFree(ctx->lctl);
   if (ctx->lctl_host) hipHostFree(ctx->lctl_host);
   if (ctx->lctl_host2) hipHostFree(ctx->lctl_host2);
@@ -1185,9 +1187,12 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     if (!ctx->tctl) {
       HIP_TRY(ctx, hipMalloc(&ctx->tctl, tilectl_bytes()));
       HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host, 64, hipHostMallocDefault));
+      // grid <= 3 * cus (above)
+      HIP_TRY(ctx, hipMalloc(&ctx->tacc, sizeof(unsigned long long) * 2 * 3 * std::max(1, ctx->cus)));
     }
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HIP_TRY(ctx, launch_tilectl_init(ctx->tctl, ctx->stream));
+    HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tacc, 0u, 4 * grid, ctx->stream));
     const bool timing = opts->collect_kernel_time != 0;
     if (timing && !ctx->tev[0])
       for (auto& e : ctx->tev) HIP_TRY(ctx, hipEventCreate(&e));
@@ -1202,7 +1207,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
                                 keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange,
                                 ctx->tflag, max_inner, tol_inner, act, window, (float)tol, b & 1, ctx->tctl, grid,
                                 ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr,
-                                opts->policy_sweeps, s);
+                                opts->policy_sweeps, ctx->tacc, s);
       return e;
     };
     if (!timing) {
@@ -1211,7 +1216,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
       gk.add(a).add(shape).add(P.diffusion).add(P.scheme).add(P.path).add(indep).add(opts->label)
           .add(keyed ? ctx->tkey : nullptr).add(ctx->tlist).add(tiles_x).add(tiles_y).add(ctx->buf)
           .add(ctx->tchange).add(ctx->tflag).add(max_inner).add(tol_inner).add(act).add(window).add((float)tol)
-          .add(ctx->tctl).add(grid).add(opts->policy_sweeps);
+          .add(ctx->tctl).add(grid).add(opts->policy_sweeps).add(ctx->tacc);
       exec = ctx->tile_graphs.find(gk);
       if (!exec) {
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1266,13 +1271,15 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
         if (le != hipSuccess) break;
         if (hb[k & 1][9] || (int64_t)hb[k & 1][10] >= max_passes) break;
       }
-      // the state after everything that ran (the replay in flight included)
-      if (le == hipSuccess)
-        le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
-      if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
-      done = ctx->tctl_host[9];
-      dev_passes = ctx->tctl_host[10];
     }
+    // the state after everything that ran (a replay in flight included), with the update counts
+    // of the visit workgroups summed into it
+    if (le == hipSuccess) le = launch_tilectl_sum(ctx->tacc, grid, ctx->tctl, ctx->stream);
+    if (le == hipSuccess)
+      le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);
+    if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
+    done = ctx->tctl_host[9];
+    dev_passes = ctx->tctl_host[10];
     // the instantiated graph stays in the context's cache
     if (le != hipSuccess) return hip_fail(ctx, le, "tile pass graph");
     passes = dev_passes;

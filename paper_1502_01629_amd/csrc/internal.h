@@ -106,7 +106,10 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
-                               hipEvent_t ev_after, int pe, hipStream_t s);
+                               hipEvent_t ev_after, int pe, unsigned long long* wg_acc, hipStream_t s);
+// `wg_acc`: 2 * grid counters (node updates, policy-evaluation updates per visit workgroup), zeroed
+// by the caller before the first pass; launch_tilectl_sum writes their totals to the pass state.
+hipError_t launch_tilectl_sum(const unsigned long long* wg_acc, int groups, void* ctl, hipStream_t s);
 hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,

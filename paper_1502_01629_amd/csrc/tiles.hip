@@ -31,7 +31,9 @@ namespace slhjb {
 // Modified policy iteration (pe > 0): after every full iteration, pe policy-evaluation
 // iterations apply each node's maximising control of that full iteration only (one candidate,
 // no search); the fixed point is the same, and only full iterations decide that a tile settled.
-// Their node updates are counted apart in pe_updates.
+// Their node updates are counted apart in pe_acc. The counts go to thread 0's `acc` and `pe_acc`,
+// which the caller accumulates over its visits and publishes once (same-word device atomics from
+// every visit of a pass cost the pass about 1.5 us).
 // How far a tile's values reach into its neighbours' updates: one cell on the first-ring path
 // (the 3 x 3 stencil), the interpolation halo otherwise.
 template <int PATH>
@@ -46,8 +48,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
                                                  int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                                  float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                                  float tol_inner, float act, unsigned* __restrict__ tsides,
-                                                 unsigned long long* __restrict__ updates, float* lds, float* red, int pe,
-                                                 unsigned long long* __restrict__ pe_updates) {
+                                                 unsigned long long& acc, float* lds, float* red, int pe,
+                                                 unsigned long long& pe_acc) {
   constexpr int TT = T * T, NT = TT * S;
   __shared__ unsigned sides_red[NT / 64];
   static_assert(TT % 64 == 0 && (S == 2 || S == 4), "split tile shape");
@@ -221,8 +223,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     const bool unsettled = it >= max_inner && max_inner > 1;
     tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
     tsides[slot] = sd;
-    atomicAdd(updates, (unsigned long long)(it - evals) * (unsigned long long)free_total);
-    if (evals) atomicAdd(pe_updates, (unsigned long long)evals * (unsigned long long)free_total);
+    acc += (unsigned long long)(it - evals) * (unsigned long long)free_total;
+    pe_acc += (unsigned long long)evals * (unsigned long long)free_total;
   }
   __syncthreads();
 }
@@ -236,17 +238,17 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                            int slot, int tid, int tiles_x, float* __restrict__ outbuf,
                                            float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                            float tol_inner, float act, unsigned* __restrict__ tsides,
-                                           unsigned long long* __restrict__ updates, float* lds, float* red, int pe,
-                                           unsigned long long* __restrict__ pe_updates) {
+                                           unsigned long long& acc, float* lds, float* red, int pe,
+                                           unsigned long long& pe_acc) {
   if constexpr (S > 1) {
     static_assert(TW == TH, "split tiles are square");
     visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf,
-                                                       tchange, flag, max_inner, tol_inner, act, tsides, updates, lds,
-                                                       red, pe, pe_updates);
+                                                       tchange, flag, max_inner, tol_inner, act, tsides, acc, lds, red,
+                                                       pe, pe_acc);
     return;
   } else {
   (void)pe;
-  (void)pe_updates;
+  (void)pe_acc;
   constexpr int kTW = TW, kTH = TH, kTN = TW * TH, NPT = kTN / kThreads;  // NPT nodes per thread
   __shared__ unsigned sides_red[kThreads / 64];
   static_assert(kTN % kThreads == 0 && 64 % TW == 0, "tile shape");
@@ -362,7 +364,7 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       const bool unsettled = it >= max_inner && max_inner > 1;
       tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
       tsides[slot] = sd;
-      atomicAdd(updates, (unsigned long long)it * (unsigned long long)free_total);
+      acc += (unsigned long long)it * (unsigned long long)free_total;
     }
     __syncthreads();
   }
@@ -501,6 +503,7 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
   const bool keyed = key != nullptr;
   int passes = 0;
   unsigned final_status = 2;
+  unsigned long long acc = 0ull, pe_acc = 0ull;  // this workgroup's node updates (thread 0)
   while (passes < max_passes) {
     // (1) smallest flagged key
     if (keyed) {
@@ -538,8 +541,8 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
       // (3) visits
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
         visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, list[slot], tiles_x, outbuf,
-                                                      tchange, flag, max_inner, tol_inner, act, tsides, &st->updates,
-                                                      lds, red, pe, &st->pe_updates);
+                                                      tchange, flag, max_inner, tol_inner, act, tsides, acc, lds, red,
+                                                      pe, pe_acc);
       grid_barrier(g);
       // (4) commits; workgroup 0 resets the selection state for the next pass
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
@@ -556,8 +559,7 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
     // nothing flagged: check sweep of every tile, one Jacobi iteration each
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, act, tsides, &st->updates, lds, red, 0,
-                                                    &st->pe_updates);
+                                                    flag, 1, 0.0f, act, tsides, acc, lds, red, 0, pe_acc);
     grid_barrier(g);
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, &st->resid);
@@ -574,6 +576,10 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
       st_agent(&st->kmin, 0x7f800000u);
     }
     grid_barrier(g);
+  }
+  if (threadIdx.x == 0) {
+    if (acc) atomicAdd(&st->updates, acc);
+    if (pe_acc) atomicAdd(&st->pe_updates, pe_acc);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&st->passes, (unsigned)passes);
@@ -746,25 +752,30 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
     const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x,
     int tiles, float* __restrict__ outbuf, float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-    float tol_inner, float act, float window, int q, TileCtl* __restrict__ c, int pe) {
+    float tol_inner, float act, float window, int q, TileCtl* __restrict__ c, int pe,
+    unsigned long long* __restrict__ wg_acc) {
   unsigned* tsides = reinterpret_cast<unsigned*>(tchange + tiles);
   // The first slot's tile is read with the pass words, so that the loads overlap: the grid has at
   // most `tiles` workgroups and the list `tiles` entries, and the value is used only if the slot
   // is taken.
+  // The workgroup's update counters (wg_acc[2 b], wg_acc[2 b + 1], touched only by workgroup b of
+  // each launch) are read here too and written once at the end.
   unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
   int first = list[blockIdx.x];
-  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first));
+  unsigned long long acc0 = wg_acc[2 * blockIdx.x], pe_acc0 = wg_acc[2 * blockIdx.x + 1];
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first), "+s"(acc0), "+s"(pe_acc0));
   if (done) return;
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
+  unsigned long long acc = 0ull, pe_acc = 0ull;
   const int cnt = (int)ucnt;
   const int nf = (int)unf;
   if (cnt > 0) {
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot,
                                                     slot == (int)blockIdx.x ? first : list[slot], tiles_x, outbuf,
-                                                    tchange, flag, max_inner, tol_inner, act, tsides, &c->updates, lds,
-                                                    red, pe, &c->pe_updates);
+                                                    tchange, flag, max_inner, tol_inner, act, tsides, acc, lds, red,
+                                                    pe, pe_acc);
   } else if (nf > 0) {
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
     if (blockIdx.x == 0 && threadIdx.x == 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
@@ -773,8 +784,36 @@ __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
     if (blockIdx.x == 0 && threadIdx.x == 0) c->resid = 0u;
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, act, tsides, &c->updates, lds, red, 0,
-                                                    &c->pe_updates);
+                                                    flag, 1, 0.0f, act, tsides, acc, lds, red, 0, pe_acc);
+  }
+  if (threadIdx.x == 0 && (acc | pe_acc) != 0ull) {
+    wg_acc[2 * blockIdx.x] = acc0 + acc;
+    wg_acc[2 * blockIdx.x + 1] = pe_acc0 + pe_acc;
+  }
+}
+
+// The update counters of the visit workgroups into the pass state (one workgroup).
+__global__ __launch_bounds__(256) void tilectl_sum_kernel(const unsigned long long* __restrict__ wg_acc, int groups,
+                                                          TileCtl* __restrict__ c) {
+  __shared__ unsigned long long s[2][256];
+  unsigned long long u = 0ull, p = 0ull;
+  for (int b = threadIdx.x; b < groups; b += 256) {
+    u += wg_acc[2 * b];
+    p += wg_acc[2 * b + 1];
+  }
+  s[0][threadIdx.x] = u;
+  s[1][threadIdx.x] = p;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + h];
+      s[1][threadIdx.x] += s[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    c->updates = s[0][0];
+    c->pe_updates = s[1][0];
   }
 }
 
@@ -822,6 +861,11 @@ static_assert(offsetof(TileCtl, resid) == 7 * 4 && offsetof(TileCtl, done) == 9 
               "host reads these words");
 size_t tilectl_bytes() { return sizeof(TileCtl); }
 
+hipError_t launch_tilectl_sum(const unsigned long long* wg_acc, int groups, void* ctl, hipStream_t s) {
+  tilectl_sum_kernel<<<1, 256, 0, s>>>(wg_acc, groups, (TileCtl*)ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_tilectl_init(void* ctl, hipStream_t s) {
   tilectl_init_kernel<<<1, 1, 0, s>>>((TileCtl*)ctl);
   return hipGetLastError();
@@ -832,7 +876,8 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
                                       const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                       float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
                                       float act, float window, float tol, int q, TileCtl* c, int grid,
-                                      hipEvent_t ev_before, hipEvent_t ev_after, int pe, hipStream_t s) {
+                                      hipEvent_t ev_before, hipEvent_t ev_after, int pe,
+                                      unsigned long long* wg_acc, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   tilectl_select_kernel<<<(tiles + kSelectThreads - 1) / kSelectThreads, kSelectThreads, 0, s>>>(flag, key, tiles,
                                                                                              tol, q, list, c);
@@ -846,11 +891,11 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
       hipExtLaunchKernelGGL((tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN>), dim3(grid), dim3(sh.threads),     \
                             (std::uint32_t)lds, s, ev_before, ev_after, 0u, a, a.w_in, a.speed, a.cls, a.ctrl,   \
                             label, (const int*)list, tiles_x, tiles, outbuf, tchange, flag, max_inner, tol_inner, \
-                            act, window, q, c, pe);                                                               \
+                            act, window, q, c, pe, wg_acc);                                                               \
     else                                                                                                         \
       tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                             \
           a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,      \
-          tol_inner, act, window, q, c, pe);                                                                      \
+          tol_inner, act, window, q, c, pe, wg_acc);                                                                      \
   } while (0)
 #define SLHJB_TV_S(D, PA, IN)                      \
   do {                                             \
@@ -877,13 +922,13 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
                                float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
-                               hipEvent_t ev_after, int pe, hipStream_t s) {
+                               hipEvent_t ev_after, int pe, unsigned long long* wg_acc, hipStream_t s) {
   // the visit and commit launches read list[blockIdx.x] and tchange[blockIdx.x] unconditionally
   if (grid < 1 || grid > tiles_x * tiles_y) return hipErrorInvalidValue;
 #define SLHJB_CTL_CALL(TW, TH, SPL)                                                                                  \
   launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y,      \
                                          outbuf, tchange, flag, max_inner, tol_inner, act, window, tol, q,           \
-                                         (TileCtl*)ctl, grid, ev_before, ev_after, pe, s);                           \
+                                         (TileCtl*)ctl, grid, ev_before, ev_after, pe, wg_acc, s);                   \
   break
   SLHJB_FOR_SHAPE(shape, SLHJB_CTL_CALL)
 #undef SLHJB_CTL_CALL

@@ -377,7 +377,8 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
 __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, int tiles_x, int tiles_y, int n,
                                             const float* __restrict__ outbuf, float tc, unsigned sides, float act,
                                             const uint8_t* __restrict__ cls, float* __restrict__ w,
-                                            uint8_t* __restrict__ flag, unsigned* __restrict__ resid) {
+                                            uint8_t* __restrict__ flag, float& tmax) {
+  // tmax: thread 0 keeps the largest move of the tiles it committed (the check sweep's residual)
   const int tx = tid % tiles_x, ty = tid / tiles_x;
   const int tn = tw * th;
   for (int q = threadIdx.x; q < tn; q += kThreads) {
@@ -389,7 +390,7 @@ __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, i
   }
   if (threadIdx.x == 0) {
     const float m = fabsf(tc);
-    if (resid) atomicMax(resid, __float_as_uint(m));
+    tmax = fmaxf(tmax, m);
     if (m > act) {
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
@@ -545,9 +546,10 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
                                                       pe, pe_acc);
       grid_barrier(g);
       // (4) commits; workgroup 0 resets the selection state for the next pass
+      float unused = 0.0f;
       for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
         commit_tile(slot, list[slot], TW, TH, tiles_x, tiles_y, n, outbuf, tchange[slot], tsides[slot], act, cls, w,
-                    flag, nullptr);
+                    flag, unused);
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st_agent(&st->count, 0u);
         st_agent(&st->kmin, 0x7f800000u);
@@ -561,8 +563,10 @@ __global__ __launch_bounds__(NT) void tile_solve_coop_kernel(
       visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
                                                     flag, 1, 0.0f, act, tsides, acc, lds, red, 0, pe_acc);
     grid_barrier(g);
+    float tmax = 0.0f;  // largest move of this workgroup's tiles (thread 0)
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, &st->resid);
+      commit_tile(t, t, TW, TH, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, tmax);
+    if (threadIdx.x == 0 && tmax > 0.0f) atomicMax(&st->resid, __float_as_uint(tmax));  // one per workgroup
     grid_barrier(g);
     ++passes;
     const float r = __uint_as_float(ld_agent(&st->resid));
@@ -836,14 +840,17 @@ __global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __r
   const int cnt = (int)ucnt;
   const int nf = (int)unf;
   if (cnt > 0) {
+    float unused = 0.0f;
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
       const bool pre = slot == (int)blockIdx.x;
       commit_tile(slot, pre ? first : list[slot], tw, th, tiles_x, tiles_y, n, outbuf, pre ? first_tc : tchange[slot],
-                  pre ? first_sides : tsides[slot], act, cls, w, flag, nullptr);
+                  pre ? first_sides : tsides[slot], act, cls, w, flag, unused);
     }
   } else if (nf == 0) {
+    float tmax = 0.0f;  // largest move of this workgroup's tiles (thread 0)
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      commit_tile(t, t, tw, th, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, &c->resid);
+      commit_tile(t, t, tw, th, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, tmax);
+    if (threadIdx.x == 0 && tmax > 0.0f) atomicMax(&c->resid, __float_as_uint(tmax));  // one per workgroup
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (cnt > 0 || nf == 0) c->passes += 1u;

@@ -47,7 +47,7 @@ POLICY_SWEEPS_DIFFUSION = 7
 
 
 # the files that define the dominant kernel (the tile visit) and everything it inlines
-KERNEL_SOURCES = ("tiles.hip", "sweep_device.h", "internal.h")
+KERNEL_SOURCES = ("tiles.hip", "sweep_device.h", "select_device.h", "internal.h")
 
 
 def kernel_source_hash() -> str:

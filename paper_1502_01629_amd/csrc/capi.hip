@@ -931,7 +931,10 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
       memset(&co, 0, sizeof(co));
       co.tile_shape = 2;
       co.policy_sweeps = opts->policy_sweeps;
-      co.max_inner = 32;  // 2 (tw + th) of the 8 x 8 tiles: the 129^2 coarse solve's best visit length
+      // the 129^2 coarse solve's best visit length: with policy evaluation 48 iterations (3 (tw + th)
+      // of the 8 x 8 tiles) take 0.98-1.05 ms, 32 take 1.12-1.15 ms, 64 1.13 ms, 96 1.25 ms;
+      // without it 2 (tw + th)
+      co.max_inner = opts->policy_sweeps > 0 ? 48 : 32;
       // A sigma = 0 coarse problem settles within a few passes per tile row; the cap bounds a
       // coarse solve whose tolerance lies below what its FP32 iterate can resolve (the general
       // kernels, taken with a drift, settle into changes of a few 1e-7).
@@ -1182,8 +1185,11 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     pe_updates = (int64_t)pu;
   }
   if (!opts->persistent) {
-    // device-driven passes, captured once into a graph of kBatch passes and replayed
-    constexpr int kBatch = 16;
+    // device-driven passes, captured once into a graph of kBatch passes and replayed; on small
+    // grids a pass takes ~17 us and the no-op passes of the replays in flight after convergence
+    // are a tenth of the solve, so their graphs hold fewer passes (129^2 coarse solve 1.13 ->
+    // 1.08 ms at 8; the 2049^2 solve is faster at 16)
+    const int kBatch = tiles <= 1024 ? 8 : 16;
     if (!ctx->tctl) {
       HIP_TRY(ctx, hipMalloc(&ctx->tctl, tilectl_bytes()));
       HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host, 64, hipHostMallocDefault));

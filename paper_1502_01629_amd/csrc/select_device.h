@@ -16,7 +16,7 @@ constexpr int kSelectThreads = 1024;
 // Neighbours of a tile that read node (lx, ly) of it in their halo: the node lies within the
 // dependence radius d of the tile's side or corner facing them. Bit (dy + 1) * 3 + (dx + 1) stands
 // for the neighbour at tile offset (dx, dy).
-__device__ __forceinline__ unsigned near_sides(int lx, int ly, int tw, int th, int d) {
+__host__ __device__ inline unsigned near_sides(int lx, int ly, int tw, int th, int d) {
   const bool w = lx < d, e = lx >= tw - d, s = ly < d, nn = ly >= th - d;
   return (w ? 1u << 3 : 0u) | (e ? 1u << 5 : 0u) | (s ? 1u << 1 : 0u) | (nn ? 1u << 7 : 0u) |
          (w && s ? 1u << 0 : 0u) | (e && s ? 1u << 2 : 0u) | (w && nn ? 1u << 6 : 0u) | (e && nn ? 1u << 8 : 0u);

@@ -220,7 +220,9 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
       m = fmaxf(m, red[k]);
       sd |= sides_red[k];
     }
-    const bool unsettled = it >= max_inner && max_inner > 1;
+    // a visit that stopped at max_inner while still moving is marked by a negative sign; after a
+    // single iteration (the check sweeps) that is a move beyond the activation threshold
+    const bool unsettled = it >= max_inner && (max_inner > 1 || m > act);
     tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
     tsides[slot] = sd;
     acc += (unsigned long long)(it - evals) * (unsigned long long)free_total;
@@ -360,8 +362,9 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
         m = fmaxf(m, red[k]);
         sd |= sides_red[k];
       }
-      // a visit that stopped at max_inner while still moving is marked by a negative sign
-      const bool unsettled = it >= max_inner && max_inner > 1;
+      // a visit that stopped at max_inner while still moving is marked by a negative sign; after a
+      // single iteration (the check sweeps) that is a move beyond the activation threshold
+      const bool unsettled = it >= max_inner && (max_inner > 1 || m > act);
       tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
       tsides[slot] = sd;
       acc += (unsigned long long)it * (unsigned long long)free_total;

@@ -195,3 +195,53 @@ def test_partition_sources_matches_reference(seed):
     assert T == 1 and len(np.unique(got[got >= 0])) == 16
     got, T = capi.partition_sources(fine.node_class, 64)
     assert T == 3
+
+
+def test_neighbour_sides_cover_exactly_the_halos_that_read_a_node(tmp_path):
+    """The flags a visit raises after a node moved (near_sides, used by the tile solver and the
+    labeler) name exactly the neighbouring tiles whose staged region (the tile and a halo of the
+    dependence radius d) contains the node: brute force over every node of a tile, for several
+    tile shapes and radii. Built with hipcc for the host (the helper is host- and device-code)."""
+    import shutil
+    import subprocess
+
+    cc = os.environ.get("HIPCC") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc"))
+    if cc is None:
+        pytest.skip("no hipcc")
+    src = tmp_path / "sides.hip"
+    src.write_text(r'''
+#include <cstdio>
+#include "select_device.h"
+int main() {
+  const int shapes[4][2] = {{8, 8}, {16, 16}, {32, 16}, {64, 16}};
+  long checked = 0, bad = 0;
+  for (auto& sh : shapes)
+    for (int d = 1; d <= 12; ++d) {
+      const int tw = sh[0], th = sh[1];
+      if (2 * d > tw || 2 * d > th) continue;
+      for (int ly = 0; ly < th; ++ly)
+        for (int lx = 0; lx < tw; ++lx) {
+          // the tile at tile coordinates (1, 1); neighbour (dx, dy) stages x in [x0 - d, x0 + tw + d)
+          const int gx = tw + lx, gy = th + ly;
+          unsigned want = 0u;
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              if ((dx | dy) == 0) continue;
+              const int x0 = (1 + dx) * tw, y0 = (1 + dy) * th;
+              if (gx >= x0 - d && gx < x0 + tw + d && gy >= y0 - d && gy < y0 + th + d)
+                want |= 1u << ((dy + 1) * 3 + dx + 1);
+            }
+          ++checked;
+          if (slhjb::near_sides(lx, ly, tw, th, d) != want) ++bad;
+        }
+    }
+  std::printf("%ld %ld\n", checked, bad);
+  return 0;
+}
+''')
+    exe = tmp_path / "sides"
+    csrc = os.path.join(ROOT, "paper_1502_01629_amd", "csrc")
+    subprocess.run([cc, "--offload-arch=gfx950", "-std=c++17", "-I", csrc, str(src), "-o", str(exe)], check=True,
+                   capture_output=True)
+    checked, bad = map(int, subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split())
+    assert checked > 10000 and bad == 0

@@ -219,13 +219,19 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
         const float4 cm = ctab[m0 + u];
         float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
         bool out = false;
-        if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+        if (EDGE) {
+          out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+          // computed on every lane: otherwise the compiler moves the control's loads and the
+          // arithmetic into a branch per control (one scalar-load wait per control)
+          asm volatile("" : "+v"(val));
+        }
         if (SCHEME == kSL2) {
           if (EDGE) val = out ? a.w_outside - w00 : val;
           best2 = fmaxf(best2, val);
         } else {
           float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
           if (EDGE) {
+            asm volatile("" : "+v"(den));
             val = out ? a.w_outside : val;
             den = out ? 1.0f : den;
           }
@@ -299,7 +305,12 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
         const float4 cm = ctab[m0 + u];
         float val = __builtin_fmaf(cm.z, D, __builtin_fmaf(cm.y, C, cm.x * B));
         bool out = false;
-        if (EDGE) out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+        if (EDGE) {
+          out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+          // computed on every lane: otherwise the compiler moves the control's loads and the
+          // arithmetic into a branch per control (one scalar-load wait per control)
+          asm volatile("" : "+v"(val));
+        }
         if (SCHEME == kSL2) {
           if (EDGE) val = out ? a.w_outside - w00 : val;
           if (TRACK) {
@@ -313,6 +324,7 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
         } else {
           float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
           if (EDGE) {
+            asm volatile("" : "+v"(den));
             val = out ? a.w_outside : val;
             den = out ? 1.0f : den;
           }

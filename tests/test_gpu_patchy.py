@@ -107,7 +107,9 @@ def test_patchy_independent_mode_error_is_measured(ctx, case):
 def test_labels_beside_the_solve_equal_the_sequential_labels(ctx, case):
     """In the transmission mode the labeler runs on its own stream beside the fine solve; its labels
     are bit-identical to those computed before the solve (independent mode), and the solution to the
-    one computed without labels."""
+    one computed without labels. (The pass counts of the two labelings may differ: a visit updates
+    phi in place and its neighbours in the same pass see the new values or the old ones depending on
+    timing; the least fixed point they reach does not.)"""
     from paper_1502_01629_amd import capi
 
     fine, coarse, _ = case
@@ -126,6 +128,6 @@ def test_labels_beside_the_solve_equal_the_sequential_labels(ctx, case):
                           label_out=lab2)
     s3 = ctx.solve_patchy(dp, dpc, v3, mode=0, tol=5e-7, policy_sweeps=4)
     assert s1["status"] == 0 and s2["status"] == 0 and s3["status"] == 0
-    assert s1["label_passes"] == s2["label_passes"] > 0
+    assert s1["label_passes"] > 0 and s2["label_passes"] > 0
     assert torch.equal(lab1, lab2)
     assert torch.equal(v1, v3)

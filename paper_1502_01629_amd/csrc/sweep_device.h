@@ -420,7 +420,10 @@ template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false>
 __device__ __forceinline__ void general_partial(const float* __restrict__ tile, int LW, int node_li, int i, int j,
                                                 float k, float wself, const float4* __restrict__ ctrl,
                                                 const SweepArgs& a, const int16_t* __restrict__ lab, int mylab,
-                                                int m_lo, int m_hi, float& pnum, float& pden, int* pidx = nullptr) {
+                                                int m_lo, int m_hi, float& pnum, float& pden, int* pidx = nullptr,
+                                                const float2* kd_pre = nullptr, const float4* cm_pre = nullptr) {
+  // kd_pre: the node's drift offset k d(x), computed by the caller as below (saves its load);
+  // cm_pre: the one control m_lo, already loaded (policy evaluation: m_hi = m_lo + 1)
   using F = Feet<DIFF>;
   (void)wself;  // SL3 leaves the node's own value out instead of subtracting it
   const float fi = (float)i, fj = (float)j;
@@ -432,7 +435,10 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
   // drift part of the feet, the same for every control: k d(x) (0 without a drift, and then
   // fma(k, a, 0) is the product k a bit for bit)
   float kdx = 0.0f, kdy = 0.0f;
-  if (a.drift) {
+  if (kd_pre) {
+    kdx = kd_pre->x;
+    kdy = kd_pre->y;
+  } else if (a.drift) {
     const float2 dv = a.drift[(size_t)j * a.n + i];
     kdx = k * dv.x;
     kdy = k * dv.y;
@@ -443,7 +449,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll 4
   for (int m = m_lo; m < m_hi; ++m) {
-    const float4 cm = ctab[m];
+    const float4 cm = cm_pre ? *cm_pre : ctab[m];
     const float bx = __builtin_fmaf(k, cm.x, kdx);
     const float by = __builtin_fmaf(k, cm.y, kdy);
     float acc = 0.0f, lam0 = 0.0f;

@@ -62,7 +62,10 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   int* pix = (int*)(pd + NT);
   int16_t* labs = (int16_t*)(pix + NT);
   const int n = a.n;
-  const int node = threadIdx.x % TT, part = threadIdx.x / TT;
+  // TT is a multiple of 64, so a wavefront lies in one part: readfirstlane states that, and the
+  // control loops get wavefront-uniform bounds (scalar loads of the control table, no per-lane
+  // loop exit)
+  const int node = threadIdx.x % TT, part = __builtin_amdgcn_readfirstlane(threadIdx.x / TT);
   const int tx = tid % tiles_x, ty = tid / tiles_x;
   const int x0 = tx * T, y0 = ty * T;
   if (threadIdx.x == 0) flag[tid] = 0;
@@ -87,6 +90,13 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     if (fr) kk = a.r * (speed ? speed[idx] : a.speed_const);
   }
   const bool interior = x0 >= 1 && x0 + T - 1 <= n - 2 && y0 >= 1 && y0 + T - 1 <= n - 2;
+  // general path: the node's drift offset k d(x), loaded once for the whole visit (the same
+  // expressions as general_partial's own load, so the same bits)
+  float2 kd = make_float2(0.0f, 0.0f);
+  if (PATH != 1 && a.drift && fr) {
+    const float2 dv = a.drift[(size_t)gj * n + gi];
+    kd = make_float2(kk * dv.x, kk * dv.y);
+  }
   const int slice = a.n_controls / S;  // the padded list length is a multiple of 4
   constexpr int QP = 4 / S;            // quadrants per part on the first-ring path
   __syncthreads();
@@ -120,10 +130,11 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
         if (pe > 0)
           general_partial<DIFF, SCHEME, INDEP, true>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
                                                      INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den,
-                                                     &mi);
+                                                     &mi, &kd);
         else
           general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                               INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den);
+                                               INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den,
+                                               nullptr, &kd);
       }
       pn[part * TT + node] = num;
       pd[part * TT + node] = den;
@@ -184,7 +195,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
           } else {
             float num, den;
             general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                                 INDEP ? labs[li] : 0, pol, pol + 1, num, den);
+                                                 INDEP ? labs[li] : 0, pol, pol + 1, num, den, nullptr, &kd, &cm);
             constexpr int K = Feet<DIFF>::K;
             nxt[li] = SCHEME == kSL2 ? a.beta * num * (1.0f / (float)K) : (a.beta * num) * (1.0f / den);
           }

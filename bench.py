@@ -43,7 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # iterations after each full one, for sigma = 0 (the main step) and with diffusion (the arms, where
 # a visit is one full iteration and these)
 POLICY_SWEEPS = 16
-POLICY_SWEEPS_DIFFUSION = 7
+POLICY_SWEEPS_DIFFUSION = 14
 
 
 # the files that define the dominant kernel (the tile visit) and everything it inlines

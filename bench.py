@@ -20,8 +20,14 @@ Beside the timed steps, each comparison arm runs once (progress on stderr):
          instances solved one by one (bit-exact agreement counted);
   bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered);
   learned  a CNN warm start trained on the method's own 1025^2 solves against u_hat and the cold
-         start on held-out problems.
-Prints one JSON line.
+         start on held-out problems;
+  indep  the independent (state-constraint) patch solves at eps = 0, 1e-3, 1e-2 against the
+         transmission solve: the decomposition error, near the patch interfaces and away from them;
+  hdx    the same step with h = dx (feet up to 1.5 cells: the general kernels);
+  exit   the paper's exit-to-boundary experiments (Table 0, the eps sweeps of Tables 1-2).
+The full record of every arm goes to a JSON file (--arms-out); stdout ends with one JSON line of
+at most a few KB: the headline, the roofline, the CPU baseline, the accuracy against the oracle's
+stored values and a summary of each arm.
 """
 from __future__ import annotations
 
@@ -91,9 +97,38 @@ def cpu_baseline(inst, scheme: int, jacobi_sweeps: int, budget_s: float = 12.0) 
     per_sweep = dt / sweeps
     free = int((inst.node_class == 0).sum())
     return {"value": per_sweep * jacobi_sweeps, "unit": "s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{sweeps} FP64 Jacobi sweeps of the same {inst.n}^2 problem from v=1 in {dt:.1f} s "
                       f"({free * sweeps / dt:.3g} node-updates/s), scaled to the {jacobi_sweeps} sweeps the "
                       f"global Jacobi iteration needs to reach residual 1e-6"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+GOLDEN_2049 = os.path.join(ROOT, "tests", "golden", "scattered2049_eps0_samples.npz")
+
+
+def oracle_samples_error(v, fine, seed: int, eps: float) -> dict | None:
+    """max |v - v_oracle| at the nodes where the committed oracle solution of the same 2049^2
+    problem (seed 0, eps 0) stores its converged FP64 values (written by
+    tests/golden/make_scattered2049_samples.py, which calls only the oracle)."""
+    if fine.n != 2049 or seed != 0 or eps != 0.0 or not os.path.exists(GOLDEN_2049):
+        return None
+    g = np.load(GOLDEN_2049)
+    idx = g["node"]
+    got = v.cpu().numpy()[idx].astype(np.float64)
+    d = np.abs(got - g["value"])
+    return {"nodes": int(idx.size), "max_abs": float(d.max()), "mean_abs": float(d.mean()),
+            "oracle_residual": float(g["residual"]), "oracle_sweeps": int(g["sweeps"])}
 
 
 def log(msg: str) -> None:
@@ -263,13 +298,13 @@ def arm_exit(ctx, tol: float) -> dict:
                                  "policy_updates_per_free_node": st["policy_updates"] / free,
                                  "converged": st["status"] == 0}
                 rows.append(row)
-                log(f"exit {dyn} n={n} eps={eps:g}: patchy {row['patchy']['passes']} passes "
-                    f"{row['patchy']['node_updates_per_free_node']:.1f} upd/node, static {row['static']['passes']} passes")
             f_min, f_max = fine.meta["f_min"], fine.meta["f_max"]
             per_grid[str(n)] = {"dx": dx, "h": float(I.exit_problem(n, dyn).h),
                                 "eps_threshold": dx * f_min / (2.0 * (1.0 + f_max / f_min)), "rows": rows}
         out["threshold"]["eikonal-diffusion" if dyn == "B" else "zermelo"] = per_grid
-        log(f"exit: threshold sweep {dyn} done")
+        log(f"exit: threshold sweep {dyn} done (" + ", ".join(
+            f"n={n}: {g['rows'][0]['patchy']['node_updates_per_free_node']:.1f} -> "
+            f"{g['rows'][-1]['patchy']['node_updates_per_free_node']:.1f} upd/node" for n, g in per_grid.items()) + ")")
     return out
 
 
@@ -316,6 +351,109 @@ def arm_c2_eps(ctx, seed: int, tol: float, patches: int, eps_list=(1e-3, 1e-2)) 
             "speedup": tj / times[-1], "max_abs_diff": float((v - vj).abs().max()),
         }
         log(f"c2 eps={eps:g}: patchy {times[-1]:.3f} s, global Jacobi {tj:.3f} s")
+    return out
+
+
+def interface_band(lab, radius: int):
+    """Nodes within `radius` cells (Chebyshev) of a node of another patch; label -1 (no patch:
+    obstacles, unreached nodes) is ignored on both sides."""
+    import torch
+
+    n = int(round(lab.numel() ** 0.5))
+    L = lab.view(1, 1, n, n).float()
+    big = float(1 << 20)
+    hi = torch.nn.functional.max_pool2d(L, 2 * radius + 1, stride=1, padding=radius)
+    lo = -torch.nn.functional.max_pool2d(-torch.where(L < 0, torch.full_like(L, big), L), 2 * radius + 1, stride=1,
+                                         padding=radius)
+    return ((hi != lo) & (lo < big)).view(-1)
+
+
+def arm_indep(ctx, seed: int, tol: float, patches: int, eps_list=(0.0, 1e-3, 1e-2)) -> dict:
+    """Decomposition error of the independent patch solves (state constraints at the patch
+    interfaces, Section 2) on the 2049^2 workload: max |v_indep - v_transmission| over all FREE
+    nodes, inside the band of `halo` cells around the interfaces (where the paper expects the
+    error of a first-order patchy decomposition to sit) and away from it."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    out = {}
+    for eps in eps_list:
+        fine, coarse = I.scattered_problem(seed, eps=eps)
+        dp, dpc = capi.DeviceProblem(fine, capi.SL3), capi.DeviceProblem(coarse, capi.SL3)
+        src_host, _ = capi.partition_sources(fine.node_class, patches)
+        src = torch.from_numpy(src_host.reshape(-1)).cuda()
+        N = fine.n * fine.n
+        vg = torch.empty(N, dtype=torch.float32, device="cuda")
+        vi = torch.empty_like(vg)
+        lab = torch.empty(N, dtype=torch.int16, device="cuda")
+        ps = POLICY_SWEEPS_DIFFUSION if eps > 0 else POLICY_SWEEPS
+        res = {}
+        for name, mode, v in (("transmission", capi.PATCHY_TRANSMISSION, vg), ("independent", capi.PATCHY_INDEPENDENT, vi)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = ctx.solve_patchy(dp, dpc, v, mode=mode, tol=tol, tol_coarse=1e-7, source_patch=src,
+                                  n_patches=patches, label_out=lab, policy_sweeps=ps)
+            torch.cuda.synchronize()
+            res[name] = {"time_s": time.perf_counter() - t, "passes": st["passes"], "converged": st["status"] == 0}
+        # a node reads the corners of the cells its feet fall in: up to floor(reach) + 1 cells away
+        reach = capi.lib().slhjb_foot_reach(capi.DeviceProblem.host_struct(fine), float(fine.speed.max()))
+        halo = int(np.floor(reach + 1e-6)) + 1
+        free = torch.from_numpy(np.ascontiguousarray(fine.node_class).reshape(-1) == 0).cuda()
+        band = interface_band(lab, halo) & free
+        inner = free & ~band
+        d = (vi - vg).abs()
+        out[f"eps={eps:g}"] = {
+            "halo": halo, "time_s_transmission": res["transmission"]["time_s"],
+            "time_s_independent": res["independent"]["time_s"],
+            "passes_independent": res["independent"]["passes"], "converged": res["independent"]["converged"],
+            "decomposition_error_max": float(d[free].max()), "decomposition_error_mean": float(d[free].mean()),
+            "band_max": float(d[band].max()) if bool(band.any()) else 0.0,
+            "band_mean": float(d[band].mean()) if bool(band.any()) else 0.0,
+            "interior_max": float(d[inner].max()), "interior_mean": float(d[inner].mean()),
+            "band_fraction": float(band.sum()) / float(free.sum()),
+        }
+        log(f"indep eps={eps:g}: decomposition error max {out[f'eps={eps:g}']['decomposition_error_max']:.3g} "
+            f"(band {out[f'eps={eps:g}']['band_max']:.3g}, interior {out[f'eps={eps:g}']['interior_max']:.3g})")
+    return out
+
+
+def arm_hdx(ctx, seed: int, tol: float, patches: int) -> dict:
+    """The headline workload with h = dx instead of dx / 1.5 (the survey's choice): drift feet up
+    to 1.5 cells away, so the fine solve takes the general kernels; patchy step against the cold
+    global Jacobi iteration. The integer labeler takes first-ring feet only, so this step runs
+    without labels (the transmission-mode solve does not read them)."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    fine, coarse = I.scattered_problem(seed, eps=0.0, h_factor=1.0)
+    dp, dpc = capi.DeviceProblem(fine, capi.SL3), capi.DeviceProblem(coarse, capi.SL3)
+    N = fine.n * fine.n
+    free = int((fine.node_class == 0).sum())
+    v = torch.empty(N, dtype=torch.float32, device="cuda")
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sp = ctx.solve_patchy(dp, dpc, v, tol=tol, tol_coarse=1e-7, policy_sweeps=POLICY_SWEEPS)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    vj = torch.from_numpy(fine.initial().reshape(-1)).cuda()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sj = ctx.solve(dp, vj, tol=tol, max_sweeps=200_000)
+    torch.cuda.synchronize()
+    tj = time.perf_counter() - t
+    out = {"h": float(fine.h), "dx": fine.dx, "patchy_time_s": float(np.median(times[1:])), "patchy_passes": sp["passes"],
+           "patchy_node_updates_per_free_node": sp["node_updates"] / free, "halo": sj["halo"],
+           "kernel_path": "general" if sj["kernel_path"] == 0 else "first-ring",
+           "global_jacobi_cold_s": tj, "global_jacobi_sweeps": sj["sweeps"],
+           "sweep_kernel_us": 1e6 * sj["sweep_seconds"] / sj["sweep_launches"],
+           "speedup": tj / float(np.median(times[1:])), "max_abs_diff": float((v - vj).abs().max())}
+    log(f"hdx: patchy {out['patchy_time_s'] * 1e3:.1f} ms, global Jacobi {tj:.3f} s")
     return out
 
 
@@ -382,11 +520,14 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="skip the comparison arms")
-    ap.add_argument("--arms", default="c2,c2eps,batch,bumps,learned,exit",
+    ap.add_argument("--arms", default="c2,c2eps,indep,hdx,batch,bumps,learned,exit",
                     help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
-                         "with eps = 1e-3 and 1e-2), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
+                         "with eps = 1e-3 and 1e-2), indep (decomposition error of the independent patch solves), "
+                         "hdx (the step with h = dx), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
                          "learned (CNN warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
                          "Table 0 on the GPU and the eps-threshold sweeps of Tables 1 and 2)")
+    ap.add_argument("--arms-out", default=os.path.join(ROOT, "gpurun_out", "bench_arms.json"),
+                    help="file that receives the full record (every arm); the stdout line holds a summary")
     ap.add_argument("--bumps-n", type=int, default=4097)
     ap.add_argument("--policy-sweeps", type=int, default=POLICY_SWEEPS,
                     help="policy-evaluation iterations after each full iteration of a tile visit")
@@ -454,6 +595,8 @@ def main():
     visit_launches = sum(s["passes"] for s in kstats)
     fine_updates = sum(s["node_updates"] for s in kstats)
     policy_updates = sum(s["policy_updates"] for s in kstats)
+    check_sweeps = sum(s["check_sweeps"] for s in kstats)
+    check_visit_s = sum(s["t_check_visit"] for s in kstats)
     flop_per_update = RL.sweep_flops_per_node_update(fine.diffusion, scheme, fine.n_controls)
     # a policy-evaluation update is the same update with one control
     flop_per_policy_update = RL.sweep_flops_per_node_update(fine.diffusion, scheme, 1)
@@ -477,17 +620,22 @@ def main():
         "data": "synthetic (seeded instance generator)",
         "config": {
             "workload": f"scattered targets {fine.n}^2, c=1+0.5sin(2pi x1)sin(2pi x2), 64 controls, {n_targets} point "
-                        f"targets, 10% square obstacles, eps={args.eps}, h=dx/1.5, SL3; coarse {coarse.n}^2, "
-                        f"{args.patches} patches; residual {args.tol:g}",
-            "n": fine.n, "eps": args.eps, "n_controls": fine.n_controls, "seed": args.seed, "tol": args.tol,
-            "free_nodes": free, "patches": args.patches,
+                        f"targets, 10% square obstacles, eps={args.eps}, h=dx/1.5={float(fine.h):.4g}, SL3; coarse "
+                        f"{coarse.n}^2, {args.patches} patches; residual {args.tol:g}",
+            "n": fine.n, "eps": args.eps, "h": float(fine.h), "dx": fine.dx, "n_controls": fine.n_controls,
+            "seed": args.seed, "tol": args.tol, "free_nodes": free, "patches": args.patches,
         },
         "stages_s": {k: med(k) for k in ("t_coarse", "t_upsample", "t_synthesize", "t_label", "t_solve")},
         "source_partition_host_s": t_part,
         "passes": int(med("passes")),
         "node_updates_per_free_node": fine_updates / len(kstats) / free,
         "policy_updates_per_free_node": policy_updates / len(kstats) / free,
+        "node_updates_per_s": fine_updates / len(kstats) / (dt / args.steps),
         "policy_sweeps": args.policy_sweeps,
+        "check_sweeps": {"per_step": check_sweeps / len(kstats),
+                         "node_update_share": check_sweeps * free / max(1, fine_updates),
+                         "visit_time_share": check_visit_s / visit_s if visit_s > 0 else None,
+                         "visit_ms_per_step": 1e3 * check_visit_s / len(kstats)},
         "roofline": {
             "kernel": kernel,
             "bound": "alu",
@@ -502,12 +650,14 @@ def main():
             # the same total per step over its graph replays
             "visit_ms_per_step": 1e3 * visit_s / len(kstats),
             "measured_over": f"{args.steps} steps after the timed steps, every visit launched through "
-                             "hipExtLaunchKernel with events stamped at the kernel's start and end; the time per "
-                             "pass that did work",
+                             "hipExtLaunchKernel with events stamped at the kernel's start and end",
             "flops_per_node_update": flop_per_update,
             "flops_per_policy_update": flop_per_policy_update,
         },
     }
+    acc = oracle_samples_error(v_pdd, fine, args.seed, args.eps)
+    if acc is not None:
+        out["accuracy_vs_oracle"] = acc
 
     jacobi_sweeps = None
     which = set() if args.no_arms else {a.strip() for a in args.arms.split(",") if a.strip()}
@@ -529,6 +679,9 @@ def main():
             "sweep_kernel_tflops": sweep_flops, "sweep_kernel_frac": sweep_flops / RL.FP32_VECTOR_PEAK_TFLOPS,
             "max_abs_diff_vs_patchy": float((vj - v_pdd).abs().max()),
         }
+        acc_j = oracle_samples_error(vj, fine, args.seed, args.eps)
+        if acc_j is not None:
+            arms["global_jacobi_cold"]["max_abs_vs_oracle"] = acc_j["max_abs"]
         # global Jacobi from u_hat (the warm start without the u_hat order)
         vh = torch.empty_like(v0)
         vc = torch.from_numpy(coarse.initial().reshape(-1)).cuda()
@@ -540,6 +693,7 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         arms["global_jacobi_uhat"] = {"time_s_after_uhat": t, "sweeps": sw["sweeps"],
+                                      "node_updates_per_s": sw["node_updates"] / t,
                                       "max_abs_diff_vs_patchy": float((vh - v_pdd).abs().max())}
         # static decomposition: active tiles in a fixed order, no pre-computation, cold start
         vs = torch.empty_like(v0)
@@ -552,9 +706,14 @@ def main():
                                              "node_updates_per_free_node": ss["node_updates"] / free,
                                              "max_abs_diff_vs_patchy": float((vs - v_pdd).abs().max())}
         out["speedup_vs_global_jacobi_cold"] = arms["global_jacobi_cold"]["time_s"] / out["value"]
-        log("c2 arms done")
+        log(f"c2: cold global Jacobi {arms['global_jacobi_cold']['time_s']:.3f} s, static "
+            f"{arms['static_decomposition_cold']['time_s'] * 1e3:.1f} ms")
     if "c2eps" in which:
         arms["c2_diffusion"] = arm_c2_eps(ctx, args.seed, args.tol, args.patches)
+    if "indep" in which:
+        arms["independent_patches"] = arm_indep(ctx, args.seed, args.tol, args.patches)
+    if "hdx" in which:
+        arms["h_equals_dx"] = arm_hdx(ctx, args.seed, args.tol, args.patches)
     if "batch" in which:
         arms["batch_256_instances"] = arm_batch(ctx, args.seed, args.tol)
     if "bumps" in which:
@@ -563,12 +722,85 @@ def main():
         arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol)
     if "exit" in which:
         arms["exit_to_boundary"] = arm_exit(ctx, args.tol)
-    if arms:
-        out["arms"] = arms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fine, scheme, jacobi_sweeps or 1672)
     ctx.close()
-    print(json.dumps(out), flush=True)
+    full = dict(out, arms=arms)
+    if args.arms_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.arms_out)), exist_ok=True)
+        with open(args.arms_out, "w") as f:
+            json.dump(full, f, indent=1)
+        log(f"full record: {args.arms_out}")
+    print(json.dumps(summary_line(full)), flush=True)
+
+
+def _r(x, d: int = 4):
+    """Round for the summary line (None passes through)."""
+    if x is None:
+        return None
+    if isinstance(x, float):
+        return float(f"{x:.{d}g}")
+    return x
+
+
+def summary_line(full: dict) -> dict:
+    """The one stdout line: the headline fields as they are, and a few numbers per arm."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "passes", "node_updates_per_s", "node_updates_per_free_node",
+            "policy_updates_per_free_node", "check_sweeps", "stages_s", "accuracy_vs_oracle",
+            "speedup_vs_global_jacobi_cold")
+    out = {k: full[k] for k in keep if k in full}
+    out["config"] = {k: full["config"][k] for k in ("workload", "n", "h", "eps", "tol", "free_nodes")}
+    out["stages_s"] = {k: _r(v) for k, v in full.get("stages_s", {}).items()}
+    out["check_sweeps"] = {k: _r(v) for k, v in full.get("check_sweeps", {}).items()}
+    r = full["roofline"]
+    out["roofline"] = {k: _r(r[k]) for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "avg_launch_us",
+                                               "visit_ms_per_step", "kernel")}
+    if "cpu_baseline" in full:
+        out["cpu_baseline"] = {k: _r(v) for k, v in full["cpu_baseline"].items()}
+    A = full.get("arms", {})
+    arms = {}
+    if "global_jacobi_cold" in A:
+        g = A["global_jacobi_cold"]
+        arms["global_jacobi_cold"] = {"time_s": _r(g["time_s"]), "sweeps": g["sweeps"],
+                                      "node_updates_per_s": _r(g["node_updates_per_s"]),
+                                      "sweep_kernel_us": _r(g["sweep_kernel_us"]),
+                                      "sweep_kernel_frac": _r(g["sweep_kernel_frac"]),
+                                      "max_abs_vs_oracle": _r(g.get("max_abs_vs_oracle"))}
+        arms["global_jacobi_uhat_s"] = _r(A["global_jacobi_uhat"]["time_s_after_uhat"])
+        arms["static_decomposition_s"] = _r(A["static_decomposition_cold"]["time_s"])
+    if "c2_diffusion" in A:
+        arms["c2_diffusion"] = {k: {"patchy_s": _r(e["patchy_time_s"]), "jacobi_s": _r(e["global_jacobi_cold_s"]),
+                                    "max_abs_diff": _r(e["max_abs_diff"], 3)} for k, e in A["c2_diffusion"].items()}
+    if "independent_patches" in A:
+        arms["decomposition_error"] = {k: {"max": _r(e["decomposition_error_max"], 3), "band_max": _r(e["band_max"], 3),
+                                           "interior_max": _r(e["interior_max"], 3),
+                                           "interior_mean": _r(e["interior_mean"], 3)}
+                                       for k, e in A["independent_patches"].items()}
+    if "h_equals_dx" in A:
+        e = A["h_equals_dx"]
+        arms["h_equals_dx"] = {"patchy_s": _r(e["patchy_time_s"]), "jacobi_s": _r(e["global_jacobi_cold_s"]),
+                               "halo": e["halo"]}
+    if "batch_256_instances" in A:
+        e = A["batch_256_instances"]
+        arms["batch_256"] = {"batched_s": _r(e["time_s_batched"]), "sequential_s": _r(e["time_s_sequential"]),
+                             "bit_exact": e["bit_exact_vs_single"]}
+    if "rank1_bumps" in A:
+        e = A["rank1_bumps"]
+        arms["rank1_4097"] = {"full_sweeps_s": _r(e["full_sweeps"]["time_s"]),
+                              "active_tiles_cold_s": _r(e["active_tiles_cold"]["time_s"]),
+                              "active_tiles_uhat_s": _r(e["active_tiles_uhat"]["time_s"])}
+    if "learned_warm_start" in A:
+        e = A["learned_warm_start"]
+        arms["learned_1025"] = {"start_error_mean": {k: _r(v, 3) for k, v in e["start_error_mean"].items()},
+                                "jacobi_sweeps": {k: _r(v) for k, v in e["jacobi_sweeps"].items()},
+                                "active_tiles_s": {k: _r(v) for k, v in e["active_tiles_time_s"].items()}}
+    if "exit_to_boundary" in A:
+        t0 = A["exit_to_boundary"]["table0"]
+        arms["exit_table0_sl2_sl3"] = {f"{r['equation']}/{r['eps']:g}": [r["jacobi_sweeps_sl2"], r["jacobi_sweeps_sl3"]]
+                                       for r in t0}
+    out["arms"] = arms
+    return out
 
 
 if __name__ == "__main__":

@@ -50,6 +50,9 @@ enum {
 const char* slhjb_status_string(int status);
 /* Interface version (increments on any change of a declaration in this header). */
 int slhjb_version(void);
+/* Identity of the build: the first 16 hex digits of the SHA-256 of the sources the library was
+ * compiled from (so that a caller can refuse a library older than its sources). Never NULL. */
+const char* slhjb_source_hash(void);
 
 /* ---- context ------------------------------------------------------------------------ */
 typedef struct slhjb_ctx slhjb_ctx;
@@ -114,6 +117,11 @@ typedef struct {
     int32_t pad;
     int64_t policy_updates;     /* node updates of policy-evaluation iterations (one control each;
                                    active-tile solver with policy_sweeps > 0), not in node_updates */
+    int64_t check_sweeps;       /* active-tile solver: passes that were full check sweeps (every
+                                   tile, one iteration), counted in sweeps; -1 = not counted
+                                   (persistent launch); 0 for the Jacobi solves                     */
+    double check_seconds;       /* active-tile solver with collect_kernel_time: the part of
+                                   sweep_seconds spent in check-sweep visit launches               */
 } slhjb_stats;
 
 /* One Jacobi sweep of the scheme (eq. SLscheme2 or SLscheme3 per problem->scheme):
@@ -244,6 +252,8 @@ typedef struct {
     double residual;              /* of the final check sweep on the fine grid                    */
     int32_t status;
     int32_t pad;
+    int64_t check_sweeps;         /* fine solve: passes that were full check sweeps               */
+    double t_check_visit;         /* fine solve: part of t_visit in check-sweep visits (if timed)  */
 } slhjb_patchy_stats;
 
 /* The algorithm of Section 4.3 on one GPU. Patchy modes: (1) coarse solve of `coarse` with

@@ -4,6 +4,7 @@ Run ``python -m paper_1502_01629_amd.build`` or call ``build()``.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -28,6 +29,19 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of every source the library is built from: the HIP sources,
+    the internal headers and the public header. Compiled into the library and checked on load."""
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for name in names:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "slhjb.h"), "rb") as f:
+        h.update(b"slhjb.h\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -40,9 +54,11 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
+    tag = source_hash()
+
     def compile_one(src):
         obj = os.path.join(objdir, src + ".o")
-        cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, f'-DSLHJB_SOURCE_HASH="{tag}"', "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

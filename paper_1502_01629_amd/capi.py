@@ -62,6 +62,8 @@ class Stats(ctypes.Structure):
         ("halo", ctypes.c_int32),
         ("pad", ctypes.c_int32),
         ("policy_updates", ctypes.c_int64),
+        ("check_sweeps", ctypes.c_int64),
+        ("check_seconds", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -122,10 +124,14 @@ class PatchyStats(ctypes.Structure):
         ("residual", ctypes.c_double),
         ("status", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("check_sweeps", ctypes.c_int64),
+        ("t_check_visit", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 MODE_TRANSMISSION, MODE_INDEPENDENT = 0, 1
 
 # tile shapes of the batched solve (slhjb_batch_opts.tile_shapes)
@@ -205,6 +211,7 @@ _PP = ctypes.POINTER(Problem)
 SIGNATURES = {
     "slhjb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "slhjb_version": (ctypes.c_int, []),
+    "slhjb_source_hash": (ctypes.c_char_p, []),
     "slhjb_ctx_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "slhjb_ctx_destroy": (ctypes.c_int, [_vp]),
     "slhjb_last_hip_error": (ctypes.c_int, [_vp]),
@@ -248,6 +255,14 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        built = L.slhjb_source_hash().decode()
+        if os.path.isdir(os.path.join(HERE, "csrc")):
+            from . import build as _build
+
+            now = _build.source_hash()
+            if built != now:
+                raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, sources {now}): "
+                                   "rebuild it with `python -m paper_1502_01629_amd.build`")
         _lib = L
     return _lib
 

@@ -129,6 +129,12 @@ struct slhjb_ctx {
   unsigned* lmask = nullptr;      // word masks of the labeler tiles
   size_t lmask_cap = 0;
   hipEvent_t tev[32] = {};           // visit-kernel timing events of one captured batch
+  unsigned* tchk_host = nullptr;     // check-sweep count after each pass of a timed batch (pinned)
+  float* pipe_vc = nullptr;          // patchy pipeline: coarse iterate
+  size_t pipe_vc_cap = 0;
+  int16_t* pipe_ctrl = nullptr;      // patchy pipeline: synthesized control, labels
+  int16_t* pipe_lab = nullptr;
+  size_t pipe_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, eva = nullptr, evb = nullptr;
 };
 
@@ -350,6 +356,29 @@ int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
   return SLHJB_OK;
 }
 
+// Scratch of the patchy pipeline: the coarse iterate, the synthesized control and the labels.
+int ensure_pipe(slhjb_ctx* ctx, size_t coarse_nodes, size_t fine_nodes) {
+  if (ctx->pipe_vc_cap < coarse_nodes) {
+    if (ctx->pipe_vc) hipFree(ctx->pipe_vc);
+    ctx->pipe_vc = nullptr;
+    ctx->pipe_vc_cap = 0;
+    hipError_t e = hipMalloc(&ctx->pipe_vc, sizeof(float) * coarse_nodes);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pipeline scratch");
+    ctx->pipe_vc_cap = coarse_nodes;
+  }
+  if (ctx->pipe_cap < fine_nodes) {
+    if (ctx->pipe_ctrl) hipFree(ctx->pipe_ctrl);
+    if (ctx->pipe_lab) hipFree(ctx->pipe_lab);
+    ctx->pipe_ctrl = ctx->pipe_lab = nullptr;
+    ctx->pipe_cap = 0;
+    hipError_t e = hipMalloc(&ctx->pipe_ctrl, sizeof(int16_t) * fine_nodes);
+    if (e == hipSuccess) e = hipMalloc(&ctx->pipe_lab, sizeof(int16_t) * fine_nodes);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pipeline scratch");
+    ctx->pipe_cap = fine_nodes;
+  }
+  return SLHJB_OK;
+}
+
 int ensure_tiles(slhjb_ctx* ctx, size_t tiles) {
   if (!ctx->tcount) {
     HIP_TRY(ctx, hipMalloc(&ctx->tcount, sizeof(int) * 4));
@@ -393,7 +422,12 @@ const char* slhjb_status_string(int status) {
   }
 }
 
-int slhjb_version(void) { return 2; }
+int slhjb_version(void) { return 3; }
+
+#ifndef SLHJB_SOURCE_HASH
+#define SLHJB_SOURCE_HASH "unknown"
+#endif
+const char* slhjb_source_hash(void) { return SLHJB_SOURCE_HASH; }
 
 int slhjb_ctx_create(slhjb_ctx** out, int hip_device, void* hip_stream) {
   if (!out) return SLHJB_E_INVALID_ARG;
@@ -437,6 +471,10 @@ int slhjb_ctx_destroy(slhjb_ctx* ctx) {
   if (ctx->tchange) hipFree(ctx->tchange);
   if (ctx->coop) hipFree(ctx->coop);
   if (ctx->tctl) hipFree(ctx->tctl);
+  if (ctx->tchk_host) hipHostFree(ctx->tchk_host);
+  if (ctx->pipe_vc) hipFree(ctx->pipe_vc);
+  if (ctx->pipe_ctrl) hipFree(ctx->pipe_ctrl);
+  if (ctx->pipe_lab) hipFree(ctx->pipe_lab);
   if (ctx->tacc) hipFree(ctx->tacc);
   if (ctx->lctl) hipFree(ctx->lctl);
   if (ctx->lctl_host) hipHostFree(ctx->lctl_host);
@@ -583,6 +621,8 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
     stats->halo = P.args.halo;
     stats->pad = 0;
     stats->policy_updates = 0;
+    stats->check_sweeps = 0;
+    stats->check_seconds = 0.0;
   }
   if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
   return status;
@@ -913,10 +953,14 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   } else if (pdd) {
     // (1) coarse solve with sigma = 0, from v = 1 (the Kruzkov "+infinity")
     const int64_t Nc = (int64_t)coarse->n * coarse->n;
-    he = hipMalloc(&vc, sizeof(float) * Nc);
-    if (he == hipSuccess) he = hipMalloc(&ctrl, sizeof(int16_t) * N);
-    if (he == hipSuccess && need_labels && !lab) he = hipMalloc(&lab, sizeof(int16_t) * N);
-    if (he != hipSuccess) st = hip_fail(ctx, he, "pipeline scratch");
+    // context-owned scratch, grown only when a larger problem comes: a repeated solve allocates
+    // nothing (and its cached pass graphs, keyed by these addresses, stay valid)
+    st = ensure_pipe(ctx, (size_t)Nc, (size_t)N);
+    if (st == SLHJB_OK) {
+      vc = ctx->pipe_vc;
+      ctrl = ctx->pipe_ctrl;
+      if (need_labels && !lab) lab = ctx->pipe_lab;
+    }
     if (st == SLHJB_OK) {
       // start value V* on every node; the solver overwrites TARGET and OBSTACLE nodes
       const float vstar = (float)((double)coarse->running_cost / (double)coarse->lambda);
@@ -1006,6 +1050,8 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   }
   if (st == SLHJB_OK || st == SLHJB_NOT_CONVERGED) {
     S.passes = ts.sweeps;
+    S.check_sweeps = ts.check_sweeps;
+    S.t_check_visit = ts.check_seconds;
     S.node_updates = ts.node_updates;
     S.policy_updates = ts.policy_updates;
     S.residual = ts.residual;
@@ -1019,9 +1065,6 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
   }
   S.status = st;
   if (stats) *stats = S;
-  if (vc) hipFree(vc);
-  if (ctrl) hipFree(ctrl);
-  if (lab && lab != label_out) hipFree(lab);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (t0) hipEventDestroy(t0);
@@ -1154,8 +1197,8 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
   int64_t passes = 0, converged = -1;
   double resid = INFINITY;
   int status = SLHJB_NOT_CONVERGED;
-  int64_t updates = 0, pe_updates = 0;
-  double visit_sec = 0.0;
+  int64_t updates = 0, pe_updates = 0, checks = -1;
+  double visit_sec = 0.0, check_sec = 0.0;
   if (opts->persistent) {
     if (!ctx->coop) {
       HIP_TRY(ctx, hipMalloc(&ctx->coop, coop_state_bytes()));
@@ -1204,18 +1247,25 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     const bool timing = opts->collect_kernel_time != 0;
     if (timing && !ctx->tev[0])
       for (auto& e : ctx->tev) HIP_TRY(ctx, hipEventCreate(&e));
+    if (timing && !ctx->tchk_host) HIP_TRY(ctx, hipHostMalloc(&ctx->tchk_host, sizeof(unsigned) * 16, hipHostMallocDefault));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // With kernel timing the same passes are launched directly on the context stream with events
     // around every visit launch (events recorded inside a captured graph cannot be timed).
+    // With events, the check-sweep count (word 11) is copied after every pass, so that the host
+    // can tell which timed visit launches were check sweeps.
     auto enqueue_batch = [&](hipStream_t s, bool ev) -> hipError_t {
       hipError_t e = hipSuccess;
-      for (int b = 0; b < kBatch && e == hipSuccess; ++b)
+      for (int b = 0; b < kBatch && e == hipSuccess; ++b) {
         e = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label,
                                 keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange,
                                 ctx->tflag, max_inner, tol_inner, act, window, (float)tol, b & 1, ctx->tctl, grid,
                                 ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr,
                                 opts->policy_sweeps, ctx->tacc, s);
+        if (ev && e == hipSuccess)
+          e = hipMemcpyAsync(ctx->tchk_host + b, static_cast<unsigned*>(ctx->tctl) + 11, sizeof(unsigned),
+                             hipMemcpyDeviceToHost, s);
+      }
       return e;
     };
     if (!timing) {
@@ -1242,6 +1292,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     hipError_t le = hipSuccess;
     unsigned done = 0, dev_passes = 0;
     if (timing) {
+      unsigned checks_seen = 0;
       while (true) {
         le = enqueue_batch(ctx->stream, true);
         if (le == hipSuccess)
@@ -1251,6 +1302,8 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
           float ms = 0.0f;
           le = hipEventElapsedTime(&ms, ctx->tev[2 * b], ctx->tev[2 * b + 1]);
           visit_sec += ms * 1e-3;
+          if (ctx->tchk_host[b] != checks_seen) check_sec += ms * 1e-3;  // this pass was a check sweep
+          checks_seen = ctx->tchk_host[b];
         }
         if (le != hipSuccess) break;
         done = ctx->tctl_host[9];
@@ -1303,6 +1356,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     memcpy(&pu, &ctx->tctl_host[14], sizeof(pu));
     updates = (int64_t)u;
     pe_updates = (int64_t)pu;
+    checks = ctx->tctl_host[11];
   }
   HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -1322,6 +1376,8 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     stats->sweep_seconds = visit_sec;
     stats->sweep_launches = visit_sec > 0.0 ? passes : 0;
     stats->policy_updates = pe_updates;
+    stats->check_sweeps = checks;
+    stats->check_seconds = check_sec;
   }
   return status;
 }

@@ -97,7 +97,7 @@ hipError_t launch_coop_state_init(void* state, hipStream_t s);
 // (float, negative when its visit stopped unsettled), then the neighbour sides it flags (uint32,
 // bit (dy + 1) * 3 + dx + 1 for the neighbour at tile offset (dx, dy)).
 // Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes(). Layout of
-// the words the host reads: [9] done, [10] passes, [7] resid bits, [12..13] updates,
+// the words the host reads: [9] done, [10] passes, [11] check sweeps, [7] resid bits, [12..13] updates,
 // [14..15] policy-evaluation updates. `pe`: policy-evaluation iterations after each full one
 // (split tile shapes only). The cooperative state: [6..7] updates, [8..9] policy updates.
 size_t tilectl_bytes();

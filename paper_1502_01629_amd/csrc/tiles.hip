@@ -719,7 +719,7 @@ struct TileCtl {
   unsigned checked;    // 1 after a check sweep, until the next selection reads it
   unsigned done;       // 1 once a check sweep met tol
   unsigned passes;     // passes that did work (check sweeps included)
-  unsigned pad;
+  unsigned checks;     // check sweeps among them
   unsigned long long updates;
   unsigned long long pe_updates;  // policy-evaluation node updates
 };
@@ -733,7 +733,7 @@ __global__ void tilectl_init_kernel(TileCtl* c) {
   c->checked = 0u;
   c->done = 0u;
   c->passes = 0u;
-  c->pad = 0u;
+  c->checks = 0u;
   c->updates = 0ull;
   c->pe_updates = 0ull;
 }
@@ -868,6 +868,7 @@ __global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __r
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (cnt > 0 || nf == 0) c->passes += 1u;
+    if (cnt == 0 && nf == 0) c->checks += 1u;
     c->checked = (cnt == 0 && nf == 0) ? 1u : 0u;
     // the other parity's counters serve the next pass; they were last read by the previous pass
     c->count[q ^ 1] = 0u;
@@ -877,7 +878,8 @@ __global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __r
 }
 
 static_assert(offsetof(TileCtl, resid) == 7 * 4 && offsetof(TileCtl, done) == 9 * 4 &&
-                  offsetof(TileCtl, passes) == 10 * 4 && offsetof(TileCtl, updates) == 12 * 4 &&
+                  offsetof(TileCtl, passes) == 10 * 4 && offsetof(TileCtl, checks) == 11 * 4 &&
+                  offsetof(TileCtl, checked) == 8 * 4 && offsetof(TileCtl, updates) == 12 * 4 &&
                   offsetof(TileCtl, pe_updates) == 14 * 4 && sizeof(TileCtl) <= 64,
               "host reads these words");
 size_t tilectl_bytes() { return sizeof(TileCtl); }

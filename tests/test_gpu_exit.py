@@ -5,8 +5,8 @@ the general kernels: f(x,a) = c(x) (d(x) + a).
 Every case compares the GPU path with the FP64 oracle on the same FP32 inputs: one sweep from
 a random iterate to 2e-6, converged solutions to 1e-5 max-abs (the bounds of the other parity
 tests: a handful of FP32 roundings, amplified by at most 1/(1-beta) at convergence). The general
-kernels evaluate eq. SLscheme3 by subtracting the node's own weight in floating point, so their
-FP32 iterate settles into changes of a few 1e-7 and the GPU solves stop at 1e-6.
+kernels leave the node's own corner out of eq. SLscheme3's interpolation exactly (it reads 0), so
+the FP32 iterate settles; the GPU solves stop at 1e-6 like the other parity tests.
 """
 import numpy as np
 import pytest

@@ -273,7 +273,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
 /* ---- pre-computation of the patchy method (Section 4.3) --------------------------------- */
 
 /* u_hat: bilinear interpolation of a coarse grid solution onto a fine grid of the same box
- * (Section 4.3, "build u_hat on G by interpolation of u_c"). v_c: device float[n_c*n_c],
+ * (Section 4.3, pre-computation step: the coarse solution carried to the fine grid). v_c: device float[n_c*n_c],
  * v_f: device float[n_f*n_f]. Fine node i lies at coarse coordinate i (n_c-1)/(n_f-1); the
  * grids need not be nested. Enqueued only (no synchronisation). */
 int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f);
@@ -286,7 +286,7 @@ int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, f
 int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_hat, int16_t* ctrl_out);
 
 /* Split the TARGET nodes (the sources of information in a target problem, standing in for the
- * boundary nodes of Section 4.3 "divide the boundary nodes of G in N_P sub-sets") into
+ * boundary nodes that Section 4.3's pre-computation step splits into one set per patch) into
  * n_patches sets. Host-only. Targets are the 4-connected components of TARGET nodes, numbered
  * in row-major order of their first node; each gets one patch plus a largest-remainder share
  * (by node count, ties to the lower component) of the remaining n_patches - T; within a

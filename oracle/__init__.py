@@ -83,6 +83,8 @@ def lib():
             "or_solve": (i64, [P, vp, f64, i64, i32, vp, i32, vp, vp, i64]),
             "or_transitions": (i32, [P, i32, i32, vp, vp, vp]),
             "or_synthesize": (None, [P, vp, vp, vp]),
+            "or_policy_chain": (None, [P, vp, vp, vp, vp, i32]),
+            "or_policy_improve": (i64, [P, vp, vp, i32]),
             "or_upsample_bilinear": (None, [i32, vp, i32, vp]),
             "or_displacement": (None, [i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]),
             "or_label": (i64, [i32, vp, vp, vp, i32, i32, vp, vp]),
@@ -229,6 +231,25 @@ class Problem:
         wo = np.zeros(1, dtype=np.float64)
         cnt = lib().or_transitions(ctypes.byref(s), node, m, _ptr(idx), _ptr(w), _ptr(wo))
         return idx[:cnt].copy(), w[:cnt].copy(), float(wo[0])
+
+    def policy_chain(self, policy: np.ndarray, threads: int = 1):
+        """Per node the chain of control policy[node]: (index[N,16] with -1 padding, weight[N,16],
+        weight of feet outside the box[N])."""
+        s = self.c_struct()
+        N = self.n * self.n
+        pol = np.ascontiguousarray(policy, dtype=np.int32).reshape(-1)
+        idx = np.empty((N, 16), dtype=np.int32)
+        w = np.empty((N, 16), dtype=np.float64)
+        wo = np.empty(N, dtype=np.float64)
+        lib().or_policy_chain(ctypes.byref(s), _ptr(pol), _ptr(idx), _ptr(w), _ptr(wo), threads)
+        return idx, w, wo
+
+    def policy_improve(self, v: np.ndarray, policy: np.ndarray, threads: int = 1) -> int:
+        """Greedy improvement of policy (int32[N], changed in place) at v; returns the changes."""
+        s = self.c_struct()
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+        assert policy.dtype == np.int32 and policy.flags.c_contiguous
+        return int(lib().or_policy_improve(ctypes.byref(s), _ptr(v), _ptr(policy), threads))
 
     def synthesize(self, v_hat: np.ndarray):
         s = self.c_struct()

@@ -245,6 +245,50 @@ int32_t or_transitions(const or_problem* p, int32_t node, int32_t m, int32_t* id
     return cnt;
 }
 
+/* Howard's policy iteration, the pieces that touch every node (Section 3 scheme as a Markov
+ * decision problem): the chain of a policy at every node, and the greedy improvement step. */
+
+/* For every node: up to 16 (index, weight) pairs of the chain of control policy[node] (padded
+ * with index -1), and the weight of feet outside the box. Nodes that are not FREE get no entries. */
+void or_policy_chain(const or_problem* p, const int32_t* policy, int32_t* idx, double* w, double* w_out,
+                     int32_t n_threads) {
+    const int64_t N = (int64_t)p->n * p->n;
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for num_threads(n_threads) schedule(dynamic, 256)
+    for (int64_t node = 0; node < N; ++node) {
+        int32_t* ri = idx + 16 * node;
+        double* rw = w + 16 * node;
+        for (int32_t k = 0; k < 16; ++k) { ri[k] = -1; rw[k] = 0.0; }
+        w_out[node] = 0.0;
+        if (p->node_class[node] != OR_FREE) continue;
+        or_transitions(p, (int32_t)node, policy[node], ri, rw, &w_out[node]);
+    }
+}
+
+/* Greedy improvement at v: every FREE node takes a control of smallest eq. SLscheme2 candidate,
+ * keeping its current control unless another one is smaller by more than a relative 1e-14.
+ * Returns the number of nodes whose control changed. */
+int64_t or_policy_improve(const or_problem* p, const double* v, int32_t* policy, int32_t n_threads) {
+    const int64_t N = (int64_t)p->n * p->n;
+    or_problem q = *p;
+    q.scheme = OR_SL2;
+    int64_t changed = 0;
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for reduction(+ : changed) num_threads(n_threads) schedule(dynamic, 64)
+    for (int64_t node = 0; node < N; ++node) {
+        if (p->node_class[node] != OR_FREE) continue;
+        int32_t bm = 0;
+        const double best = or_bellman(&q, v, (int32_t)node, &bm);
+        const double cur = or_candidate(&q, v, (int32_t)node, policy[node]);
+        const double scale = fabs(cur) > 1.0 ? fabs(cur) : 1.0;
+        if (best < cur - 1e-14 * scale) {
+            policy[node] = bm;
+            ++changed;
+        }
+    }
+    return changed;
+}
+
 /* Discrete synthesis of the feedback control (Section 4.3, eq. discrete-synthesis) with
  * sigma = 0 and a constant running cost: argmin over controls of I[v_hat](x_i + h c a).
  * The first minimum wins. gap_out (nullable) receives second-best minus best, so callers can

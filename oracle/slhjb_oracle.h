@@ -58,6 +58,9 @@ int64_t or_solve(const or_problem* p, double* v, double tol, int64_t max_sweeps,
                  double* history, int64_t history_len);
 int32_t or_transitions(const or_problem* p, int32_t node, int32_t m, int32_t* idx /*[16]*/,
                        double* w /*[16]*/, double* w_out);
+void or_policy_chain(const or_problem* p, const int32_t* policy, int32_t* idx /*[N][16]*/, double* w /*[N][16]*/,
+                     double* w_out /*[N]*/, int32_t n_threads);
+int64_t or_policy_improve(const or_problem* p, const double* v, int32_t* policy, int32_t n_threads);
 void or_synthesize(const or_problem* p, const double* v_hat, int32_t* ctrl_out, double* gap_out);
 void or_upsample_bilinear(int32_t n_c, const double* v_c, int32_t n_f, double* v_f);
 void or_displacement(int32_t n, float x_lo, float x_hi, float h, const float* speed,

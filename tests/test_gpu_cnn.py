@@ -137,8 +137,17 @@ def test_gradients_match_reference(ctx):
         k = int(np.prod(shape))
         a, b = g[o:o + k], rg[o:o + k]
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        print(f"{name}: |g| {np.linalg.norm(b):.3e} rel err {rel:.2e}", flush=True)
-        assert rel <= 2e-2, name
+        scale = np.abs(b).max()
+        d = np.abs(a - b) / max(scale, 1e-30)
+        print(f"{name}: |g| {np.linalg.norm(b):.3e} rel err {rel:.2e}; per element / block max: max {d.max():.2e} "
+              f"p99 {np.quantile(d, 0.99):.2e} median {np.median(d):.2e}", flush=True)
+        # Element by element, relative to the block's largest gradient: both sides round the same
+        # activations and back-propagated errors to bfloat16 (relative step 2^-8), so the only
+        # difference is FP32 against FP64 accumulation order, which moves a rounding of the
+        # reference by one bfloat16 ulp where a sum lands near a rounding boundary. Measured: at
+        # most 4.5e-4 of the block scale; the bound is 2^-9 (half a bfloat16 ulp) of it.
+        assert d.max() <= 2.0 ** -9, name
+        assert rel <= 2e-3, name
     net.close()
 
 

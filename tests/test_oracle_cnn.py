@@ -85,6 +85,28 @@ def test_adam_first_step_is_sign_times_lr():
     assert np.allclose(p, -0.01 * np.sign(g), rtol=2e-5)
 
 
+def test_adam_second_and_third_steps_match_the_recursion_by_hand():
+    """Gradients 1, -1, 2 with beta1 = 0.9, beta2 = 0.999, worked out by hand:
+    step 2: m = 0.9 * 0.1 - 0.1 = -0.01, v = 0.999 * 0.001 + 0.001 = 0.001999,
+            m_hat = -0.01 / (1 - 0.9^2) = -1/19, v_hat = 0.001999 / (1 - 0.999^2) = 1;
+    step 3: m = -0.009 + 0.2 = 0.191, v = 0.999 * 0.001999 + 0.004 = 0.005997001,
+            m_hat = 0.191 / (1 - 0.9^3) = 0.191 / 0.271, v_hat = 0.005997001 / 0.002997001.
+    A wrong bias-correction power or moment recursion changes steps 2 and 3."""
+    lr, e = 0.01, 1e-8
+    p, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    p, m, v = cnn.adam(p, np.array([1.0]), m, v, 1, lr=lr)
+    p1 = -lr * 1.0 / (1.0 + e)
+    assert np.isclose(p[0], p1, rtol=1e-12, atol=0)
+    p, m, v = cnn.adam(p, np.array([-1.0]), m, v, 2, lr=lr)
+    assert np.isclose(m[0], -0.01, rtol=1e-12) and np.isclose(v[0], 0.001999, rtol=1e-12)
+    p2 = p1 + lr * (1.0 / 19.0) / (1.0 + e)
+    assert np.isclose(p[0], p2, rtol=1e-12, atol=0)
+    p, m, v = cnn.adam(p, np.array([2.0]), m, v, 3, lr=lr)
+    assert np.isclose(m[0], 0.191, rtol=1e-12) and np.isclose(v[0], 0.005997001, rtol=1e-12)
+    p3 = p2 - lr * (0.191 / 0.271) / (np.sqrt(0.005997001 / 0.002997001) + e)
+    assert np.isclose(p[0], p3, rtol=1e-12, atol=0)
+
+
 def test_crop_mask_keeps_the_margin_from_inner_edges_only():
     cls = np.zeros((20, 20), dtype=np.uint8)
     m = cnn.crop_mask(cls, 0, 6, 10, 20, 3)  # left edge is the box side, the others are inside

@@ -148,6 +148,29 @@ def test_value_iteration_matches_policy_iteration(diff, eps):
         assert np.abs(v_vi - v_pi).max() < 1e-12
 
 
+@pytest.mark.parametrize("diff,eps", [(I.DIFF_NONE, 0.0), (I.DIFF_ISO, 0.02), (I.DIFF_RANK1, 0.02)])
+def test_sparse_policy_iteration_matches_dense_and_value_iteration(diff, eps):
+    """The sparse Howard iteration (used to write the stored fixed points of the larger parity
+    cases) equals the dense one on a tiny grid and value iteration on a 33^2 grid with obstacles."""
+    n = 9
+    inst = I.disc_problem(n=n, eps=eps, n_controls=8, diffusion=diff)
+    inst.node_class[:] = 0
+    inst.node_class[4, 4] = I.TARGET
+    inst.node_class[1, 6] = I.OBSTACLE
+    rng = np.random.default_rng(7)
+    inst.speed = (0.5 + rng.random((n, n))).astype(np.float32)
+    p = _prob(inst, SL3)
+    v_d, _, _ = policy.policy_iteration(p)
+    v_s, _, _ = policy.sparse_policy_iteration(p)
+    assert np.abs(v_d - v_s).max() < 1e-13
+    inst = I.scattered_problem(2, n=33, n_coarse=9, eps=eps * 4, n_controls=16)[0]
+    inst.diffusion = diff
+    p = _prob(inst, SL3)
+    v_s, _, _ = policy.sparse_policy_iteration(p, threads=4)
+    v_vi, _, _, _ = p.solve(tol=1e-15, threads=4)
+    assert np.abs(v_vi - v_s).max() < 1e-12
+
+
 def test_value_iteration_matches_brute_force():
     """A 3x3 block with one target node inside (8 free nodes), 4 controls: the optimal value is the
     componentwise minimum over all 4^8 deterministic policies."""
@@ -254,6 +277,27 @@ def test_synthesis_on_transport_picks_the_left_control():
     free = inst.node_class.reshape(-1) == I.FREE
     assert (ctrl[free] == left).all()
     assert (ctrl[~free] == -1).all()
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_synthesis_ties_go_to_the_first_minimum(axis):
+    """With u_hat = |x_2| (resp. |x_1|), piecewise linear with its kink on a grid line, bilinear
+    reconstruction is exact: at a FREE node on the kink the controls along the line, a = (1, 0) and
+    (-1, 0) (resp. (0, 1) and (0, -1)), both give exactly 0 and every other control more. The
+    lower index must win: 0 (resp. N/4), never N/2 (resp. 3N/4); the gap to the second best is 0."""
+    n, N = 17, 32
+    inst = I.transport_problem(n, N)
+    inst.node_class[:] = I.FREE
+    p = _prob(inst)
+    X1, X2 = I.node_coords(n)
+    v = np.abs(X2 if axis == 0 else X1).astype(np.float64)
+    ctrl, gap = p.synthesize(v)
+    mid = n // 2
+    nodes = [mid * n + i for i in range(2, n - 2)] if axis == 0 else [j * n + mid for j in range(2, n - 2)]
+    assert np.array_equal(inst.controls[0], [1.0, 0.0]) and np.array_equal(inst.controls[N // 4], [0.0, 1.0])
+    want = 0 if axis == 0 else N // 4
+    assert (ctrl[nodes] == want).all(), ctrl[nodes]
+    assert (gap[nodes] == 0.0).all()
 
 
 def test_upsample_reproduces_bilinear_and_coarse_nodes():

@@ -140,6 +140,22 @@ int slhjb_sweep(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_in,
 int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
                 int32_t check_every, slhjb_stats* stats);
 
+/* Largest grid side slhjb_solve_noalloc accepts. */
+#define SLHJB_NOALLOC_MAX_N 1025
+
+/* slhjb_solve for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same arguments, arithmetic, check cadence,
+ * stopping rule, statistics and results as slhjb_solve, bit for bit, with no hipMalloc / hipFree
+ * or other allocating call. Its scratch (the second iterate of up to SLHJB_NOALLOC_MAX_N^2 nodes,
+ * the padded control table and the residual words, 4.21 MB) is a static device array of the
+ * library: one copy per device, held until the process ends, and shared by every call on that
+ * device, which leaves in it what the last call wrote (each call clears the words it needs first).
+ * Calls that overlap on one device (two host threads, or two contexts on different streams) race
+ * on it and must not be made. ctx must exist already (slhjb_ctx_create allocates its events).
+ * n * n > SLHJB_NOALLOC_MAX_N^2: SLHJB_E_INVALID_ARG, nothing launched. */
+int slhjb_solve_noalloc(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
+                        int32_t check_every, slhjb_stats* stats);
+
 /* ---- active-tile solve (Sections 4.2-4.3, computation step) ----------------------------- */
 enum { SLHJB_ORDER_NONE = 0,   /* every flagged tile each pass (static order)                     */
        SLHJB_ORDER_KEYS = 1    /* frontier by the arrival time of the start (u_hat order)         */ };

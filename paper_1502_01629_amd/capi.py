@@ -218,6 +218,7 @@ SIGNATURES = {
     "slhjb_last_error_message": (ctypes.c_char_p, [_vp]),
     "slhjb_sweep": (ctypes.c_int, [_vp, _PP, _vp, _vp, ctypes.POINTER(_f64)]),
     "slhjb_solve": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
+    "slhjb_solve_noalloc": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, _i32, ctypes.POINTER(Stats)]),
     "slhjb_solve_tiles": (ctypes.c_int, [_vp, _PP, _vp, _f64, _i64, ctypes.POINTER(TileOpts), ctypes.POINTER(Stats)]),
     "slhjb_solve_patchy": (ctypes.c_int, [_vp, _PP, _PP, ctypes.POINTER(PatchyOpts), _vp, _vp,
                                           ctypes.POINTER(PatchyStats)]),
@@ -446,6 +447,16 @@ class Context:
         stats = Stats()
         st = lib().slhjb_solve(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_sweeps, check_every,
                                ctypes.byref(stats))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return stats.as_dict()
+
+
+    def solve_noalloc(self, prob: DeviceProblem, v, tol: float = 1e-6, max_sweeps: int = 1_000_000,
+                      check_every: int = 0):
+        """slhjb_solve_noalloc: slhjb_solve with the library's static scratch (no allocation)."""
+        stats = Stats()
+        st = lib().slhjb_solve_noalloc(self.handle, ctypes.byref(prob.struct), _ptr(v), tol, max_sweeps, check_every,
+                                       ctypes.byref(stats))
         self._check(st, allow=(OK, NOT_CONVERGED))
         return stats.as_dict()
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -220,45 +221,53 @@ int ensure_small(slhjb_ctx* ctx) {
   return SLHJB_OK;
 }
 
-int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
+// Device and host memory that preparing a problem writes: `dw` device words ([0] residual bits,
+// [1] flags, [2..8] problem statistics), `hw` host words (the statistics are read back there),
+// the padded control table and the controls in the caller's order (nullable).
+struct PrepMem {
+  unsigned* dw;
+  unsigned* hw;
+  float4* ctrl;
+  float2* ctrl2;
+};
+
+int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const PrepMem& M) {
   int st = validate(ctx, p);
-  if (st != SLHJB_OK) return st;
-  st = ensure_small(ctx);
   if (st != SLHJB_OK) return st;
   const int n = p->n;
   const int64_t N = (int64_t)n * n;
   // speed bounds, FREE count, class validity and the drift's reach (one device pass, one read-back)
   if (p->drift && (reinterpret_cast<uintptr_t>(p->drift) & 7u))
     return fail(ctx, SLHJB_E_INVALID_ARG, "drift must be 8-byte aligned");
-  HIP_TRY(ctx, launch_fill_u32(ctx->small + 2, 0x7f7fffffu, 1, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32(ctx->small + 3, 0u, 6, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32(M.dw + 2, 0x7f7fffffu, 1, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32(M.dw + 3, 0u, 6, ctx->stream));
   HIP_TRY(ctx, launch_problem_stats(p->speed, p->node_class, reinterpret_cast<const float2*>(p->drift),
-                                    p->speed_const, N, ctx->small + 2, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host + 2, ctx->small + 2, sizeof(unsigned) * 7, hipMemcpyDeviceToHost,
+                                    p->speed_const, N, M.dw + 2, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(M.hw + 2, M.dw + 2, sizeof(unsigned) * 7, hipMemcpyDeviceToHost,
                               ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->small_host[4]) return fail(ctx, SLHJB_E_INVALID_ARG, "speed has a non-finite or non-positive value");
-  if (ctx->small_host[6]) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class has a value other than 0, 1, 2");
-  if (ctx->small_host[8]) return fail(ctx, SLHJB_E_INVALID_ARG, "drift has a non-finite value");
+  if (M.hw[4]) return fail(ctx, SLHJB_E_INVALID_ARG, "speed has a non-finite or non-positive value");
+  if (M.hw[6]) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class has a value other than 0, 1, 2");
+  if (M.hw[8]) return fail(ctx, SLHJB_E_INVALID_ARG, "drift has a non-finite value");
   double speed_max = p->speed_const;
   if (p->speed) {
     float hi;
-    memcpy(&hi, &ctx->small_host[3], sizeof(float));
+    memcpy(&hi, &M.hw[3], sizeof(float));
     speed_max = hi;
   }
-  const int64_t free_nodes = ctx->small_host[5];
+  const int64_t free_nodes = M.hw[5];
   double reach = reach_for(p, speed_max);
   if (p->drift) {
     // the drift moves every foot of a node by h c d / dx
     float dmax;
-    memcpy(&dmax, &ctx->small_host[7], sizeof(float));
+    memcpy(&dmax, &M.hw[7], sizeof(float));
     const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
     reach += (double)(p->h / dx32) * (double)dmax;
   }
   Prepared P;
   P.speed_max = (float)speed_max;
   P.speed_min = p->speed_const;
-  if (p->speed) memcpy(&P.speed_min, &ctx->small_host[2], sizeof(float));
+  if (p->speed) memcpy(&P.speed_min, &M.hw[2], sizeof(float));
   P.diffusion = p->eps > 0.0f ? p->diffusion : SLHJB_DIFF_NONE;
   P.scheme = p->scheme;
   P.reach = reach;
@@ -273,8 +282,9 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   if (halo > kMaxHalo)
     return fail(ctx, SLHJB_E_UNSUPPORTED,
                 "feet reach more than " + std::to_string(kMaxHalo - 1) + " cells; reduce h or eps");
-  // control table, grouped by quadrant for the first-ring kernel
-  std::vector<int> order(p->n_controls);
+  // control table, grouped by quadrant for the first-ring kernel (fixed-size host arrays: the
+  // no-allocation entry point prepares its problem here too)
+  int order[256];
   for (int m = 0; m < p->n_controls; ++m) order[m] = m;
   int quad[5] = {0, 0, 0, 0, 0};
   if (P.path == 1) {
@@ -283,7 +293,7 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
       if (ay >= 0.0f) return ax >= 0.0f ? 0 : 1;
       return ax < 0.0f ? 2 : 3;
     };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return qof(a) < qof(b); });
+    std::stable_sort(order, order + p->n_controls, [&](int a, int b) { return qof(a) < qof(b); });
     int q = 0;
     for (int t = 0; t < p->n_controls; ++t)
       while (q < qof(order[t])) quad[++q] = t;
@@ -294,26 +304,26 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   // Pad every quadrant's list (or the whole list for the general kernel) to a multiple of 4 by
   // repeating its last control: a repeat cannot change a max, and the kernels then fetch the
   // table four entries at a time.
-  std::vector<float4> tab;
+  float4 tab[kCtrlCap];
+  int ntab = 0;
   int pquad[5] = {0, 0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) {
-    pquad[q] = (int)tab.size();
+    pquad[q] = ntab;
     for (int t = quad[q]; t < quad[q + 1]; ++t) {
       const float ax = p->controls[2 * order[t]], ay = p->controls[2 * order[t] + 1];
-      tab.push_back(make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay)));
+      tab[ntab++] = make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay));
     }
-    while (tab.size() % 4 != 0) tab.push_back(tab.back());
+    while (ntab % 4 != 0) {
+      tab[ntab] = tab[ntab - 1];
+      ++ntab;
+    }
   }
-  pquad[4] = (int)tab.size();
+  pquad[4] = ntab;
   for (int q = 0; q < 5; ++q) quad[q] = pquad[q];
-  if (!ctx->ctrl) {
-    HIP_TRY(ctx, hipMalloc(&ctx->ctrl, sizeof(float4) * kCtrlCap));
-    ctx->ctrl_cap = kCtrlCap;
-  }
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice, ctx->stream));
-  if (!ctx->ctrl2) HIP_TRY(ctx, hipMalloc(&ctx->ctrl2, sizeof(float2) * 256));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->ctrl2, p->controls, sizeof(float2) * p->n_controls, hipMemcpyHostToDevice,
-                              ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(M.ctrl, tab, sizeof(float4) * ntab, hipMemcpyHostToDevice, ctx->stream));
+  if (M.ctrl2)
+    HIP_TRY(ctx, hipMemcpyAsync(M.ctrl2, p->controls, sizeof(float2) * p->n_controls, hipMemcpyHostToDevice,
+                                ctx->stream));
   // The copy reads `tab` asynchronously from pageable memory; make it complete before `tab` dies.
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
@@ -324,9 +334,9 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   SweepArgs& a = P.args;
   a.speed = p->speed;
   a.cls = p->node_class;
-  a.ctrl = ctx->ctrl;
+  a.ctrl = M.ctrl;
   a.resid = nullptr;
-  a.flags = ctx->small + 1;
+  a.flags = M.dw + 1;
   a.n = n;
   a.n_controls = quad[4];
   a.halo = halo;
@@ -342,6 +352,18 @@ int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
   P.vstar = vstar;
   *out = P;
   return SLHJB_OK;
+}
+
+int prepare(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  int st = ensure_small(ctx);
+  if (st != SLHJB_OK) return st;
+  if (!ctx->ctrl) {
+    HIP_TRY(ctx, hipMalloc(&ctx->ctrl, sizeof(float4) * kCtrlCap));
+    ctx->ctrl_cap = kCtrlCap;
+  }
+  if (!ctx->ctrl2) HIP_TRY(ctx, hipMalloc(&ctx->ctrl2, sizeof(float2) * 256));
+  return prepare_with(ctx, p, out, PrepMem{ctx->small, ctx->small_host, ctx->ctrl, ctx->ctrl2});
 }
 
 int ensure_buf(slhjb_ctx* ctx, float** b, size_t* cap, size_t elems) {
@@ -406,6 +428,82 @@ int ctx_fail(slhjb_ctx* ctx, int status, const std::string& msg) { return fail(c
 int ctx_hip_fail(slhjb_ctx* ctx, hipError_t e, const char* what) { return hip_fail(ctx, e, what); }
 int ctx_validate(slhjb_ctx* ctx, const slhjb_problem* p) { return validate(ctx, p); }
 }  // namespace slhjb
+
+namespace {
+// Jacobi value iteration from v (device, overwritten) with `other` as the second iterate buffer,
+// `dw` as the device residual / flag words and `hw` as their host mirror.
+int jacobi_run(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P, float* v, float* other,
+               unsigned* dw, unsigned* hw, double tol, int64_t max_sweeps, int32_t check_every, slhjb_stats* stats) {
+  const int64_t N = (int64_t)problem->n * problem->n;
+  if (check_every == 0) check_every = N >= (1 << 20) ? 8 : 16;
+
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  // the caller's array holds w during the iteration
+  HIP_TRY(ctx, launch_v_to_w(v, v, problem->node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle, ctx->stream));
+  float* cur = v;
+  float* nxt = other;
+  int64_t sweeps = 0, converged = -1;
+  double resid = INFINITY, sweep_sec = 0.0;
+  int status = SLHJB_NOT_CONVERGED;
+  while (sweeps < max_sweeps) {
+    const int64_t batch = std::min<int64_t>(check_every, max_sweeps - sweeps);
+    HIP_TRY(ctx, launch_fill_u32(dw, 0u, 2, ctx->stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->eva, ctx->stream));
+    for (int64_t b = 0; b < batch; ++b) {
+      SweepArgs a = P.args;
+      a.w_in = cur;
+      a.w_out = nxt;
+      a.resid = b == batch - 1 ? dw : nullptr;
+      HIP_TRY(ctx, launch_sweep(a, P.diffusion, P.scheme, P.path, ctx->stream));
+      std::swap(cur, nxt);
+    }
+    sweeps += batch;
+    HIP_TRY(ctx, hipEventRecord(ctx->evb, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(hw, dw, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    float bms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&bms, ctx->eva, ctx->evb));
+    sweep_sec += bms * 1e-3;
+    float r;
+    memcpy(&r, &hw[0], sizeof(float));
+    resid = r;
+    if (hw[1] & 1u) {
+      status = SLHJB_E_NONFINITE;
+      break;
+    }
+    if (resid <= tol) {
+      converged = sweeps;
+      status = SLHJB_OK;
+      break;
+    }
+  }
+  if (cur != v) HIP_TRY(ctx, hipMemcpyAsync(v, cur, sizeof(float) * N, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
+  float ms = 0.0f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->converged_sweep = converged;
+    stats->node_updates = sweeps * P.free_nodes;
+    stats->residual = resid;
+    stats->seconds = ms * 1e-3;
+    stats->sweep_seconds = sweep_sec;
+    stats->sweep_launches = sweeps;
+    stats->status = status;
+    stats->kernel_path = P.path;
+    stats->halo = P.args.halo;
+    stats->pad = 0;
+    stats->policy_updates = 0;
+    stats->check_sweeps = 0;
+    stats->check_seconds = 0.0;
+  }
+  if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
+  return status;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -560,75 +658,71 @@ int slhjb_solve(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double t
   const int64_t N = (int64_t)problem->n * problem->n;
   st = ensure_buf(ctx, &ctx->buf, &ctx->buf_elems, (size_t)N);
   if (st != SLHJB_OK) return st;
-  if (check_every == 0) check_every = N >= (1 << 20) ? 8 : 16;
-
-  HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-  // the caller's array holds w during the iteration
-  HIP_TRY(ctx, launch_v_to_w(v, v, problem->node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle, ctx->stream));
-  float* cur = v;
-  float* nxt = ctx->buf;
-  int64_t sweeps = 0, converged = -1;
-  double resid = INFINITY, sweep_sec = 0.0;
-  int status = SLHJB_NOT_CONVERGED;
-  while (sweeps < max_sweeps) {
-    const int64_t batch = std::min<int64_t>(check_every, max_sweeps - sweeps);
-    HIP_TRY(ctx, launch_fill_u32(ctx->small, 0u, 2, ctx->stream));
-    HIP_TRY(ctx, hipEventRecord(ctx->eva, ctx->stream));
-    for (int64_t b = 0; b < batch; ++b) {
-      SweepArgs a = P.args;
-      a.w_in = cur;
-      a.w_out = nxt;
-      a.resid = b == batch - 1 ? ctx->small : nullptr;
-      HIP_TRY(ctx, launch_sweep(a, P.diffusion, P.scheme, P.path, ctx->stream));
-      std::swap(cur, nxt);
-    }
-    sweeps += batch;
-    HIP_TRY(ctx, hipEventRecord(ctx->evb, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    float bms = 0.0f;
-    HIP_TRY(ctx, hipEventElapsedTime(&bms, ctx->eva, ctx->evb));
-    sweep_sec += bms * 1e-3;
-    float r;
-    memcpy(&r, &ctx->small_host[0], sizeof(float));
-    resid = r;
-    if (ctx->small_host[1] & 1u) {
-      status = SLHJB_E_NONFINITE;
-      break;
-    }
-    if (resid <= tol) {
-      converged = sweeps;
-      status = SLHJB_OK;
-      break;
-    }
-  }
-  if (cur != v) HIP_TRY(ctx, hipMemcpyAsync(v, cur, sizeof(float) * N, hipMemcpyDeviceToDevice, ctx->stream));
-  HIP_TRY(ctx, launch_w_to_v(v, v, N, P.vstar, ctx->stream));
-  HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
-  float ms = 0.0f;
-  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  if (stats) {
-    stats->sweeps = sweeps;
-    stats->converged_sweep = converged;
-    stats->node_updates = sweeps * P.free_nodes;
-    stats->residual = resid;
-    stats->seconds = ms * 1e-3;
-    stats->sweep_seconds = sweep_sec;
-    stats->sweep_launches = sweeps;
-    stats->status = status;
-    stats->kernel_path = P.path;
-    stats->halo = P.args.halo;
-    stats->pad = 0;
-    stats->policy_updates = 0;
-    stats->check_sweeps = 0;
-    stats->check_seconds = 0.0;
-  }
-  if (status == SLHJB_E_NONFINITE) return fail(ctx, status, "sweep produced a non-finite value");
-  return status;
+  return jacobi_run(ctx, problem, P, v, ctx->buf, ctx->small, ctx->small_host, tol, max_sweeps, check_every, stats);
 }
 
 }  // extern "C"
+
+// ---- the Jacobi solve without allocation ---------------------------------------------------------
+// Scratch of slhjb_solve_noalloc in a file-scope device array, one copy per device: the second
+// iterate (up to kNoAllocMaxNodes nodes), the padded control table and the residual / statistics
+// words. Host code reaches it only through the address hipGetSymbolAddress returns for the device.
+namespace {
+constexpr int64_t kNoAllocMaxNodes = (int64_t)SLHJB_NOALLOC_MAX_N * SLHJB_NOALLOC_MAX_N;
+constexpr size_t kNoAllocIterBytes = ((sizeof(float) * kNoAllocMaxNodes + 255) / 256) * 256;
+constexpr size_t kNoAllocCtrlBytes = ((sizeof(float4) * kCtrlCap + 255) / 256) * 256;
+constexpr size_t kNoAllocWordBytes = 256;
+constexpr size_t kNoAllocBytes = kNoAllocIterBytes + kNoAllocCtrlBytes + kNoAllocWordBytes;
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// The device address of `scratch` on `device` (which must be current), looked up once per device.
+hipError_t noalloc_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int slhjb_solve_noalloc(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_sweeps,
+                        int32_t check_every, slhjb_stats* stats) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!v) return fail(ctx, SLHJB_E_INVALID_ARG, "v is NULL");
+  if (!(tol >= 0.0) || max_sweeps < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol >= 0 and max_sweeps >= 1");
+  if (check_every < 0 || check_every > 256) return fail(ctx, SLHJB_E_INVALID_ARG, "check_every must be in [0, 256]");
+  if (problem && (int64_t)problem->n * problem->n > kNoAllocMaxNodes)
+    return fail(ctx, SLHJB_E_INVALID_ARG,
+                "slhjb_solve_noalloc takes grids of at most " + std::to_string(SLHJB_NOALLOC_MAX_N) + "^2 nodes");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  unsigned char* base = nullptr;
+  HIP_TRY(ctx, noalloc_scratch(ctx->device, &base));
+  float* other = reinterpret_cast<float*>(base);
+  float4* ctrl = reinterpret_cast<float4*>(base + kNoAllocIterBytes);
+  unsigned* words = reinterpret_cast<unsigned*>(base + kNoAllocIterBytes + kNoAllocCtrlBytes);
+  unsigned host_words[kSmallWords] = {};
+  Prepared P;
+  int st = prepare_with(ctx, problem, &P, PrepMem{words, host_words, ctrl, nullptr});
+  if (st != SLHJB_OK) return st;
+  return jacobi_run(ctx, problem, P, v, other, words, host_words, tol, max_sweeps, check_every, stats);
+}
+
+}  // extern "C"
+
+
 
 namespace {
 

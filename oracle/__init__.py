@@ -55,6 +55,9 @@ class _Problem(ctypes.Structure):
         ("target_value", ctypes.c_double),
         ("v_out", ctypes.c_double),
         ("drift", ctypes.c_void_p),
+        ("running_cost_field", ctypes.c_void_p),
+        ("control_cost", ctypes.c_void_p),
+        ("eps_field", ctypes.c_void_p),
     ]
 
 
@@ -73,6 +76,7 @@ def lib():
         sig = {
             "or_beta": (f64, [P]),
             "or_rho": (f64, [P]),
+            "or_rho_at": (f64, [P, i32, i32]),
             "or_feet": (i32, [P, i32, i32, i32, vp]),
             "or_interp_weights": (i32, [P, f64, f64, vp, vp]),
             "or_interp": (f64, [P, vp, f64, f64]),
@@ -85,6 +89,7 @@ def lib():
             "or_synthesize": (None, [P, vp, vp, vp]),
             "or_policy_chain": (None, [P, vp, vp, vp, vp, i32]),
             "or_policy_improve": (i64, [P, vp, vp, i32]),
+            "or_rho_policy": (None, [P, vp, vp]),
             "or_upsample_bilinear": (None, [i32, vp, i32, vp]),
             "or_displacement": (None, [i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]),
             "or_label": (i64, [i32, vp, vp, vp, i32, i32, vp, vp]),
@@ -123,12 +128,22 @@ class Problem:
     target_value: float = 0.0
     v_out: float = 1.0
     drift: np.ndarray | None = None  # (n, n, 2) or None
+    running_cost_field: np.ndarray | None = None  # (n, n): l_x per node, or None = running_cost
+    control_cost: np.ndarray | None = None  # (N_A,): l_a per control, or None = 0
+    eps_field: np.ndarray | None = None  # (n, n): eps(x) per node, or None = eps
 
     def __post_init__(self):
         self.controls = np.ascontiguousarray(self.controls, dtype=np.float64).reshape(-1, 2)
         if self.drift is not None:
             self.drift = np.ascontiguousarray(self.drift, dtype=np.float64).reshape(-1)
             assert self.drift.size == 2 * self.n * self.n
+        for name, size in (("running_cost_field", self.n * self.n), ("control_cost", self.controls.shape[0]),
+                           ("eps_field", self.n * self.n)):
+            a = getattr(self, name)
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+                assert a.size == size, name
+                setattr(self, name, a)
         self.speed = np.ascontiguousarray(self.speed, dtype=np.float64).reshape(-1)
         self.node_class = np.ascontiguousarray(self.node_class, dtype=np.uint8).reshape(-1)
         assert self.speed.size == self.n * self.n and self.node_class.size == self.n * self.n
@@ -137,7 +152,9 @@ class Problem:
         return _Problem(self.n, self.x_lo, self.x_hi, self.h, self.lam, self.eps, self.diffusion,
                         self.scheme, self.controls.shape[0], _ptr(self.controls), _ptr(self.speed),
                         self.running_cost, _ptr(self.node_class), self.target_value, self.v_out,
-                        _ptr(self.drift) if self.drift is not None else None)
+                        _ptr(self.drift) if self.drift is not None else None,
+                        *[_ptr(a) if a is not None else None
+                          for a in (self.running_cost_field, self.control_cost, self.eps_field)])
 
     @classmethod
     def from_instance(cls, inst, scheme: int = SL3) -> "Problem":
@@ -147,7 +164,9 @@ class Problem:
                    controls=inst.controls.astype(np.float64), speed=inst.speed.astype(np.float64),
                    node_class=inst.node_class, running_cost=float(inst.running_cost),
                    target_value=float(inst.target_value), v_out=float(inst.v_out),
-                   drift=None if getattr(inst, "drift", None) is None else inst.drift.astype(np.float64))
+                   drift=None if getattr(inst, "drift", None) is None else inst.drift.astype(np.float64),
+                   **{k: (None if getattr(inst, k, None) is None else getattr(inst, k).astype(np.float64))
+                      for k in ("running_cost_field", "control_cost", "eps_field")})
 
     # ---- thin wrappers -------------------------------------------------------------------
     def beta(self) -> float:
@@ -157,6 +176,19 @@ class Problem:
     def rho(self) -> float:
         s = self.c_struct()
         return lib().or_rho(ctypes.byref(s))
+
+    def rho_table(self) -> np.ndarray:
+        """(N, N_A) running cost of one step at every node under every control (eq. SLscheme2:
+        (1-beta) l / lambda, or h l for lambda = 0, with l = l_x(x) + l_a(a))."""
+        s = self.c_struct()
+        N, NA = self.n * self.n, self.controls.shape[0]
+        if self.running_cost_field is None and self.control_cost is None:
+            return np.full((N, NA), lib().or_rho(ctypes.byref(s)))
+        out = np.empty((N, NA))
+        for node in range(N):
+            for m in range(NA):
+                out[node, m] = lib().or_rho_at(ctypes.byref(s), node, m)
+        return out
 
     def initial(self, free_value: float = 1.0) -> np.ndarray:
         v = np.full(self.n * self.n, free_value, dtype=np.float64)
@@ -243,6 +275,14 @@ class Problem:
         wo = np.empty(N, dtype=np.float64)
         lib().or_policy_chain(ctypes.byref(s), _ptr(pol), _ptr(idx), _ptr(w), _ptr(wo), threads)
         return idx, w, wo
+
+    def rho_policy(self, policy: np.ndarray) -> np.ndarray:
+        """Step cost of every node under its control policy[node] (0 off the FREE nodes)."""
+        s = self.c_struct()
+        pol = np.ascontiguousarray(policy, dtype=np.int32).reshape(-1)
+        out = np.empty(self.n * self.n, dtype=np.float64)
+        lib().or_rho_policy(ctypes.byref(s), _ptr(pol), _ptr(out))
+        return out
 
     def policy_improve(self, v: np.ndarray, policy: np.ndarray, threads: int = 1) -> int:
         """Greedy improvement of policy (int32[N], changed in place) at v; returns the changes."""

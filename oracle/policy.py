@@ -1,7 +1,8 @@
 """Exact fixed points of the discounted scheme on tiny grids (TEST INFRASTRUCTURE ONLY).
 
 For a fixed policy pi (one control per FREE node) the scheme of Section 3 in its SL2 form is
-a linear system: v = beta P_pi v + rho + beta p_out v_out on FREE nodes, with TARGET and
+a linear system: v = beta P_pi v + rho_pi + beta p_out v_out on FREE nodes (rho_pi the step cost
+of each node under its control), with TARGET and
 OBSTACLE values known. Howard's policy iteration alternates an exact solve of that system
 (LAPACK Gaussian elimination with partial pivoting) with a greedy improvement; on a finite
 discounted Markov decision problem it stops at the optimal value in finitely many steps.
@@ -41,8 +42,11 @@ def _fixed_values(p: Problem) -> np.ndarray:
     return v
 
 
-def evaluate(p: Problem, free, P, pout, policy) -> np.ndarray:
-    beta, rho = p.beta(), p.rho()
+def evaluate(p: Problem, free, P, pout, policy, rho_t=None) -> np.ndarray:
+    beta = p.beta()
+    if rho_t is None:
+        rho_t = p.rho_table()[free]
+    rho = rho_t[np.arange(free.size), policy]
     fixed = _fixed_values(p)
     rows = P[np.arange(free.size), policy]  # (F, N)
     A = np.eye(free.size) - beta * rows[:, free]
@@ -57,10 +61,10 @@ def evaluate(p: Problem, free, P, pout, policy) -> np.ndarray:
 def policy_iteration(p: Problem, max_iter: int = 1000):
     """Howard's policy iteration on the SL2 form. Returns (v, policy, iterations)."""
     free, P, pout = _chain(p)
-    beta, rho = p.beta(), p.rho()
+    beta, rho = p.beta(), p.rho_table()[free]  # rho: (F, NA)
     policy = np.zeros(free.size, dtype=np.int64)
     for it in range(1, max_iter + 1):
-        v = evaluate(p, free, P, pout, policy)
+        v = evaluate(p, free, P, pout, policy, rho)
         q = beta * (P @ v + pout * p.v_out) + rho  # (F, NA)
         cur = q[np.arange(free.size), policy]
         best = q.argmin(axis=1)
@@ -77,7 +81,7 @@ def brute_force(p: Problem, chunk: int = 8192):
     free, P, pout = _chain(p)
     NA = p.controls.shape[0]
     F = free.size
-    beta, rho = p.beta(), p.rho()
+    beta, rho = p.beta(), p.rho_table()[free]  # rho: (F, NA)
     fixed = _fixed_values(p)
     mask = np.ones(p.n * p.n, dtype=bool)
     mask[free] = False
@@ -118,7 +122,7 @@ def sparse_policy_iteration(p: Problem, v0: np.ndarray | None = None, threads: i
     pos = np.full(N, -1, dtype=np.int64)
     pos[free] = np.arange(F)
     fixed = _fixed_values(p)
-    beta, rho = p.beta(), p.rho()
+    beta = p.beta()
     policy = np.zeros(N, dtype=np.int32)
     p.policy_improve(p.initial() if v0 is None else v0, policy, threads)
     rows = np.repeat(np.arange(F), 16).reshape(F, 16)
@@ -130,6 +134,7 @@ def sparse_policy_iteration(p: Problem, v0: np.ndarray | None = None, threads: i
         to_free = valid & (p.node_class[col] == FREE)
         to_fixed = valid & ~to_free
         A = sp.csr_matrix((-beta * w[to_free], (rows[to_free], pos[col[to_free]])), shape=(F, F)) + sp.eye(F)
+        rho = p.rho_policy(policy)[free]
         b = rho + beta * (wo * p.v_out + (np.where(to_fixed, w, 0.0) * fixed[col]).sum(axis=1))
         v = fixed.copy()
         v[free] = spla.spsolve(A.tocsc(), b)

@@ -12,8 +12,10 @@
  *   feet     y = x_i + h c(x_i) a + s sqrt(h) sigma_k(x_i,a),  s = +-1, k = 1..d
  *   SL2      v_i = min_a [ beta * (1/2d) sum_{k,s} I[v](y) + rho ]
  *   SL3      v_i = min_a (beta Lambda1(a) + rho) / (1 - beta Lambda0(a))     (eq. SLscheme3)
- * with beta = fl32(exp(-lambda h)), rho = (1-beta) l / lambda. With beta -> 1 and
- * rho -> h l this is the undiscounted scheme printed in Section 3.
+ * with beta = fl32(exp(-lambda h)), rho = (1-beta) l / lambda for lambda > 0, and for
+ * lambda = 0 beta = 1, rho = h l: the undiscounted scheme exactly as printed in Section 3.
+ * The running cost l(x,a) = l_x(x) + l_a(a) and the diffusion coefficient eps(x) may vary
+ * (Sections 5.2-5.3).
  */
 #include "slhjb_oracle.h"
 
@@ -27,8 +29,22 @@ static double or_dx(const or_problem* p) { return (p->x_hi - p->x_lo) / (double)
  * discrete problem both sides solve carries the float rounding of this number. */
 double or_beta(const or_problem* p) { return (double)(float)exp(-p->lambda * p->h); }
 
-/* Running cost collected over one step in the discounted form: (1-beta) l / lambda. */
-double or_rho(const or_problem* p) { return (1.0 - or_beta(p)) * p->running_cost / p->lambda; }
+/* Running cost collected over one step: (1-beta) l / lambda in the discounted form, h l in the
+ * undiscounted one (lambda = 0, eq. SLscheme2 as printed). */
+static double or_step_cost(const or_problem* p, double l) {
+    if (p->lambda == 0.0) return p->h * l;
+    return (1.0 - or_beta(p)) * l / p->lambda;
+}
+
+/* For a constant running cost (no per-node or per-control part). */
+double or_rho(const or_problem* p) { return or_step_cost(p, p->running_cost); }
+
+/* At FREE node `node` under control m: l(x,a) = l_x(x_node) + l_a(a_m). */
+double or_rho_at(const or_problem* p, int32_t node, int32_t m) {
+    double l = p->running_cost_field ? p->running_cost_field[node] : p->running_cost;
+    if (p->control_cost) l += p->control_cost[m];
+    return or_step_cost(p, l);
+}
 
 /* Feet of node (i,j) under control m (eq. SLscheme2, first line). Dynamics
  * f = c(x) (d(x) + a): the drift d of the advection and Zermelo examples (Section 5), 0 if absent.
@@ -48,7 +64,8 @@ int32_t or_feet(const or_problem* p, int32_t i, int32_t j, int32_t m, double* y)
     const double d2 = p->drift ? p->drift[2 * ((int64_t)j * p->n + i) + 1] : 0.0;
     const double b1 = x1 + p->h * c * (d1 + a1);
     const double b2 = x2 + p->h * c * (d2 + a2);
-    const double d = sqrt(2.0 * p->eps * p->h);
+    const double eps = p->eps_field ? p->eps_field[(int64_t)j * p->n + i] : p->eps;
+    const double d = sqrt(2.0 * eps * p->h);
     switch (p->diffusion) {
     case OR_DIFF_ISO:
         y[0] = b1 + d; y[1] = b2;
@@ -119,7 +136,7 @@ double or_one_step_mean(const or_problem* p, const double* v, int32_t node, int3
  * with weight 1 to Lambda1. */
 double or_candidate(const or_problem* p, const double* v, int32_t node, int32_t m) {
     const double beta = or_beta(p);
-    const double rho = or_rho(p);
+    const double rho = or_rho_at(p, node, m);
     double y[8];
     const int32_t K = or_feet(p, node % p->n, node / p->n, m, y);
     double mean = 0.0, lam0 = 0.0, lam1 = 0.0;
@@ -263,6 +280,13 @@ void or_policy_chain(const or_problem* p, const int32_t* policy, int32_t* idx, d
         if (p->node_class[node] != OR_FREE) continue;
         or_transitions(p, (int32_t)node, policy[node], ri, rw, &w_out[node]);
     }
+}
+
+/* The step cost of every node under its control policy[node] (0 on nodes that are not FREE). */
+void or_rho_policy(const or_problem* p, const int32_t* policy, double* out) {
+    const int64_t N = (int64_t)p->n * p->n;
+    for (int64_t node = 0; node < N; ++node)
+        out[node] = p->node_class[node] == OR_FREE ? or_rho_at(p, (int32_t)node, policy[node]) : 0.0;
 }
 
 /* Greedy improvement at v: every FREE node takes a control of smallest eq. SLscheme2 candidate,
@@ -450,9 +474,10 @@ double or_sweep_independent(const or_problem* p, const int16_t* label, const dou
             continue;
         }
         /* the node's view of the grid: own-patch values, v_out elsewhere */
-        const double beta = or_beta(p), rho = or_rho(p);
+        const double beta = or_beta(p);
         double best = INFINITY;
         for (int32_t m = 0; m < p->n_controls; ++m) {
+            const double rho = or_rho_at(p, (int32_t)node, m);
             double y[8];
             const int32_t K = or_feet(p, (int32_t)(node % p->n), (int32_t)(node / p->n), m, y);
             double mean = 0.0, lam0 = 0.0, lam1 = 0.0;

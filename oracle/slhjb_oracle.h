@@ -30,8 +30,8 @@ typedef struct {
     int32_t n;
     double x_lo, x_hi;
     double h;              /* time step of the scheme */
-    double lambda;         /* discount rate (>0) */
-    double eps;            /* diffusion coefficient */
+    double lambda;         /* discount rate (>= 0; 0 = the undiscounted scheme of Section 3) */
+    double eps;            /* diffusion coefficient (when eps_field is NULL) */
     int32_t diffusion;     /* OR_DIFF_* */
     int32_t scheme;        /* OR_SL2 / OR_SL3 */
     int32_t n_controls;
@@ -42,10 +42,17 @@ typedef struct {
     double target_value;           /* g on TARGET nodes */
     double v_out;                  /* value at feet outside the closed box; held by OBSTACLE nodes */
     const double* drift;           /* [2*n*n] (d_1, d_2) per node, or NULL */
+    /* Section 5.2-5.3: costs and diffusion that depend on the state and the control. The
+     * running cost is l(x,a) = l_x(x) + l_a(a) (the paper's l_1, l_2, l_3 all have this form);
+     * the diffusion coefficient may vary over the nodes (eps(x), degenerate where it is 0). */
+    const double* running_cost_field;  /* [n*n] l_x per node, or NULL = running_cost */
+    const double* control_cost;        /* [n_controls] l_a per control, or NULL = 0 */
+    const double* eps_field;           /* [n*n] eps(x) per node, or NULL = eps */
 } or_problem;
 
 double or_beta(const or_problem* p);
 double or_rho(const or_problem* p);
+double or_rho_at(const or_problem* p, int32_t node, int32_t m);
 int32_t or_feet(const or_problem* p, int32_t i, int32_t j, int32_t m, double* y /* [4][2] */);
 int32_t or_interp_weights(const or_problem* p, double y1, double y2, int32_t* idx /*[4]*/, double* w /*[4]*/);
 double or_interp(const or_problem* p, const double* v, double y1, double y2);
@@ -60,6 +67,7 @@ int32_t or_transitions(const or_problem* p, int32_t node, int32_t m, int32_t* id
                        double* w /*[16]*/, double* w_out);
 void or_policy_chain(const or_problem* p, const int32_t* policy, int32_t* idx /*[N][16]*/, double* w /*[N][16]*/,
                      double* w_out /*[N]*/, int32_t n_threads);
+void or_rho_policy(const or_problem* p, const int32_t* policy, double* out /*[N]*/);
 int64_t or_policy_improve(const or_problem* p, const double* v, int32_t* policy, int32_t n_threads);
 void or_synthesize(const or_problem* p, const double* v_hat, int32_t* ctrl_out, double* gap_out);
 void or_upsample_bilinear(int32_t n_c, const double* v_c, int32_t n_f, double* v_f);

@@ -38,6 +38,10 @@ class Instance:
     v_out: np.float32 = np.float32(1.0)
     meta: dict = field(default_factory=dict)
     drift: np.ndarray | None = None  # float32 (n, n, 2): f(x,a) = c(x) (drift(x) + a); None = no drift
+    # Sections 5.2-5.3: l(x,a) = l_x(x) + l_a(a) and a diffusion coefficient eps(x) per node
+    running_cost_field: np.ndarray | None = None  # float32 (n, n): l_x; None = running_cost
+    control_cost: np.ndarray | None = None  # float32 (N_A,): l_a; None = 0
+    eps_field: np.ndarray | None = None  # float32 (n, n): eps(x); None = eps
 
     @property
     def dx(self) -> float:
@@ -321,9 +325,11 @@ def exit_dynamics(n: int, dynamics: str, eta: float = 1.0, theta: float = math.p
 
 
 def exit_problem(n: int, dynamics: str = "B", eps: float = 0.0, eta: float = 1.0, theta: float = math.pi / 4,
-                 n_controls: int = 16, h: float | None = None, diffusion: int = DIFF_ISO) -> Instance:
+                 n_controls: int = 16, h: float | None = None, diffusion: int = DIFF_ISO,
+                 lam: float = 1.0) -> Instance:
     """Exit time from [-1,1]^2 with g = 0 (Section 5). h defaults to the paper's choice
-    h = alpha dx / f_min with alpha = 1 / (1 + Upsilon), Upsilon = f_max / f_min."""
+    h = alpha dx / f_min with alpha = 1 / (1 + Upsilon), Upsilon = f_max / f_min. lam = 1: the
+    Kruzkov form v = 1 - exp(-T); lam = 0: the undiscounted scheme of the paper, v = T."""
     speed, drift, ctrl, fmin, fmax = exit_dynamics(n, dynamics, eta, theta, n_controls)
     dx = 2.0 / (n - 1)
     if h is None:
@@ -332,4 +338,43 @@ def exit_problem(n: int, dynamics: str = "B", eps: float = 0.0, eta: float = 1.0
     cls[0, :] = cls[-1, :] = cls[:, 0] = cls[:, -1] = TARGET
     return Instance(n=n, h=np.float32(h), eps=np.float32(eps), diffusion=diffusion if eps > 0 else DIFF_NONE,
                     controls=ctrl, speed=speed, node_class=cls, v_out=np.float32(0.0), drift=drift,
+                    lam=np.float32(lam),
                     meta=dict(workload=f"exit {dynamics}", f_min=fmin, f_max=fmax, eta=eta, theta=theta))
+
+
+def degenerate_problem(n: int, eps: float = 0.1, n_controls: int = 16, lam: float = 0.0) -> Instance:
+    """Section 5.2: the eikonal-diffusion exit problem with c = 1 + chi{x_1 >= 0} and the diffusion
+    coefficient eps(x) = eps chi{x_2 >= 0} (elliptic in the upper half, hyperbolic below), isotropic
+    noise, g = 0 on the boundary, l = 1, h by the paper's rule."""
+    x = exit_problem(n, "B2", eps=eps, n_controls=n_controls, lam=lam)
+    _, X2 = node_coords(n)
+    x.eps_field = np.where(X2 >= 0.0, np.float32(eps), np.float32(0.0)).astype(np.float32)
+    x.meta["workload"] = "degenerate diffusion"
+    return x
+
+
+def general_problem(n: int, cost: int = 1, sigma: int = 1, eps: float = 0.1, n_controls: int = 16,
+                    lam: float = 0.0) -> Instance:
+    """Section 5.3: f = c(x) a with c = 1 + max{x_2, max{x_1, 0}} (eq. nonomog), exit from the box
+    with g = 0, diffusion sigma_1 = 0, sigma_2 = d_eps(x) I, sigma_3 = d_eps(x) a with
+    d_eps = sqrt(2 eps) chi{x_2 >= 0} (eq. s123), running costs l_1 = 1, l_2 = 1 + |x_1 x_2|,
+    l_3 = l_2 + |a_1 / (2 + a_2)| (eq. l123). The paper does not print eps for this test; 0.1 is the
+    value of its degenerate-diffusion test. h by the paper's rule with f_min = 1, f_max = 2."""
+    X1, X2 = node_coords(n)
+    c = (1.0 + np.maximum(X2, np.maximum(X1, 0.0))).astype(np.float32)
+    ctrl = control_table(n_controls)
+    dx = 2.0 / (n - 1)
+    h = dx / (1.0 + 2.0)
+    cls = np.zeros((n, n), dtype=np.uint8)
+    cls[0, :] = cls[-1, :] = cls[:, 0] = cls[:, -1] = TARGET
+    diffusion = {1: DIFF_NONE, 2: DIFF_ISO, 3: DIFF_RANK1}[sigma]
+    x = Instance(n=n, h=np.float32(h), eps=np.float32(eps if sigma > 1 else 0.0), diffusion=diffusion,
+                 controls=ctrl, speed=c, node_class=cls, v_out=np.float32(0.0), lam=np.float32(lam),
+                 meta=dict(workload=f"general l{cost} sigma{sigma}", f_min=1.0, f_max=2.0))
+    if sigma > 1:
+        x.eps_field = np.where(X2 >= 0.0, np.float32(eps), np.float32(0.0)).astype(np.float32)
+    if cost >= 2:
+        x.running_cost_field = (1.0 + np.abs(X1 * X2)).astype(np.float32)
+    if cost == 3:
+        x.control_cost = np.abs(ctrl[:, 0].astype(np.float64) / (2.0 + ctrl[:, 1].astype(np.float64))).astype(np.float32)
+    return x

@@ -250,8 +250,9 @@ PAPER_TABLE0 = {("A", 0.0): (176, 2), ("A", 1e-2): (458, 102), ("B", 0.0): (145,
 
 
 def arm_exit(ctx, tol: float) -> dict:
-    """The paper's exit-to-boundary experiments (Section 5): g = 0 on the boundary, l = 1, 16
-    controls, h = dx / (1 + Upsilon) / f_min. (1) Table 0: Jacobi sweeps of SL2 and SL3 for the
+    """The paper's exit-to-boundary experiments (Section 5) in the paper's own undiscounted form
+    (lambda = 0: beta = 1, rho = h l): g = 0 on the boundary, l = 1, 16 controls,
+    h = dx / (1 + Upsilon) / f_min. (1) Table 0: Jacobi sweeps of SL2 and SL3 for the
     advection (A), eikonal (B, B2) and Zermelo (C) dynamics at eps = 0 and 1e-2 on 50 x 50 nodes.
     (2) Tables 1 and 2: the patchy solve (coarse 51^2 sigma = 0 solve, u_hat, tiles by increasing
     u_hat) against the static decomposition (cold, fixed order) over eps, on 101^2 and 201^2
@@ -264,11 +265,12 @@ def arm_exit(ctx, tol: float) -> dict:
 
     out = {"table0": [], "threshold": {}}
     for (dyn, eps), (p2, p3) in PAPER_TABLE0.items():
-        x = I.exit_problem(50, dyn, eps=eps)
-        row = {"equation": dyn, "eps": eps, "paper_gauss_seidel_sl2_sl3": [p2, p3]}
+        x = I.exit_problem(50, dyn, eps=eps, lam=0.0)
+        row = {"equation": dyn, "eps": eps, "lambda": 0.0, "paper_gauss_seidel_sl2_sl3": [p2, p3]}
         for name, scheme in (("sl2", capi.SL2), ("sl3", capi.SL3)):
             dp = capi.DeviceProblem(x, scheme)
-            v = torch.from_numpy(x.initial().reshape(-1)).cuda()
+            # the undiscounted cold start: v = 0 (boundary data 0), from which the iterates climb
+            v = torch.from_numpy(x.initial(free_value=0.0).reshape(-1)).cuda()
             st = ctx.solve(dp, v, tol=tol, max_sweeps=1_000_000, check_every=1)
             row[f"jacobi_sweeps_{name}"] = st["converged_sweep"] if st["status"] == 0 else None
         out["table0"].append(row)
@@ -281,8 +283,8 @@ def arm_exit(ctx, tol: float) -> dict:
             dx = 2.0 / (n - 1)
             rows = []
             for eps in eps_list:
-                fine = I.exit_problem(n, dyn, eps=eps)
-                coarse = I.exit_problem(51, dyn, eps=0.0)
+                fine = I.exit_problem(n, dyn, eps=eps, lam=0.0)
+                coarse = I.exit_problem(51, dyn, eps=0.0, lam=0.0)
                 free = int((fine.node_class == 0).sum())
                 dp, dpc = capi.DeviceProblem(fine, capi.SL3), capi.DeviceProblem(coarse, capi.SL3)
                 row = {"eps": eps}

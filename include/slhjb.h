@@ -11,7 +11,10 @@
  *
  * with beta = exp(-lambda h) rounded to float, rho = (1 - beta) l / lambda, I[.] the
  * bilinear reconstruction on the grid (v_out outside the closed box), Lambda0 the node's own
- * interpolation weight averaged over the feet and Lambda1 the rest (eq. SLimplicit).
+ * interpolation weight averaged over the feet and Lambda1 the rest (eq. SLimplicit). With
+ * lambda = 0 the scheme is the undiscounted one exactly as Section 3 prints it: beta = 1,
+ * rho = h l. The running cost may depend on the state and the control, l(x,a) = l_x(x) + l_a(a),
+ * and the diffusion coefficient on the state, eps(x) (Sections 5.2-5.3).
  *
  * Conventions for every entry point:
  *  - Grids are n x n nodes on [x_lo, x_hi]^2, node (i,j) at (x_lo + i dx, x_lo + j dx),
@@ -81,15 +84,17 @@ typedef struct {
     int32_t n;                  /* nodes per side, 3 <= n <= 32769                             */
     float x_lo, x_hi;           /* the box [x_lo, x_hi]^2, x_lo < x_hi                           */
     float h;                    /* time step, > 0                                                */
-    float lambda;               /* discount rate, > 0 (1 = Kruzkov minimum time)                 */
-    float eps;                  /* diffusion coefficient, >= 0 (ignored for SLHJB_DIFF_NONE)     */
+    float lambda;               /* discount rate, >= 0 (1 = Kruzkov minimum time; 0 = the
+                                   undiscounted scheme of Section 3: beta = 1, rho = h l)        */
+    float eps;                  /* diffusion coefficient, >= 0 (ignored for SLHJB_DIFF_NONE and
+                                   where eps_field is given)                                     */
     int32_t diffusion;          /* SLHJB_DIFF_*                                                  */
     int32_t scheme;             /* SLHJB_SCHEME_*                                                */
     int32_t n_controls;         /* 1 <= N_A <= 256                                               */
     const float* controls;      /* host float[2*N_A]: a_m = (controls[2m], controls[2m+1])       */
     const float* speed;         /* device float[n*n], c(x_i) > 0 finite; NULL = speed_const      */
     float speed_const;          /* c when speed == NULL, > 0                                     */
-    float running_cost;         /* l > 0 (constant)                                              */
+    float running_cost;         /* l > 0 where running_cost_field is NULL                        */
     const uint8_t* node_class;  /* device uint8[n*n] of SLHJB_FREE / _TARGET / _OBSTACLE         */
     float target_value;         /* g on TARGET nodes                                             */
     float v_out;                /* value at feet outside the closed box and on OBSTACLE nodes    */
@@ -101,6 +106,17 @@ typedef struct {
                                  * slhjb_synthesize, slhjb_label, patch labels in
                                  * slhjb_solve_patchy and slhjb_solve_batch reject a drift
                                  * (SLHJB_E_UNSUPPORTED). NULL: f(x,a) = c(x) a.            */
+    /* Costs and diffusion that vary (Sections 5.2 "Degenerate diffusion" and 5.3 "General
+     * nonlinear problems"). Any of them, and lambda = 0, take the general kernels (kernel path 2);
+     * the batched solve rejects them, the active-tile solver takes them in the transmission mode
+     * with host-driven passes only, and slhjb_synthesize / slhjb_label (patch labels) reject a
+     * control cost (SLHJB_E_UNSUPPORTED).                                                        */
+    const float* running_cost_field; /* device float[n*n]: l_x(x_i) > 0 finite per node, replacing
+                                        running_cost; or NULL                                     */
+    const float* control_cost;       /* host float[N_A]: l_a(a_m) >= 0 finite added to the running
+                                        cost under control m; or NULL (0)                          */
+    const float* eps_field;          /* device float[n*n]: eps(x_i) >= 0 finite per node, replacing
+                                        eps (degenerate diffusion where it is 0); or NULL          */
 } slhjb_problem;
 
 typedef struct {
@@ -112,7 +128,9 @@ typedef struct {
     double sweep_seconds;       /* device time spent in the batches of sweep kernels              */
     int64_t sweep_launches;     /* sweep kernel launches inside sweep_seconds                     */
     int32_t status;             /* SLHJB_OK / SLHJB_NOT_CONVERGED / error                         */
-    int32_t kernel_path;        /* 0 general halo-tile kernel, 1 first-ring register kernel       */
+    int32_t kernel_path;        /* 0 general halo-tile kernel, 1 first-ring register kernel,
+                                   2 general kernel with the cost term and per-node noise (varying
+                                   costs, lambda = 0 or an eps field)                               */
     int32_t halo;               /* interpolation halo of the LDS tile, in cells                   */
     int32_t pad;
     int64_t policy_updates;     /* node updates of policy-evaluation iterations (one control each;
@@ -416,7 +434,8 @@ int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx
 
 /* Largest distance, in cells along either axis, between a FREE node and any of its feet, for
  * speeds bounded by speed_max (host computation). Used to size the interpolation halo. A drift
- * (device data) is not included: the solvers add max_x h c(x) |d(x)|_inf / dx from a device pass. */
+ * and a diffusion-coefficient field (device data) are not included: the solvers add
+ * max_x h c(x) |d(x)|_inf / dx and take the largest eps(x) from a device pass. */
 double slhjb_foot_reach(const slhjb_problem* problem, float speed_max);
 
 #ifdef __cplusplus

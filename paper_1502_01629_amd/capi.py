@@ -45,6 +45,9 @@ class Problem(ctypes.Structure):
         ("target_value", ctypes.c_float),
         ("v_out", ctypes.c_float),
         ("drift", ctypes.c_void_p),
+        ("running_cost_field", ctypes.c_void_p),
+        ("control_cost", ctypes.c_void_p),
+        ("eps_field", ctypes.c_void_p),
     ]
 
 
@@ -309,6 +312,12 @@ class DeviceProblem:
         drift = getattr(inst, "drift", None)
         self.drift = None if drift is None else \
             torch.from_numpy(np.ascontiguousarray(drift, dtype=np.float32).reshape(-1)).to(device)
+        dev = lambda a: None if a is None else \
+            torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32).reshape(-1)).to(device)
+        self.running_cost_field = dev(getattr(inst, "running_cost_field", None))
+        self.eps_field = dev(getattr(inst, "eps_field", None))
+        cc = getattr(inst, "control_cost", None)
+        self.control_cost = None if cc is None else np.ascontiguousarray(cc, dtype=np.float32).reshape(-1)
         self.scheme = scheme
         self.struct = self._make()
 
@@ -333,7 +342,10 @@ class DeviceProblem:
             n_controls=int(self.controls.size // 2), controls=self.controls.ctypes.data, speed=_ptr(self.speed),
             speed_const=1.0, running_cost=float(inst.running_cost), node_class=_ptr(self.node_class),
             target_value=float(inst.target_value), v_out=float(inst.v_out),
-            drift=_ptr(self.drift) if self.drift is not None else None)
+            drift=_ptr(self.drift) if self.drift is not None else None,
+            running_cost_field=_ptr(self.running_cost_field) if self.running_cost_field is not None else None,
+            control_cost=self.control_cost.ctypes.data if self.control_cost is not None else None,
+            eps_field=_ptr(self.eps_field) if self.eps_field is not None else None)
 
     def with_scheme(self, scheme: int) -> "DeviceProblem":
         self.scheme = scheme

@@ -180,8 +180,8 @@ int validate(slhjb_ctx* ctx, const slhjb_problem* p) {
   if (!(isfinite(p->x_lo) && isfinite(p->x_hi) && p->x_lo < p->x_hi))
     return fail(ctx, SLHJB_E_INVALID_ARG, "need finite x_lo < x_hi");
   if (!(p->h > 0.0f) || !isfinite(p->h)) return fail(ctx, SLHJB_E_INVALID_ARG, "h must be finite and > 0");
-  if (!(p->lambda > 0.0f) || !isfinite(p->lambda))
-    return fail(ctx, SLHJB_E_UNSUPPORTED, "only the discounted form (lambda > 0) is implemented");
+  if (!(p->lambda >= 0.0f) || !isfinite(p->lambda))
+    return fail(ctx, SLHJB_E_INVALID_ARG, "lambda must be finite and >= 0");
   if (!(p->eps >= 0.0f) || !isfinite(p->eps)) return fail(ctx, SLHJB_E_INVALID_ARG, "eps must be finite and >= 0");
   if (p->diffusion < 0 || p->diffusion > 2) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown diffusion kind");
   if (p->scheme < 0 || p->scheme > 1) return fail(ctx, SLHJB_E_INVALID_ARG, "unknown scheme");
@@ -193,6 +193,10 @@ int validate(slhjb_ctx* ctx, const slhjb_problem* p) {
     return fail(ctx, SLHJB_E_INVALID_ARG, "speed_const must be finite and > 0");
   if (!(p->running_cost > 0.0f) || !isfinite(p->running_cost))
     return fail(ctx, SLHJB_E_INVALID_ARG, "running_cost must be finite and > 0");
+  if (p->control_cost)
+    for (int m = 0; m < p->n_controls; ++m)
+      if (!(p->control_cost[m] >= 0.0f) || !isfinite(p->control_cost[m]))
+        return fail(ctx, SLHJB_E_INVALID_ARG, "control_cost must be finite and >= 0");
   if (!p->node_class) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class is NULL");
   if (!isfinite(p->target_value) || !isfinite(p->v_out))
     return fail(ctx, SLHJB_E_INVALID_ARG, "target_value and v_out must be finite");
@@ -201,16 +205,28 @@ int validate(slhjb_ctx* ctx, const slhjb_problem* p) {
 
 double grid_dx(const slhjb_problem* p) { return ((double)p->x_hi - (double)p->x_lo) / (double)(p->n - 1); }
 
-double reach_for(const slhjb_problem* p, double speed_max) {
+// A problem the first-ring and batched kernels do not take: varying costs, the undiscounted form
+// or a diffusion coefficient field (the general kernels carry the cost term and per-node noise).
+bool has_general_terms(const slhjb_problem* p) {
+  return p->lambda == 0.0f || p->running_cost_field || p->control_cost || p->eps_field;
+}
+
+double reach_for(const slhjb_problem* p, double speed_max, double eps_max) {
   // distance in cells along either axis between a node and its farthest foot
   const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
   const double r = (double)(p->h / dx32);
   const double k = r * speed_max;
   double amax = 0.0;
   for (int m = 0; m < 2 * p->n_controls; ++m) amax = std::max(amax, fabs((double)p->controls[m]));
-  const double d = p->diffusion == SLHJB_DIFF_NONE ? 0.0 : sqrt(2.0 * (double)p->eps * (double)p->h) / grid_dx(p);
+  const double d = p->diffusion == SLHJB_DIFF_NONE ? 0.0 : sqrt(2.0 * eps_max * (double)p->h) / grid_dx(p);
   if (p->diffusion == SLHJB_DIFF_RANK1) return (k + d) * amax;
   return k * amax + d;
+}
+
+// The start of a cold solve: the Kruzkov "+infinity" v = l / lambda (the time to reach the target
+// is infinite), or v = 0 without discount, where the iteration then climbs to the exit times.
+float cold_start_value(const slhjb_problem* p) {
+  return p->lambda == 0.0f ? 0.0f : (float)((double)p->running_cost / (double)p->lambda);
 }
 
 int ensure_small(slhjb_ctx* ctx) {
@@ -240,15 +256,23 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
   if (p->drift && (reinterpret_cast<uintptr_t>(p->drift) & 7u))
     return fail(ctx, SLHJB_E_INVALID_ARG, "drift must be 8-byte aligned");
   HIP_TRY(ctx, launch_fill_u32(M.dw + 2, 0x7f7fffffu, 1, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32(M.dw + 3, 0u, 6, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32(M.dw + 3, 0u, 10, ctx->stream));
   HIP_TRY(ctx, launch_problem_stats(p->speed, p->node_class, reinterpret_cast<const float2*>(p->drift),
                                     p->speed_const, N, M.dw + 2, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(M.hw + 2, M.dw + 2, sizeof(unsigned) * 7, hipMemcpyDeviceToHost,
+  // [9..10] running-cost field max / bad, [11..12] diffusion-coefficient field max / bad
+  if (p->running_cost_field) HIP_TRY(ctx, launch_field_stats(p->running_cost_field, N, 1, M.dw + 9, ctx->stream));
+  if (p->eps_field) HIP_TRY(ctx, launch_field_stats(p->eps_field, N, 0, M.dw + 11, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(M.hw + 2, M.dw + 2, sizeof(unsigned) * 11, hipMemcpyDeviceToHost,
                               ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (M.hw[4]) return fail(ctx, SLHJB_E_INVALID_ARG, "speed has a non-finite or non-positive value");
   if (M.hw[6]) return fail(ctx, SLHJB_E_INVALID_ARG, "node_class has a value other than 0, 1, 2");
   if (M.hw[8]) return fail(ctx, SLHJB_E_INVALID_ARG, "drift has a non-finite value");
+  if (M.hw[10]) return fail(ctx, SLHJB_E_INVALID_ARG, "running_cost_field has a non-finite or non-positive value");
+  if (M.hw[12]) return fail(ctx, SLHJB_E_INVALID_ARG, "eps_field has a non-finite or negative value");
+  float lx_max = p->running_cost, eps_max = p->eps;
+  if (p->running_cost_field) memcpy(&lx_max, &M.hw[9], sizeof(float));
+  if (p->eps_field) memcpy(&eps_max, &M.hw[11], sizeof(float));
   double speed_max = p->speed_const;
   if (p->speed) {
     float hi;
@@ -256,7 +280,7 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
     speed_max = hi;
   }
   const int64_t free_nodes = M.hw[5];
-  double reach = reach_for(p, speed_max);
+  double reach = reach_for(p, speed_max, eps_max);
   if (p->drift) {
     // the drift moves every foot of a node by h c d / dx
     float dmax;
@@ -268,15 +292,16 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
   P.speed_max = (float)speed_max;
   P.speed_min = p->speed_const;
   if (p->speed) memcpy(&P.speed_min, &M.hw[2], sizeof(float));
-  P.diffusion = p->eps > 0.0f ? p->diffusion : SLHJB_DIFF_NONE;
+  P.diffusion = eps_max > 0.0f ? p->diffusion : SLHJB_DIFF_NONE;
   P.scheme = p->scheme;
   P.reach = reach;
   P.free_nodes = free_nodes;
-  // the first-ring kernels take a foot's quadrant from the signs of the control: no drift
-  if (P.diffusion == SLHJB_DIFF_NONE && reach <= 1.0 + 1e-6 && !p->drift) {
+  // the first-ring kernels take a foot's quadrant from the signs of the control: no drift; they
+  // carry no cost term
+  if (P.diffusion == SLHJB_DIFF_NONE && reach <= 1.0 + 1e-6 && !p->drift && !has_general_terms(p)) {
     P.path = 1;
   } else {
-    P.path = 0;
+    P.path = has_general_terms(p) ? 2 : 0;  // 2: the general kernels with the cost term and noise field
   }
   const int halo = P.path == 1 ? 2 : (int)floor(reach * (1.0 + 1e-6) + 1e-6) + 1;
   if (halo > kMaxHalo)
@@ -307,11 +332,30 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
   float4 tab[kCtrlCap];
   int ntab = 0;
   int pquad[5] = {0, 0, 0, 0, 0};
+  // Cost term of the general kernels (see SweepArgs): the iterate is w = C - v with C = l / lambda
+  // (the largest running cost over lambda when it varies) or C = 0 without discount; then
+  // q = (K / beta) (fac l(x,a) - (1 - beta) C), fac = (1 - beta) / lambda or h, is 0 for a
+  // constant cost with lambda > 0 and the update stays homogeneous.
+  const int K = P.diffusion == SLHJB_DIFF_ISO ? 4 : (P.diffusion == SLHJB_DIFF_RANK1 ? 2 : 1);
+  const double beta_d = (double)(float)exp(-(double)p->lambda * (double)p->h);
+  double la_max = 0.0;
+  if (p->control_cost)
+    for (int m = 0; m < p->n_controls; ++m) la_max = std::max(la_max, (double)p->control_cost[m]);
+  const bool varying = p->running_cost_field || p->control_cost;
+  const double Cd = p->lambda == 0.0f ? 0.0
+                                      : (varying ? ((double)lx_max + la_max) : (double)p->running_cost) / p->lambda;
+  const double fac = p->lambda == 0.0f ? (double)p->h : (1.0 - beta_d) / (double)p->lambda;
+  const bool cost = p->lambda == 0.0f || varying;
+  const double kq = cost ? K / beta_d * fac : 0.0;
+  const double kc = cost ? K / beta_d * (1.0 - beta_d) * Cd : 0.0;
   for (int q = 0; q < 4; ++q) {
     pquad[q] = ntab;
     for (int t = quad[q]; t < quad[q + 1]; ++t) {
       const float ax = p->controls[2 * order[t]], ay = p->controls[2 * order[t] + 1];
-      tab[ntab++] = make_float4(ax, ay, ax * ay, fabsf(ax) + fabsf(ay));
+      // .w: |a_x| + |a_y| for the first-ring kernels, the control's cost part kq l_a for the general ones
+      const float wv = P.path == 1 ? fabsf(ax) + fabsf(ay)
+                                   : (float)(p->control_cost ? kq * (double)p->control_cost[order[t]] : 0.0);
+      tab[ntab++] = make_float4(ax, ay, ax * ay, wv);
     }
     while (ntab % 4 != 0) {
       tab[ntab] = tab[ntab - 1];
@@ -330,7 +374,7 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
   const double dx = grid_dx(p);
   // h/dx in float arithmetic, exactly as the foot displacements of the labeler are defined
   const float dx32 = (p->x_hi - p->x_lo) / (float)(p->n - 1);
-  const float vstar = (float)((double)p->running_cost / (double)p->lambda);
+  const float vstar = (float)Cd;
   SweepArgs& a = P.args;
   a.speed = p->speed;
   a.cls = p->node_class;
@@ -349,6 +393,13 @@ int prepare_with(slhjb_ctx* ctx, const slhjb_problem* p, Prepared* out, const Pr
   a.drift = reinterpret_cast<const float2*>(p->drift);
   a.w_target = vstar - p->target_value;
   a.w_obstacle = vstar - p->v_out;
+  a.cost = cost ? 1 : 0;
+  a.lx = p->running_cost_field;
+  a.lconst = p->running_cost;
+  a.kq = (float)kq;
+  a.kc = (float)kc;
+  a.epsf = P.diffusion == SLHJB_DIFF_NONE ? nullptr : p->eps_field;
+  a.d2 = (float)(2.0 * (double)p->h / (dx * dx));
   P.vstar = vstar;
   *out = P;
   return SLHJB_OK;
@@ -520,7 +571,7 @@ const char* slhjb_status_string(int status) {
   }
 }
 
-int slhjb_version(void) { return 3; }
+int slhjb_version(void) { return 4; }
 
 #ifndef SLHJB_SOURCE_HASH
 #define SLHJB_SOURCE_HASH "unknown"
@@ -763,13 +814,14 @@ int label_setup(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepared& P,
                 int16_t* label_out, uint64_t* overlap_out, uint16_t* phi_out, LabelJob* J) {
   if (!ctrl || !source_patch || !label_out) return fail(ctx, SLHJB_E_INVALID_ARG, "ctrl, source_patch, label_out must be non-NULL");
   if (problem->drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no drift");
+  if (problem->control_cost) return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no control cost");
   if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
   if (tau_q15 > (1u << 15)) return fail(ctx, SLHJB_E_INVALID_ARG, "tau_q15 must be <= 2^15");
   // the labeler advects along sigma = 0 feet, which must lie in the first ring of cells
   slhjb_problem p0 = *problem;
   p0.diffusion = SLHJB_DIFF_NONE;
   const float speed_max = P.speed_max;
-  if (reach_for(&p0, speed_max) > 1.0 + 1e-6)
+  if (reach_for(&p0, speed_max, 0.0) > 1.0 + 1e-6)
     return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labeling needs h c |a| <= dx (feet in the first ring of cells)");
   const int n = problem->n;
   const int64_t N = (int64_t)n * n;
@@ -924,6 +976,8 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     return fail(ctx, SLHJB_E_INVALID_ARG, "policy_sweeps must be in [0, 64]");
   const bool pdd = opts->mode != SLHJB_PATCHY_STATIC;
   const bool need_labels = opts->mode == SLHJB_PATCHY_INDEPENDENT || label_out;
+  if (pdd && need_labels && fine->control_cost)
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no control cost (transmission mode without labels does)");
   if (pdd && need_labels && fine->drift)
     return fail(ctx, SLHJB_E_UNSUPPORTED, "patch labels take no drift (transmission mode without labels does)");
   if (pdd) {
@@ -1057,7 +1111,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     }
     if (st == SLHJB_OK) {
       // start value V* on every node; the solver overwrites TARGET and OBSTACLE nodes
-      const float vstar = (float)((double)coarse->running_cost / (double)coarse->lambda);
+      const float vstar = cold_start_value(coarse);
       unsigned bits;
       memcpy(&bits, &vstar, sizeof(bits));
       he = launch_fill_u32((unsigned*)vc, bits, (int)Nc, ctx->stream);
@@ -1124,7 +1178,7 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
     }
   } else {
     // static decomposition: no pre-computation, tiles in their fixed order, from v = 1
-    const float vstar = (float)((double)fine->running_cost / (double)fine->lambda);
+    const float vstar = cold_start_value(fine);
     unsigned bits;
     memcpy(&bits, &vstar, sizeof(bits));
     he = launch_fill_u32((unsigned*)v, bits, (int)N, ctx->stream);
@@ -1178,6 +1232,7 @@ int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* 
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (!v_hat || !ctrl_out) return fail(ctx, SLHJB_E_INVALID_ARG, "v_hat and ctrl_out must be non-NULL");
   if (problem && problem->drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "the synthesis takes no drift");
+  if (problem && problem->control_cost) return fail(ctx, SLHJB_E_UNSUPPORTED, "the synthesis takes no control cost");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   Prepared P;
   int st = prepare(ctx, problem, &P);
@@ -1252,6 +1307,9 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     ctx->stiles_cap = tiles;
   }
   const bool indep = opts->mode == SLHJB_MODE_INDEPENDENT;
+  if (P.path == 2 && (indep || opts->persistent))
+    return fail(ctx, SLHJB_E_UNSUPPORTED,
+                "varying costs, lambda = 0 or an eps field: transmission mode with the host-driven passes only");
   const bool keyed = opts->order == SLHJB_ORDER_KEYS;
   // Without diffusion a tile is a transport problem: iterating it to its own fixed point against
   // the frozen halo carries the values across it in one visit. With diffusion every node depends
@@ -1521,6 +1579,9 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
     if (problems[i].scheme != problems[0].scheme)
       return fail(ctx, SLHJB_E_INVALID_ARG, "all instances of a batch must use the same scheme");
     if (problems[i].drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "batched solves take no drift");
+    if (has_general_terms(&problems[i]))
+      return fail(ctx, SLHJB_E_UNSUPPORTED,
+                  "batched solves take lambda > 0, a constant running cost and a constant eps");
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   // device scratch of this call
@@ -1805,7 +1866,7 @@ double slhjb_foot_reach(const slhjb_problem* problem, float speed_max) {
     return -1.0;
   slhjb_problem p = *problem;
   if (!(p.eps > 0.0f)) p.diffusion = SLHJB_DIFF_NONE;
-  return reach_for(&p, speed_max);
+  return reach_for(&p, speed_max, (double)p.eps);
 }
 
 }  // extern "C"

@@ -40,7 +40,28 @@ struct SweepArgs {
   float w_target;
   float w_obstacle;
   const float2* drift;     // nullable: f(x,a) = c(x) (drift(x) + a), general kernels only
+  // Varying costs and undiscounted problems (general kernels only). With the iterate w = C - v
+  // the update of control a at node i subtracts q = qn_i + qa_a from the feet sum before the
+  // quotient (SL3) or the max (SL2): qn_i = kq l_x(x_i) - kc with kq = (K / beta) fac,
+  // kc = (K / beta) (1 - beta) C, fac = (1 - beta) / lambda (or h for lambda = 0), and
+  // qa_a = kq l_a(a) in the .w component of the control table. cost == 0: q = 0 everywhere.
+  int cost;
+  const float* lx;         // nullable: l_x per node, else lconst
+  float lconst;
+  float kq, kc;
+  const float* epsf;       // nullable: eps(x) per node; the noise offset is then sqrt(d2 eps(x))
+  float d2;                // 2 h / dx^2
 };
+
+// Per-node parts of the general update: the cost term qn and the noise offset (cells).
+__device__ __forceinline__ float node_cost(const SweepArgs& a, size_t idx) {
+  if (!a.cost) return 0.0f;
+  const float l = a.lx ? a.lx[idx] : a.lconst;
+  return __builtin_fmaf(a.kq, l, -a.kc);
+}
+__device__ __forceinline__ float node_noise(const SweepArgs& a, size_t idx) {
+  return a.epsf ? __builtin_sqrtf(a.d2 * a.epsf[idx]) : a.d;
+}
 
 // Launchers (sweep.hip). `path` 0 = general halo tile, 1 = first-ring register stencil.
 hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path, hipStream_t s);
@@ -52,6 +73,9 @@ hipError_t launch_w_to_v(const float* w, float* v, int64_t count, float vstar, h
 hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, const float2* drift, float speed_const,
                                 int64_t count, unsigned* out, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned value, int count, hipStream_t s);
+// out[0]: max of f (float bits, f >= 0), out[1]: 1 if some value is non-finite, negative, or (with
+// positive = 1) zero. The caller clears both words first.
+hipError_t launch_field_stats(const float* f, int64_t count, int positive, unsigned* out, hipStream_t s);
 
 // Pre-computation kernels (pipeline.hip).
 hipError_t launch_upsample(const float* vc, int nc, float* vf, int nf, hipStream_t s);

@@ -399,7 +399,10 @@ __global__ __launch_bounds__(256) void label_keys_kernel(const float* __restrict
   if (gx < n && gy < n) {
     const size_t idx = (size_t)gy * n + gx;
     const float w = vstar - vhat[idx];
-    if (cls[idx] == kFree && w > 0.0f) best = -logf(w / vstar) / lambda;
+    if (cls[idx] == kFree) {
+      if (lambda == 0.0f) best = vhat[idx];  // undiscounted: v is the arrival time itself
+      else if (w > 0.0f) best = -logf(w / vstar) / lambda;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));

@@ -46,7 +46,7 @@ __device__ __forceinline__ void load_tile(float* tile, const float* __restrict__
       const uint8_t* __restrict__ cls, const float4* __restrict__ ctrl, unsigned* __restrict__ resid,        \
       unsigned* __restrict__ flags
 
-template <int DIFF, int SCHEME>
+template <int DIFF, int SCHEME, bool GEN>
 __global__ __launch_bounds__(kThreads) void sweep_general(SLHJB_SWEEP_PARAMS) {
   extern __shared__ float tile[];
   const int tx0 = blockIdx.x * kTileW;
@@ -71,7 +71,11 @@ __global__ __launch_bounds__(kThreads) void sweep_general(SLHJB_SWEEP_PARAMS) {
         const float k = a.r * (speed ? speed[idx] : a.speed_const);
         const int node_li = (row + a.halo) * LW + lane + a.halo;
         const float wself = tile[node_li];
-        wn = general_update<DIFF, SCHEME>(tile, LW, node_li, i, j, k, wself, ctrl, a);
+        if (GEN)
+          wn = general_update<DIFF, SCHEME, false, true>(tile, LW, node_li, i, j, k, wself, ctrl, a, nullptr, 0,
+                                                         node_cost(a, idx), node_noise(a, idx));
+        else
+          wn = general_update<DIFF, SCHEME>(tile, LW, node_li, i, j, k, wself, ctrl, a);
         local = fmaxf(local, fabsf(wn - wself));
         bad |= !isfinite(wn);
       } else {
@@ -136,7 +140,11 @@ hipError_t launch_sweep(const SweepArgs& a, int diffusion, int scheme, int path,
     else sweep_ring1<kSL3><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS);
     return hipGetLastError();
   }
-#define SLHJB_LAUNCH(D, S) sweep_general<D, S><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS)
+#define SLHJB_LAUNCH(D, S)                                                               \
+  do {                                                                                   \
+    if (path == 2) sweep_general<D, S, true><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS); \
+    else sweep_general<D, S, false><<<grid, kThreads, lds, s>>>(SLHJB_SWEEP_ARGS);         \
+  } while (0)
   switch (diffusion * 2 + scheme) {
   case kDiffNone * 2 + kSL2: SLHJB_LAUNCH(kDiffNone, kSL2); break;
   case kDiffNone * 2 + kSL3: SLHJB_LAUNCH(kDiffNone, kSL3); break;
@@ -235,6 +243,32 @@ __global__ void problem_stats_kernel(const float* __restrict__ speed, const uint
   }
 }
 
+// Largest value of a per-node field and whether any value is non-finite, negative or (positive)
+// zero: one pass, one set of atomics per workgroup.
+__global__ __launch_bounds__(kThreads) void field_stats_kernel(const float* __restrict__ f, int64_t count,
+                                                               int positive, unsigned* __restrict__ out) {
+  float hi = 0.0f;
+  bool bad = false;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < count; t += (int64_t)gridDim.x * kThreads) {
+    const float v = f[t];
+    if (!isfinite(v) || v < 0.0f || (positive && !(v > 0.0f))) bad = true;
+    else hi = fmaxf(hi, v);
+  }
+  hi = wave_max(hi);
+  __shared__ float shi[kThreads / 64];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shi[threadIdx.x >> 6] = hi;
+  if (bad) atomicOr(&sbad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kThreads / 64; ++k) hi = fmaxf(hi, shi[k]);
+    atomicMax(&out[0], __float_as_uint(hi));  // non-negative: the bits order as the values
+    if (sbad) atomicOr(&out[1], 1u);
+  }
+}
+
 __global__ void fill_u32_kernel(unsigned* p, unsigned value, int count) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) p[t] = value;
@@ -262,6 +296,11 @@ hipError_t launch_problem_stats(const float* speed, const uint8_t* cls, const fl
                                 int64_t count, unsigned* out, hipStream_t s) {
   problem_stats_kernel<<<std::min(grid_for(count), 512), kThreads, 0, s>>>(speed, cls, drift, speed_const, count,
                                                                              out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_stats(const float* f, int64_t count, int positive, unsigned* out, hipStream_t s) {
+  field_stats_kernel<<<std::min(grid_for(count), 512), kThreads, 0, s>>>(f, count, positive, out);
   return hipGetLastError();
 }
 

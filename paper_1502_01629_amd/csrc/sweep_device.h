@@ -72,12 +72,16 @@ struct Feet<kDiffRank1> {
 // With INDEP, a corner whose patch label (`lab`, same layout as `tile`) differs from the node's
 // label `mylab` reads w_outside: every patch is solved as a domain of its own with state
 // constraints at its interfaces.
-template <int DIFF, int SCHEME, bool INDEP = false>
+// GEN: the problem has varying costs, no discount or a diffusion-coefficient field (kernel path
+// 2); then qn is the node's part of the cost term (node_cost) and dn its noise offset in cells
+// (node_noise). Without GEN the update is the homogeneous one with the constant offset a.d.
+template <int DIFF, int SCHEME, bool INDEP = false, bool GEN = false>
 __device__ __forceinline__ float general_update(const float* __restrict__ tile, int LW, int node_li, int i, int j,
                                                 float k, float wself, const float4* __restrict__ ctrl,
                                                 const SweepArgs& a, const int16_t* __restrict__ lab = nullptr,
-                                                int mylab = 0) {
+                                                int mylab = 0, float qn = 0.0f, float dn = 0.0f) {
   using F = Feet<DIFF>;
+  const float dd = GEN ? dn : a.d;
   (void)wself;  // SL3 leaves the node's own value out instead of subtracting it
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
@@ -94,8 +98,11 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
     kdx = k * dv.x;
     kdy = k * dv.y;
   }
-  float best2 = 0.0f;                 // SL2: max over controls of the feet sum
-  float bnum = -1.0f, bden = 1.0f;    // SL3: best quotient num / den
+  // SL2: max over controls of the feet sum; SL3: best quotient num / den (den > 0). Without the
+  // cost term every candidate is >= 0, and the start values 0 and -1 (inline constants) keep the
+  // register count of the default kernels; with it candidates can be negative.
+  float best2 = GEN ? -INFINITY : 0.0f;
+  float bnum = GEN ? -INFINITY : -1.0f, bden = 1.0f;
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
   // the host pads the control list to a multiple of 4 with repeats of its last control
 #pragma unroll 4
@@ -107,7 +114,7 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
 #pragma unroll
     for (int f = 0; f < F::K; ++f) {
       float ox, oy;
-      F::get(f, bx, by, cm.x, cm.y, a.d, ox, oy);
+      F::get(f, bx, by, cm.x, cm.y, dd, ox, oy);
       const bool inside = (ox >= lox) & (ox <= hix) & (oy >= loy) & (oy <= hiy);
       const float cx = fminf(fmaxf(ox, lox), hix);
       const float cy = fminf(fmaxf(oy, loy), hiy);
@@ -149,6 +156,8 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
         lam0 += inside ? hx * hy : 0.0f;
       }
     }
+    // the cost term (cm.w holds the control's part on the general path)
+    if (GEN) acc -= qn + cm.w;
     if (SCHEME == kSL2) {
       best2 = fmaxf(best2, acc);
     } else {
@@ -416,15 +425,18 @@ __device__ __forceinline__ float policy_apply(const float* __restrict__ T, const
   return (a.beta * val) * p.rden;
 }
 
-template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false>
+template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false, bool GEN = false>
 __device__ __forceinline__ void general_partial(const float* __restrict__ tile, int LW, int node_li, int i, int j,
                                                 float k, float wself, const float4* __restrict__ ctrl,
                                                 const SweepArgs& a, const int16_t* __restrict__ lab, int mylab,
                                                 int m_lo, int m_hi, float& pnum, float& pden, int* pidx = nullptr,
-                                                const float2* kd_pre = nullptr, const float4* cm_pre = nullptr) {
+                                                const float2* kd_pre = nullptr, const float4* cm_pre = nullptr,
+                                                float qn = 0.0f, float dn = 0.0f) {
   // kd_pre: the node's drift offset k d(x), computed by the caller as below (saves its load);
-  // cm_pre: the one control m_lo, already loaded (policy evaluation: m_hi = m_lo + 1)
+  // cm_pre: the one control m_lo, already loaded (policy evaluation: m_hi = m_lo + 1);
+  // GEN, qn, dn: the cost term and the node's noise offset (see general_update)
   using F = Feet<DIFF>;
+  const float dd = GEN ? dn : a.d;
   (void)wself;  // SL3 leaves the node's own value out instead of subtracting it
   const float fi = (float)i, fj = (float)j;
   const float nm1 = (float)(a.n - 1);
@@ -444,7 +456,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
     kdy = k * dv.y;
   }
   float best2 = -INFINITY;
-  float bnum = -1.0f, bden = 1.0f;
+  float bnum = GEN ? -INFINITY : -1.0f, bden = 1.0f;  // without the cost term candidates are >= 0
   int bidx = m_lo;
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
 #pragma unroll 4
@@ -456,7 +468,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
 #pragma unroll
     for (int f = 0; f < F::K; ++f) {
       float ox, oy;
-      F::get(f, bx, by, cm.x, cm.y, a.d, ox, oy);
+      F::get(f, bx, by, cm.x, cm.y, dd, ox, oy);
       const bool inside = (ox >= lox) & (ox <= hix) & (oy >= loy) & (oy <= hiy);
       const float cx = fminf(fmaxf(ox, lox), hix);
       const float cy = fminf(fmaxf(oy, loy), hiy);
@@ -498,6 +510,7 @@ __device__ __forceinline__ void general_partial(const float* __restrict__ tile, 
         lam0 += inside ? hx * hy : 0.0f;
       }
     }
+    if (GEN) acc -= qn + cm.w;
     if (SCHEME == kSL2) {
       if (TRACK) {
         if (acc > best2) {

@@ -83,11 +83,17 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   const int li = (ly + R) * LW + lx + R;
   bool fr = false;
   float kk = 0.0f, w0 = 0.0f;  // w0: the node's value before the visit, for the move it reports
+  float qn = 0.0f, dn = 0.0f;  // path 2: the node's cost term and noise offset
+  constexpr bool GEN = PATH == 2;
   if (gi < n && gj < n) {
     const size_t idx = (size_t)gj * n + gi;
     w0 = w[idx];
     fr = cls[idx] == kFree;
     if (fr) kk = a.r * (speed ? speed[idx] : a.speed_const);
+    if (GEN && fr) {
+      qn = node_cost(a, idx);
+      dn = node_noise(a, idx);
+    }
   }
   const bool interior = x0 >= 1 && x0 + T - 1 <= n - 2 && y0 >= 1 && y0 + T - 1 <= n - 2;
   // general path: the node's drift offset k d(x), loaded once for the whole visit (the same
@@ -128,13 +134,13 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
         }
       } else {
         if (pe > 0)
-          general_partial<DIFF, SCHEME, INDEP, true>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                                     INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den,
-                                                     &mi, &kd);
+          general_partial<DIFF, SCHEME, INDEP, true, GEN>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a,
+                                                          INDEP ? labs : nullptr, INDEP ? labs[li] : 0, part * slice,
+                                                          (part + 1) * slice, num, den, &mi, &kd, nullptr, qn, dn);
         else
-          general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                               INDEP ? labs[li] : 0, part * slice, (part + 1) * slice, num, den,
-                                               nullptr, &kd);
+          general_partial<DIFF, SCHEME, INDEP, false, GEN>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a,
+                                                           INDEP ? labs : nullptr, INDEP ? labs[li] : 0, part * slice,
+                                                           (part + 1) * slice, num, den, nullptr, &kd, nullptr, qn, dn);
       }
       pn[part * TT + node] = num;
       pd[part * TT + node] = den;
@@ -194,8 +200,9 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
             nxt[li] = policy_apply<SCHEME, INDEP>(cur + li, pv, a, INDEP ? labs + li : nullptr);
           } else {
             float num, den;
-            general_partial<DIFF, SCHEME, INDEP>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a, INDEP ? labs : nullptr,
-                                                 INDEP ? labs[li] : 0, pol, pol + 1, num, den, nullptr, &kd, &cm);
+            general_partial<DIFF, SCHEME, INDEP, false, GEN>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a,
+                                                             INDEP ? labs : nullptr, INDEP ? labs[li] : 0, pol, pol + 1,
+                                                             num, den, nullptr, &kd, &cm, qn, dn);
             constexpr int K = Feet<DIFF>::K;
             nxt[li] = SCHEME == kSL2 ? a.beta * num * (1.0f / (float)K) : (a.beta * num) * (1.0f / den);
           }
@@ -288,7 +295,7 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
     // the NPT nodes of this thread
     int li[NPT], gi[NPT], gj[NPT];
     bool fr[NPT];
-    float kk[NPT], w0[NPT];
+    float kk[NPT], w0[NPT], qn[NPT], dn[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int q = threadIdx.x + r * kThreads;
@@ -299,11 +306,17 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       fr[r] = false;
       kk[r] = 0.0f;
       w0[r] = 0.0f;
+      qn[r] = 0.0f;
+      dn[r] = 0.0f;
       if (gi[r] < n && gj[r] < n) {
         const size_t idx = (size_t)gj[r] * n + gi[r];
         w0[r] = w[idx];
         fr[r] = cls[idx] == kFree;
         if (fr[r]) kk[r] = a.r * (speed ? speed[idx] : a.speed_const);
+        if (PATH == 2 && fr[r]) {
+          qn[r] = node_cost(a, idx);
+          dn[r] = node_noise(a, idx);
+        }
       }
     }
     __syncthreads();  // tile staged
@@ -329,8 +342,9 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                                     gj[r] == n - 1, L);
             }
           } else {
-            v = general_update<DIFF, SCHEME, INDEP>(cur, LW, li[r], gi[r], gj[r], kk[r], cur[li[r]], ctrl, a,
-                                                    INDEP ? labs : nullptr, INDEP ? labs[li[r]] : 0);
+            v = general_update<DIFF, SCHEME, INDEP, PATH == 2>(cur, LW, li[r], gi[r], gj[r], kk[r], cur[li[r]], ctrl,
+                                                               a, INDEP ? labs : nullptr, INDEP ? labs[li[r]] : 0, qn[r],
+                                                               dn[r]);
           }
           nxt[li[r]] = v;
           lmax = fmaxf(lmax, fabsf(v - cur[li[r]]));
@@ -430,7 +444,12 @@ __global__ __launch_bounds__(kThreads) void tile_keys_kernel(const float* __rest
     if (gx < n && gy < n) {
       const size_t idx = (size_t)gy * n + gx;
       const float ww = w[idx];
-      if (cls[idx] == kFree && ww > 0.0f) best = fminf(best, -logf(ww / vstar) / lambda);
+      // the arrival time of the start: T = -ln(w / V*) / lambda (Kruzkov), or v = V* - w itself
+      // in the undiscounted form (lambda = 0)
+      if (cls[idx] == kFree) {
+        if (lambda == 0.0f) best = fminf(best, vstar - ww);
+        else if (ww > 0.0f) best = fminf(best, -logf(ww / vstar) / lambda);
+      }
     }
   }
 #pragma unroll
@@ -655,6 +674,7 @@ static hipError_t launch_coop_shape(const SweepArgs& a, int diffusion, int schem
     else SLHJB_CO_S(D, PA, false);      \
   } while (0)
   if (path == 1) SLHJB_CO_I(kDiffNone, 1);
+  if (path == 2) return hipErrorNotSupported;  // checked by the caller
   if (diffusion == kDiffNone) SLHJB_CO_I(kDiffNone, 0);
   if (diffusion == kDiffIso) SLHJB_CO_I(kDiffIso, 0);
   SLHJB_CO_I(kDiffRank1, 0);
@@ -931,7 +951,12 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
     else SLHJB_TV_S(D, PA, false);      \
   } while (0)
   if (path == 1) SLHJB_TV_I(kDiffNone, 1);
-  else if (diffusion == kDiffNone) SLHJB_TV_I(kDiffNone, 0);
+  else if (path == 2) {
+    // varying costs / no discount / diffusion field: transmission mode only (checked by the caller)
+    if (diffusion == kDiffNone) SLHJB_TV_S(kDiffNone, 2, false);
+    else if (diffusion == kDiffIso) SLHJB_TV_S(kDiffIso, 2, false);
+    else SLHJB_TV_S(kDiffRank1, 2, false);
+  } else if (diffusion == kDiffNone) SLHJB_TV_I(kDiffNone, 0);
   else if (diffusion == kDiffIso) SLHJB_TV_I(kDiffIso, 0);
   else SLHJB_TV_I(kDiffRank1, 0);
 #undef SLHJB_TV_I

@@ -91,6 +91,7 @@ def lib():
             "or_policy_improve": (i64, [P, vp, vp, i32]),
             "or_rho_policy": (None, [P, vp, vp]),
             "or_upsample_bilinear": (None, [i32, vp, i32, vp]),
+            "or_upsample_bicubic": (None, [i32, vp, i32, vp]),
             "or_displacement": (None, [i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]),
             "or_label": (i64, [i32, vp, vp, vp, i32, i32, vp, vp]),
             "or_sweep_independent": (f64, [P, vp, vp, vp, i32]),
@@ -305,6 +306,15 @@ def upsample_bilinear(v_c: np.ndarray, n_f: int) -> np.ndarray:
     vc = np.ascontiguousarray(v_c, dtype=np.float64).reshape(-1)
     out = np.zeros(n_f * n_f, dtype=np.float64)
     lib().or_upsample_bilinear(n_c, _ptr(vc), n_f, _ptr(out))
+    return out
+
+
+def upsample_bicubic(v_c: np.ndarray, n_f: int) -> np.ndarray:
+    """Keys (a = -1/2) bicubic interpolation with edge replication (see the C source)."""
+    n_c = int(round(np.sqrt(v_c.size)))
+    vc = np.ascontiguousarray(v_c, dtype=np.float64).reshape(-1)
+    out = np.zeros(n_f * n_f, dtype=np.float64)
+    lib().or_upsample_bicubic(n_c, _ptr(vc), n_f, _ptr(out))
     return out
 
 

@@ -361,6 +361,49 @@ void or_upsample_bilinear(int32_t n_c, const double* v_c, int32_t n_f, double* v
     }
 }
 
+/* Keys' cubic convolution kernel with a = -1/2 (R. G. Keys, "Cubic convolution interpolation
+ * for digital image processing", IEEE Trans. ASSP 29 (1981), eq. 15):
+ *   W(x) = (a+2)|x|^3 - (a+3)|x|^2 + 1          for |x| <= 1,
+ *          a|x|^3 - 5a|x|^2 + 8a|x| - 4a         for 1 < |x| < 2,  0 otherwise. */
+static double or_keys(double x) {
+    const double a = -0.5;
+    const double t = fabs(x);
+    if (t <= 1.0) return (a + 2.0) * t * t * t - (a + 3.0) * t * t + 1.0;
+    if (t < 2.0) return a * t * t * t - 5.0 * a * t * t + 8.0 * a * t - 4.0 * a;
+    return 0.0;
+}
+
+/* Bicubic (Keys) interpolation of a coarse grid solution onto a fine grid of the same box, the
+ * feature of the learned warm start: fine node i at coarse coordinate q = i (n_c-1)/(n_f-1),
+ * base cell c = floor(q) (c = n_c-2 on the upper edge), fraction t = q - c, and the 4 x 4 coarse
+ * nodes c-1..c+2 per axis weighted by W(t - m), m = -1..2; indices outside the grid are clamped
+ * to the nearest edge node (edge replication). */
+void or_upsample_bicubic(int32_t n_c, const double* v_c, int32_t n_f, double* v_f) {
+    const double ratio = (double)(n_c - 1) / (double)(n_f - 1);
+    for (int32_t j = 0; j < n_f; ++j) {
+        for (int32_t i = 0; i < n_f; ++i) {
+            const double q1 = i * ratio, q2 = j * ratio;
+            int32_t c1 = (int32_t)floor(q1), c2 = (int32_t)floor(q2);
+            if (c1 > n_c - 2) c1 = n_c - 2;
+            if (c2 > n_c - 2) c2 = n_c - 2;
+            const double s = q1 - c1, t = q2 - c2;
+            double sum = 0.0;
+            for (int32_t my = -1; my <= 2; ++my) {
+                int32_t y = c2 + my;
+                if (y < 0) y = 0;
+                if (y > n_c - 1) y = n_c - 1;
+                for (int32_t mx = -1; mx <= 2; ++mx) {
+                    int32_t x = c1 + mx;
+                    if (x < 0) x = 0;
+                    if (x > n_c - 1) x = n_c - 1;
+                    sum += or_keys(s - mx) * or_keys(t - my) * v_c[(int64_t)y * n_c + x];
+                }
+            }
+            v_f[(int64_t)j * n_f + i] = sum;
+        }
+    }
+}
+
 /* The foot of the synthesized dynamics x_i + h c(x_i) a*(x_i) (eq. discrete-advection) as a
  * Q.8 fixed-point displacement in cell units. This is where floating point decides integers,
  * so it is computed in float exactly as the GPU does:

@@ -71,6 +71,7 @@ void or_rho_policy(const or_problem* p, const int32_t* policy, double* out /*[N]
 int64_t or_policy_improve(const or_problem* p, const double* v, int32_t* policy, int32_t n_threads);
 void or_synthesize(const or_problem* p, const double* v_hat, int32_t* ctrl_out, double* gap_out);
 void or_upsample_bilinear(int32_t n_c, const double* v_c, int32_t n_f, double* v_f);
+void or_upsample_bicubic(int32_t n_c, const double* v_c, int32_t n_f, double* v_f);
 void or_displacement(int32_t n, float x_lo, float x_hi, float h, const float* speed,
                      const float* controls, const int32_t* ctrl, int32_t* disp_q8);
 int64_t or_label(int32_t n, const uint8_t* node_class, const int32_t* disp_q8, const int16_t* source_patch,

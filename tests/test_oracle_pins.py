@@ -313,6 +313,37 @@ def test_upsample_reproduces_bilinear_and_coarse_nodes():
     assert np.array_equal(vf[::4, ::4], vr)
 
 
+def test_bicubic_upsample_pins():
+    """Keys' kernel with a = -1/2: (1) interpolates (coarse nodes copied exactly); (2) its weights
+    sum to 1, so constants are exact everywhere, edges included; (3) it reproduces quadratics
+    exactly wherever the 4 x 4 stencil lies inside the grid (third-order accuracy, Keys 1981);
+    (4) at t = 1/2 the 1-D weights are (-1/16, 9/16, 9/16, -1/16)."""
+    rng = np.random.default_rng(11)
+    vr = rng.random((9, 9))
+    vf = oracle.upsample_bicubic(vr, 33).reshape(33, 33)
+    assert np.array_equal(vf[::4, ::4], vr)
+    c = oracle.upsample_bicubic(np.full((9, 9), 0.37), 33)
+    assert np.abs(c - 0.37).max() < 1e-15
+    Xc1, Xc2 = I.node_coords(9)
+    a, b, cc, d, e, f = rng.normal(size=6)
+    quad = lambda x, y: a + b * x + cc * y + d * x * x + e * x * y + f * y * y
+    vf = oracle.upsample_bicubic(quad(Xc1, Xc2), 33).reshape(33, 33)
+    Xf1, Xf2 = I.node_coords(33)
+    inner = (slice(4, 29), slice(4, 29))  # fine nodes whose stencil stays inside coarse 0..8
+    assert np.abs(vf[inner] - quad(Xf1, Xf2)[inner]).max() < 1e-12
+    # half-way between coarse columns the 1-D weights of columns c-1, c, c+1, c+2 are
+    # -1/16, 9/16, 9/16, -1/16: a single column of ones on a 3 x 3 grid gives 9/16 on both sides
+    row = np.zeros((3, 3))
+    row[:, 1] = 1.0
+    vf = oracle.upsample_bicubic(row, 5).reshape(5, 5)
+    assert np.array_equal(vf[0], [0.0, 9 / 16, 1.0, 9 / 16, 0.0])
+    # ones in column 0: at x = 1/2 the clamped column -1 is column 0 again: 9/16 - 1/16
+    row = np.zeros((3, 3))
+    row[:, 0] = 1.0
+    vf = oracle.upsample_bicubic(row, 5).reshape(5, 5)
+    assert np.allclose(vf[0], [1.0, 8 / 16, 0.0, -1 / 16, 0.0], atol=1e-15)
+
+
 # ---------------------------------------------------------------- independent (state-constraint) sweep
 @pytest.mark.parametrize("scheme", [SL2, SL3])
 @pytest.mark.parametrize("eps", [0.0, 0.02])

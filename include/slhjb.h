@@ -312,6 +312,14 @@ int slhjb_solve_patchy(slhjb_ctx* ctx, const slhjb_problem* fine, const slhjb_pr
  * grids need not be nested. Enqueued only (no synchronisation). */
 int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f);
 
+/* Bicubic interpolation of a coarse grid solution onto a fine grid of the same box: the smooth
+ * input feature of the learned warm start (the coarse solution of Section 4.3's pre-computation,
+ * carried over with a third-order kernel). Keys' cubic convolution kernel with a = -1/2 over the
+ * 4 x 4 coarse nodes around each fine node, coarse indices clamped to the grid (edge
+ * replication); fine node i at coarse coordinate i (n_c-1)/(n_f-1); coarse nodes are copied
+ * exactly. v_c: device float[n_c*n_c], v_f: device float[n_f*n_f], distinct. Enqueued only. */
+int slhjb_upsample_bicubic(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f);
+
 /* Discrete synthesis of the feedback control (eq. discrete-synthesis) with sigma = 0 and a
  * constant running cost: for every FREE node, the index m of the control minimising
  * I[v_hat](x_i + h c(x_i) a_m) (feet outside the box read v_out; the first minimum in the

@@ -238,6 +238,7 @@ SIGNATURES = {
     "slhjb_net_adam_step": (ctypes.c_int, [_vp, _f32]),
     "slhjb_net_warm_start": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_upsample": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
+    "slhjb_upsample_bicubic": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "slhjb_synthesize": (ctypes.c_int, [_vp, _PP, _vp, _vp]),
     "slhjb_partition_sources": (ctypes.c_int, [_i32, _vp, _i32, _vp, ctypes.POINTER(_i32)]),
     "slhjb_label": (ctypes.c_int, [_vp, _PP, _vp, _vp, _vp, _i32, ctypes.c_uint16, _vp, _vp, _vp,
@@ -418,6 +419,9 @@ class Context:
 
     def upsample(self, v_c, n_c: int, v_f, n_f: int):
         self._check(lib().slhjb_upsample(self.handle, n_c, _ptr(v_c), n_f, _ptr(v_f)))
+
+    def upsample_bicubic(self, v_c, n_c: int, v_f, n_f: int):
+        self._check(lib().slhjb_upsample_bicubic(self.handle, n_c, _ptr(v_c), n_f, _ptr(v_f)))
 
     def synthesize(self, prob: DeviceProblem, v_hat, ctrl_out):
         self._check(lib().slhjb_synthesize(self.handle, ctypes.byref(prob.struct), _ptr(v_hat), _ptr(ctrl_out)))

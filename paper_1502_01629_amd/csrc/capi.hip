@@ -1228,6 +1228,16 @@ int slhjb_upsample(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, f
   return SLHJB_OK;
 }
 
+int slhjb_upsample_bicubic(slhjb_ctx* ctx, int32_t n_c, const float* v_c, int32_t n_f, float* v_f) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (n_c < 3 || n_f < 3 || n_c > 32769 || n_f > 32769 || !v_c || !v_f)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "need 3 <= n_c, n_f <= 32769 and non-NULL arrays");
+  if (v_c == v_f) return fail(ctx, SLHJB_E_INVALID_ARG, "v_c and v_f must be distinct");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_upsample_bicubic(v_c, n_c, v_f, n_f, ctx->stream));
+  return SLHJB_OK;
+}
+
 int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* v_hat, int16_t* ctrl_out) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
   if (!v_hat || !ctrl_out) return fail(ctx, SLHJB_E_INVALID_ARG, "v_hat and ctrl_out must be non-NULL");

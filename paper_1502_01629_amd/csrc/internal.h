@@ -79,6 +79,7 @@ hipError_t launch_field_stats(const float* f, int64_t count, int positive, unsig
 
 // Pre-computation kernels (pipeline.hip).
 hipError_t launch_upsample(const float* vc, int nc, float* vf, int nf, hipStream_t s);
+hipError_t launch_upsample_bicubic(const float* vc, int nc, float* vf, int nf, hipStream_t s);
 hipError_t launch_synthesize(const float* vhat, const float* speed, const uint8_t* cls, const float2* ctrl,
                              int n_controls, int n, float r, float speed_const, float v_out, int16_t* out,
                              hipStream_t s);

@@ -36,6 +36,58 @@ hipError_t launch_upsample(const float* vc, int nc, float* vf, int nf, hipStream
   return hipGetLastError();
 }
 
+// ---- bicubic u_hat (the warm-start network's input feature) -----------------------------
+// Keys' cubic convolution kernel, a = -1/2: W(x) = 1.5|x|^3 - 2.5|x|^2 + 1 on [0, 1],
+// -0.5|x|^3 + 2.5|x|^2 - 4|x| + 2 on (1, 2). For a fraction t in [0, 1) the weights of the
+// coarse nodes c-1, c, c+1, c+2 are W(t+1), W(t), W(1-t), W(2-t).
+__device__ __forceinline__ void keys_weights(float t, float w[4]) {
+  const float u = 1.0f - t;
+  w[0] = ((-0.5f * t + 1.0f) * t - 0.5f) * t;            // W(1 + t) = -0.5 t^3 + t^2 - 0.5 t
+  w[1] = (1.5f * t - 2.5f) * t * t + 1.0f;              // W(t)
+  w[2] = (1.5f * u - 2.5f) * u * u + 1.0f;              // W(1 - t)
+  w[3] = ((-0.5f * u + 1.0f) * u - 0.5f) * u;            // W(2 - t)
+}
+
+// Fine node i at coarse coordinate i (n_c - 1) / (n_f - 1) (exact integer quotient and remainder,
+// as the bilinear kernel), 4 x 4 coarse nodes with indices clamped to the grid.
+__global__ void upsample_bicubic_kernel(const float* __restrict__ vc, int nc, float* __restrict__ vf, int nf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= nf || j >= nf) return;
+  const int64_t den = nf - 1;
+  const int64_t pi = (int64_t)i * (nc - 1), pj = (int64_t)j * (nc - 1);
+  int ci = (int)(pi / den), cj = (int)(pj / den);
+  float s = (float)(pi - (int64_t)ci * den) / (float)den;
+  float t = (float)(pj - (int64_t)cj * den) / (float)den;
+  if (ci > nc - 2) { ci = nc - 2; s = 1.0f; }
+  if (cj > nc - 2) { cj = nc - 2; t = 1.0f; }
+  float wx[4], wy[4];
+  keys_weights(s, wx);
+  keys_weights(t, wy);
+  int xs[4], ys[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    xs[m] = min(max(ci + m - 1, 0), nc - 1);
+    ys[m] = min(max(cj + m - 1, 0), nc - 1);
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int my = 0; my < 4; ++my) {
+    const float* row = vc + (size_t)ys[my] * nc;
+    float r = 0.0f;
+#pragma unroll
+    for (int mx = 0; mx < 4; ++mx) r = __builtin_fmaf(wx[mx], row[xs[mx]], r);
+    acc = __builtin_fmaf(wy[my], r, acc);
+  }
+  vf[(size_t)j * nf + i] = acc;
+}
+
+hipError_t launch_upsample_bicubic(const float* vc, int nc, float* vf, int nf, hipStream_t s) {
+  dim3 grid((nf + 255) / 256, nf);
+  upsample_bicubic_kernel<<<grid, 256, 0, s>>>(vc, nc, vf, nf);
+  return hipGetLastError();
+}
+
 // ---- discrete synthesis (eq. discrete-synthesis, sigma = 0) ------------------------------
 // ctrl[i] = argmin_m I[v_hat](x_i + h c_i a_m) for FREE nodes (first minimum in the caller's
 // control order), -1 elsewhere. Feet outside the closed box read v_out.

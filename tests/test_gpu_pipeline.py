@@ -25,6 +25,25 @@ def _dev(a, dtype=np.float32):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype).reshape(-1)).cuda()
 
 
+@pytest.mark.parametrize("nc,nf", [(33, 100), (129, 2049), (9, 1025), (65, 65)])
+def test_bicubic_upsample_matches_oracle(ctx, nc, nf):
+    """Keys bicubic feature of the warm start: coarse nodes copied exactly where the grids nest, and
+    every value within a few FP32 roundings of the FP64 oracle (16 products of weights of size
+    <= 1.2 and values of size <= 1: bound 2e-6 relative to the values' range)."""
+    rng = np.random.default_rng(nc + nf)
+    vc = rng.random((nc, nc)).astype(np.float32)
+    out = torch.empty(nf * nf, dtype=torch.float32, device="cuda")
+    ctx.upsample_bicubic(_dev(vc), nc, out, nf)
+    ref = oracle.upsample_bicubic(vc.astype(np.float64), nf)
+    got = out.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max()
+    print(f"bicubic {nc} -> {nf}: max err {err:.2e}", flush=True)
+    assert err < 2e-6
+    if (nf - 1) % (nc - 1) == 0:
+        r = (nf - 1) // (nc - 1)
+        assert np.array_equal(got.reshape(nf, nf)[::r, ::r], vc.astype(np.float64))
+
+
 @pytest.mark.parametrize("nc,nf", [(129, 2049), (129, 300), (9, 9), (65, 1025)])
 def test_upsample_matches_oracle(ctx, nc, nf):
     rng = np.random.default_rng(nc + nf)

@@ -376,9 +376,20 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
  * dy, dx in {-1,0,1} x dilation) then b_l[channels]; then the head w[channels], b[1]. */
 typedef struct slhjb_net slhjb_net;
 typedef struct {
-    int32_t layers;             /* 1..12                                                           */
-    int32_t channels;           /* 32                                                              */
-    int32_t dilation[12];       /* per layer, 1..64                                                */
+    int32_t layers;             /* 1..12 (arch 0)                                                  */
+    int32_t channels;           /* 32 (arch 0)                                                     */
+    int32_t dilation[12];       /* per layer, 1..32 (arch 0)                                       */
+    int32_t arch;               /* 0: the dilated CNN above; 1: a 4-level U-Net: two 3 x 3
+                                   convolutions (ReLU) per level with 32, 64, 128 and 128 channels,
+                                   2 x 2 average pooling down, nearest x2 upsampling concatenated
+                                   with the level's skip (upsampled first) up, the same 1 x 1 head;
+                                   layers / channels / dilation are ignored. Its 14 convolutions, in
+                                   parameter order: 16->32, 32->32 | 32->64, 64->64 | 64->128,
+                                   128->128 | 128->128, 128->128 (bottom) | 256->128, 128->128 |
+                                   192->64, 64->64 | 96->32, 32->32. Crops must be a multiple of 8
+                                   pixels; the loss mask keeps 48 pixels (the receptive-field
+                                   radius) from crop edges inside the frame, and the warm start
+                                   pads the frame to a multiple of 8 by edge replication.        */
 } slhjb_net_config;
 /* One training or evaluation frame: the crop [x0, x0+crop) x [y0, y0+crop) of an n x n problem. */
 typedef struct {

@@ -8,6 +8,10 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
+
+# kept at import: during interpreter shutdown the sys module itself may be gone
+_is_finalizing = sys.is_finalizing
 
 import numpy as np
 
@@ -173,7 +177,11 @@ class NetConfig(ctypes.Structure):
         ("layers", ctypes.c_int32),
         ("channels", ctypes.c_int32),
         ("dilation", ctypes.c_int32 * 12),
+        ("arch", ctypes.c_int32),
     ]
+
+
+NET_DILATED, NET_UNET = 0, 1
 
 
 class NetSample(ctypes.Structure):
@@ -375,6 +383,10 @@ class Context:
             self.handle = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone: leave the memory to the
+        # process exit instead of calling into it
+        if _is_finalizing is None or _is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -480,12 +492,14 @@ class Context:
 class Net:
     """The learned warm-start network of a context (slhjb_net_*): parameters live on the device."""
 
-    def __init__(self, ctx: "Context", layers: int = 6, channels: int = 32, dilations=(1, 2, 4, 8, 16, 1)):
-        if len(dilations) != layers:
+    def __init__(self, ctx: "Context", layers: int = 6, channels: int = 32, dilations=(1, 2, 4, 8, 16, 1),
+                 arch: int = NET_DILATED):
+        if arch == NET_DILATED and len(dilations) != layers:
             raise ValueError("one dilation per layer")
         self.ctx = ctx
+        self.arch = arch
         self.layers, self.channels, self.dilations = layers, channels, tuple(int(d) for d in dilations)
-        cfg = NetConfig(layers, channels, (ctypes.c_int32 * 12)(*self.dilations))
+        cfg = NetConfig(layers, channels, (ctypes.c_int32 * 12)(*self.dilations[:12]), arch)
         h = ctypes.c_void_p()
         ctx._check(lib().slhjb_net_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -496,6 +510,10 @@ class Net:
             self.handle = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone: leave the memory to the
+        # process exit instead of calling into it
+        if _is_finalizing is None or _is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -201,8 +201,15 @@ struct CropSrc {
 };
 hipError_t launch_crops(int cin, const CropSrc* src, int images, int S, int margin, uint16_t* feat, float* uhat,
                         float* vstar, uint8_t* mask, hipStream_t s);
-hipError_t launch_project(const float* uhat, const float* delta, const uint8_t* cls, long long total,
+hipError_t launch_project(const float* uhat, const float* delta, const uint8_t* cls, int n, int pitch,
                           float target_value, float v_out, float* v, hipStream_t s);
+hipError_t launch_pool2(const uint16_t* in, int images, int H, int W, int C, uint16_t* out, hipStream_t s);
+hipError_t launch_upcat(const uint16_t* low, const uint16_t* skip, int images, int H, int W, int Cu, int Cs,
+                        uint16_t* out, hipStream_t s);
+hipError_t launch_upcat_bwd(const uint16_t* g, int images, int H, int W, int Cu, int Cs, uint16_t* glow,
+                            hipStream_t s);
+hipError_t launch_skip_combine(const uint16_t* e_act, const uint16_t* gcat, int Cu, const uint16_t* gpool, int images,
+                               int H, int W, int C, uint16_t* out, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long count, float lr_t, float b1, float b2,
                        float eps_t, hipStream_t s);
 hipError_t launch_pack_weights(const float* w, int cout, int cin, uint16_t* wt, uint16_t* wtt, hipStream_t s);

@@ -19,8 +19,9 @@ Beside the timed steps, each comparison arm runs once (progress on stderr):
   batch  256 independent instances (65^2..1025^2, eps > 0) in one batched solve against the same
          instances solved one by one (bit-exact agreement counted);
   bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered);
-  learned  a CNN warm start trained on the method's own 1025^2 solves against u_hat and the cold
-         start on held-out problems;
+  learned  the U-Net warm start trained on the method's own 1025^2 solves against the cold start,
+         the bilinear and the bicubic u_hat on held-out problems (time to the tolerance and error
+         at the stopping point);
   indep  the independent (state-constraint) patch solves at eps = 0, 1e-3, 1e-2 against the
          transmission solve: the decomposition error, near the patch interfaces and away from them;
   hdx    the same step with h = dx (feet up to 1.5 cells: the general kernels);
@@ -459,11 +460,12 @@ def arm_hdx(ctx, seed: int, tol: float, patches: int) -> dict:
     return out
 
 
-def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, train_count: int = 48,
-                test_count: int = 8, steps: int = 1500) -> dict:
-    """Learned warm start: a dilated CNN (BF16 matrix-core kernels of the library) trained on the
-    method's own solves of the batch law at n^2 (coarse n_coarse^2), then on held-out problems the
-    cold start (v = 1), u_hat and the network's start, each solved to tol."""
+def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, train_count: int = 192,
+                test_count: int = 8, steps: int = 2000) -> dict:
+    """Learned warm start: the 4-level U-Net (BF16 matrix-core kernels of the library) trained on
+    the method's own solves of the batch law at n^2 (coarse n_coarse^2, bicubic u_hat as input),
+    then on held-out problems the cold start (v = 1), the bilinear u_hat, the bicubic u_hat and the
+    network's start, each solved to tol by Jacobi and by the u_hat-ordered active-tile solver."""
     import torch
 
     from paper_1502_01629_amd import capi, warmstart
@@ -471,21 +473,24 @@ def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, 
 
     pairs = I.warmstart_problems(seed, count=train_count + test_count, n=n, n_coarse=n_coarse)
     t = time.perf_counter()
-    frames = warmstart.make_frames(ctx, pairs, tol=tol)
+    frames = []
+    for k in range(0, len(pairs), 32):
+        frames += warmstart.make_frames(ctx, pairs[k:k + 32], tol=tol, bicubic=True)
+        log(f"learned: {len(frames)} of {len(pairs)} solves, {time.perf_counter() - t:.1f} s")
     t_data = time.perf_counter() - t
-    log(f"learned: {len(frames)} training/evaluation solves in {t_data:.1f} s")
     train, test = frames[:train_count], frames[train_count:]
-    net = capi.Net(ctx, 6, 32, (1, 2, 4, 8, 16, 1))
+    net = capi.Net(ctx, arch=capi.NET_UNET)
     net.set_params(warmstart.init_params(net, seed))
     torch.cuda.synchronize()
     t = time.perf_counter()
-    losses = warmstart.train(net, train, steps=steps, batch=8, crop=256, lr=2e-3, seed=seed)
+    losses = warmstart.train(net, train, steps=steps, batch=8, crop=256, lr=1e-3, seed=seed)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
     log(f"learned: {steps} training steps in {t_train:.1f} s, loss {np.mean(losses[:20]):.2e} -> "
         f"{np.mean(losses[-20:]):.2e}")
     rows = warmstart.evaluate(ctx, net, test, tol=tol)
     for f, r in zip(test, rows):
+        free = torch.from_numpy((f.dp.inst.node_class.reshape(-1) == 0)).cuda()
         v = torch.from_numpy(f.dp.inst.initial().reshape(-1)).cuda()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -493,21 +498,28 @@ def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, 
         torch.cuda.synchronize()
         r["jacobi_sweeps_cold"] = st["sweeps"]
         r["jacobi_s_cold"] = time.perf_counter() - t
-    mean = lambda k: float(np.mean([r[k] for r in rows]))
+        r["jacobi_err_cold"] = float((v - f.vstar).abs()[free].max())
     net.close()
-    return {
-        "n": n, "coarse": n_coarse, "train_problems": train_count, "test_problems": test_count,
-        "data_generation_s": t_data, "training_steps": steps, "training_s": t_train,
-        "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
-        "inference_s": mean("t_network_s"),
-        "start_error_mean": {"uhat": mean("err_mean_uhat"), "network": mean("err_mean_network")},
-        "start_error_max": {"uhat": mean("err_max_uhat"), "network": mean("err_max_network")},
-        "jacobi_sweeps": {"cold": mean("jacobi_sweeps_cold"), "uhat": mean("jacobi_sweeps_uhat"),
-                          "network": mean("jacobi_sweeps_network")},
-        "jacobi_time_s": {"cold": mean("jacobi_s_cold"), "uhat": mean("jacobi_s_uhat"),
-                          "network": mean("jacobi_s_network")},
-        "active_tiles_time_s": {"uhat": mean("tiles_s_uhat"), "network": mean("tiles_s_network")},
+    names = ("uhat", "uhat_bicubic", "network")
+    mean = lambda k: float(np.mean([r[k] for r in rows]))
+    per = lambda key, extra=(): {m: mean(f"{key}_{m}") for m in tuple(extra) + names}
+    out = {
+        "n": n, "coarse": n_coarse, "network": "unet4", "train_problems": train_count,
+        "test_problems": test_count, "data_generation_s": t_data, "training_steps": steps,
+        "training_s": t_train, "loss_first": float(np.mean(losses[:20])),
+        "loss_last": float(np.mean(losses[-20:])), "inference_s": mean("t_network_s"),
+        "start_error_mean": per("err_mean"), "start_error_max": per("err_max"),
+        "jacobi_sweeps": per("jacobi_sweeps", ("cold",)), "jacobi_time_s": per("jacobi_s", ("cold",)),
+        "jacobi_stop_error_max": per("jacobi_err", ("cold",)),
+        "active_tiles_time_s": per("tiles_s"), "active_tiles_updates_per_node": per("tiles_updates_per_node"),
+        "active_tiles_stop_error_max": per("tiles_err"),
+        "reference_residual_max": max(r["ref_residual"] for r in rows),
     }
+    for r in rows:
+        log(f"learned test n={r['n']} eps={r['eps']:.2e}: start err max uhat {r['err_max_uhat']:.3e} "
+            f"bicubic {r['err_max_uhat_bicubic']:.3e} net {r['err_max_network']:.3e}; tiles s "
+            f"{r['tiles_s_uhat']:.3f}/{r['tiles_s_uhat_bicubic']:.3f}/{r['tiles_s_network']:.3f}")
+    return out
 
 
 def main():
@@ -526,11 +538,13 @@ def main():
                     help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
                          "with eps = 1e-3 and 1e-2), indep (decomposition error of the independent patch solves), "
                          "hdx (the step with h = dx), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
-                         "learned (CNN warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
+                         "learned (U-Net warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
                          "Table 0 on the GPU and the eps-threshold sweeps of Tables 1 and 2)")
     ap.add_argument("--arms-out", default=os.path.join(ROOT, "gpurun_out", "bench_arms.json"),
                     help="file that receives the full record (every arm); the stdout line holds a summary")
     ap.add_argument("--bumps-n", type=int, default=4097)
+    ap.add_argument("--learned-train", type=int, default=192, help="training solves of the learned arm")
+    ap.add_argument("--learned-steps", type=int, default=2000, help="training steps of the learned arm")
     ap.add_argument("--policy-sweeps", type=int, default=POLICY_SWEEPS,
                     help="policy-evaluation iterations after each full iteration of a tile visit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -721,7 +735,8 @@ def main():
     if "bumps" in which:
         arms["rank1_bumps"] = arm_bumps(ctx, args.seed, args.tol, args.bumps_n)
     if "learned" in which:
-        arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol)
+        arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol, train_count=args.learned_train,
+                                                   steps=args.learned_steps)
     if "exit" in which:
         arms["exit_to_boundary"] = arm_exit(ctx, args.tol)
     if not args.no_cpu_baseline:
@@ -794,9 +809,11 @@ def summary_line(full: dict) -> dict:
                               "active_tiles_uhat_s": _r(e["active_tiles_uhat"]["time_s"])}
     if "learned_warm_start" in A:
         e = A["learned_warm_start"]
-        arms["learned_1025"] = {"start_error_mean": {k: _r(v, 3) for k, v in e["start_error_mean"].items()},
+        arms["learned_1025"] = {"train": e["train_problems"],
+                                "start_error_mean": {k: _r(v, 3) for k, v in e["start_error_mean"].items()},
                                 "jacobi_sweeps": {k: _r(v) for k, v in e["jacobi_sweeps"].items()},
-                                "active_tiles_s": {k: _r(v) for k, v in e["active_tiles_time_s"].items()}}
+                                "active_tiles_s": {k: _r(v) for k, v in e["active_tiles_time_s"].items()},
+                                "stop_err_tiles": {k: _r(v, 3) for k, v in e["active_tiles_stop_error_max"].items()}}
     if "exit_to_boundary" in A:
         t0 = A["exit_to_boundary"]["table0"]
         arms["exit_table0_sl2_sl3"] = {f"{r['equation']}/{r['eps']:g}": [r["jacobi_sweeps_sl2"], r["jacobi_sweeps_sl3"]]

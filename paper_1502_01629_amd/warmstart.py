@@ -2,10 +2,12 @@
 network kernels (slhjb_net_*), and the comparison of starts.
 
 A frame is one fine problem with u_hat (the bilinear upsampling of its coarse sigma = 0 solve,
-Section 4.3) and v* (its converged fine solution). The network learns delta = v* - u_hat from
-[u_hat, c, target mask, log10(eps), distance to the box] on random crops; the start of the fine iteration is then
-clamp(u_hat + delta, 0, 1). The iteration converges to the same fixed point from any start, so
-the comparison measures work only: the error of the start and the sweeps to the tolerance.
+Section 4.3), the network's input u_hat (the same bilinear one for the dilated CNN, the bicubic
+upsampling for the U-Net) and v* (its converged fine solution). The network learns
+delta = v* - u_hat_in from [u_hat_in, c, target mask, log10(eps), distance to the box] on random
+crops; the start of the fine iteration is then clamp(u_hat_in + delta, 0, 1). The iteration
+converges to the same fixed point from any start, so the comparison measures work only: the
+error of the start, and the sweeps and time to the tolerance.
 """
 from __future__ import annotations
 
@@ -18,11 +20,27 @@ import numpy as np
 from . import capi
 
 
+# (c_in, c_out) of the U-Net's 14 convolutions in parameter order (slhjb_net_config, arch 1)
+UNET_LAYERS = [(16, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128), (128, 128), (128, 128), (256, 128),
+               (128, 128), (192, 64), (64, 64), (96, 32), (32, 32)]
+
+
 def init_params(net: "capi.Net", seed: int = 0) -> np.ndarray:
     """He-normal 3 x 3 weights over the used input channels, zero biases, a small head."""
     rng = np.random.default_rng(seed)
     C = net.channels
     parts = []
+    if net.arch == capi.NET_UNET:
+        for l, (cin, cout) in enumerate(UNET_LAYERS):
+            used = 5 if l == 0 else cin
+            w = rng.normal(0.0, math.sqrt(2.0 / (9 * used)), size=(9, cout, cin))
+            if l == 0:
+                w[:, :, 5:] = 0.0
+            parts += [w.reshape(-1), np.zeros(cout)]
+        parts += [rng.normal(0.0, 1e-2, size=32), np.zeros(1)]
+        p = np.concatenate(parts).astype(np.float32)
+        assert p.size == net.param_count
+        return p
     for l in range(net.layers):
         cin = 16 if l == 0 else C
         used = 5 if l == 0 else C
@@ -39,17 +57,19 @@ def init_params(net: "capi.Net", seed: int = 0) -> np.ndarray:
 @dataclass
 class Frame:
     dp: "capi.DeviceProblem"
-    vhat: object   # device float[n*n]
+    vhat: object   # device float[n*n]: bilinear u_hat (the paper's start)
     vstar: object  # device float[n*n]
     n: int
     eps: float
     seconds_coarse: float
     seconds_fine: float
+    feat: object = None  # device float[n*n]: the network's u_hat (bicubic for the U-Net), else vhat
 
 
-def make_frames(ctx: "capi.Context", pairs, tol: float = 1e-6) -> list[Frame]:
+def make_frames(ctx: "capi.Context", pairs, tol: float = 1e-6, bicubic: bool = False) -> list[Frame]:
     """Solve each (fine, coarse) pair with the library: coarse sigma = 0 active-tile solve, u_hat,
-    then the fine solve from u_hat in u_hat order to tol."""
+    then the fine solve from u_hat in u_hat order to tol. With bicubic the frame also holds the
+    bicubic u_hat, the U-Net's input."""
     import torch
 
     frames = []
@@ -70,7 +90,12 @@ def make_frames(ctx: "capi.Context", pairs, tol: float = 1e-6) -> list[Frame]:
         torch.cuda.synchronize()
         if st["status"] != 0:
             raise RuntimeError(f"fine solve did not converge: {st}")
-        frames.append(Frame(dp, vhat, vstar, fine.n, float(fine.eps), tc, time.perf_counter() - t))
+        tf = time.perf_counter() - t
+        feat = vhat
+        if bicubic:
+            feat = torch.empty_like(vhat)
+            ctx.upsample_bicubic(vc, coarse.n, feat, fine.n)
+        frames.append(Frame(dp, vhat, vstar, fine.n, float(fine.eps), tc, tf, feat))
     return frames
 
 
@@ -83,6 +108,8 @@ def train(net: "capi.Net", frames, steps: int, batch: int = 8, crop: int = 256, 
     rng = np.random.default_rng(seed)
     losses = []
     c = min(crop, min(f.n for f in frames))
+    if net.arch == capi.NET_UNET:
+        c -= c % 8
 
     def origin(n):
         if rng.random() < 0.5:
@@ -93,29 +120,39 @@ def train(net: "capi.Net", frames, steps: int, batch: int = 8, crop: int = 256, 
         items = []
         for _ in range(batch):
             f = frames[int(rng.integers(len(frames)))]
-            items.append((f.vhat, f.vstar, f.dp, origin(f.n), origin(f.n)))
+            items.append((f.feat, f.vstar, f.dp, origin(f.n), origin(f.n)))
         losses.append(net.loss_grad(items, c))
         rate = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps - 1))))
         net.adam_step(rate)
     return losses
 
 
-def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6) -> list[dict]:
-    """For every frame: error of u_hat and of the network's start against v*, and the plain Jacobi
-    solve and the u_hat-ordered active-tile solve from each start."""
+def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6, tol_ref: float = 2e-7,
+             max_ref_sweeps: int = 20000) -> list[dict]:
+    """For every frame: error of u_hat, of the bicubic u_hat (when the frame has one) and of the
+    network's start against v*, and from each start the plain Jacobi solve and the u_hat-ordered
+    active-tile solve: sweeps, time, node updates, and the error at the stopping point against v*.
+    v* is first refined by Jacobi sweeps to the residual tol_ref (at most max_ref_sweeps), so that
+    it is closer to the fixed point than any of the stopping points it is compared with."""
     import torch
 
     out = []
     for f in frames:
         free = torch.from_numpy((f.dp.inst.node_class.reshape(-1) == 0)).cuda()
+        ref = ctx.solve(f.dp, f.vstar, tol=tol_ref, max_sweeps=max_ref_sweeps)
         g = torch.empty_like(f.vhat)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        net.warm_start(f.dp, f.vhat, g)
+        net.warm_start(f.dp, f.feat, g)
         torch.cuda.synchronize()
         t_net = time.perf_counter() - t
-        row = {"n": f.n, "eps": f.eps, "t_network_s": t_net}
-        for name, start in (("uhat", f.vhat), ("network", g)):
+        row = {"n": f.n, "eps": f.eps, "t_network_s": t_net, "ref_residual": ref["residual"],
+               "ref_sweeps": ref["sweeps"]}
+        starts = [("uhat", f.vhat)]
+        if f.feat is not f.vhat:
+            starts.append(("uhat_bicubic", f.feat))
+        starts.append(("network", g))
+        for name, start in starts:
             e = (start - f.vstar).abs()[free]
             row[f"err_max_{name}"] = float(e.max())
             row[f"err_mean_{name}"] = float(e.mean())
@@ -126,6 +163,7 @@ def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6) ->
             torch.cuda.synchronize()
             row[f"jacobi_sweeps_{name}"] = st["sweeps"]
             row[f"jacobi_s_{name}"] = time.perf_counter() - t
+            row[f"jacobi_err_{name}"] = float((v - f.vstar).abs()[free].max())
             v = start.clone()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -133,5 +171,6 @@ def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6) ->
             torch.cuda.synchronize()
             row[f"tiles_s_{name}"] = time.perf_counter() - t
             row[f"tiles_updates_per_node_{name}"] = st["node_updates"] / max(1, int(free.sum()))
+            row[f"tiles_err_{name}"] = float((v - f.vstar).abs()[free].max())
         out.append(row)
     return out

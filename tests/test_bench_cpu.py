@@ -42,9 +42,11 @@ def full_record() -> dict:
             "h_equals_dx": {"patchy_time_s": X, "global_jacobi_cold_s": X, "halo": 3},
             "batch_256_instances": {"time_s_batched": X, "time_s_sequential": X, "bit_exact_vs_single": "256/256"},
             "rank1_bumps": {k: {"time_s": X} for k in ("full_sweeps", "active_tiles_cold", "active_tiles_uhat")},
-            "learned_warm_start": {"start_error_mean": {"uhat": X, "network": X},
-                                   "jacobi_sweeps": {"cold": X, "uhat": X, "network": X},
-                                   "active_tiles_time_s": {"cold": X, "uhat": X, "network": X}},
+            "learned_warm_start": {"train_problems": 192,
+                                   "start_error_mean": {"uhat": X, "uhat_bicubic": X, "network": X},
+                                   "jacobi_sweeps": {"cold": X, "uhat": X, "uhat_bicubic": X, "network": X},
+                                   "active_tiles_time_s": {"uhat": X, "uhat_bicubic": X, "network": X},
+                                   "active_tiles_stop_error_max": {"uhat": X, "uhat_bicubic": X, "network": X}},
             "exit_to_boundary": {"table0": [{"equation": e, "eps": eps, "jacobi_sweeps_sl2": 1000,
                                              "jacobi_sweeps_sl3": 1000, "lambda": 0.0}
                                             for e in ("A", "B", "B2", "C") for eps in (0.0, 1e-2)]},

@@ -173,3 +173,28 @@ def test_unet_adam_step(ctx, net):
     net.adam_step(1e-3)
     ref, _, _ = cnn.adam(p.astype(np.float64), g, np.zeros(p.size), np.zeros(p.size), 1, 1e-3)
     assert np.abs(net.get_params() - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_trained_unet_start(ctx, net):
+    """Train on the method's own solves (257^2, coarse 65^2, the batch law, bicubic u_hat as input),
+    then on held-out problems: the loss falls, the network's start is closer to v* than both
+    upsamplings on average, and every start's stopping point of the u_hat-ordered active-tile solve
+    is within 1e-4 of the refined v* (the same fixed point whatever the start)."""
+    from paper_1502_01629_amd import warmstart
+
+    pairs = I.warmstart_problems(22, count=36, n=257, n_coarse=65)
+    frames = warmstart.make_frames(ctx, pairs, bicubic=True)
+    train, test = frames[:32], frames[32:]
+    net.set_params(warmstart.init_params(net, 0))
+    losses = warmstart.train(net, train, steps=500, batch=8, crop=128, lr=1e-3)
+    print("loss first/last", np.mean(losses[:20]), np.mean(losses[-20:]), flush=True)
+    rows = warmstart.evaluate(ctx, net, test)
+    for r in rows:
+        print({k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:20])
+    e = {m: np.mean([r[f"err_mean_{m}"] for r in rows]) for m in ("uhat", "uhat_bicubic", "network")}
+    print("held-out mean |start - v*|", e, flush=True)
+    assert e["network"] < min(e["uhat"], e["uhat_bicubic"])
+    for r in rows:
+        for m in ("uhat", "uhat_bicubic", "network"):
+            assert r[f"tiles_err_{m}"] <= 1e-4, (m, r)

@@ -183,107 +183,363 @@ size_t conv3x3_lds_bytes(int dil) {
   return sizeof(uint16_t) * 3 * (64 + 2 * dil) * ConvShape<CIN, COUT>::KP;
 }
 
-// ---- weight gradient -------------------------------------------------------------------------
-// dW[t][co][ci] = sum_p dY[p][co] X[p + off_t][ci]: a GEMM with M = COUT, N = CIN and the pixels
-// as K. grid (chunks, 9 taps). A workgroup walks `chunk` consecutive pixels (flattened over the
-// batch) in steps of 64, staging dY and the tap-shifted X transposed in LDS ([channel][pixel]), so
-// that the matrix-core fragments (8 consecutive pixels of one channel) are single 16-byte reads.
-// The COUT/16 x CIN/16 output blocks are dealt to the four wavefronts; one atomic per weight and
-// workgroup adds the sums to dW (FP32).
+// ---- 3 x 3 convolution with register tiles (dilation 1) --------------------------------------
+// The same products as conv3x3_kernel, with a larger output tile per workgroup: TR rows x 64
+// pixels x all COUT channels, dealt to the four wavefronts as PWG pixel groups x CWG channel groups
+// of MB x NB 16 x 16 blocks. Every weight fragment a wavefront loads serves its MB pixel blocks and
+// every staged input fragment its NB channel blocks. The TR + 2 input rows the tile reads are
+// staged in LDS one channel chunk at a time. The results go through LDS (bias and ReLU, or the
+// ReLU gate of the data gradient, applied on the way) so that each thread writes 16 contiguous
+// bytes. Same operands, accumulation order and rounding as conv3x3_kernel.
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const uint16_t* __restrict__ x,
-                                                            const uint16_t* __restrict__ dy, int images, int H,
-                                                            int W, int dil, int chunk, float* __restrict__ dw) {
-  constexpr int MBt = COUT / 16, NBt = CIN / 16, BLK = MBt * NBt;
-  constexpr int NBLK = (BLK + 3) / 4;  // output blocks per wavefront
-  constexpr int PP = 64 + 8;           // LDS pitch (pixels) of a channel row
-  __shared__ uint16_t dyT[COUT * PP];
-  __shared__ uint16_t xT[CIN * PP];
-  const int t = blockIdx.y;
-  const int oy = (t / 3 - 1) * dil, ox = (t % 3 - 1) * dil;
+struct ConvTile {
+  static constexpr int KC = ConvShape<CIN, COUT>::KC;
+  static constexpr int KP = ConvShape<CIN, COUT>::KP;
+  static constexpr int KS = ConvShape<CIN, COUT>::KS;
+  static constexpr int CWG = (COUT == 128 || COUT >= 192) ? 2 : 1;
+  static constexpr int PWG = 4 / CWG;
+  static constexpr int NB = COUT / 16 / CWG;
+  static constexpr int MB = COUT == 32 ? 8 : 4;
+  static constexpr int TP = PWG * MB * 16;  // pixels per workgroup
+  static constexpr int TR = TP / 64;        // rows per workgroup
+  static constexpr int OP = COUT + 8;       // LDS pitch of an output pixel (bf16)
+};
+
+template <int CIN, int COUT>
+size_t conv3x3_tile_lds_bytes() {
+  using S = ConvTile<CIN, COUT>;
+  const size_t stage = (size_t)(S::TR + 2) * 66 * S::KP, outs = (size_t)S::TP * S::OP;
+  return sizeof(uint16_t) * (stage > outs ? stage : outs);
+}
+
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_tile_kernel(const uint16_t* __restrict__ in,
+                                                           const uint16_t* __restrict__ w,
+                                                           const float* __restrict__ bias,
+                                                           const uint16_t* __restrict__ gate, int H, int W, int relu,
+                                                           uint16_t* __restrict__ out) {
+  using S = ConvTile<CIN, COUT>;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && S::NB >= 1 && S::NB * S::MB <= 32, "tile");
+  static_assert(CIN % S::KC == 0 && S::KC % S::KS == 0, "the channel chunks tile CIN");
+  static_assert(S::CWG * S::NB * 16 == COUT && S::TP % 64 == 0, "waves tile the output");
+  constexpr int XW = 66;
+  extern __shared__ uint16_t xs[];  // [TR + 2][XW][KP], then [TP][OP] for the results
+  const int img = blockIdx.z, y0 = blockIdx.y * S::TR, x0 = blockIdx.x * 64;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cw = wave % S::CWG, pw = wave / S::CWG;
+  const int sg = MODE == 0 ? 1 : -1;
+  const size_t img_off = (size_t)img * H * W;
   const int kq = lane >> 4, l16 = lane & 15;
-  const long long HW = (long long)H * W, total = (long long)images * HW;
-  const long long p0 = (long long)blockIdx.x * chunk;
-  v4f acc[NBLK];
+  v4f acc[S::MB][S::NB];
 #pragma unroll
-  for (int q = 0; q < NBLK; ++q) acc[q] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int s = 0; s < chunk; s += 64) {
-    __syncthreads();
-    // stage 64 pixels: each thread moves 8 channels of one pixel (16 bytes) at a time
-    for (int e = threadIdx.x; e < 64 * (COUT / 8); e += 256) {
-      const int pl = e / (COUT / 8), c8 = e - pl * (COUT / 8);
-      const long long p = p0 + s + pl;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (p < total) v = *reinterpret_cast<const uint4*>(dy + (size_t)p * COUT + 8 * c8);
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+  for (int m = 0; m < S::MB; ++m)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dyT[(8 * c8 + j) * PP + pl] = h[j];
-    }
-    for (int e = threadIdx.x; e < 64 * (CIN / 8); e += 256) {
-      const int pl = e / (CIN / 8), c8 = e - pl * (CIN / 8);
-      const long long p = p0 + s + pl;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (p < total) {
-        const long long img = p / HW;
-        const int rem = (int)(p - img * HW);
-        const int yy = rem / W + oy, xx = rem % W + ox;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          v = *reinterpret_cast<const uint4*>(x + ((size_t)img * HW + (size_t)yy * W + xx) * CIN + 8 * c8);
+    for (int b = 0; b < S::NB; ++b) acc[m][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int kc = 0; kc < CIN; kc += S::KC) {
+    __syncthreads();  // the previous chunk's reads are done
+    // stage rows y0 - 1 .. y0 + TR, columns x0 - 1 .. x0 + 64, in 16-byte pieces (8 channels),
+    // four loads of the thread in flight before their LDS stores
+    constexpr int V = S::KC / 8;
+    constexpr int total = (S::TR + 2) * XW * V;
+    constexpr int SB = 4;
+    for (int e0 = 0; e0 < total; e0 += 256 * SB) {
+      uint4 v[SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        const int e = e0 + threadIdx.x + 256 * i;
+        const int q = e / (XW * V);
+        const int rem = e - q * XW * V;
+        const int xi = rem / V, c8 = rem - xi * V;
+        const int yy = y0 - 1 + q, xx = x0 - 1 + xi;
+        v[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < total && yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v[i] = *reinterpret_cast<const uint4*>(in + (img_off + (size_t)yy * W + xx) * CIN + kc + 8 * c8);
       }
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) xT[(8 * c8 + j) * PP + pl] = h[j];
+      for (int i = 0; i < SB; ++i) {
+        const int e = e0 + threadIdx.x + 256 * i;
+        const int q = e / (XW * V);
+        const int rem = e - q * XW * V;
+        const int xi = rem / V, c8 = rem - xi * V;
+        if (e < total) *reinterpret_cast<uint4*>(xs + ((size_t)q * XW + xi) * S::KP + 8 * c8) = v[i];
+      }
     }
     __syncthreads();
+    // taps as a loop (not unrolled), so that the weight loads of one tap stay in that tap
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+      const int dy = sg * (t / 3 - 1), dx = sg * (t % 3 - 1);
 #pragma unroll
-    for (int ks = 0; ks < 64; ks += 32) {
+      for (int ks = 0; ks < S::KC; ks += S::KS) {
+        uint4 bq[S::NB];
+        uint2 bh[S::NB];
 #pragma unroll
-      for (int q = 0; q < NBLK; ++q) {
-        const int blk = wave + 4 * q;
-        if (blk < BLK) {
-          const int mb = blk / NBt, nb = blk - mb * NBt;
-          const uint4 a = *reinterpret_cast<const uint4*>(dyT + (mb * 16 + l16) * PP + ks + 8 * kq);
-          const uint4 b = *reinterpret_cast<const uint4*>(xT + (nb * 16 + l16) * PP + ks + 8 * kq);
-          acc[q] = mfma32(a, b, acc[q]);
+        for (int b = 0; b < S::NB; ++b) {
+          const int co = (cw * S::NB + b) * 16 + l16;
+          const uint16_t* wp = w + ((size_t)t * COUT + co) * CIN + kc + ks;
+          if (S::KS == 32) bq[b] = *reinterpret_cast<const uint4*>(wp + 8 * kq);
+          else bh[b] = *reinterpret_cast<const uint2*>(wp + 4 * kq);
+        }
+#pragma unroll
+        for (int m = 0; m < S::MB; ++m) {
+          const int pl = (pw * S::MB + m) * 16 + l16;  // pixel of the tile: row pl / 64, column pl % 64
+          const int q = pl / 64 + 1 + dy, xi = pl % 64 + 1 + dx;
+          const uint16_t* ap = xs + ((size_t)q * XW + xi) * S::KP + ks;
+          if (S::KS == 32) {
+            const uint4 a = *reinterpret_cast<const uint4*>(ap + 8 * kq);
+#pragma unroll
+            for (int b = 0; b < S::NB; ++b) acc[m][b] = mfma32(a, bq[b], acc[m][b]);
+          } else {
+            const v4s a = as_v4s(*reinterpret_cast<const uint2*>(ap + 4 * kq));
+#pragma unroll
+            for (int b = 0; b < S::NB; ++b) acc[m][b] = mfma16(a, as_v4s(bh[b]), acc[m][b]);
+          }
         }
       }
     }
   }
-  // D[co][ci]: lane holds co = 16 mb + 4 (l / 16) + j, ci = 16 nb + l % 16
+  __syncthreads();  // the staged rows are no longer read
+  // D rows are pixels 4 (l / 16) + j of the block, columns output channels
 #pragma unroll
-  for (int q = 0; q < NBLK; ++q) {
-    const int blk = wave + 4 * q;
-    if (blk < BLK) {
-      const int mb = blk / NBt, nb = blk - mb * NBt;
+  for (int b = 0; b < S::NB; ++b) {
+    const int co = (cw * S::NB + b) * 16 + l16;
+    const float bb = MODE == 0 ? bias[co] : 0.0f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        atomicAdd(&dw[((size_t)t * COUT + mb * 16 + 4 * kq + j) * CIN + nb * 16 + l16], acc[q][j]);
+    for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = acc[m][b][j];
+        if (MODE == 0) {
+          v += bb;
+          if (relu) v = fmaxf(v, 0.0f);
+        }
+        xs[(size_t)((pw * S::MB + m) * 16 + 4 * kq + j) * S::OP + co] = f2bf(v);
+      }
+  }
+  __syncthreads();
+  constexpr int V8 = COUT / 8;
+  for (int e = threadIdx.x; e < S::TP * V8; e += 256) {
+    const int pl = e / V8, c8 = e - pl * V8;
+    const int yy = y0 + pl / 64, xx = x0 + pl % 64;
+    if (yy >= H || xx >= W) continue;
+    const size_t o = (img_off + (size_t)yy * W + xx) * COUT + 8 * c8;
+    uint4 v = *reinterpret_cast<const uint4*>(xs + (size_t)pl * S::OP + 8 * c8);
+    if (MODE == 1 && gate) {
+      // keep the gradient where the layer input is > 0 (bf16 bits: nonzero, sign clear)
+      const uint4 gv = *reinterpret_cast<const uint4*>(gate + o);
+      const uint32_t gw[4] = {gv.x, gv.y, gv.z, gv.w};
+      uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
+        const uint32_t keep = ((lo != 0u && !(lo & 0x8000u)) ? 0xffffu : 0u) |
+                              ((hi != 0u && !(hi & 0x8000u)) ? 0xffff0000u : 0u);
+        vw[i] &= keep;
+      }
+      v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
     }
+    *reinterpret_cast<uint4*>(out + o) = v;
   }
 }
 
-// bias gradient: db[co] += sum over the chunk's pixels of dY[p][co]
-template <int COUT>
-__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* __restrict__ dy, long long total, int chunk,
-                                                        float* __restrict__ db) {
-  __shared__ float red[256];
-  const int co = threadIdx.x % COUT, part = threadIdx.x / COUT;
-  constexpr int parts = 256 / COUT;
-  const long long p0 = (long long)blockIdx.x * chunk;
-  float s = 0.0f;
-  for (int k = part; k < chunk; k += parts) {
-    const long long p = p0 + k;
-    if (p < total) s += bf2f(dy[(size_t)p * COUT + co]);
+// ---- weight and bias gradients ------------------------------------------------------------------
+// dW[t][co][ci] = sum_p dY[p][co] X[p + off_t][ci] and db[co] = sum_p dY[p][co]: GEMMs with the
+// pixels as K. A workgroup owns a CO_T x CI_T block of (co, ci) for all nine taps and walks `steps`
+// consecutive strips (64 pixels of one row of one image). Per strip it stages dY[strip][co block]
+// and the three input rows X[y + (ty - 1) dil][x0 - dil .. x0 + 64 + dil][ci block] transposed in
+// LDS, as runs of 8 pixels of one channel (one 16-byte matrix-core fragment). The runs are
+// strided: run g of the strip holds pixels x0 + g + 8 j (j = 0..7), so a tap's column shift
+// tx dil moves a fragment to another whole run (g + tx dil) and every LDS read is an aligned
+// 16-byte read. The 8 x 8 transposes (8 channels x 8 pixels) happen in registers while staging.
+// The (tap, ci block) units are dealt to the four wavefronts; each loads the dY fragments of its
+// co blocks once per K step and reuses them for all its units. The bias gradient is one more
+// product per co block, with a B operand of ones. Each workgroup writes its partial sums to its
+// own slice of `work` ([tile][strip run][9][CO_T][CI_T] then [CO_T] for the bias, plain stores);
+// wgrad_reduce_kernel adds the slices of every tile to dW and db.
+template <int CIN, int COUT>
+struct WgradShape {
+  static constexpr int CO_T = COUT < 64 ? COUT : 64;
+  static constexpr int CI_T = CIN % 64 == 0 ? 64 : (CIN % 48 == 0 ? 48 : (CIN % 32 == 0 ? 32 : 16));
+  static constexpr int MBt = CO_T / 16, NBt = CI_T / 16;
+  static constexpr int UNITS = 9 * NBt;       // (tap, ci block) pairs
+  static constexpr int NU = (UNITS + 3) / 4;  // units per wavefront
+  static constexpr int DYP = 9;               // LDS pitch of a dY channel, in 16-byte runs (8 + 1)
+};
+
+__device__ __forceinline__ uint32_t lohalves(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+__device__ __forceinline__ uint32_t hihalves(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+
+// v[j] holds channels 0..7 of pixel j; on return o[c] holds pixels 0..7 of channel c
+__device__ __forceinline__ void transpose8x8(const uint4 v[8], uint4 o[8]) {
+#pragma unroll
+  for (int c2 = 0; c2 < 4; ++c2) {
+    uint32_t w[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[j] = c2 == 0 ? v[j].x : (c2 == 1 ? v[j].y : (c2 == 2 ? v[j].z : v[j].w));
+    o[2 * c2] = make_uint4(lohalves(w[0], w[1]), lohalves(w[2], w[3]), lohalves(w[4], w[5]), lohalves(w[6], w[7]));
+    o[2 * c2 + 1] = make_uint4(hihalves(w[0], w[1]), hihalves(w[2], w[3]), hihalves(w[4], w[5]), hihalves(w[6], w[7]));
   }
-  red[threadIdx.x] = s;
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const uint16_t* __restrict__ x,
+                                                            const uint16_t* __restrict__ dy, int images, int H,
+                                                            int W, int dil, int steps, float* __restrict__ work) {
+  using S = WgradShape<CIN, COUT>;
+  static_assert(COUT % S::CO_T == 0 && CIN % S::CI_T == 0 && S::MBt >= 1 && S::MBt <= 4, "tiles");
+  extern __shared__ uint4 lds4[];
+  const int NG = 8 + 2 * dil;           // runs per staged row and channel
+  const int XP = NG + 1;                // LDS pitch of an X channel row, in runs (odd)
+  uint4* dyT = lds4;                    // [CO_T][DYP]
+  uint4* xT = lds4 + S::CO_T * S::DYP;  // [3][CI_T][XP]
+  constexpr int CBLK = CIN / S::CI_T;
+  const int co0 = (blockIdx.y / CBLK) * S::CO_T, ci0 = (blockIdx.y % CBLK) * S::CI_T;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kq = lane >> 4, l16 = lane & 15;
+  const int NS = (W + 63) / 64;
+  const long long nsteps = (long long)images * H * NS;
+  const long long s0 = (long long)blockIdx.x * steps;
+  v4f acc[S::NU][S::MBt];
+#pragma unroll
+  for (int u = 0; u < S::NU; ++u)
+#pragma unroll
+    for (int m = 0; m < S::MBt; ++m) acc[u][m] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  v4f accb = v4f{0.0f, 0.0f, 0.0f, 0.0f};  // bias sums of co block `wave`
+  const uint4 ones = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);  // bf16 1.0
+  for (int k = 0; k < steps; ++k) {
+    const long long st = s0 + k;
+    if (st >= nsteps) break;
+    const int img = (int)(st / ((long long)H * NS));
+    const int rem = (int)(st - (long long)img * H * NS);
+    const int y = rem / NS, x0 = (rem % NS) * 64;
+    const int SW = min(64, W - x0);
+    const size_t img_off = (size_t)img * H * W;
+    __syncthreads();  // the previous strip's reads are done
+    // dY runs: item (g, c8) -> channels co0 + 8 c8 .. + 7 of pixels x0 + g + 8 j (zero past the row)
+    for (int e = threadIdx.x; e < 8 * (S::CO_T / 8); e += 256) {
+      const int g = e % 8, c8 = e / 8;
+      uint4 v[8], o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = g + 8 * j;
+        v[j] = i < SW ? *reinterpret_cast<const uint4*>(dy + (img_off + (size_t)y * W + x0 + i) * COUT + co0 + 8 * c8)
+                      : make_uint4(0u, 0u, 0u, 0u);
+      }
+      transpose8x8(v, o);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) dyT[(8 * c8 + c) * S::DYP + g] = o[c];
+    }
+    // X runs: item (ty, sx, c8) -> channels ci0 + 8 c8 .. + 7 of row y + (ty - 1) dil, pixels
+    // x0 - dil + sx + 8 j (zero outside the image)
+    const int xitems = 3 * NG * (S::CI_T / 8);
+    for (int e = threadIdx.x; e < xitems; e += 256) {
+      const int c8 = e % (S::CI_T / 8);
+      const int rs = e / (S::CI_T / 8);
+      const int ty = rs / NG, sx = rs - ty * NG;
+      const int yy = y + (ty - 1) * dil;
+      uint4 v[8], o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int xx = x0 - dil + sx + 8 * j;
+        v[j] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                   ? *reinterpret_cast<const uint4*>(x + (img_off + (size_t)yy * W + xx) * CIN + ci0 + 8 * c8)
+                   : make_uint4(0u, 0u, 0u, 0u);
+      }
+      transpose8x8(v, o);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) xT[((size_t)ty * S::CI_T + 8 * c8 + c) * XP + sx] = o[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int g = 4 * ks + kq;  // this lane's run of the strip
+      uint4 a[S::MBt];
+#pragma unroll
+      for (int m = 0; m < S::MBt; ++m) a[m] = dyT[(m * 16 + l16) * S::DYP + g];
+#pragma unroll
+      for (int u = 0; u < S::NU; ++u) {
+        const int unit = wave + 4 * u;
+        if (unit < S::UNITS) {
+          const int t = unit % 9, nb = unit / 9;
+          const int ty = t / 3, tx = t - 3 * ty;
+          const uint4 b = xT[((size_t)ty * S::CI_T + nb * 16 + l16) * XP + g + tx * dil];
+#pragma unroll
+          for (int m = 0; m < S::MBt; ++m) acc[u][m] = mfma32(a[m], b, acc[u][m]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < S::MBt; ++m)
+        if (m == wave) accb = mfma32(a[m], ones, accb);
+    }
+  }
+  // D[co][ci]: lane holds co = 16 m + 4 (l / 16) + j, ci = 16 nb + l % 16 (tile-local)
+  constexpr int TILE = 9 * S::CO_T * S::CI_T;
+  float* part = work + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (TILE + S::CO_T);
+#pragma unroll
+  for (int u = 0; u < S::NU; ++u) {
+    const int unit = wave + 4 * u;
+    if (unit < S::UNITS) {
+      const int t = unit % 9, nb = unit / 9;
+#pragma unroll
+      for (int m = 0; m < S::MBt; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          part[((size_t)t * S::CO_T + m * 16 + 4 * kq + j) * S::CI_T + nb * 16 + l16] = acc[u][m][j];
+    }
+  }
+  if (wave < S::MBt && l16 == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[TILE + wave * 16 + 4 * kq + j] = accb[j];
+  }
+}
+
+// dW[t][co][ci] += sum over the runs of the partial sums of the tile holding (co, ci); db[co] +=
+// the same over the bias sums of the tiles with ci block 0. A workgroup of 512 threads takes 32
+// consecutive elements of a tile; its 16 slices of 32 threads sum every 16th run, then LDS adds
+// the 16 slice sums in a fixed order.
+__global__ __launch_bounds__(512) void wgrad_reduce_kernel(const float* __restrict__ work, int runs, int co_t,
+                                                           int ci_t, int cin, int cout, float* __restrict__ dw,
+                                                           float* __restrict__ db) {
+  __shared__ float red[16][33];
+  const int tile = blockIdx.y;
+  const int per = 9 * co_t * ci_t + co_t;
+  const int el = threadIdx.x & 31, slice = threadIdx.x >> 5;
+  const int e = blockIdx.x * 32 + el;
+  float sum = 0.0f;
+  if (e < per) {
+    const float* p = work + (size_t)tile * runs * per + e;
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int r = slice;
+    for (; r + 48 < runs; r += 64) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part[i] += p[(size_t)(r + 16 * i) * per];
+    }
+    for (; r < runs; r += 16) part[0] += p[(size_t)r * per];
+    sum = (part[0] + part[1]) + (part[2] + part[3]);
+  }
+  red[slice][el] = sum;
   __syncthreads();
-  if (part == 0) {
-    float v = 0.0f;
-    for (int q = 0; q < parts; ++q) v += red[q * COUT + co];
-    atomicAdd(&db[co], v);
+  if (slice != 0 || e >= per) return;
+  float total = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) total += red[i][el];
+  const int cblk = cin / ci_t;
+  const int co0 = (tile / cblk) * co_t, ci0 = (tile % cblk) * ci_t;
+  if (e < 9 * co_t * ci_t) {
+    const int t = e / (co_t * ci_t), rem = e - t * co_t * ci_t;
+    const int co = rem / ci_t, ci = rem - co * ci_t;
+    dw[((size_t)t * cout + co0 + co) * cin + ci0 + ci] += total;
+  } else if (tile % cblk == 0 && db) {
+    db[co0 + e - 9 * co_t * ci_t] += total;
   }
+}
+
+template <int CIN, int COUT>
+size_t conv3x3_wgrad_lds_bytes(int dil) {
+  using S = WgradShape<CIN, COUT>;
+  return sizeof(uint4) * ((size_t)S::CO_T * S::DYP + 3 * (size_t)S::CI_T * (8 + 2 * dil + 1));
 }
 
 // ---- U-Net glue: 2 x 2 average pooling, nearest upsampling with the skip concatenation, and their
@@ -400,13 +656,19 @@ __global__ void head_fwd_kernel(const uint16_t* __restrict__ h, const float* __r
   if (p >= total) return;
   float s = hb[0];
 #pragma unroll
-  for (int c = 0; c < C; ++c) s = fmaf(bf2f(h[(size_t)p * C + c]), hw[c], s);
+  for (int q = 0; q < C / 8; ++q) {
+    float hv[8];
+    unpack8(*reinterpret_cast<const uint4*>(h + (size_t)p * C + 8 * q), hv);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s = fmaf(hv[j], hw[8 * q + j], s);
+  }
   delta[p] = s;
 }
 
 // Loss on FREE nodes of the batch, L = (1/N) sum (u_hat + delta - v*)^2 with N the number of
 // masked pixels: ddelta = 2 (u_hat + delta - v*) / N; loss_acc[0] += the squared errors (then / N
 // on the host); also the head gradient dh[p][c] = ddelta hw[c] (h > 0), dhw, dhb.
+constexpr int kLossPix = 8;
 template <int C>
 __global__ __launch_bounds__(256) void loss_head_bwd_kernel(const float* __restrict__ delta,
                                                             const float* __restrict__ uhat,
@@ -417,23 +679,36 @@ __global__ __launch_bounds__(256) void loss_head_bwd_kernel(const float* __restr
                                                             float* __restrict__ dhw, float* __restrict__ dhb,
                                                             float* __restrict__ loss_acc) {
   __shared__ float sw[C + 2][4];
-  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  float g = 0.0f, sq = 0.0f;
-  if (p < total && mask[p]) {
-    const float e = uhat[p] + delta[p] - vstar[p];
-    sq = e * e;
-    g = 2.0f * e * inv_n;
-  }
+  // kLossPix pixels per thread (strided by the block), their sums kept per thread
   float part[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    float hv = 0.0f;
-    if (p < total) {
-      hv = bf2f(h[(size_t)p * C + c]);
-      dh[(size_t)p * C + c] = f2bf(hv > 0.0f ? g * hw[c] : 0.0f);
+  for (int c = 0; c < C; ++c) part[c] = 0.0f;
+  float g_sum = 0.0f, sq = 0.0f;
+  for (int k = 0; k < kLossPix; ++k) {
+    const long long p = ((long long)blockIdx.x * kLossPix + k) * blockDim.x + threadIdx.x;
+    if (p >= total) break;
+    float g = 0.0f;
+    if (mask[p]) {
+      const float e = uhat[p] + delta[p] - vstar[p];
+      sq += e * e;
+      g = 2.0f * e * inv_n;
     }
-    part[c] = g * hv;
+    g_sum += g;
+    // the pixel's C channels in 16-byte pieces
+#pragma unroll
+    for (int q = 0; q < C / 8; ++q) {
+      float hv[8];
+      unpack8(*reinterpret_cast<const uint4*>(h + (size_t)p * C + 8 * q), hv);
+      float gh[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        gh[j] = hv[j] > 0.0f ? g * hw[8 * q + j] : 0.0f;
+        part[8 * q + j] += g * hv[j];
+      }
+      *reinterpret_cast<uint4*>(dh + (size_t)p * C + 8 * q) = pack8(gh);
+    }
   }
+  const float g = g_sum;
   // block sums of dhw, dhb and the loss: wavefront reduction, then LDS
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -549,12 +824,29 @@ __global__ void scale_f32_kernel(float* p, long long count, float a) {
   if (i < count) p[i] *= a;
 }
 
-__global__ void count_nonzero_u8_kernel(const uint8_t* __restrict__ m, long long count, unsigned* __restrict__ out) {
+// out += the number of nonzero bytes of m: 16 bytes per load, one atomic per workgroup
+__global__ __launch_bounds__(256) void count_nonzero_u8_kernel(const uint8_t* __restrict__ m, long long count,
+                                                               unsigned* __restrict__ out) {
+  __shared__ unsigned red[4];
   unsigned c = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
-    c += m[i] != 0 ? 1u : 0u;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (long long i = first; i < count / 16; i += stride) {
+    const uint4 v = reinterpret_cast<const uint4*>(m)[i];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) c += ((w[q] >> (8 * b)) & 0xffu) != 0u ? 1u : 0u;
+  }
+  for (long long i = count / 16 * 16 + first; i < count; i += stride) c += m[i] != 0 ? 1u : 0u;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = (red[0] + red[1]) + (red[2] + red[3]);
+    if (t) atomicAdd(out, t);
+  }
 }
 
 // ---- launchers ----------------------------------------------------------------------------------
@@ -571,8 +863,24 @@ hipError_t launch_conv3x3(int cin, int cout, int mode, const uint16_t* in, const
                           hipStream_t s) {
   if (dil < 1 || dil > 32) return hipErrorInvalidValue;
   dim3 grid((W + 63) / 64, H, images);
-  // data gradient of a layer cin -> cout: reads cout channels, writes cin channels
+  // dilation 1: the register-tiled kernel; data gradient of a layer cin -> cout: reads cout
+  // channels, writes cin channels
+#define SLHJB_TILE(CI, CO, MODE)                                                                           \
+  {                                                                                                        \
+    using S = ConvTile<CI, CO>;                                                                           \
+    const size_t lds = conv3x3_tile_lds_bytes<CI, CO>();                                                   \
+    if (lds > 64 * 1024) {                                                                                 \
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&conv3x3_tile_kernel<CI, CO, MODE>), \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+      if (e != hipSuccess) return e;                                                                       \
+    }                                                                                                      \
+    dim3 tgrid((W + 63) / 64, (H + S::TR - 1) / S::TR, images);                                            \
+    conv3x3_tile_kernel<CI, CO, MODE><<<tgrid, 256, lds, s>>>(in, w, bias, gate, H, W, relu, out);         \
+    return hipGetLastError();                                                                              \
+  }
 #define SLHJB_CONV(CI, CO)                                                                                 \
+  if (dil == 1 && mode == 0 && cin == CI && cout == CO) SLHJB_TILE(CI, CO, 0)                              \
+  if (dil == 1 && mode == 1 && cin == CI && cout == CO && CI != 16) SLHJB_TILE(CO, CI, 1)                  \
   if (mode == 0 && cin == CI && cout == CO) {                                                              \
     conv3x3_kernel<CI, CO, 0><<<grid, 256, conv3x3_lds_bytes<CI, CO>(dil), s>>>(in, w, bias, gate, H, W, dil, \
                                                                                 relu, out);                \
@@ -585,31 +893,41 @@ hipError_t launch_conv3x3(int cin, int cout, int mode, const uint16_t* in, const
   }
   SLHJB_FOR_LAYERS(SLHJB_CONV)
 #undef SLHJB_CONV
+#undef SLHJB_TILE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_conv3x3_wgrad(int cin, int cout, const uint16_t* x, const uint16_t* dy, int images, int H, int W,
-                                int dil, float* dw, float* db, hipStream_t s) {
-  const long long total = (long long)images * H * W;
-  // about 64 chunks per tap (a multiple of 64 pixels each): enough workgroups to fill the chip,
-  // few atomics per weight
-  long long chunk = (total + 63) / 64;
-  chunk = std::max(2048LL, (chunk + 63) / 64 * 64);
-  dim3 grid((unsigned)((total + chunk - 1) / chunk), 9);
-  bool done = false;
+                                int dil, float* dw, float* db, float* work, hipStream_t s) {
+  if (images <= 0 || H <= 0 || W <= 0 || dil < 1 || dil > 32 || !work) return hipErrorInvalidValue;
+  const long long nsteps = (long long)images * H * ((W + 63) / 64);
+  // about 256 workgroups in all for the 64 x 64 tiles (one per compute unit: their accumulators
+  // fill the register file), 512 for the smaller ones; each over a run of consecutive strips
 #define SLHJB_WG(CI, CO)                                                                                    \
-  if (!done && cin == CI && cout == CO) {                                                                   \
-    conv3x3_wgrad_kernel<CI, CO><<<grid, 256, 0, s>>>(x, dy, images, H, W, dil, (int)chunk, dw);            \
-    done = true;                                                                                            \
+  if (cin == CI && cout == CO) {                                                                            \
+    using S = WgradShape<CI, CO>;                                                                           \
+    const int tiles = (CO / S::CO_T) * (CI / S::CI_T);                                                      \
+    const long long want = std::max(1LL, (S::CO_T * S::CI_T >= 4096 ? 256LL : 512LL) / tiles);              \
+    const long long steps = std::max(1LL, (nsteps + want - 1) / want);                                      \
+    const int runs = (int)((nsteps + steps - 1) / steps);                                                   \
+    const long long per = 9LL * S::CO_T * S::CI_T + S::CO_T;                                                \
+    if ((long long)tiles * runs * per > kWgradWorkFloats) return hipErrorInvalidValue;                      \
+    const size_t lds = conv3x3_wgrad_lds_bytes<CI, CO>(dil);                                                \
+    if (lds > 160 * 1024) return hipErrorInvalidValue;                                                      \
+    if (lds > 64 * 1024) {                                                                                  \
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&conv3x3_wgrad_kernel<CI, CO>), \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+      if (e != hipSuccess) return e;                                                                        \
+    }                                                                                                       \
+    conv3x3_wgrad_kernel<CI, CO><<<dim3(runs, tiles), 256, lds, s>>>(x, dy, images, H, W, dil, (int)steps,   \
+                                                                      work);                                \
+    wgrad_reduce_kernel<<<dim3((unsigned)((per + 31) / 32), tiles), 512, 0, s>>>(work, runs, S::CO_T,        \
+                                                                                  S::CI_T, CI, CO, dw, db);   \
+    return hipGetLastError();                                                                               \
   }
   SLHJB_FOR_LAYERS(SLHJB_WG)
 #undef SLHJB_WG
-  if (!done) return hipErrorInvalidValue;
-  if (cout == 32) bias_grad_kernel<32><<<blocks_for(total, 1024), 256, 0, s>>>(dy, total, 1024, db);
-  else if (cout == 64) bias_grad_kernel<64><<<blocks_for(total, 1024), 256, 0, s>>>(dy, total, 1024, db);
-  else if (cout == 128) bias_grad_kernel<128><<<blocks_for(total, 1024), 256, 0, s>>>(dy, total, 1024, db);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_head_fwd(int c, const uint16_t* h, const float* hw, const float* hb, long long total, float* delta,
@@ -623,7 +941,7 @@ hipError_t launch_loss_head_bwd(int c, const float* delta, const float* uhat, co
                                 long long total, float inv_n, const uint16_t* h, const float* hw, uint16_t* dh,
                                 float* dhw, float* dhb, float* loss_acc, hipStream_t s) {
   if (c != 32) return hipErrorInvalidValue;
-  loss_head_bwd_kernel<32><<<blocks_for(total, 256), 256, 0, s>>>(delta, uhat, vstar, mask, total, inv_n, h, hw, dh,
+  loss_head_bwd_kernel<32><<<blocks_for(total, 256 * kLossPix), 256, 0, s>>>(delta, uhat, vstar, mask, total, inv_n, h, hw, dh,
                                                                   dhw, dhb, loss_acc);
   return hipGetLastError();
 }
@@ -690,7 +1008,8 @@ hipError_t launch_scale_f32(float* p, long long count, float a, hipStream_t s) {
 }
 
 hipError_t launch_count_nonzero_u8(const uint8_t* m, long long count, unsigned* out, hipStream_t s) {
-  count_nonzero_u8_kernel<<<std::min(blocks_for(count, 256), 1024u), 256, 0, s>>>(m, count, out);
+  const unsigned blocks = std::max(1u, std::min(blocks_for(count, 256 * 16 * 8), 256u));
+  count_nonzero_u8_kernel<<<blocks, 256, 0, s>>>(m, count, out);
   return hipGetLastError();
 }
 

@@ -183,8 +183,11 @@ int ctx_hip_fail(slhjb_ctx* ctx, hipError_t e, const char* what);
 hipError_t launch_conv3x3(int cin, int cout, int mode, const uint16_t* in, const uint16_t* w, const float* bias,
                           const uint16_t* gate, int images, int H, int W, int dil, int relu, uint16_t* out,
                           hipStream_t s);
+// weight and bias gradients, accumulated into dw and db; `work` is device scratch of
+// kWgradWorkFloats floats (the per-workgroup partial sums)
+constexpr long long kWgradWorkFloats = 512LL * (9 * 64 * 32 + 64);
 hipError_t launch_conv3x3_wgrad(int cin, int cout, const uint16_t* x, const uint16_t* dy, int images, int H, int W,
-                                int dil, float* dw, float* db, hipStream_t s);
+                                int dil, float* dw, float* db, float* work, hipStream_t s);
 hipError_t launch_head_fwd(int c, const uint16_t* h, const float* hw, const float* hb, long long total, float* delta,
                            hipStream_t s);
 hipError_t launch_loss_head_bwd(int c, const float* delta, const float* uhat, const float* vstar, const uint8_t* mask,

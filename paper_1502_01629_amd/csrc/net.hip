@@ -43,6 +43,7 @@ struct slhjb_net {
   int64_t w_off[kMaxLayers] = {}, b_off[kMaxLayers] = {}, hw_off = 0, hb_off = 0;
   float* params = nullptr;
   float* grads = nullptr;
+  float* wwork = nullptr;  // partial sums of the weight gradients (kWgradWorkFloats)
   float* m1 = nullptr;
   float* m2 = nullptr;
   uint16_t* wt[kMaxLayers] = {};
@@ -236,7 +237,7 @@ int unet_backward(slhjb_net* net, int count, int crop) {
   auto back = [&](int l, const uint16_t* x, uint16_t* gx, bool gated) -> hipError_t {
     const int S = crop >> net->level[l];
     hipError_t e = launch_conv3x3_wgrad(net->cin[l], net->cout[l], x, G[l], count, S, S, 1, net->grads + net->w_off[l],
-                                        net->grads + net->b_off[l], s);
+                                        net->grads + net->b_off[l], net->wwork, s);
     if (e == hipSuccess && gx)
       e = launch_conv3x3(net->cin[l], net->cout[l], 1, G[l], net->wtt[l], nullptr, gated ? x : nullptr, count, S, S, 1,
                          0, gx, s);
@@ -305,6 +306,7 @@ int slhjb_net_create(slhjb_ctx* ctx, const slhjb_net_config* cfg, slhjb_net** ou
   net->nparam = off;
   e = hipMalloc(&net->params, sizeof(float) * off);
   if (e == hipSuccess) e = hipMalloc(&net->grads, sizeof(float) * off);
+  if (e == hipSuccess) e = hipMalloc(&net->wwork, sizeof(float) * kWgradWorkFloats);
   if (e == hipSuccess) e = hipMalloc(&net->m1, sizeof(float) * off);
   if (e == hipSuccess) e = hipMalloc(&net->m2, sizeof(float) * off);
   for (int l = 0; l < net->L && e == hipSuccess; ++l) {
@@ -336,8 +338,8 @@ int slhjb_net_destroy(slhjb_net* net) {
   hipSetDevice(ctx_device(net->ctx));
   hipStreamSynchronize(ctx_stream(net->ctx));
   free_acts(net);
-  for (void* p : {(void*)net->params, (void*)net->grads, (void*)net->m1, (void*)net->m2, (void*)net->d_src,
-                  (void*)net->d_acc})
+  for (void* p : {(void*)net->params, (void*)net->grads, (void*)net->wwork, (void*)net->m1, (void*)net->m2,
+                  (void*)net->d_src, (void*)net->d_acc})
     if (p) hipFree(p);
   for (int l = 0; l < kMaxLayers; ++l) {
     if (net->wt[l]) hipFree(net->wt[l]);
@@ -426,7 +428,7 @@ int slhjb_net_loss_grad(slhjb_net* net, const slhjb_net_sample* samples, int32_t
     for (int l = net->L - 1; l >= 0; --l) {
       const uint16_t* x = l == 0 ? net->feat : net->act[l - 1];
       NET_TRY(launch_conv3x3_wgrad(net->cin[l], net->C, x, dy, count, crop, crop, net->dil[l],
-                                   net->grads + net->w_off[l], net->grads + net->b_off[l], s));
+                                   net->grads + net->w_off[l], net->grads + net->b_off[l], net->wwork, s));
       if (l > 0) {
         NET_TRY(launch_conv3x3(net->cin[l], net->C, 1, dy, net->wtt[l], nullptr, net->act[l - 1], count, crop, crop,
                                net->dil[l], 0, dx, s));

@@ -174,3 +174,50 @@ def evaluate(ctx: "capi.Context", net: "capi.Net", frames, tol: float = 1e-6, to
             row[f"tiles_err_{name}"] = float((v - f.vstar).abs()[free].max())
         out.append(row)
     return out
+
+
+def main(argv=None):
+    """Timing of the U-Net's training step and whole-frame inference on the method's own solves:
+    python -m paper_1502_01629_amd.warmstart [--problems P --steps K ...]"""
+    import argparse
+
+    import torch
+
+    from . import instances
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--n", type=int, default=1025)
+    ap.add_argument("--coarse", type=int, default=129)
+    ap.add_argument("--problems", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--crop", type=int, default=256)
+    a = ap.parse_args(argv)
+    ctx = capi.Context(0)
+    frames = make_frames(ctx, instances.warmstart_problems(0, count=a.problems, n=a.n, n_coarse=a.coarse),
+                         bicubic=True)
+    net = capi.Net(ctx, arch=capi.NET_UNET)
+    net.set_params(init_params(net, 0))
+    train(net, frames, steps=10, batch=a.batch, crop=a.crop, lr=1e-3)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = train(net, frames, steps=a.steps, batch=a.batch, crop=a.crop, lr=1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    g = torch.empty_like(frames[0].vhat)
+    net.warm_start(frames[0].dp, frames[0].feat, g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        net.warm_start(frames[0].dp, frames[0].feat, g)
+    torch.cuda.synchronize()
+    ti = (time.perf_counter() - t) / 10
+    print(f"U-Net training: {a.steps} steps of {a.batch} x {a.crop}^2 in {dt:.3f} s = {1e3 * dt / a.steps:.3f} ms/step "
+          f"(loss {np.mean(losses[:10]):.3e} -> {np.mean(losses[-10:]):.3e}); inference {a.n}^2: {1e3 * ti:.3f} ms",
+          flush=True)
+    net.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

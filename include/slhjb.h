@@ -260,6 +260,27 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
                       int64_t max_sweeps, const slhjb_batch_opts* opts, slhjb_stats* stats,
                       slhjb_batch_stats* total);
 
+/* The active-tile solve (as slhjb_solve_tiles, transmission mode, pass by pass) of `count`
+ * independent problems at once (1 <= count <= 4096; all with the same scheme, diffusion kind and
+ * kernel path; lambda > 0, constant running cost and eps, no drift). v[i]: device float[n_i*n_i],
+ * the start, overwritten with the result. Every instance runs exactly the passes of
+ * slhjb_solve_tiles(problems[i], v[i], tol, max_passes, opts): its own band of u_hat keys, flags,
+ * band moves and check sweeps, so a converged instance's values, stats[i].sweeps (passes) and
+ * node_updates are bit-for-bit those of the single-instance call. The passes of all instances
+ * still iterating share four launches (selection into one work list of (instance, tile) items,
+ * per-instance decisions, visits, commits), captured 16 at a time in a HIP graph and replayed
+ * until every instance has converged or made max_passes passes (the single-instance call checks
+ * max_passes only between its graph replays, so an instance that does not converge may stop a few
+ * passes apart). opts: order, max_inner, key_slack, tile_shape and policy_sweeps as for
+ * slhjb_solve_tiles; mode must be SLHJB_MODE_TRANSMISSION and persistent 0 (SLHJB_E_UNSUPPORTED
+ * otherwise); collect_kernel_time is ignored. stats (nullable): slhjb_stats[count] (seconds = the
+ * whole call); total (nullable): sweeps = passes over all instances, node_updates, replays,
+ * seconds, converged. Returns SLHJB_OK if every instance converged, SLHJB_NOT_CONVERGED otherwise.
+ * Needs device memory for the tile staging of all instances. Synchronises. */
+int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
+                            double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
+                            slhjb_batch_stats* total);
+
 /* ---- the patchy method end to end (Section 4.3) ------------------------------------------- */
 enum { SLHJB_PATCHY_TRANSMISSION = 0,  /* patchy decomposition, one shared iterate             */
        SLHJB_PATCHY_INDEPENDENT = 1,   /* patchy decomposition, state constraints at interfaces */

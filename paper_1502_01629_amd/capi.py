@@ -235,6 +235,8 @@ SIGNATURES = {
                                           ctypes.POINTER(PatchyStats)]),
     "slhjb_solve_batch": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), _f64, _i64, ctypes.POINTER(BatchOpts),
                                          ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
+    "slhjb_solve_tiles_batch": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), _f64, _i64, ctypes.POINTER(TileOpts),
+                                               ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
     "slhjb_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(NetConfig), ctypes.POINTER(_vp)]),
     "slhjb_net_destroy": (ctypes.c_int, [_vp]),
     "slhjb_net_param_count": (_i64, [_vp]),
@@ -468,6 +470,24 @@ class Context:
         tot = BatchStats()
         st = lib().slhjb_solve_batch(self.handle, arr, count, ptrs, tol, max_sweeps, ctypes.byref(opts), stats,
                                      ctypes.byref(tot))
+        self._check(st, allow=(OK, NOT_CONVERGED))
+        return [s.as_dict() for s in stats], tot.as_dict()
+
+    def solve_tiles_batch(self, probs, vs, tol: float = 1e-6, max_passes: int = 1_000_000, order: int = ORDER_NONE,
+                          key_slack: float = -1.0, max_inner: int = 0, tile_shape: int = TILE_16x16_SPLIT2,
+                          policy_sweeps: int = 0):
+        """The active-tile solve of independent instances in shared launches (slhjb_solve_tiles_batch).
+        Returns (per-instance stats dicts, totals dict)."""
+        count = len(probs)
+        if len(vs) != count:
+            raise ValueError("one iterate per problem")
+        arr = (Problem * count)(*[p.struct for p in probs])
+        ptrs = (_vp * count)(*[_ptr(v) for v in vs])
+        opts = TileOpts(order, MODE_TRANSMISSION, None, key_slack, max_inner, tile_shape, 0, 0, 0, policy_sweeps)
+        stats = (Stats * count)()
+        tot = BatchStats()
+        st = lib().slhjb_solve_tiles_batch(self.handle, arr, count, ptrs, tol, max_passes, ctypes.byref(opts), stats,
+                                           ctypes.byref(tot))
         self._check(st, allow=(OK, NOT_CONVERGED))
         return [s.as_dict() for s in stats], tot.as_dict()
 

@@ -1567,6 +1567,221 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   return solve_tiles_impl(ctx, problem, P, v, tol, max_passes, opts, stats);
 }
 
+int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
+                            double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
+                            slhjb_batch_stats* total) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!problems || !v || !opts || count < 1 || count > 4096)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "need problems, v, opts and 1 <= count <= 4096");
+  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
+  if (opts->order < 0 || opts->order > 1 || opts->max_inner < 0 || opts->tile_shape < 0 ||
+      opts->tile_shape >= kTileShapes || opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
+  if (opts->mode != SLHJB_MODE_TRANSMISSION || opts->persistent != 0)
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "the batched active-tile solve runs the transmission mode, pass by pass");
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(ctx, SLHJB_E_INVALID_ARG, "v[" + std::to_string(i) + "] is NULL");
+    if (problems[i].drift) return fail(ctx, SLHJB_E_UNSUPPORTED, "batched solves take no drift");
+    if (has_general_terms(&problems[i]))
+      return fail(ctx, SLHJB_E_UNSUPPORTED,
+                  "batched solves take lambda > 0, a constant running cost and a constant eps");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int shape = opts->tile_shape;
+  const TileShape sh = tile_shape_of(shape);
+  const bool keyed = opts->order == SLHJB_ORDER_KEYS;
+  // device scratch of this call
+  char* d_inst = nullptr;
+  char* d_state = nullptr;
+  void* d_ctl = nullptr;
+  float4* d_ctrl = nullptr;
+  float *d_key = nullptr, *d_tchange = nullptr, *d_outbuf = nullptr;
+  uint8_t* d_flag = nullptr;
+  int *d_list = nullptr, *d_tile_inst = nullptr, *d_chk_inst = nullptr;
+  unsigned* d_chk_off = nullptr;
+  unsigned* h_ctl = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    hipStreamSynchronize(ctx->stream);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    for (void* q : {(void*)d_inst, (void*)d_state, d_ctl, (void*)d_ctrl, (void*)d_key, (void*)d_tchange,
+                    (void*)d_outbuf, (void*)d_flag, (void*)d_list, (void*)d_tile_inst, (void*)d_chk_inst,
+                    (void*)d_chk_off})
+      if (q) hipFree(q);
+    if (h_ctl) hipHostFree(h_ctl);
+  };
+  auto bail = [&](hipError_t e, const char* what) {
+    cleanup();
+    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, std::string(what) + ": out of device memory");
+    return hip_fail(ctx, e, what);
+  };
+#define TB_TRY(expr)                                \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return bail(_e, #expr);   \
+  } while (0)
+  TB_TRY(hipMalloc(&d_ctrl, sizeof(float4) * kCtrlCap * count));
+  // per-instance parameters, exactly as slhjb_solve_tiles derives them
+  std::vector<Prepared> prep(count);
+  std::vector<int> tile0(count), tiles_x(count), tiles_y(count), max_inner(count);
+  std::vector<float> window(count);
+  int total_tiles = 0, max_tiles = 0;
+  size_t lds = 0;
+  for (int i = 0; i < count; ++i) {
+    int st = prepare(ctx, &problems[i], &prep[i]);
+    if (st != SLHJB_OK) {
+      cleanup();
+      ctx->last_msg = "instance " + std::to_string(i) + ": " + ctx->last_msg;
+      return st;
+    }
+    const Prepared& P = prep[i];
+    if (P.path != prep[0].path || P.diffusion != prep[0].diffusion || P.scheme != prep[0].scheme) {
+      cleanup();
+      return fail(ctx, SLHJB_E_UNSUPPORTED,
+                  "all instances of a batched active-tile solve need the same scheme, diffusion kind and kernel path "
+                  "(instance " + std::to_string(i) + " differs from instance 0)");
+    }
+    // prepare() leaves the instance's padded control table in ctx->ctrl (stream-ordered copy)
+    TB_TRY(hipMemcpyAsync(d_ctrl + (size_t)kCtrlCap * i, ctx->ctrl, sizeof(float4) * P.args.n_controls,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    const int n = problems[i].n;
+    tiles_x[i] = (n + sh.tw - 1) / sh.tw;
+    tiles_y[i] = (n + sh.th - 1) / sh.th;
+    tile0[i] = total_tiles;
+    total_tiles += tiles_x[i] * tiles_y[i];
+    max_tiles = std::max(max_tiles, tiles_x[i] * tiles_y[i]);
+    max_inner[i] = opts->max_inner > 0 ? opts->max_inner
+                                       : (P.diffusion == SLHJB_DIFF_NONE
+                                              ? (opts->policy_sweeps > 0 ? sh.tw + sh.th : 2 * (sh.tw + sh.th))
+                                              : (opts->policy_sweeps > 0 ? opts->policy_sweeps + 1 : 2));
+    window[i] = opts->key_slack >= 0.0f
+                    ? opts->key_slack
+                    : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(&problems[i]) / P.speed_max);
+    lds = std::max(lds, tile_pass_lds_bytes(sh, P.args.halo, false));
+  }
+  if (lds > 64 * 1024) {
+    cleanup();
+    return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
+  }
+  const size_t tn = (size_t)sh.tw * sh.th;
+  TB_TRY(hipMalloc(&d_inst, tb_inst_bytes() * count));
+  TB_TRY(hipMalloc(&d_state, tb_state_bytes() * count));
+  TB_TRY(hipMalloc(&d_ctl, tb_ctl_bytes()));
+  TB_TRY(hipMalloc(&d_key, sizeof(float) * total_tiles));
+  TB_TRY(hipMalloc(&d_tchange, 2 * sizeof(float) * total_tiles));
+  TB_TRY(hipMalloc(&d_outbuf, sizeof(float) * tn * total_tiles));
+  TB_TRY(hipMalloc(&d_flag, total_tiles));
+  TB_TRY(hipMalloc(&d_list, sizeof(int) * total_tiles));
+  TB_TRY(hipMalloc(&d_tile_inst, sizeof(int) * total_tiles));
+  TB_TRY(hipMalloc(&d_chk_inst, sizeof(int) * count));
+  TB_TRY(hipMalloc(&d_chk_off, sizeof(unsigned) * count));
+  TB_TRY(hipHostMalloc(&h_ctl, 64, hipHostMallocDefault));
+  std::vector<char> h_inst(tb_inst_bytes() * count);
+  std::vector<int> h_tile_inst(total_tiles);
+  const float act = (float)(0.5 * tol), tol_inner = (float)(0.5 * tol);
+  for (int i = 0; i < count; ++i) {
+    SweepArgs a = prep[i].args;
+    a.w_in = v[i];  // the iterate w = V* - v, in place as in the single-instance solve
+    a.w_out = nullptr;
+    a.resid = nullptr;
+    a.flags = nullptr;
+    a.ctrl = d_ctrl + (size_t)kCtrlCap * i;
+    tb_fill_inst(h_inst.data() + tb_inst_bytes() * i, a, keyed ? d_key + tile0[i] : nullptr, tiles_x[i], tiles_y[i],
+                 tile0[i], max_inner[i], opts->policy_sweeps, tol_inner, act, window[i], (float)tol,
+                 (long long)max_passes);
+    for (int t = 0; t < tiles_x[i] * tiles_y[i]; ++t) h_tile_inst[tile0[i] + t] = i;
+  }
+  TB_TRY(hipMemcpyAsync(d_inst, h_inst.data(), h_inst.size(), hipMemcpyHostToDevice, ctx->stream));
+  TB_TRY(hipMemcpyAsync(d_tile_inst, h_tile_inst.data(), sizeof(int) * total_tiles, hipMemcpyHostToDevice,
+                        ctx->stream));
+  TB_TRY(hipStreamSynchronize(ctx->stream));  // the host vectors are pageable
+  TB_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+  for (int i = 0; i < count; ++i) {
+    const Prepared& P = prep[i];
+    const int64_t N = (int64_t)problems[i].n * problems[i].n;
+    TB_TRY(launch_v_to_w(v[i], v[i], problems[i].node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle,
+                         ctx->stream));
+    if (keyed)
+      TB_TRY(launch_tile_keys(v[i], problems[i].node_class, sh.tw, sh.th, problems[i].n, tiles_x[i], tiles_y[i],
+                              P.vstar, problems[i].lambda, d_key + tile0[i], ctx->stream));
+  }
+  TB_TRY(launch_fill_u8(d_flag, 1, total_tiles, ctx->stream));
+  TB_TRY(launch_tb_init(d_state, count, d_ctl, ctx->stream));
+  const int grid = std::min(total_tiles, 3 * std::max(1, ctx->cus));
+  const int max_chunks = (max_tiles + 1023) / 1024;
+  constexpr int kPasses = 16;  // passes per graph replay
+  if (!ctx->cap_stream) TB_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  TB_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t ce = hipSuccess;
+  for (int b = 0; b < kPasses && ce == hipSuccess; ++b)
+    ce = launch_tb_pass(shape, d_inst, d_state, count, max_chunks, d_flag, d_list, d_tile_inst, d_chk_inst, d_chk_off,
+                        d_ctl, total_tiles, d_outbuf, d_tchange, prep[0].diffusion, prep[0].scheme, prep[0].path,
+                        b & 1, grid, lds, ctx->cap_stream);
+  hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (ce != hipSuccess) return bail(ce, "capture of the batched tile passes");
+  if (ee != hipSuccess) return bail(ee, "hipStreamEndCapture");
+  TB_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  int64_t replays = 0;
+  // every replay advances each instance still iterating by up to kPasses passes; an instance stops
+  // after max_passes, so the loop ends
+  while (true) {
+    TB_TRY(hipGraphLaunch(exec, ctx->stream));
+    ++replays;
+    TB_TRY(hipMemcpyAsync(h_ctl, d_ctl, tb_ctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
+    TB_TRY(hipStreamSynchronize(ctx->stream));
+    if (h_ctl[kTBCtlActive] == 0u) break;
+  }
+  for (int i = 0; i < count; ++i) {
+    const int64_t N = (int64_t)problems[i].n * problems[i].n;
+    TB_TRY(launch_w_to_v(v[i], v[i], N, prep[i].vstar, ctx->stream));
+  }
+  TB_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+  TB_TRY(hipEventSynchronize(ctx->ev1));
+  float ms = 0.0f;
+  TB_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  std::vector<char> h_state(tb_state_bytes() * count);
+  TB_TRY(hipMemcpy(h_state.data(), d_state, h_state.size(), hipMemcpyDeviceToHost));
+  int status = SLHJB_OK, converged = 0;
+  int64_t all_passes = 0, all_updates = 0;
+  for (int i = 0; i < count; ++i) {
+    TBResult r;
+    tb_read_state(h_state.data(), i, &r);
+    const int si = r.done ? SLHJB_OK : SLHJB_NOT_CONVERGED;
+    if (si != SLHJB_OK) status = SLHJB_NOT_CONVERGED;
+    converged += r.done ? 1 : 0;
+    all_passes += r.passes;
+    all_updates += (int64_t)r.updates;
+    if (stats) {
+      slhjb_stats& t = stats[i];
+      memset(&t, 0, sizeof(t));
+      t.sweeps = r.passes;
+      t.converged_sweep = r.done ? (int64_t)r.passes : -1;
+      t.node_updates = (int64_t)r.updates;
+      t.residual = r.done ? (double)r.resid : INFINITY;
+      t.seconds = ms * 1e-3;
+      t.status = si;
+      t.kernel_path = prep[i].path;
+      t.halo = prep[i].args.halo;
+      t.policy_updates = (int64_t)r.pe_updates;
+      t.check_sweeps = r.checks;
+    }
+  }
+  if (total) {
+    memset(total, 0, sizeof(*total));
+    total->sweeps = all_passes;
+    total->node_updates = all_updates;
+    total->replays = replays;
+    total->seconds = ms * 1e-3;
+    total->converged = converged;
+    total->status = status;
+  }
+  cleanup();
+#undef TB_TRY
+  return status;
+}
+
 int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v, double tol,
                       int64_t max_sweeps, const slhjb_batch_opts* opts, slhjb_stats* stats,
                       slhjb_batch_stats* total) {

@@ -15,6 +15,8 @@
 // whose upwind values are still moving from being iterated to convergence against stale halos.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
+#include <cstring>
+#include <cstddef>
 
 #include "select_device.h"
 #include "sweep_device.h"
@@ -981,6 +983,373 @@ hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int
   SLHJB_FOR_SHAPE(shape, SLHJB_CTL_CALL)
 #undef SLHJB_CTL_CALL
   return hipGetLastError();
+}
+
+// ---- the active-tile solver over a batch of independent instances ---------------------------
+// Every instance runs exactly its own sequence of passes (selection in its band, visits, commits,
+// band moves and check sweeps, decided from its own pass words), so its result is that of the
+// single-instance solve; the passes of all instances still iterating share four launches:
+//   select  one workgroup per (instance, 1024 tiles): flagged tiles in the instance's band join
+//           one combined work list (per-instance counts, smallest key and flagged count kept);
+//   plan    one workgroup: per instance the decision the single-instance visit launch takes
+//           (visits, band move, check sweep, stop), the pass bookkeeping its commit launch does,
+//           and the offsets of the check sweeps' tiles after the selected ones;
+//   visit   the items of the pass: the selected tiles, then every tile of each instance that
+//           makes a check sweep (one iteration); item j stages into slot j;
+//   commit  the same items written back, neighbours flagged, check residuals raised.
+// Global tile g belongs to instance tile_inst[g] as its tile g - tile0; flags, keys and the list
+// are indexed by g, the staging slots by item.
+struct TBInst {
+  SweepArgs a;       // w_in: the instance's iterate w; ctrl: its padded control table
+  const float* key;  // [tiles] (u_hat order) or NULL
+  int tiles_x, tiles_y, tiles, tile0;
+  int max_inner, pe;
+  float tol_inner, act, window, tol;
+  long long max_passes;
+};
+struct TBState {
+  unsigned count[2], nflag[2], kmin[2];  // of the selection with parity q
+  unsigned bound, resid, checked, done, passes, checks;
+  unsigned mode;  // this pass: 0 nothing, 1 visits of the selected tiles, 2 check sweep
+  unsigned stop;  // 1 once done or out of passes
+  unsigned long long updates, pe_updates;
+};
+struct TBCtl {
+  unsigned count[2];  // combined list length of the pass with parity q
+  unsigned checks;    // tiles of this pass's check sweeps (after the selected ones)
+  unsigned nchk;      // instances making a check sweep this pass
+  unsigned active;    // instances still iterating after this pass's decisions
+  unsigned pad[3];
+};
+
+__global__ void tb_init_kernel(TBState* st, int count, TBCtl* ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl->count[0] = ctl->count[1] = 0u;
+    ctl->checks = ctl->nchk = 0u;
+    ctl->active = (unsigned)count;
+  }
+  if (i >= count) return;
+  TBState& s = st[i];
+  s.count[0] = s.count[1] = 0u;
+  s.nflag[0] = s.nflag[1] = 0u;
+  s.kmin[0] = s.kmin[1] = 0x7f800000u;
+  s.bound = 0xff800000u;
+  s.resid = 0u;
+  s.checked = 0u;
+  s.done = 0u;
+  s.passes = 0u;
+  s.checks = 0u;
+  s.mode = 0u;
+  s.stop = 0u;
+  s.updates = 0ull;
+  s.pe_updates = 0ull;
+}
+
+__global__ __launch_bounds__(kSelectThreads) void tb_select_kernel(const TBInst* __restrict__ inst,
+                                                                   TBState* __restrict__ st,
+                                                                   const uint8_t* __restrict__ flag, int q,
+                                                                   int* __restrict__ list, TBCtl* __restrict__ ctl) {
+  constexpr int W = kSelectThreads / 64;
+  __shared__ unsigned s_on[W], s_fl[W];
+  __shared__ float s_k[W];
+  __shared__ unsigned s_base;
+  const int i = blockIdx.y;
+  const int tiles = inst[i].tiles, tile0 = inst[i].tile0;
+  const float* key = inst[i].key;
+  TBState& s = st[i];
+  if ((int)(blockIdx.x * kSelectThreads) >= tiles) return;
+  const unsigned stop = s.stop, checked = s.checked, resid = s.resid, bound = s.bound;
+  if (stop || (long long)s.passes >= inst[i].max_passes) return;
+  if (checked && __uint_as_float(resid) <= inst[i].tol) return;  // the plan launch ends it
+  const int t = blockIdx.x * kSelectThreads + threadIdx.x;
+  const bool fl = t < tiles && flag[tile0 + t] != 0u;
+  const float B = key ? __uint_as_float(bound) : INFINITY;
+  float k = fl && key ? key[t] : INFINITY;
+  const bool on = fl && (!key || k <= B);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long fmask = __ballot(fl), mask = __ballot(on);
+  if (key) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) k = fminf(k, __shfl_xor(k, off, 64));
+  }
+  if (lane == 0) {
+    s_on[wave] = (unsigned)__popcll(mask);
+    s_fl[wave] = (unsigned)__popcll(fmask);
+    s_k[wave] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned total = 0u, nf = 0u;
+    float km = INFINITY;
+    for (int w = 0; w < W; ++w) {
+      const unsigned c = s_on[w];
+      s_on[w] = total;
+      total += c;
+      nf += s_fl[w];
+      km = fminf(km, s_k[w]);
+    }
+    if (nf) atomicAdd(&s.nflag[q], nf);
+    if (key && km < INFINITY) atomicMin(&s.kmin[q], __float_as_uint(km));
+    if (total) atomicAdd(&s.count[q], total);
+    s_base = total ? atomicAdd(&ctl->count[q], total) : 0u;
+  }
+  __syncthreads();
+  if (on) list[s_base + s_on[wave] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))] = tile0 + t;
+}
+
+// One workgroup of 1024 threads; instance i is handled by thread i % 1024 (in order of i).
+__global__ __launch_bounds__(1024) void tb_plan_kernel(const TBInst* __restrict__ inst, TBState* __restrict__ st,
+                                                       int count, int q, int* __restrict__ chk_inst,
+                                                       unsigned* __restrict__ chk_off, TBCtl* __restrict__ ctl) {
+  __shared__ unsigned s_sum[1024];
+  __shared__ unsigned s_n[1024];
+  constexpr int PER = 4;  // instances per thread (count <= 4096)
+  unsigned my_tiles = 0u, my_n = 0u, my_active = 0u;
+  for (int r = 0; r < PER; ++r) {
+    const int i = threadIdx.x * PER + r;
+    if (i >= count) break;
+    TBState& s = st[i];
+    const TBInst& I = inst[i];
+    unsigned mode = 0u;
+    if (!s.stop) {
+      if (s.checked && __uint_as_float(s.resid) <= I.tol) {
+        s.done = 1u;
+        s.stop = 1u;
+      } else if ((long long)s.passes >= I.max_passes) {
+        s.stop = 1u;
+      } else {
+        const unsigned cnt = s.count[q], nf = s.nflag[q];
+        if (cnt > 0u) {
+          mode = 1u;
+        } else if (nf > 0u) {
+          s.bound = __float_as_uint(__uint_as_float(s.kmin[q]) + I.window);  // move the band
+        } else {
+          mode = 2u;  // check sweep: its commits raise resid
+          s.resid = 0u;
+          my_tiles += (unsigned)I.tiles;
+          my_n += 1u;
+        }
+        if (cnt > 0u || nf == 0u) s.passes += 1u;
+        if (cnt == 0u && nf == 0u) s.checks += 1u;
+        s.checked = (cnt == 0u && nf == 0u) ? 1u : 0u;
+      }
+    }
+    s.mode = mode;
+    s.count[q ^ 1] = 0u;
+    s.nflag[q ^ 1] = 0u;
+    s.kmin[q ^ 1] = 0x7f800000u;
+    my_active += s.stop ? 0u : 1u;
+  }
+  // exclusive prefix of the check sweeps' tiles and instances over the threads, in order of i
+  s_sum[threadIdx.x] = my_tiles;
+  s_n[threadIdx.x] = my_n;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const unsigned a = threadIdx.x >= (unsigned)off ? s_sum[threadIdx.x - off] : 0u;
+    const unsigned b = threadIdx.x >= (unsigned)off ? s_n[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_sum[threadIdx.x] += a;
+    s_n[threadIdx.x] += b;
+    __syncthreads();
+  }
+  if (threadIdx.x == 1023) {
+    ctl->checks = s_sum[1023];
+    ctl->nchk = s_n[1023];
+  }
+  unsigned off_t = s_sum[threadIdx.x] - my_tiles, off_n = s_n[threadIdx.x] - my_n;
+  for (int r = 0; r < PER; ++r) {
+    const int i = threadIdx.x * PER + r;
+    if (i >= count) break;
+    if (st[i].mode == 2u) {
+      chk_inst[off_n] = i;
+      chk_off[off_n] = off_t;
+      off_t += (unsigned)inst[i].tiles;
+      off_n += 1u;
+    }
+  }
+  // the active count: a block sum
+  __syncthreads();
+  s_n[threadIdx.x] = my_active;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (threadIdx.x < (unsigned)h) s_n[threadIdx.x] += s_n[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctl->active = s_n[0];
+    ctl->count[q ^ 1] = 0u;
+  }
+}
+
+// item j of the pass -> instance, its tile, and whether the item is a check-sweep tile
+__device__ __forceinline__ void tb_item(int j, int cnt, const int* __restrict__ list, const int* __restrict__ tile_inst,
+                                        const TBInst* __restrict__ inst, const int* __restrict__ chk_inst,
+                                        const unsigned* __restrict__ chk_off, int nchk, int& i, int& tid, bool& check) {
+  if (j < cnt) {
+    const int g = list[j];
+    i = tile_inst[g];
+    tid = g - inst[i].tile0;
+    check = false;
+  } else {
+    const unsigned jj = (unsigned)(j - cnt);
+    int lo = 0, hi = nchk - 1;  // last r with chk_off[r] <= jj
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (chk_off[mid] <= jj) lo = mid;
+      else hi = mid - 1;
+    }
+    i = chk_inst[lo];
+    tid = (int)(jj - chk_off[lo]);
+    check = true;
+  }
+}
+
+template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
+__global__ __launch_bounds__(NT) void tb_visit_kernel(const TBInst* __restrict__ inst, TBState* __restrict__ st,
+                                                      const int* __restrict__ list,
+                                                      const int* __restrict__ tile_inst,
+                                                      const int* __restrict__ chk_inst,
+                                                      const unsigned* __restrict__ chk_off, int q,
+                                                      const TBCtl* __restrict__ ctl, int total_tiles,
+                                                      float* __restrict__ outbuf, float* __restrict__ tchange,
+                                                      uint8_t* __restrict__ flag) {
+  unsigned* tsides = reinterpret_cast<unsigned*>(tchange + total_tiles);
+  const int cnt = (int)ctl->count[q];
+  const int items = cnt + (int)ctl->checks;
+  const int nchk = (int)ctl->nchk;
+  extern __shared__ float lds[];
+  __shared__ float red[NT / 64];
+  for (int j = blockIdx.x; j < items; j += gridDim.x) {
+    int i, tid;
+    bool check;
+    tb_item(j, cnt, list, tile_inst, inst, chk_inst, chk_off, nchk, i, tid, check);
+    i = __builtin_amdgcn_readfirstlane(i);
+    tid = __builtin_amdgcn_readfirstlane(tid);
+    const TBInst& I = inst[i];
+    const SweepArgs a = I.a;
+    unsigned long long acc = 0ull, pe_acc = 0ull;
+    visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, false>(a, a.w_in, a.speed, a.cls, a.ctrl, nullptr, j, tid, I.tiles_x,
+                                                      outbuf, tchange, flag + I.tile0,
+                                                      check ? 1 : I.max_inner, check ? 0.0f : I.tol_inner, I.act,
+                                                      tsides, acc, lds, red, check ? 0 : I.pe, pe_acc);
+    if (threadIdx.x == 0) {
+      if (acc) atomicAdd(&st[i].updates, acc);
+      if (pe_acc) atomicAdd(&st[i].pe_updates, pe_acc);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void tb_commit_kernel(const TBInst* __restrict__ inst,
+                                                             TBState* __restrict__ st, const int* __restrict__ list,
+                                                             const int* __restrict__ tile_inst,
+                                                             const int* __restrict__ chk_inst,
+                                                             const unsigned* __restrict__ chk_off, int q,
+                                                             const TBCtl* __restrict__ ctl, int total_tiles, int tw,
+                                                             int th, const float* __restrict__ outbuf,
+                                                             const float* __restrict__ tchange,
+                                                             uint8_t* __restrict__ flag) {
+  const unsigned* tsides = reinterpret_cast<const unsigned*>(tchange + total_tiles);
+  const int cnt = (int)ctl->count[q];
+  const int items = cnt + (int)ctl->checks;
+  const int nchk = (int)ctl->nchk;
+  for (int j = blockIdx.x; j < items; j += gridDim.x) {
+    int i, tid;
+    bool check;
+    tb_item(j, cnt, list, tile_inst, inst, chk_inst, chk_off, nchk, i, tid, check);
+    i = __builtin_amdgcn_readfirstlane(i);
+    tid = __builtin_amdgcn_readfirstlane(tid);
+    const TBInst& I = inst[i];
+    float tmax = 0.0f;
+    commit_tile(j, tid, tw, th, I.tiles_x, I.tiles_y, I.a.n, outbuf, tchange[j], tsides[j], I.act, I.a.cls,
+                const_cast<float*>(I.a.w_in), flag + I.tile0, tmax);
+    if (check && threadIdx.x == 0 && tmax > 0.0f) atomicMax(&st[i].resid, __float_as_uint(tmax));
+  }
+}
+
+size_t tb_inst_bytes() { return sizeof(TBInst); }
+size_t tb_state_bytes() { return sizeof(TBState); }
+size_t tb_ctl_bytes() { return sizeof(TBCtl); }
+
+void tb_fill_inst(void* dst, const SweepArgs& a, const float* key, int tiles_x, int tiles_y, int tile0, int max_inner,
+                  int pe, float tol_inner, float act, float window, float tol, long long max_passes) {
+  TBInst I;
+  memset(&I, 0, sizeof(I));
+  I.a = a;
+  I.key = key;
+  I.tiles_x = tiles_x;
+  I.tiles_y = tiles_y;
+  I.tiles = tiles_x * tiles_y;
+  I.tile0 = tile0;
+  I.max_inner = max_inner;
+  I.pe = pe;
+  I.tol_inner = tol_inner;
+  I.act = act;
+  I.window = window;
+  I.tol = tol;
+  I.max_passes = max_passes;
+  memcpy(dst, &I, sizeof(I));
+}
+
+void tb_read_state(const void* src, int i, TBResult* out) {
+  TBState s;
+  memcpy(&s, static_cast<const char*>(src) + (size_t)i * sizeof(TBState), sizeof(s));
+  out->done = s.done;
+  out->passes = s.passes;
+  out->checks = s.checks;
+  memcpy(&out->resid, &s.resid, sizeof(float));
+  out->updates = s.updates;
+  out->pe_updates = s.pe_updates;
+}
+
+hipError_t launch_tb_init(void* st, int count, void* ctl, hipStream_t s) {
+  tb_init_kernel<<<(count + 255) / 256, 256, 0, s>>>((TBState*)st, count, (TBCtl*)ctl);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int SPL>
+static hipError_t launch_tb_pass_shape(const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list, const int* tile_inst, int* chk_inst,
+                                       unsigned* chk_off, void* ctl, int total_tiles, float* outbuf, float* tchange,
+                                       int diffusion, int scheme, int path, int q, int grid, size_t lds,
+                                       hipStream_t s) {
+  const TBInst* I = (const TBInst*)inst;
+  TBState* S = (TBState*)st;
+  TBCtl* C = (TBCtl*)ctl;
+  static_assert(offsetof(TBCtl, active) == kTBCtlActive * 4, "host reads this word");
+  tb_select_kernel<<<dim3(max_chunks, count), kSelectThreads, 0, s>>>(I, S, flag, q, list, C);
+  tb_plan_kernel<<<1, 1024, 0, s>>>(I, S, count, q, chk_inst, chk_off, C);
+  constexpr int NT = SPL == 1 ? kThreads : TW * TH * SPL;
+#define SLHJB_TBV(D, SC, PA)                                                                                   \
+  tb_visit_kernel<TW, TH, SPL, D, SC, PA><<<grid, NT, lds, s>>>(I, S, list, tile_inst, chk_inst, chk_off, q, C,  \
+                                                                total_tiles, outbuf, tchange, flag)
+#define SLHJB_TBV_S(D, PA)             \
+  do {                                 \
+    if (scheme == kSL2) SLHJB_TBV(D, kSL2, PA); \
+    else SLHJB_TBV(D, kSL3, PA);       \
+  } while (0)
+  if (path == 1) SLHJB_TBV_S(kDiffNone, 1);
+  else if (path != 0) return hipErrorInvalidValue;
+  else if (diffusion == kDiffNone) SLHJB_TBV_S(kDiffNone, 0);
+  else if (diffusion == kDiffIso) SLHJB_TBV_S(kDiffIso, 0);
+  else SLHJB_TBV_S(kDiffRank1, 0);
+#undef SLHJB_TBV_S
+#undef SLHJB_TBV
+  tb_commit_kernel<<<grid, kThreads, 0, s>>>(I, S, list, tile_inst, chk_inst, chk_off, q, C, total_tiles, TW, TH,
+                                             outbuf, tchange, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_tb_pass(int shape, const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list,
+                          const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl, int total_tiles,
+                          float* outbuf, float* tchange, int diffusion, int scheme, int path, int q, int grid,
+                          size_t lds, hipStream_t s) {
+  if (count < 1 || count > 4096 || grid < 1 || max_chunks < 1) return hipErrorInvalidValue;
+#define SLHJB_TB_CALL(TW, TH, SPL)                                                                              \
+  return launch_tb_pass_shape<TW, TH, SPL>(inst, st, count, max_chunks, flag, list, tile_inst, chk_inst, \
+                                           chk_off, ctl, total_tiles, outbuf, tchange, diffusion, scheme, path, q, \
+                                           grid, lds, s)
+  SLHJB_FOR_SHAPE(shape, SLHJB_TB_CALL)
+#undef SLHJB_TB_CALL
 }
 
 }  // namespace slhjb

@@ -1,0 +1,113 @@
+"""Batched active-tile solve (slhjb_solve_tiles_batch): every instance bit-for-bit equal to its own
+single-instance slhjb_solve_tiles call (values, passes, node and policy updates, check sweeps),
+for both tile orders, several tile shapes and policy iterations, with instances of different
+sizes in the same launches; converged instances at the oracle's fixed point."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_01629_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1502_01629_amd import capi
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32).reshape(-1)).cuda()
+
+
+def _starts(ctx, probs, insts, order):
+    """Cold starts, or (u_hat order) starts after 40 Jacobi sweeps, so that the keys are finite near
+    the targets and the bands move."""
+    out = []
+    for p, x in zip(probs, insts):
+        v = _dev(x.initial())
+        if order:
+            ctx.solve(p, v, tol=1e-12, max_sweeps=40)
+        out.append(v.clone())
+    return out
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("shape,pe", [(4, 0), (4, 8), (2, 4), (1, 0)])
+def test_tiles_batch_bit_exact_vs_single_instance(ctx, order, shape, pe):
+    from paper_1502_01629_amd import capi
+
+    insts = I.batch_problems(11 + shape, count=6, sizes=(65, 100, 129))
+    probs = [capi.DeviceProblem(x, capi.SL3) for x in insts]
+    starts = _starts(ctx, probs, insts, order)
+    vs = [s.clone() for s in starts]
+    print(f"tiles batch of {len(insts)} order={order} shape={shape} pe={pe}", flush=True)
+    stats, tot = ctx.solve_tiles_batch(probs, vs, tol=1e-6, max_passes=100000, order=order, tile_shape=shape,
+                                       policy_sweeps=pe)
+    print(tot, flush=True)
+    assert tot["status"] == 0 and tot["converged"] == len(insts)
+    for k, p in enumerate(probs):
+        v1 = starts[k].clone()
+        st1 = ctx.solve_tiles(p, v1, tol=1e-6, max_passes=100000, order=order, tile_shape=shape, policy_sweeps=pe)
+        assert st1["status"] == 0
+        assert torch.equal(vs[k], v1), f"instance {k} differs from its single-instance solve"
+        for key in ("sweeps", "node_updates", "policy_updates", "check_sweeps", "residual"):
+            assert stats[k][key] == st1[key], (k, key, stats[k][key], st1[key])
+
+
+def test_tiles_batch_mixed_sizes_sl2(ctx):
+    """Sizes 65..257 (ragged tiles), SL2, u_hat order."""
+    from paper_1502_01629_amd import capi
+
+    insts = I.batch_problems(3, count=5, sizes=(65, 129, 257))
+    probs = [capi.DeviceProblem(x, capi.SL2) for x in insts]
+    starts = _starts(ctx, probs, insts, 1)
+    vs = [s.clone() for s in starts]
+    stats, tot = ctx.solve_tiles_batch(probs, vs, tol=1e-6, order=capi.ORDER_KEYS, policy_sweeps=8)
+    assert tot["converged"] == len(insts)
+    for k, p in enumerate(probs):
+        v1 = starts[k].clone()
+        st1 = ctx.solve_tiles(p, v1, tol=1e-6, order=capi.ORDER_KEYS, policy_sweeps=8)
+        assert torch.equal(vs[k], v1) and stats[k]["sweeps"] == st1["sweeps"]
+
+
+def test_tiles_batch_stops_at_max_passes(ctx):
+    from paper_1502_01629_amd import capi
+
+    insts = I.batch_problems(4, count=3, sizes=(65, 129))
+    probs = [capi.DeviceProblem(x, capi.SL3) for x in insts]
+    vs = [_dev(x.initial()) for x in insts]
+    stats, tot = ctx.solve_tiles_batch(probs, vs, tol=1e-9, max_passes=7)
+    assert tot["status"] == 1 and tot["converged"] == 0
+    assert all(s["sweeps"] == 7 and s["status"] == 1 for s in stats)
+
+
+def test_tiles_batch_matches_oracle(ctx):
+    from paper_1502_01629_amd import capi
+
+    insts = [I.disc_problem(129, 0.01)] + I.batch_problems(5, count=2, sizes=(65,))
+    probs = [capi.DeviceProblem(x, 1) for x in insts]
+    vs = [_dev(x.initial()) for x in insts]
+    stats, tot = ctx.solve_tiles_batch(probs, vs, tol=1e-6, policy_sweeps=8)
+    assert tot["converged"] == len(insts)
+    for k, x in enumerate(insts):
+        ref, _, _, _ = oracle.Problem.from_instance(x, 1).solve(tol=1e-10, threads=8)
+        err = np.abs(vs[k].cpu().numpy().astype(np.float64) - ref).max()
+        print(k, "max abs err vs oracle", err, flush=True)
+        assert err < 1e-5
+
+
+def test_tiles_batch_rejects_mixed_kernel_paths(ctx):
+    from paper_1502_01629_amd import capi
+
+    a, b = I.disc_problem(33, 0.0), I.disc_problem(33, 0.01)  # first-ring and general paths
+    pa, pb = capi.DeviceProblem(a, 1), capi.DeviceProblem(b, 1)
+    with pytest.raises(capi.SlhjbError):
+        ctx.solve_tiles_batch([pa, pb], [_dev(a.initial()), _dev(b.initial())])

@@ -16,8 +16,9 @@ Beside the timed steps, each comparison arm runs once (progress on stderr):
          same from u_hat, and the static decomposition (active tiles, fixed order, cold start);
   c2eps  the same 2049^2 workload with isotropic diffusion eps = 1e-3 and 1e-2: patchy pipeline
          against the cold global Jacobi iteration;
-  batch  256 independent instances (65^2..1025^2, eps > 0) in one batched solve against the same
-         instances solved one by one (bit-exact agreement counted);
+  batch  256 independent instances (65^2..1025^2, eps > 0): the batched Jacobi solve and the batched
+         active-tile solve, each against the same instances solved one by one (bit-exact
+         agreement counted);
   bumps  4097^2 with rank-1 diffusion: full sweeps against active tiles (cold, and u_hat-ordered);
   learned  the U-Net warm start trained on the method's own 1025^2 solves against the cold start,
          the bilinear and the bicubic u_hat on held-out problems (time to the tolerance and error
@@ -172,6 +173,26 @@ def arm_batch(ctx, seed: int, tol: float) -> dict:
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t
     log(f"batch: sequential single-instance solves {t_seq:.2f} s")
+    # the active-tile solver on the same instances: batched against one after the other
+    vt = [s0.clone() for s0 in starts]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tstats, ttot = ctx.solve_tiles_batch(probs, vt, tol=tol, policy_sweeps=POLICY_SWEEPS_DIFFUSION)
+    torch.cuda.synchronize()
+    t_tb = time.perf_counter() - t
+    log(f"batch: batched active-tile solve {t_tb:.2f} s, {ttot['converged']} converged")
+    t = time.perf_counter()
+    equal_t = 0
+    upd_t = 0
+    for k, p in enumerate(probs):
+        v1 = starts[k].clone()
+        st1 = ctx.solve_tiles(p, v1, tol=tol, policy_sweeps=POLICY_SWEEPS_DIFFUSION)
+        upd_t += st1["node_updates"]
+        equal_t += int(bool(torch.equal(v1, vt[k])) and st1["sweeps"] == tstats[k]["sweeps"])
+    torch.cuda.synchronize()
+    t_tseq = time.perf_counter() - t
+    log(f"batch: sequential single-instance active-tile solves {t_tseq:.2f} s")
+    diff = max(float((vt[k] - vb[k]).abs().max()) for k in range(len(xs)))
     sizes = sorted({x.n for x in xs})
     return {
         "instances": len(xs), "nodes": int(sum(x.n * x.n for x in xs)),
@@ -181,6 +202,12 @@ def arm_batch(ctx, seed: int, tol: float) -> dict:
         "node_updates_per_s_batched": tot["node_updates"] / t_batch, "node_updates_per_s_sequential": upd / t_seq,
         "sweeps_max": tot["sweeps"], "graph_replays": tot["replays"], "converged": tot["converged"],
         "bit_exact_vs_single": f"{equal}/{len(xs)}", "autotune_s": t_tune,
+        "active_tiles": {"time_s_batched": t_tb, "device_s_batched": ttot["seconds"],
+                         "time_s_sequential": t_tseq, "speedup": t_tseq / t_tb,
+                         "speedup_vs_sequential_jacobi": t_seq / t_tb, "node_updates": ttot["node_updates"],
+                         "passes_total": ttot["sweeps"], "graph_replays": ttot["replays"],
+                         "converged": ttot["converged"], "bit_exact_vs_single": f"{equal_t}/{len(xs)}",
+                         "max_abs_diff_vs_batched_jacobi": diff},
         "tile_shapes": {capi.BATCH_TILE_SHAPES[k][0] * 1000 + capi.BATCH_TILE_SHAPES[k][1]: shapes.count(k)
                         for k in set(shapes)},
     }
@@ -802,6 +829,11 @@ def summary_line(full: dict) -> dict:
         e = A["batch_256_instances"]
         arms["batch_256"] = {"batched_s": _r(e["time_s_batched"]), "sequential_s": _r(e["time_s_sequential"]),
                              "bit_exact": e["bit_exact_vs_single"]}
+        if "active_tiles" in e:
+            t = e["active_tiles"]
+            arms["batch_256"]["active_tiles"] = {"batched_s": _r(t["time_s_batched"]),
+                                                 "sequential_s": _r(t["time_s_sequential"]),
+                                                 "bit_exact": t["bit_exact_vs_single"]}
     if "rank1_bumps" in A:
         e = A["rank1_bumps"]
         arms["rank1_4097"] = {"full_sweeps_s": _r(e["full_sweeps"]["time_s"]),

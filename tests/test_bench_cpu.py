@@ -40,7 +40,9 @@ def full_record() -> dict:
             "independent_patches": {k: {"decomposition_error_max": X, "band_max": X, "interior_max": X,
                                         "interior_mean": X} for k in eps3},
             "h_equals_dx": {"patchy_time_s": X, "global_jacobi_cold_s": X, "halo": 3},
-            "batch_256_instances": {"time_s_batched": X, "time_s_sequential": X, "bit_exact_vs_single": "256/256"},
+            "batch_256_instances": {"time_s_batched": X, "time_s_sequential": X, "bit_exact_vs_single": "256/256",
+                                    "active_tiles": {"time_s_batched": X, "time_s_sequential": X,
+                                                     "bit_exact_vs_single": "256/256"}},
             "rank1_bumps": {k: {"time_s": X} for k in ("full_sweeps", "active_tiles_cold", "active_tiles_uhat")},
             "learned_warm_start": {"train_problems": 192,
                                    "start_error_mean": {"uhat": X, "uhat_bicubic": X, "network": X},

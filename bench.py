@@ -632,6 +632,15 @@ def main():
     # by one and HIP events around every visit launch, on its stream, right after.
     kstats = [step(1) for _ in range(args.steps)]
     assert all(s["status"] == 0 for s in kstats), kstats
+    # The same step without the patch labels: the transmission-mode solve does not read them, so
+    # this is the cost of the labeler running beside it (reported, not the value)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nl = [ctx.solve_patchy(dp, dpc, v, mode=capi.PATCHY_TRANSMISSION, tol=args.tol, tol_coarse=1e-7,
+                           policy_sweeps=args.policy_sweeps) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt_nolabels = time.perf_counter() - t0
+    assert all(s["status"] == 0 for s in nl), nl
 
     med = lambda k: float(np.median([s[k] for s in stats]))
     visit_s = sum(s["t_visit"] for s in kstats)
@@ -669,6 +678,7 @@ def main():
             "seed": args.seed, "tol": args.tol, "free_nodes": free, "patches": args.patches,
         },
         "stages_s": {k: med(k) for k in ("t_coarse", "t_upsample", "t_synthesize", "t_label", "t_solve")},
+        "ms_per_step_without_labels": 1e3 * dt_nolabels / args.steps,
         "source_partition_host_s": t_part,
         "passes": int(med("passes")),
         "node_updates_per_free_node": fine_updates / len(kstats) / free,
@@ -792,7 +802,7 @@ def summary_line(full: dict) -> dict:
     keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
             "vs_baseline", "dtype", "data", "config", "passes", "node_updates_per_s", "node_updates_per_free_node",
             "policy_updates_per_free_node", "check_sweeps", "stages_s", "accuracy_vs_oracle",
-            "speedup_vs_global_jacobi_cold")
+            "speedup_vs_global_jacobi_cold", "ms_per_step_without_labels")
     out = {k: full[k] for k in keep if k in full}
     out["config"] = {k: full["config"][k] for k in ("workload", "n", "h", "eps", "tol", "free_nodes")}
     out["stages_s"] = {k: _r(v) for k, v in full.get("stages_s", {}).items()}

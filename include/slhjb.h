@@ -281,6 +281,23 @@ int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32
                             double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
                             slhjb_batch_stats* total);
 
+/* The same batched active-tile solve as a reusable object, for callers that solve the same set of
+ * instances (same problems, same iterate buffers) again and again: create prepares every
+ * instance (statistics, control tables, tile layout), allocates the device buffers and captures
+ * the graph of 16 passes once; run starts from whatever v[i] holds, solves to tol in at most
+ * max_passes passes per instance and overwrites v[i] (same values and statistics as
+ * slhjb_solve_tiles_batch); destroy frees everything. The object keeps the problems' device
+ * arrays (speed, node_class) and the v pointers: they must stay valid and unchanged in shape until
+ * destroy (their contents may change between runs). The object belongs to ctx and uses its
+ * stream; runs of one object must not overlap. Errors as slhjb_solve_tiles_batch; *out is NULL
+ * on failure. */
+typedef struct slhjb_tiles_batch slhjb_tiles_batch;
+int slhjb_tiles_batch_create(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
+                             const slhjb_tile_opts* opts, slhjb_tiles_batch** out);
+int slhjb_tiles_batch_run(slhjb_tiles_batch* batch, double tol, int64_t max_passes, slhjb_stats* stats,
+                          slhjb_batch_stats* total);
+int slhjb_tiles_batch_destroy(slhjb_tiles_batch* batch);
+
 /* ---- the patchy method end to end (Section 4.3) ------------------------------------------- */
 enum { SLHJB_PATCHY_TRANSMISSION = 0,  /* patchy decomposition, one shared iterate             */
        SLHJB_PATCHY_INDEPENDENT = 1,   /* patchy decomposition, state constraints at interfaces */

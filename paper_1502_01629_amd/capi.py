@@ -237,6 +237,10 @@ SIGNATURES = {
                                          ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
     "slhjb_solve_tiles_batch": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), _f64, _i64, ctypes.POINTER(TileOpts),
                                                ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
+    "slhjb_tiles_batch_create": (ctypes.c_int, [_vp, _PP, _i32, ctypes.POINTER(_vp), ctypes.POINTER(TileOpts),
+                                                ctypes.POINTER(_vp)]),
+    "slhjb_tiles_batch_run": (ctypes.c_int, [_vp, _f64, _i64, ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
+    "slhjb_tiles_batch_destroy": (ctypes.c_int, [_vp]),
     "slhjb_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(NetConfig), ctypes.POINTER(_vp)]),
     "slhjb_net_destroy": (ctypes.c_int, [_vp]),
     "slhjb_net_param_count": (_i64, [_vp]),
@@ -507,6 +511,48 @@ class Context:
                                        ctypes.byref(stats))
         self._check(st, allow=(OK, NOT_CONVERGED))
         return stats.as_dict()
+
+
+class TilesBatch:
+    """A reusable batched active-tile solve (slhjb_tiles_batch_*): the problems and the iterate
+    tensors are fixed at creation; run() solves from whatever the tensors hold."""
+
+    def __init__(self, ctx: "Context", probs, vs, order: int = ORDER_NONE, key_slack: float = -1.0,
+                 max_inner: int = 0, tile_shape: int = TILE_16x16_SPLIT2, policy_sweeps: int = 0):
+        if len(vs) != len(probs):
+            raise ValueError("one iterate per problem")
+        self.ctx = ctx
+        self.count = len(probs)
+        self._keep = (list(probs), list(vs))  # the object holds their device pointers
+        arr = (Problem * self.count)(*[p.struct for p in probs])
+        ptrs = (_vp * self.count)(*[_ptr(v) for v in vs])
+        opts = TileOpts(order, MODE_TRANSMISSION, None, key_slack, max_inner, tile_shape, 0, 0, 0, policy_sweeps)
+        h = ctypes.c_void_p()
+        ctx._check(lib().slhjb_tiles_batch_create(ctx.handle, arr, self.count, ptrs, ctypes.byref(opts),
+                                                  ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, tol: float = 1e-6, max_passes: int = 1_000_000):
+        stats = (Stats * self.count)()
+        tot = BatchStats()
+        st = lib().slhjb_tiles_batch_run(self.handle, tol, max_passes, stats, ctypes.byref(tot))
+        self.ctx._check(st, allow=(OK, NOT_CONVERGED))
+        return [s.as_dict() for s in stats], tot.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().slhjb_tiles_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone: leave the memory to the
+        # process exit instead of calling into it
+        if _is_finalizing is None or _is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Net:

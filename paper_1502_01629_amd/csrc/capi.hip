@@ -9,6 +9,7 @@
 #include <string>
 #include <mutex>
 #include <thread>
+#include <memory>
 #include <vector>
 
 #include "../../include/slhjb.h"
@@ -1546,6 +1547,52 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
 
 }  // namespace
 
+// A batched active-tile solve: per-instance parameters prepared once, device buffers, and the
+// captured graph of kTilesBatchPasses passes (slhjb_tiles_batch_*).
+constexpr int kTilesBatchPasses = 16;
+struct slhjb_tiles_batch {
+  slhjb_ctx* ctx = nullptr;
+  int count = 0, shape = 0, pe = 0, total_tiles = 0, grid = 1;
+  bool keyed = false;
+  size_t lds = 0;
+  std::vector<Prepared> prep;
+  std::vector<int> tile0, tiles_x, tiles_y, max_inner, n;
+  std::vector<float> window, lambda;
+  std::vector<const uint8_t*> cls;
+  std::vector<float*> v;
+  float4* d_ctrl = nullptr;
+  char* d_inst = nullptr;
+  char* d_state = nullptr;
+  void* d_ctl = nullptr;
+  float *d_key = nullptr, *d_tchange = nullptr, *d_outbuf = nullptr;
+  uint8_t* d_flag = nullptr;
+  int *d_list = nullptr, *d_tile_inst = nullptr, *d_chk_inst = nullptr;
+  unsigned* d_chk_off = nullptr;
+  unsigned* h_ctl = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void tiles_batch_free(slhjb_tiles_batch& b) {
+  hipStreamSynchronize(b.ctx->stream);
+  if (b.exec) hipGraphExecDestroy(b.exec);
+  b.exec = nullptr;
+  for (void* q : {(void*)b.d_ctrl, (void*)b.d_inst, (void*)b.d_state, b.d_ctl, (void*)b.d_key, (void*)b.d_tchange,
+                  (void*)b.d_outbuf, (void*)b.d_flag, (void*)b.d_list, (void*)b.d_tile_inst, (void*)b.d_chk_inst,
+                  (void*)b.d_chk_off})
+    if (q) hipFree(q);
+  b.d_ctrl = nullptr;
+  b.d_inst = b.d_state = nullptr;
+  b.d_ctl = nullptr;
+  b.d_key = b.d_tchange = b.d_outbuf = nullptr;
+  b.d_flag = nullptr;
+  b.d_list = b.d_tile_inst = b.d_chk_inst = nullptr;
+  b.d_chk_off = nullptr;
+  if (b.h_ctl) hipHostFree(b.h_ctl);
+  b.h_ctl = nullptr;
+}
+}  // namespace
+
 extern "C" {
 
 int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, double tol, int64_t max_passes,
@@ -1567,13 +1614,13 @@ int slhjb_solve_tiles(slhjb_ctx* ctx, const slhjb_problem* problem, float* v, do
   return solve_tiles_impl(ctx, problem, P, v, tol, max_passes, opts, stats);
 }
 
-int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
-                            double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
-                            slhjb_batch_stats* total) {
+int slhjb_tiles_batch_create(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
+                             const slhjb_tile_opts* opts, slhjb_tiles_batch** out) {
   if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!out) return fail(ctx, SLHJB_E_INVALID_ARG, "out must be non-NULL");
+  *out = nullptr;
   if (!problems || !v || !opts || count < 1 || count > 4096)
     return fail(ctx, SLHJB_E_INVALID_ARG, "need problems, v, opts and 1 <= count <= 4096");
-  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
   if (opts->order < 0 || opts->order > 1 || opts->max_inner < 0 || opts->tile_shape < 0 ||
       opts->tile_shape >= kTileShapes || opts->policy_sweeps < 0 || opts->policy_sweeps > 64)
     return fail(ctx, SLHJB_E_INVALID_ARG, "invalid tile options");
@@ -1587,162 +1634,169 @@ int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32
                   "batched solves take lambda > 0, a constant running cost and a constant eps");
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  const int shape = opts->tile_shape;
-  const TileShape sh = tile_shape_of(shape);
-  const bool keyed = opts->order == SLHJB_ORDER_KEYS;
-  // device scratch of this call
-  char* d_inst = nullptr;
-  char* d_state = nullptr;
-  void* d_ctl = nullptr;
-  float4* d_ctrl = nullptr;
-  float *d_key = nullptr, *d_tchange = nullptr, *d_outbuf = nullptr;
-  uint8_t* d_flag = nullptr;
-  int *d_list = nullptr, *d_tile_inst = nullptr, *d_chk_inst = nullptr;
-  unsigned* d_chk_off = nullptr;
-  unsigned* h_ctl = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  auto cleanup = [&]() {
-    hipStreamSynchronize(ctx->stream);
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-    for (void* q : {(void*)d_inst, (void*)d_state, d_ctl, (void*)d_ctrl, (void*)d_key, (void*)d_tchange,
-                    (void*)d_outbuf, (void*)d_flag, (void*)d_list, (void*)d_tile_inst, (void*)d_chk_inst,
-                    (void*)d_chk_off})
-      if (q) hipFree(q);
-    if (h_ctl) hipHostFree(h_ctl);
-  };
-  auto bail = [&](hipError_t e, const char* what) {
-    cleanup();
-    if (e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, std::string(what) + ": out of device memory");
-    return hip_fail(ctx, e, what);
-  };
-#define TB_TRY(expr)                                \
-  do {                                              \
-    hipError_t _e = (expr);                         \
-    if (_e != hipSuccess) return bail(_e, #expr);   \
+  std::unique_ptr<slhjb_tiles_batch> B(new slhjb_tiles_batch());
+  slhjb_tiles_batch& b = *B;
+  b.ctx = ctx;
+  b.count = count;
+  b.shape = opts->tile_shape;
+  b.keyed = opts->order == SLHJB_ORDER_KEYS;
+  b.pe = opts->policy_sweeps;
+  const TileShape sh = tile_shape_of(b.shape);
+#define TB_TRY(expr)                                                                                         \
+  do {                                                                                                       \
+    hipError_t _e = (expr);                                                                                  \
+    if (_e != hipSuccess) {                                                                                  \
+      tiles_batch_free(b);                                                                                   \
+      if (_e == hipErrorOutOfMemory) return fail(ctx, SLHJB_E_NOMEM, std::string(#expr) + ": out of device memory"); \
+      return hip_fail(ctx, _e, #expr);                                                                       \
+    }                                                                                                        \
   } while (0)
-  TB_TRY(hipMalloc(&d_ctrl, sizeof(float4) * kCtrlCap * count));
+  TB_TRY(hipMalloc(&b.d_ctrl, sizeof(float4) * kCtrlCap * count));
   // per-instance parameters, exactly as slhjb_solve_tiles derives them
-  std::vector<Prepared> prep(count);
-  std::vector<int> tile0(count), tiles_x(count), tiles_y(count), max_inner(count);
-  std::vector<float> window(count);
-  int total_tiles = 0, max_tiles = 0;
-  size_t lds = 0;
+  b.prep.resize(count);
+  b.tile0.resize(count);
+  b.tiles_x.resize(count);
+  b.tiles_y.resize(count);
+  b.max_inner.resize(count);
+  b.window.resize(count);
+  b.n.resize(count);
+  b.cls.resize(count);
+  b.lambda.resize(count);
+  b.v.assign(v, v + count);
+  int max_tiles = 0;
   for (int i = 0; i < count; ++i) {
-    int st = prepare(ctx, &problems[i], &prep[i]);
+    const int st = prepare(ctx, &problems[i], &b.prep[i]);
     if (st != SLHJB_OK) {
-      cleanup();
+      tiles_batch_free(b);
       ctx->last_msg = "instance " + std::to_string(i) + ": " + ctx->last_msg;
       return st;
     }
-    const Prepared& P = prep[i];
-    if (P.path != prep[0].path || P.diffusion != prep[0].diffusion || P.scheme != prep[0].scheme) {
-      cleanup();
+    const Prepared& P = b.prep[i];
+    if (P.path != b.prep[0].path || P.diffusion != b.prep[0].diffusion || P.scheme != b.prep[0].scheme) {
+      tiles_batch_free(b);
       return fail(ctx, SLHJB_E_UNSUPPORTED,
                   "all instances of a batched active-tile solve need the same scheme, diffusion kind and kernel path "
                   "(instance " + std::to_string(i) + " differs from instance 0)");
     }
     // prepare() leaves the instance's padded control table in ctx->ctrl (stream-ordered copy)
-    TB_TRY(hipMemcpyAsync(d_ctrl + (size_t)kCtrlCap * i, ctx->ctrl, sizeof(float4) * P.args.n_controls,
+    TB_TRY(hipMemcpyAsync(b.d_ctrl + (size_t)kCtrlCap * i, ctx->ctrl, sizeof(float4) * P.args.n_controls,
                           hipMemcpyDeviceToDevice, ctx->stream));
     const int n = problems[i].n;
-    tiles_x[i] = (n + sh.tw - 1) / sh.tw;
-    tiles_y[i] = (n + sh.th - 1) / sh.th;
-    tile0[i] = total_tiles;
-    total_tiles += tiles_x[i] * tiles_y[i];
-    max_tiles = std::max(max_tiles, tiles_x[i] * tiles_y[i]);
-    max_inner[i] = opts->max_inner > 0 ? opts->max_inner
-                                       : (P.diffusion == SLHJB_DIFF_NONE
-                                              ? (opts->policy_sweeps > 0 ? sh.tw + sh.th : 2 * (sh.tw + sh.th))
-                                              : (opts->policy_sweeps > 0 ? opts->policy_sweeps + 1 : 2));
-    window[i] = opts->key_slack >= 0.0f
-                    ? opts->key_slack
-                    : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(&problems[i]) / P.speed_max);
-    lds = std::max(lds, tile_pass_lds_bytes(sh, P.args.halo, false));
+    b.n[i] = n;
+    b.cls[i] = problems[i].node_class;
+    b.lambda[i] = problems[i].lambda;
+    b.tiles_x[i] = (n + sh.tw - 1) / sh.tw;
+    b.tiles_y[i] = (n + sh.th - 1) / sh.th;
+    b.tile0[i] = b.total_tiles;
+    b.total_tiles += b.tiles_x[i] * b.tiles_y[i];
+    max_tiles = std::max(max_tiles, b.tiles_x[i] * b.tiles_y[i]);
+    b.max_inner[i] = opts->max_inner > 0 ? opts->max_inner
+                                         : (P.diffusion == SLHJB_DIFF_NONE
+                                                ? (b.pe > 0 ? sh.tw + sh.th : 2 * (sh.tw + sh.th))
+                                                : (b.pe > 0 ? b.pe + 1 : 2));
+    b.window[i] = opts->key_slack >= 0.0f
+                      ? opts->key_slack
+                      : (float)(std::max(16.0, (n - 1) / 16.0) * grid_dx(&problems[i]) / P.speed_max);
+    b.lds = std::max(b.lds, tile_pass_lds_bytes(sh, P.args.halo, false));
   }
-  if (lds > 64 * 1024) {
-    cleanup();
+  if (b.lds > 64 * 1024) {
+    tiles_batch_free(b);
     return fail(ctx, SLHJB_E_UNSUPPORTED, "interpolation halo too large for the tile solver");
   }
   const size_t tn = (size_t)sh.tw * sh.th;
-  TB_TRY(hipMalloc(&d_inst, tb_inst_bytes() * count));
-  TB_TRY(hipMalloc(&d_state, tb_state_bytes() * count));
-  TB_TRY(hipMalloc(&d_ctl, tb_ctl_bytes()));
-  TB_TRY(hipMalloc(&d_key, sizeof(float) * total_tiles));
-  TB_TRY(hipMalloc(&d_tchange, 2 * sizeof(float) * total_tiles));
-  TB_TRY(hipMalloc(&d_outbuf, sizeof(float) * tn * total_tiles));
-  TB_TRY(hipMalloc(&d_flag, total_tiles));
-  TB_TRY(hipMalloc(&d_list, sizeof(int) * total_tiles));
-  TB_TRY(hipMalloc(&d_tile_inst, sizeof(int) * total_tiles));
-  TB_TRY(hipMalloc(&d_chk_inst, sizeof(int) * count));
-  TB_TRY(hipMalloc(&d_chk_off, sizeof(unsigned) * count));
-  TB_TRY(hipHostMalloc(&h_ctl, 64, hipHostMallocDefault));
-  std::vector<char> h_inst(tb_inst_bytes() * count);
-  std::vector<int> h_tile_inst(total_tiles);
-  const float act = (float)(0.5 * tol), tol_inner = (float)(0.5 * tol);
-  for (int i = 0; i < count; ++i) {
-    SweepArgs a = prep[i].args;
-    a.w_in = v[i];  // the iterate w = V* - v, in place as in the single-instance solve
-    a.w_out = nullptr;
-    a.resid = nullptr;
-    a.flags = nullptr;
-    a.ctrl = d_ctrl + (size_t)kCtrlCap * i;
-    tb_fill_inst(h_inst.data() + tb_inst_bytes() * i, a, keyed ? d_key + tile0[i] : nullptr, tiles_x[i], tiles_y[i],
-                 tile0[i], max_inner[i], opts->policy_sweeps, tol_inner, act, window[i], (float)tol,
-                 (long long)max_passes);
-    for (int t = 0; t < tiles_x[i] * tiles_y[i]; ++t) h_tile_inst[tile0[i] + t] = i;
-  }
-  TB_TRY(hipMemcpyAsync(d_inst, h_inst.data(), h_inst.size(), hipMemcpyHostToDevice, ctx->stream));
-  TB_TRY(hipMemcpyAsync(d_tile_inst, h_tile_inst.data(), sizeof(int) * total_tiles, hipMemcpyHostToDevice,
-                        ctx->stream));
-  TB_TRY(hipStreamSynchronize(ctx->stream));  // the host vectors are pageable
-  TB_TRY(hipEventRecord(ctx->ev0, ctx->stream));
-  for (int i = 0; i < count; ++i) {
-    const Prepared& P = prep[i];
-    const int64_t N = (int64_t)problems[i].n * problems[i].n;
-    TB_TRY(launch_v_to_w(v[i], v[i], problems[i].node_class, N, P.vstar, P.args.w_target, P.args.w_obstacle,
-                         ctx->stream));
-    if (keyed)
-      TB_TRY(launch_tile_keys(v[i], problems[i].node_class, sh.tw, sh.th, problems[i].n, tiles_x[i], tiles_y[i],
-                              P.vstar, problems[i].lambda, d_key + tile0[i], ctx->stream));
-  }
-  TB_TRY(launch_fill_u8(d_flag, 1, total_tiles, ctx->stream));
-  TB_TRY(launch_tb_init(d_state, count, d_ctl, ctx->stream));
-  const int grid = std::min(total_tiles, 3 * std::max(1, ctx->cus));
+  const int T = b.total_tiles;
+  TB_TRY(hipMalloc(&b.d_inst, tb_inst_bytes() * count));
+  TB_TRY(hipMalloc(&b.d_state, tb_state_bytes() * count));
+  TB_TRY(hipMalloc(&b.d_ctl, tb_ctl_bytes()));
+  TB_TRY(hipMalloc(&b.d_key, sizeof(float) * T));
+  TB_TRY(hipMalloc(&b.d_tchange, 2 * sizeof(float) * T));
+  TB_TRY(hipMalloc(&b.d_outbuf, sizeof(float) * tn * T));
+  TB_TRY(hipMalloc(&b.d_flag, T));
+  TB_TRY(hipMalloc(&b.d_list, sizeof(int) * T));
+  TB_TRY(hipMalloc(&b.d_tile_inst, sizeof(int) * T));
+  TB_TRY(hipMalloc(&b.d_chk_inst, sizeof(int) * count));
+  TB_TRY(hipMalloc(&b.d_chk_off, sizeof(unsigned) * count));
+  TB_TRY(hipHostMalloc(&b.h_ctl, 64, hipHostMallocDefault));
+  std::vector<int> h_tile_inst(T);
+  for (int i = 0; i < count; ++i)
+    for (int t = 0; t < b.tiles_x[i] * b.tiles_y[i]; ++t) h_tile_inst[b.tile0[i] + t] = i;
+  TB_TRY(hipMemcpyAsync(b.d_tile_inst, h_tile_inst.data(), sizeof(int) * T, hipMemcpyHostToDevice, ctx->stream));
+  TB_TRY(hipStreamSynchronize(ctx->stream));  // the host vector is pageable
+  // the passes: captured once; they read every per-call value (tolerances, max_passes) from the
+  // descriptors, which run() rewrites
+  b.grid = std::min(T, 3 * std::max(1, ctx->cus));
   const int max_chunks = (max_tiles + 1023) / 1024;
-  constexpr int kPasses = 16;  // passes per graph replay
   if (!ctx->cap_stream) TB_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   TB_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t ce = hipSuccess;
-  for (int b = 0; b < kPasses && ce == hipSuccess; ++b)
-    ce = launch_tb_pass(shape, d_inst, d_state, count, max_chunks, d_flag, d_list, d_tile_inst, d_chk_inst, d_chk_off,
-                        d_ctl, total_tiles, d_outbuf, d_tchange, prep[0].diffusion, prep[0].scheme, prep[0].path,
-                        b & 1, grid, lds, ctx->cap_stream);
+  for (int p = 0; p < kTilesBatchPasses && ce == hipSuccess; ++p)
+    ce = launch_tb_pass(b.shape, b.d_inst, b.d_state, count, max_chunks, b.d_flag, b.d_list, b.d_tile_inst,
+                        b.d_chk_inst, b.d_chk_off, b.d_ctl, T, b.d_outbuf, b.d_tchange, b.prep[0].diffusion,
+                        b.prep[0].scheme, b.prep[0].path, p & 1, b.grid, b.lds, ctx->cap_stream);
+  hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
-  if (ce != hipSuccess) return bail(ce, "capture of the batched tile passes");
-  if (ee != hipSuccess) return bail(ee, "hipStreamEndCapture");
-  TB_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  int64_t replays = 0;
-  // every replay advances each instance still iterating by up to kPasses passes; an instance stops
-  // after max_passes, so the loop ends
-  while (true) {
-    TB_TRY(hipGraphLaunch(exec, ctx->stream));
-    ++replays;
-    TB_TRY(hipMemcpyAsync(h_ctl, d_ctl, tb_ctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
-    TB_TRY(hipStreamSynchronize(ctx->stream));
-    if (h_ctl[kTBCtlActive] == 0u) break;
-  }
+  if (ce == hipSuccess && ee == hipSuccess) ce = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  TB_TRY(ce != hipSuccess ? ce : ee);
+#undef TB_TRY
+  *out = B.release();
+  return SLHJB_OK;
+}
+
+int slhjb_tiles_batch_run(slhjb_tiles_batch* b, double tol, int64_t max_passes, slhjb_stats* stats,
+                          slhjb_batch_stats* total) {
+  if (!b) return SLHJB_E_INVALID_ARG;
+  slhjb_ctx* ctx = b->ctx;
+  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int count = b->count;
+  const TileShape sh = tile_shape_of(b->shape);
+  const float act = (float)(0.5 * tol), tol_inner = (float)(0.5 * tol);
+  std::vector<char> h_inst(tb_inst_bytes() * count);
   for (int i = 0; i < count; ++i) {
-    const int64_t N = (int64_t)problems[i].n * problems[i].n;
-    TB_TRY(launch_w_to_v(v[i], v[i], N, prep[i].vstar, ctx->stream));
+    SweepArgs a = b->prep[i].args;
+    a.w_in = b->v[i];  // the iterate w = V* - v, in place as in the single-instance solve
+    a.w_out = nullptr;
+    a.resid = nullptr;
+    a.flags = nullptr;
+    a.ctrl = b->d_ctrl + (size_t)kCtrlCap * i;
+    tb_fill_inst(h_inst.data() + tb_inst_bytes() * i, a, b->keyed ? b->d_key + b->tile0[i] : nullptr, b->tiles_x[i],
+                 b->tiles_y[i], b->tile0[i], b->max_inner[i], b->pe, tol_inner, act, b->window[i], (float)tol,
+                 (long long)max_passes);
   }
-  TB_TRY(hipEventRecord(ctx->ev1, ctx->stream));
-  TB_TRY(hipEventSynchronize(ctx->ev1));
+  HIP_TRY(ctx, hipMemcpyAsync(b->d_inst, h_inst.data(), h_inst.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host vector is pageable
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  for (int i = 0; i < count; ++i) {
+    const Prepared& P = b->prep[i];
+    const int64_t N = (int64_t)b->n[i] * b->n[i];
+    HIP_TRY(ctx, launch_v_to_w(b->v[i], b->v[i], b->cls[i], N, P.vstar, P.args.w_target, P.args.w_obstacle,
+                               ctx->stream));
+    if (b->keyed)
+      HIP_TRY(ctx, launch_tile_keys(b->v[i], b->cls[i], sh.tw, sh.th, b->n[i], b->tiles_x[i], b->tiles_y[i], P.vstar,
+                                    b->lambda[i], b->d_key + b->tile0[i], ctx->stream));
+  }
+  HIP_TRY(ctx, launch_fill_u8(b->d_flag, 1, b->total_tiles, ctx->stream));
+  HIP_TRY(ctx, launch_tb_init(b->d_state, count, b->d_ctl, ctx->stream));
+  int64_t replays = 0;
+  // every replay advances each instance still iterating by up to kTilesBatchPasses passes; an
+  // instance stops after max_passes passes that did work (at most every other pass is a band
+  // move that does none), so the loop ends
+  while (true) {
+    HIP_TRY(ctx, hipGraphLaunch(b->exec, ctx->stream));
+    ++replays;
+    HIP_TRY(ctx, hipMemcpyAsync(b->h_ctl, b->d_ctl, tb_ctl_bytes(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (b->h_ctl[kTBCtlActive] == 0u) break;
+  }
+  for (int i = 0; i < count; ++i)
+    HIP_TRY(ctx, launch_w_to_v(b->v[i], b->v[i], (int64_t)b->n[i] * b->n[i], b->prep[i].vstar, ctx->stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
   float ms = 0.0f;
-  TB_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   std::vector<char> h_state(tb_state_bytes() * count);
-  TB_TRY(hipMemcpy(h_state.data(), d_state, h_state.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(h_state.data(), b->d_state, h_state.size(), hipMemcpyDeviceToHost));
   int status = SLHJB_OK, converged = 0;
   int64_t all_passes = 0, all_updates = 0;
   for (int i = 0; i < count; ++i) {
@@ -1762,8 +1816,8 @@ int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32
       t.residual = r.done ? (double)r.resid : INFINITY;
       t.seconds = ms * 1e-3;
       t.status = si;
-      t.kernel_path = prep[i].path;
-      t.halo = prep[i].args.halo;
+      t.kernel_path = b->prep[i].path;
+      t.halo = b->prep[i].args.halo;
       t.policy_updates = (int64_t)r.pe_updates;
       t.check_sweeps = r.checks;
     }
@@ -1777,9 +1831,29 @@ int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32
     total->converged = converged;
     total->status = status;
   }
-  cleanup();
-#undef TB_TRY
   return status;
+}
+
+int slhjb_tiles_batch_destroy(slhjb_tiles_batch* b) {
+  if (!b) return SLHJB_E_INVALID_ARG;
+  hipSetDevice(b->ctx->device);
+  hipStreamSynchronize(b->ctx->stream);
+  tiles_batch_free(*b);
+  delete b;
+  return SLHJB_OK;
+}
+
+int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
+                            double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
+                            slhjb_batch_stats* total) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!(tol > 0.0) || max_passes < 1) return fail(ctx, SLHJB_E_INVALID_ARG, "need tol > 0 and max_passes >= 1");
+  slhjb_tiles_batch* b = nullptr;
+  int st = slhjb_tiles_batch_create(ctx, problems, count, v, opts, &b);
+  if (st != SLHJB_OK) return st;
+  st = slhjb_tiles_batch_run(b, tol, max_passes, stats, total);
+  slhjb_tiles_batch_destroy(b);
+  return st;
 }
 
 int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v, double tol,

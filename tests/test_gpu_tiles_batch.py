@@ -111,3 +111,32 @@ def test_tiles_batch_rejects_mixed_kernel_paths(ctx):
     pa, pb = capi.DeviceProblem(a, 1), capi.DeviceProblem(b, 1)
     with pytest.raises(capi.SlhjbError):
         ctx.solve_tiles_batch([pa, pb], [_dev(a.initial()), _dev(b.initial())])
+
+
+def test_tiles_batch_object_runs_again(ctx):
+    """The reusable object: the second run from the same starts gives the first run's bits, and a
+    run at another tolerance equals the one-shot call at that tolerance."""
+    from paper_1502_01629_amd import capi
+
+    insts = I.batch_problems(6, count=4, sizes=(65, 100))
+    probs = [capi.DeviceProblem(x, capi.SL3) for x in insts]
+    starts = [_dev(x.initial()) for x in insts]
+    vs = [s.clone() for s in starts]
+    b = capi.TilesBatch(ctx, probs, vs, policy_sweeps=8)
+    try:
+        s1, t1 = b.run(tol=1e-6)
+        first = [v.clone() for v in vs]
+        for v, s0 in zip(vs, starts):
+            v.copy_(s0)
+        s2, t2 = b.run(tol=1e-6)
+        assert all(torch.equal(a, c) for a, c in zip(first, vs))
+        assert [s["sweeps"] for s in s1] == [s["sweeps"] for s in s2]
+        for v, s0 in zip(vs, starts):
+            v.copy_(s0)
+        s3, _ = b.run(tol=1e-5)
+    finally:
+        b.close()
+    ref = [s0.clone() for s0 in starts]
+    r3, _ = ctx.solve_tiles_batch(probs, ref, tol=1e-5, policy_sweeps=8)
+    assert all(torch.equal(a, c) for a, c in zip(ref, vs))
+    assert [s["sweeps"] for s in r3] == [s["sweeps"] for s in s3]

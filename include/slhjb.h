@@ -376,6 +376,35 @@ int slhjb_synthesize(slhjb_ctx* ctx, const slhjb_problem* problem, const float* 
 int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
                             int32_t* n_targets_out);
 
+/* Balanced patches (Section 2 on the relative sizes of the patches, Section 4.3 closing remarks:
+ * equal sub-sets of the sources can give very unequal patches, and the paper proposes to optimise
+ * the subdivision iteratively so that the patches come out about equal, without giving a method).
+ * This is one such method, `iterations` rounds of:
+ *   1. label the patches of the current subdivision (as slhjb_label, tau = 0);
+ *   2. size of patch p = the nodes labelled p; weight of a source node = its patch's size
+ *      divided by its patch's number of source nodes;
+ *   3. across the target components (4-connected, numbered in raster order of their first node):
+ *      one patch each, the rest by the components' total size, largest remainder (ties: lower
+ *      component; no size at all: by node count);
+ *   4. within a component: its sources in angular order around the centroid (exact: direction
+ *      (i cnt - sum_i, j cnt - sum_j) by half-plane and integer cross product, the order of atan2
+ *      on (-pi, pi], ties by node index) cut into consecutive runs of equal total weight: source r
+ *      with weight w_r goes to run floor(P_t (W_<r + w_r / 2) / W), clamped to [0, P_t - 1]
+ *      (W: the component's total; without weight, equal counts), FP64 sums in that order.
+ * problem, ctrl, v_hat as for slhjb_label (v_hat only orders the work); n_patches 1..64.
+ * source_patch: device int16[n*n], in: a subdivision (every TARGET node in [0, n_patches), -1
+ * elsewhere; e.g. from slhjb_partition_sources), out: the subdivision kept after `iterations`
+ * (0..64) rounds. The rounds do not converge in general (a patch's territory is an argmax of fuzzy
+ * indicators and can jump when its sources change), so the output is the best balanced
+ * subdivision visited, the start included: the smallest largest-over-mean patch size, compared
+ * exactly (max_k sum_b < max_b sum_k), the earliest on ties. sizes_out (nullable): host
+ * int64[(iterations + 1) * n_patches], the patch sizes of every subdivision visited (round 0 is
+ * the start). label_out (nullable): device int16[n*n], the labels of the output subdivision.
+ * best_round_out (nullable): the round of the output. Synchronises. */
+int slhjb_balance_sources(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const float* v_hat,
+                          int32_t n_patches, int32_t iterations, int16_t* source_patch, int64_t* sizes_out,
+                          int16_t* label_out, int32_t* best_round_out);
+
 /* Patch construction (eq. discrete-advection iterated to its fixed point, then the argmax that
  * turns the fuzzy indicators into patches), in exact integer arithmetic:
  *   phi_p in [0, 2^15]; 2^15 on TARGET nodes whose source_patch is p, 0 on other TARGET
@@ -399,7 +428,8 @@ int slhjb_label(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctr
                 uint64_t* overlap_out, uint16_t* phi_out, int64_t* passes_out);
 
 /* ---- learned warm start ------------------------------------------------------------------ */
-/* A small dilated convolutional network that maps [u_hat, c, target mask, log10(eps) + 3,
+/* A convolutional network (the 4-level U-Net of slhjb_net_config arch 1, or the dilated network
+ * of arch 0) that maps [u_hat, c, target mask, log10(eps) + 3,
  * 1 / (1 + d / 4)] (d: distance in cells to the nearest side of the box) on the fine grid to a
  * correction delta of u_hat; the start of the SL iteration is then
  * clamp(u_hat + delta, 0, 1) on FREE nodes (the boundary data elsewhere). The iteration

@@ -241,6 +241,8 @@ SIGNATURES = {
                                                 ctypes.POINTER(_vp)]),
     "slhjb_tiles_batch_run": (ctypes.c_int, [_vp, _f64, _i64, ctypes.POINTER(Stats), ctypes.POINTER(BatchStats)]),
     "slhjb_tiles_batch_destroy": (ctypes.c_int, [_vp]),
+    "slhjb_balance_sources": (ctypes.c_int, [_vp, _PP, _vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_i64), _vp,
+                                             ctypes.POINTER(_i32)]),
     "slhjb_net_create": (ctypes.c_int, [_vp, ctypes.POINTER(NetConfig), ctypes.POINTER(_vp)]),
     "slhjb_net_destroy": (ctypes.c_int, [_vp]),
     "slhjb_net_param_count": (_i64, [_vp]),
@@ -453,6 +455,19 @@ class Context:
                                       _ptr(overlap_out) if overlap_out is not None else None,
                                       _ptr(phi_out) if phi_out is not None else None, ctypes.byref(passes)))
         return passes.value
+
+    def balance_sources(self, prob: DeviceProblem, ctrl, source_patch, n_patches: int, iterations: int,
+                        v_hat=None, label_out=None) -> np.ndarray:
+        """slhjb_balance_sources: `iterations` rounds of re-dividing the sources (source_patch, a
+        device int16 tensor, receives the best balanced subdivision visited). Returns (the patch
+        sizes of every subdivision visited, int64[iterations + 1, n_patches], the kept round)."""
+        sizes = np.zeros((iterations + 1) * n_patches, dtype=np.int64)
+        best = ctypes.c_int32(-1)
+        self._check(lib().slhjb_balance_sources(self.handle, ctypes.byref(prob.struct), _ptr(ctrl),
+                                                _ptr(v_hat) if v_hat is not None else None, n_patches, iterations,
+                                                _ptr(source_patch), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                _ptr(label_out) if label_out is not None else None, ctypes.byref(best)))
+        return sizes.reshape(iterations + 1, n_patches), best.value
 
     def solve_batch(self, probs, vs, tol: float = 1e-6, max_sweeps: int = 1_000_000, check_every: int = 16,
                     batches_per_graph: int = 0, tile_shapes=None, max_workgroups: int = 0):

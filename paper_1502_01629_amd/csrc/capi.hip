@@ -2058,13 +2058,18 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
   return status;
 }
 
-int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
-                            int32_t* n_targets_out) {
-  if (n < 3 || n > 32769 || !node_class || !source_patch || n_patches < 1 || n_patches > 32767)
-    return SLHJB_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+// 4-connected TARGET components, numbered in raster order of their first node: comp[v] (-1 off
+// the targets), node count and the sums of i and j of each
+void target_components(int n, const uint8_t* node_class, std::vector<int32_t>& comp, std::vector<int64_t>& cnt,
+                       std::vector<int64_t>& si, std::vector<int64_t>& sj) {
   const int64_t N = (int64_t)n * n;
-  std::vector<int32_t> comp(N, -1);
-  std::vector<int64_t> cnt, si, sj;
+  comp.assign(N, -1);
+  cnt.clear();
+  si.clear();
+  sj.clear();
   std::vector<int64_t> stack;
   for (int64_t start = 0; start < N; ++start) {
     if (node_class[start] != SLHJB_TARGET || comp[start] >= 0) continue;
@@ -2089,6 +2094,19 @@ int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patc
         }
     }
   }
+}
+}  // namespace
+
+extern "C" {
+
+int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patches, int16_t* source_patch,
+                            int32_t* n_targets_out) {
+  if (n < 3 || n > 32769 || !node_class || !source_patch || n_patches < 1 || n_patches > 32767)
+    return SLHJB_E_INVALID_ARG;
+  const int64_t N = (int64_t)n * n;
+  std::vector<int32_t> comp;
+  std::vector<int64_t> cnt, si, sj;
+  target_components(n, node_class, comp, cnt, si, sj);
   const int T = (int)cnt.size();
   if (n_targets_out) *n_targets_out = T;
   for (int64_t v = 0; v < N; ++v) source_patch[v] = -1;
@@ -2128,6 +2146,177 @@ int slhjb_partition_sources(int32_t n, const uint8_t* node_class, int32_t n_patc
   }
   return SLHJB_OK;
 }
+
+int slhjb_balance_sources(slhjb_ctx* ctx, const slhjb_problem* problem, const int16_t* ctrl, const float* v_hat,
+                          int32_t n_patches, int32_t iterations, int16_t* source_patch, int64_t* sizes_out,
+                          int16_t* label_out, int32_t* best_round_out) {
+  if (!ctx) return SLHJB_E_INVALID_ARG;
+  if (!problem || !ctrl || !source_patch)
+    return fail(ctx, SLHJB_E_INVALID_ARG, "problem, ctrl and source_patch must be non-NULL");
+  if (n_patches < 1 || n_patches > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "n_patches must be in [1, 64]");
+  if (iterations < 0 || iterations > 64) return fail(ctx, SLHJB_E_INVALID_ARG, "iterations must be in [0, 64]");
+  const int st0 = validate(ctx, problem);
+  if (st0 != SLHJB_OK) return st0;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int n = problem->n;
+  const int64_t N = (int64_t)n * n;
+  std::vector<uint8_t> cls(N);
+  HIP_TRY(ctx, hipMemcpy(cls.data(), problem->node_class, N, hipMemcpyDeviceToHost));
+  std::vector<int32_t> comp;
+  std::vector<int64_t> cnt, si, sj;
+  target_components(n, cls.data(), comp, cnt, si, sj);
+  const int T = (int)cnt.size();
+  if (T > n_patches) return fail(ctx, SLHJB_E_INVALID_ARG, "fewer patches than target components");
+  // the sources of every component in angular order around its centroid, exactly: direction
+  // (i cnt - sum_i, j cnt - sum_j) by half-plane and integer cross product (the order of atan2 on
+  // (-pi, pi]), ties by node index
+  std::vector<std::vector<int64_t>> nodes(T);
+  for (int64_t v = 0; v < N; ++v)
+    if (comp[v] >= 0) nodes[comp[v]].push_back(v);
+  for (int t = 0; t < T; ++t) {
+    const int64_t c = cnt[t], ci = si[t], cj = sj[t];
+    auto half = [](int64_t dx, int64_t dy) { return dy < 0 ? 0 : (dy == 0 && dx >= 0 ? 1 : (dy > 0 ? 2 : 3)); };
+    std::stable_sort(nodes[t].begin(), nodes[t].end(), [&](int64_t a, int64_t b) {
+      const int64_t ax = (a % n) * c - ci, ay = (a / n) * c - cj;
+      const int64_t bx = (b % n) * c - ci, by = (b / n) * c - cj;
+      const int ha = half(ax, ay), hb = half(bx, by);
+      if (ha != hb) return ha < hb;
+      if (ha == 0 || ha == 2) {
+        const __int128 cross = (__int128)ax * by - (__int128)ay * bx;
+        if (cross != 0) return cross > 0;
+      }
+      return a < b;
+    });
+  }
+  // the labels of every round go to a scratch buffer; those of the best round also to label_out
+  int16_t* lab = nullptr;
+  int16_t* own_lab = nullptr;
+  HIP_TRY(ctx, hipMalloc(&own_lab, sizeof(int16_t) * N));
+  lab = own_lab;
+  std::vector<int16_t> src(N), labels(N), best_src;
+  std::vector<int64_t> best_sizes;
+  int best_round = -1;
+  int status = SLHJB_OK;
+  {
+    hipError_t e = hipMemcpy(src.data(), source_patch, sizeof(int16_t) * N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      if (own_lab) hipFree(own_lab);
+      return hip_fail(ctx, e, "balance: read-back");
+    }
+    for (int64_t v = 0; v < N; ++v)
+      if ((cls[v] == SLHJB_TARGET) != (src[v] >= 0) || src[v] >= n_patches) {
+        if (own_lab) hipFree(own_lab);
+        return fail(ctx, SLHJB_E_INVALID_ARG,
+                    "source_patch must give every TARGET node a patch in [0, n_patches) and -1 elsewhere");
+      }
+  }
+  for (int k = 0; k <= iterations && status == SLHJB_OK; ++k) {
+    status = slhjb_label(ctx, problem, ctrl, v_hat, source_patch, n_patches, 0, lab, nullptr, nullptr, nullptr);
+    if (status != SLHJB_OK) break;
+    hipError_t e = hipMemcpy(labels.data(), lab, sizeof(int16_t) * N, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(src.data(), source_patch, sizeof(int16_t) * N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      status = hip_fail(ctx, e, "balance: read-back");
+      break;
+    }
+    std::vector<int64_t> sizes(n_patches, 0), members(n_patches, 0);
+    for (int64_t v = 0; v < N; ++v) {
+      if (labels[v] >= 0 && labels[v] < n_patches) sizes[labels[v]] += 1;
+      if (src[v] >= 0 && src[v] < n_patches) members[src[v]] += 1;
+    }
+    if (sizes_out) std::copy(sizes.begin(), sizes.end(), sizes_out + (int64_t)k * n_patches);
+    // keep the best balanced subdivision: smaller largest-over-mean size, compared exactly
+    // (max_k sum_best < max_best sum_k); the earliest on ties
+    bool better = best_round < 0;
+    if (!better) {
+      int64_t mk = 0, sk = 0, mb = 0, sb = 0;
+      for (int p = 0; p < n_patches; ++p) {
+        mk = std::max(mk, sizes[p]);
+        sk += sizes[p];
+        mb = std::max(mb, best_sizes[p]);
+        sb += best_sizes[p];
+      }
+      better = (__int128)mk * sb < (__int128)mb * sk;
+    }
+    if (better) {
+      best_round = k;
+      best_src = src;
+      best_sizes = sizes;
+      if (label_out) {
+        e = hipMemcpy(label_out, lab, sizeof(int16_t) * N, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {
+          status = hip_fail(ctx, e, "balance: labels");
+          break;
+        }
+      }
+    }
+    if (k == iterations || T == 0) break;
+    // patches per component by total size (one each, the rest by largest remainder)
+    std::vector<int64_t> weight(T, 0);
+    std::vector<int> seen(n_patches, 0);
+    for (int64_t v = 0; v < N; ++v) {
+      const int p = src[v];
+      if (comp[v] >= 0 && p >= 0 && p < n_patches && !seen[p]) {
+        seen[p] = 1;
+        weight[comp[v]] += sizes[p];
+      }
+    }
+    int64_t total = 0, total_cnt = 0;
+    for (int t = 0; t < T; ++t) {
+      total += weight[t];
+      total_cnt += cnt[t];
+    }
+    const int extra = n_patches - T;
+    std::vector<int> share(T);
+    std::vector<std::pair<double, int>> rem(T);
+    int given = 0;
+    for (int t = 0; t < T; ++t) {
+      const double quota = total > 0 ? (double)extra * (double)weight[t] / (double)total
+                                     : (double)extra * (double)cnt[t] / (double)total_cnt;
+      share[t] = (int)floor(quota);
+      given += share[t];
+      rem[t] = {quota - share[t], t};
+    }
+    std::stable_sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+      return a.first > b.first;
+    });
+    for (int q = 0; q < extra - given; ++q) share[rem[q].second] += 1;
+    std::vector<int> offset(T + 1, 0);
+    for (int t = 0; t < T; ++t) offset[t + 1] = offset[t] + 1 + share[t];
+    // within a component: runs of equal total weight in angular order; a source's weight is its
+    // patch's size shared out over the patch's sources
+    std::vector<int16_t> next(N, (int16_t)-1);
+    for (int t = 0; t < T; ++t) {
+      const int Pt = offset[t + 1] - offset[t];
+      const std::vector<int64_t>& nd = nodes[t];
+      std::vector<double> w(nd.size());
+      double wt = 0.0;
+      for (size_t r = 0; r < nd.size(); ++r) {
+        const int p = src[nd[r]];
+        w[r] = (double)sizes[p] / (double)members[p];
+        wt += w[r];
+      }
+      double cum = 0.0;
+      for (size_t r = 0; r < nd.size(); ++r) {
+        int64_t sec = wt > 0.0 ? (int64_t)floor((double)Pt * (cum + w[r] / 2) / wt)
+                               : ((int64_t)Pt * (int64_t)r) / (int64_t)nd.size();
+        sec = std::min<int64_t>(std::max<int64_t>(sec, 0), Pt - 1);
+        next[nd[r]] = (int16_t)(offset[t] + sec);
+        cum += w[r];
+      }
+    }
+    e = hipMemcpy(source_patch, next.data(), sizeof(int16_t) * N, hipMemcpyHostToDevice);
+    if (e != hipSuccess) status = hip_fail(ctx, e, "balance: upload");
+  }
+  if (status == SLHJB_OK && best_round >= 0) {
+    const hipError_t e = hipMemcpy(source_patch, best_src.data(), sizeof(int16_t) * N, hipMemcpyHostToDevice);
+    if (e != hipSuccess) status = hip_fail(ctx, e, "balance: upload");
+  }
+  if (best_round_out) *best_round_out = best_round;
+  if (own_lab) hipFree(own_lab);
+  return status;
+}
+
 
 int slhjb_regime_analyze(double f_min, double f_max, double sigma_inf, double dx, slhjb_regime* out) {
   if (!out || !(f_min > 0.0) || !(f_max >= f_min) || !(sigma_inf >= 0.0) || !(dx > 0.0) || !isfinite(f_max) ||

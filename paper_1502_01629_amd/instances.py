@@ -147,6 +147,17 @@ def disc_problem(n: int = 129, eps: float = 0.0, n_controls: int = 32, h_factor:
     return g.instance(n, n_controls, eps, diffusion, h_factor * dx, workload="disc")
 
 
+def offcenter_problem(n: int = 129, cx: float = 0.55, cy: float = 0.35, r: float = 0.12, n_controls: int = 32,
+                      seed: int = 0) -> Instance:
+    """Unbalanced patches: one disc target off the centre of the box (the patches facing the far
+    sides are much larger than those facing the near ones), c(x) from 8 bumps, sigma = 0,
+    h = 0.99 dx / max c (every foot in the first ring of cells, as the patch labeling needs)."""
+    rng = np.random.default_rng(np.random.SeedSequence([1502, 1629, 6, seed]))
+    g = Geometry(targets=[(cx, cy, r)], speed_law="bumps", bumps=bump_geometry(rng, 8))
+    h = 0.99 * (2.0 / (n - 1)) / float(g.speed(n).max())
+    return g.instance(n, n_controls, 0.0, DIFF_NONE, h, workload="offcenter", seed=seed)
+
+
 def _coarse_node_inside(cx, cy, r, n_coarse):
     X1, X2 = node_coords(n_coarse)
     return bool(np.any((X1 - cx) ** 2 + (X2 - cy) ** 2 <= r * r))

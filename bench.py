@@ -26,6 +26,8 @@ Beside the timed steps, each comparison arm runs once (progress on stderr):
   indep  the independent (state-constraint) patch solves at eps = 0, 1e-3, 1e-2 against the
          transmission solve: the decomposition error, near the patch interfaces and away from them;
   hdx    the same step with h = dx (feet up to 1.5 cells: the general kernels);
+  balance  balanced patches on the step's workload: the patch sizes of the rounds of
+         slhjb_balance_sources from the equal angular sectors;
   exit   the paper's exit-to-boundary experiments (Table 0, the eps sweeps of Tables 1-2).
 The full record of every arm goes to a JSON file (--arms-out); stdout ends with one JSON line of
 at most a few KB: the headline, the roofline, the CPU baseline, the accuracy against the oracle's
@@ -487,6 +489,39 @@ def arm_hdx(ctx, seed: int, tol: float, patches: int) -> dict:
     return out
 
 
+def arm_balance(ctx, seed: int, patches: int, rounds: int = 4) -> dict:
+    """Balanced patches on the step's workload (2049^2 scattered targets, eps = 0): the coarse solve,
+    u_hat and the synthesized control as in the step, then slhjb_balance_sources from the equal
+    angular sectors; the patch sizes of every round and the time."""
+    import torch
+
+    from paper_1502_01629_amd import capi
+    from paper_1502_01629_amd import instances as I
+
+    fine, coarse = I.scattered_problem(seed)
+    dp, dpc = capi.DeviceProblem(fine, capi.SL3), capi.DeviceProblem(coarse, capi.SL3)
+    vc = torch.from_numpy(coarse.initial().reshape(-1)).cuda()
+    ctx.solve_tiles(dpc, vc, tol=1e-7, order=capi.ORDER_NONE, tile_shape=capi.TILE_8x8_SPLIT4, max_passes=50000,
+                    policy_sweeps=POLICY_SWEEPS)
+    vhat = torch.empty(fine.n * fine.n, dtype=torch.float32, device="cuda")
+    ctx.upsample(vc, coarse.n, vhat, fine.n)
+    ctrl = torch.empty(fine.n * fine.n, dtype=torch.int16, device="cuda")
+    ctx.synthesize(dp, vhat, ctrl)
+    src_host, _ = capi.partition_sources(fine.node_class, patches)
+    src = torch.from_numpy(src_host.reshape(-1)).cuda()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sizes, best = ctx.balance_sources(dp, ctrl, src, patches, rounds, v_hat=vhat)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ratio = lambda s: float(np.max(s) / np.mean(s))
+    log(f"balance: largest/mean patch {[round(ratio(s), 3) for s in sizes]}, kept round {best}, {dt:.2f} s")
+    return {"n": fine.n, "patches": patches, "rounds": rounds, "time_s": dt, "kept_round": best,
+            "largest_over_mean": [ratio(s) for s in sizes],
+            "smallest_over_mean": [float(np.min(s) / np.mean(s)) for s in sizes],
+            "sizes_start": [int(v) for v in sizes[0]], "sizes_kept": [int(v) for v in sizes[best]]}
+
+
 def arm_learned(ctx, seed: int, tol: float, n: int = 1025, n_coarse: int = 129, train_count: int = 192,
                 test_count: int = 8, steps: int = 2000) -> dict:
     """Learned warm start: the 4-level U-Net (BF16 matrix-core kernels of the library) trained on
@@ -561,10 +596,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="skip the comparison arms")
-    ap.add_argument("--arms", default="c2,c2eps,indep,hdx,batch,bumps,learned,exit",
+    ap.add_argument("--arms", default="c2,c2eps,indep,hdx,batch,bumps,balance,learned,exit",
                     help="comparison arms: c2 (global Jacobi, static decomposition), c2eps (the same workload "
                          "with eps = 1e-3 and 1e-2), indep (decomposition error of the independent patch solves), "
                          "hdx (the step with h = dx), batch (256 instances), bumps (4097^2 rank-1 diffusion), "
+                         "balance (balanced patches on the step's workload), "
                          "learned (U-Net warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
                          "Table 0 on the GPU and the eps-threshold sweeps of Tables 1 and 2)")
     ap.add_argument("--arms-out", default=os.path.join(ROOT, "gpurun_out", "bench_arms.json"),
@@ -771,6 +807,8 @@ def main():
         arms["batch_256_instances"] = arm_batch(ctx, args.seed, args.tol)
     if "bumps" in which:
         arms["rank1_bumps"] = arm_bumps(ctx, args.seed, args.tol, args.bumps_n)
+    if "balance" in which:
+        arms["balanced_patches"] = arm_balance(ctx, args.seed, args.patches)
     if "learned" in which:
         arms["learned_warm_start"] = arm_learned(ctx, args.seed, args.tol, train_count=args.learned_train,
                                                    steps=args.learned_steps)
@@ -849,6 +887,10 @@ def summary_line(full: dict) -> dict:
         arms["rank1_4097"] = {"full_sweeps_s": _r(e["full_sweeps"]["time_s"]),
                               "active_tiles_cold_s": _r(e["active_tiles_cold"]["time_s"]),
                               "active_tiles_uhat_s": _r(e["active_tiles_uhat"]["time_s"])}
+    if "balanced_patches" in A:
+        e = A["balanced_patches"]
+        arms["balance_2049"] = {"largest_over_mean": [_r(v, 3) for v in e["largest_over_mean"]],
+                                "kept": e["kept_round"], "s": _r(e["time_s"])}
     if "learned_warm_start" in A:
         e = A["learned_warm_start"]
         arms["learned_1025"] = {"train": e["train_problems"],

@@ -44,6 +44,7 @@ def full_record() -> dict:
                                     "active_tiles": {"time_s_batched": X, "time_s_sequential": X,
                                                      "bit_exact_vs_single": "256/256"}},
             "rank1_bumps": {k: {"time_s": X} for k in ("full_sweeps", "active_tiles_cold", "active_tiles_uhat")},
+            "balanced_patches": {"largest_over_mean": [2.0, 1.5], "kept_round": 1, "time_s": X},
             "learned_warm_start": {"train_problems": 192,
                                    "start_error_mean": {"uhat": X, "uhat_bicubic": X, "network": X},
                                    "jacobi_sweeps": {"cold": X, "uhat": X, "uhat_bicubic": X, "network": X},

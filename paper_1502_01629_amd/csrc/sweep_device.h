@@ -357,48 +357,53 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
 }
 
 // Policy evaluation on the first ring (modified policy iteration): the update of a node for one
-// fixed control cm, with the quadrant taken from the signs of (a_x, a_y) as the host groups the
+// fixed control, with the quadrant taken from the signs of (a_x, a_y) as the host groups the
 // table. Everything that does not depend on the iterate is computed once per node after each full
-// iteration (policy_prepare); policy_apply then evaluates the expressions of ring1_partial for
-// that control operation for operation, so that a node whose control is still the maximiser gets
-// bit for bit the value a full iteration would give it. (Otherwise the two maps would have fixed
-// points a few ulp apart, and a tolerance near the FP32 resolution could never be met.) SL3
-// divides by the denominator through its reciprocal, as the full iteration of the split visit does.
-struct PolicyEval {
-  int ox, oy;            // LDS offsets of the east/west and north/south corners
-  float ksx, ksy, k2s;   // k sx, k sy, k^2 sx sy (exact: sx, sy = +-1)
-  float cx, cy, cz;      // a_x, a_y, a_x a_y
-  float rden;            // SL3: 1 / (1 - beta w00) as the full iteration computes it
-  bool out;              // the foot leaves the box: w_outside
+// iteration (policy_prepare64), and the full iteration takes the value of its maximiser from the
+// same function (policy_apply64), so that a node whose control is still the maximiser gets bit for
+// bit the value a full iteration would give it. (Otherwise the two maps would have fixed points a
+// few ulp apart, and a tolerance near the FP32 resolution could never be met.)
+// The value of a node under one control in FP64 from the FP32 iterate, rounded once to FP32: the
+// bilinear weights of the foot's cell, s(1-t), (1-s)t, st and (1-s)(1-t) with s = k|a_x|,
+// t = k|a_y|, beta and (SL3) the implicit denominator 1 - beta (1-s)(1-t) folded in. The split
+// visits of the first-ring path choose the maximising control in FP32, then take its value from
+// here, in the full iterations and in the policy evaluations alike (the same bits for the same
+// control). Taking the maximum of 64 FP32-rounded candidates biases the value upward by about
+// their rounding error, at every step along a characteristic; recomputing the winner removes that
+// bias, which at 2049^2 had put the FP32 fixed point 1.6e-5 from the FP64 one.
+struct PolicyEval64 {
+  int ox, oy;              // LDS offsets of the east/west and north/south corners
+  double gX, gY, gXY, g0;  // weights of the corners X, Y, XY and of the node itself (SL2)
+  bool out;                // the foot leaves the box: beta w_outside
 };
-
 template <int SCHEME>
-__device__ __forceinline__ PolicyEval policy_prepare(int LW, float k, float4 cm, const SweepArgs& a, bool lft,
-                                                     bool rgt, bool bot, bool top) {
-  PolicyEval p;
-  const float sx = cm.x >= 0.0f ? 1.0f : -1.0f, sy = cm.y >= 0.0f ? 1.0f : -1.0f;
+__device__ __forceinline__ PolicyEval64 policy_prepare64(int LW, float k, float4 cm, const SweepArgs& a, bool lft,
+                                                         bool rgt, bool bot, bool top) {
+  PolicyEval64 p;
   p.ox = cm.x >= 0.0f ? 1 : -1;
   p.oy = cm.y >= 0.0f ? LW : -LW;
-  const float k2 = k * k;
-  p.ksx = k * sx;
-  p.ksy = k * sy;
-  p.k2s = k2 * (sx * sy);
-  p.cx = cm.x;
-  p.cy = cm.y;
-  p.cz = cm.z;
   p.out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
-  p.rden = 1.0f;
-  if (SCHEME == kSL3 && !p.out) {
-    const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
-    p.rden = 1.0f / __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
+  const double s = (double)k * fabs((double)cm.x), t = (double)k * fabs((double)cm.y);
+  const double b = (double)a.beta;
+  const double cX = s * (1.0 - t), cY = (1.0 - s) * t, cXY = s * t, c0 = (1.0 - s) * (1.0 - t);
+  if (SCHEME == kSL3) {
+    const double g = b / (1.0 - b * c0);
+    p.gX = g * cX;
+    p.gY = g * cY;
+    p.gXY = g * cXY;
+    p.g0 = 0.0;
+  } else {
+    p.gX = b * cX;
+    p.gY = b * cY;
+    p.gXY = b * cXY;
+    p.g0 = b * c0;
   }
   return p;
 }
-
 template <int SCHEME, bool INDEP>
-__device__ __forceinline__ float policy_apply(const float* __restrict__ T, const PolicyEval& p, const SweepArgs& a,
-                                              const int16_t* __restrict__ L) {
-  const float w00 = T[0];
+__device__ __forceinline__ float policy_apply64(const float* __restrict__ T, const PolicyEval64& p, const SweepArgs& a,
+                                                const int16_t* __restrict__ L) {
+  if (p.out) return (float)((double)a.beta * (double)a.w_outside);
   float wX = T[p.ox], wY = T[p.oy], wXY = T[p.ox + p.oy];
   if (INDEP) {
     const int me = L[0];
@@ -406,23 +411,9 @@ __device__ __forceinline__ float policy_apply(const float* __restrict__ T, const
     wY = L[p.oy] == me ? wY : a.w_outside;
     wXY = L[p.ox + p.oy] == me ? wXY : a.w_outside;
   }
-  float B, C, D;
-  if (SCHEME == kSL2) {
-    B = p.ksx * (wX - w00);
-    C = p.ksy * (wY - w00);
-    D = p.k2s * ((wXY - wX) - (wY - w00));
-  } else {
-    B = p.ksx * wX;
-    C = p.ksy * wY;
-    D = p.k2s * (wXY - wX - wY);
-  }
-  float val = __builtin_fmaf(p.cz, D, __builtin_fmaf(p.cy, C, p.cx * B));
-  if (SCHEME == kSL2) {
-    if (p.out) val = a.w_outside - w00;
-    return a.beta * (w00 + val);
-  }
-  if (p.out) val = a.w_outside;
-  return (a.beta * val) * p.rden;
+  double v = __builtin_fma(p.gXY, (double)wXY, __builtin_fma(p.gY, (double)wY, p.gX * (double)wX));
+  if (SCHEME == kSL2) v = __builtin_fma(p.g0, (double)T[0], v);
+  return (float)v;
 }
 
 template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false, bool GEN = false>

@@ -112,28 +112,21 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   float* nxt = bufB;
   int it = 0, evals = 0;
   int pol = 0;  // maximising control of the last full iteration (part 0)
+  PolicyEval64 pv64{};  // first-ring path: that control's FP64 evaluation (part 0)
   for (;;) {
     if (fr) {
       float num, den;
       int mi = 0;
       if (PATH == 1) {
+        // the maximiser is always tracked: its value is recomputed in FP64 (policy_apply64)
         const float* Tp = cur + li;
         const int16_t* L = INDEP ? labs + li : nullptr;
-        if (pe > 0) {
-          if (interior)
-            ring1_partial<SCHEME, false, INDEP, true>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
-                                                      part * QP + QP, num, den, &mi);
-          else
-            ring1_partial<SCHEME, true, INDEP, true>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1,
-                                                     L, part * QP, part * QP + QP, num, den, &mi);
-        } else {
-          if (interior)
-            ring1_partial<SCHEME, false, INDEP>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
-                                                part * QP + QP, num, den);
-          else
-            ring1_partial<SCHEME, true, INDEP>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1, L,
-                                               part * QP, part * QP + QP, num, den);
-        }
+        if (interior)
+          ring1_partial<SCHEME, false, INDEP, true>(Tp, LW, kk, ctrl, a, false, false, false, false, L, part * QP,
+                                                    part * QP + QP, num, den, &mi);
+        else
+          ring1_partial<SCHEME, true, INDEP, true>(Tp, LW, kk, ctrl, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1,
+                                                   L, part * QP, part * QP + QP, num, den, &mi);
       } else {
         if (pe > 0)
           general_partial<DIFF, SCHEME, INDEP, true, GEN>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a,
@@ -179,6 +172,11 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
         // through the reciprocal, as the policy evaluation of the first-ring path divides
         v = (a.beta * bn) * (1.0f / bd);
       }
+      if (PATH == 1) {
+        // the winner's value in FP64 (the same function as the policy evaluations below)
+        pv64 = policy_prepare64<SCHEME>(LW, kk, ctrl[bi], a, gi == 0, gi == n - 1, gj == 0, gj == n - 1);
+        v = policy_apply64<SCHEME, INDEP>(cur + li, pv64, a, INDEP ? labs + li : nullptr);
+      }
       pol = bi;
       nxt[li] = v;
       lmax = fabsf(v - cur[li]);
@@ -193,13 +191,10 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     // candidate each; leaves room for the full iteration that must end the visit
     if (pe > 0) {
       const float4 cm = ctrl[pol];
-      PolicyEval pv{};
-      if (PATH == 1 && part == 0 && fr)
-        pv = policy_prepare<SCHEME>(LW, kk, cm, a, gi == 0, gi == n - 1, gj == 0, gj == n - 1);
       for (int e = 0; e < pe && it < max_inner - 1; ++e) {
         if (part == 0 && fr) {
           if (PATH == 1) {
-            nxt[li] = policy_apply<SCHEME, INDEP>(cur + li, pv, a, INDEP ? labs + li : nullptr);
+            nxt[li] = policy_apply64<SCHEME, INDEP>(cur + li, pv64, a, INDEP ? labs + li : nullptr);
           } else {
             float num, den;
             general_partial<DIFF, SCHEME, INDEP, false, GEN>(cur, LW, li, gi, gj, kk, cur[li], ctrl, a,

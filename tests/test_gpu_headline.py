@@ -4,12 +4,18 @@ tests/golden/make_scattered2049_samples.py (oracle Jacobi iteration to a sweep c
 within 1.2e-8 of the fixed point by the contraction bound).
 
 The step stops at a full-sweep change `tol`. With h = dx / 1.5 the a-posteriori factor
-beta / (1 - beta) is about 1.5e3, so tol = 1e-6 alone bounds the error only to ~1.5e-3. Measured,
-the error does not depend on the stopping tolerance (1.56e-5 at 1e-6, 1.68e-5 at 1e-7, the global
-Jacobi iteration 1.68e-5 at 1e-7; mean 2.4e-6): it is the distance between the fixed points of the
-FP32 map and of the exact one. Each update rounds, the maximum over 64 candidates favours the ones
-rounded up, and along characteristics of ~2300 steps (damped by beta per step) that bias adds up.
-The bound here is therefore 2.5e-5 at 2049^2 (1e-5 holds on every grid of 257^2 and below)."""
+beta / (1 - beta) is about 1.5e3, so tol = 1e-6 alone bounds the error only to ~1.5e-3; measured,
+the stopping point is much closer. Two errors remain:
+* the stopping point's distance to the fixed point: 1.2e-5 at tol 1e-6, 9.8e-6 at 5e-7, 2.1e-6
+  at 2e-7 (the north star's 1e-5 from tol 5e-7 on);
+* the distance between the fixed point of the FP32 iteration and the exact one: the tile visits
+  take the maximising control in FP32 and its value in FP64 (policy_apply64), which leaves
+  ~2e-6 (2.2e-6 at tol 1e-7). The global Jacobi sweep keeps the value of the FP32 maximum: a
+  maximum over 64 FP32-rounded candidates favours the ones rounded up, and along characteristics
+  of ~2300 steps that bias adds up to 1.7e-5.
+Bounds: 1.5e-5 for the step at 1e-6, 1e-5 at 5e-7, 4e-6 at 2e-7; 2.5e-5 for the global Jacobi
+iteration."""
+BOUND_STEP = {1e-6: 1.5e-5, 5e-7: 1e-5, 2e-7: 4e-6}
 FP32_BOUND_2049 = 2.5e-5
 import os
 
@@ -38,7 +44,7 @@ def setup():
     ctx.close()
 
 
-@pytest.mark.parametrize("tol", [1e-6, 1e-7])
+@pytest.mark.parametrize("tol", [1e-6, 5e-7, 2e-7])
 def test_patchy_step_matches_oracle_samples(setup, tol):
     from paper_1502_01629_amd import capi
 
@@ -56,7 +62,7 @@ def test_patchy_step_matches_oracle_samples(setup, tol):
     print(f"  status {st['status']} passes {st['passes']} max|gpu - oracle| {err.max():.3e} mean {err.mean():.3e}",
           flush=True)
     assert st["status"] == 0
-    assert err.max() <= FP32_BOUND_2049
+    assert err.max() <= BOUND_STEP[tol]
 
 
 def test_global_jacobi_matches_oracle_samples(setup):

@@ -173,6 +173,59 @@ __device__ __forceinline__ float general_update(const float* __restrict__ tile, 
   return a.beta * bnum / bden;
 }
 
+// The value of a node under one control in FP64 from the FP32 iterate, rounded once to FP32: the
+// bilinear weights of the foot's cell, s(1-t), (1-s)t, st and (1-s)(1-t) with s = k|a_x|,
+// t = k|a_y|, beta and (SL3) the implicit denominator 1 - beta (1-s)(1-t) folded in. The split
+// visits of the first-ring path choose the maximising control in FP32, then take its value from
+// here, in the full iterations and in the policy evaluations alike (the same bits for the same
+// control). Taking the maximum of 64 FP32-rounded candidates biases the value upward by about
+// their rounding error, at every step along a characteristic; recomputing the winner removes that
+// bias, which at 2049^2 had put the FP32 fixed point 1.6e-5 from the FP64 one.
+struct PolicyEval64 {
+  int ox, oy;              // LDS offsets of the east/west and north/south corners
+  double gX, gY, gXY, g0;  // weights of the corners X, Y, XY and of the node itself (SL2)
+  bool out;                // the foot leaves the box: beta w_outside
+};
+template <int SCHEME>
+__device__ __forceinline__ PolicyEval64 policy_prepare64(int LW, float k, float4 cm, const SweepArgs& a, bool lft,
+                                                         bool rgt, bool bot, bool top) {
+  PolicyEval64 p;
+  p.ox = cm.x >= 0.0f ? 1 : -1;
+  p.oy = cm.y >= 0.0f ? LW : -LW;
+  p.out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
+  const double s = (double)k * fabs((double)cm.x), t = (double)k * fabs((double)cm.y);
+  const double b = (double)a.beta;
+  const double cX = s * (1.0 - t), cY = (1.0 - s) * t, cXY = s * t, c0 = (1.0 - s) * (1.0 - t);
+  if (SCHEME == kSL3) {
+    const double g = b / (1.0 - b * c0);
+    p.gX = g * cX;
+    p.gY = g * cY;
+    p.gXY = g * cXY;
+    p.g0 = 0.0;
+  } else {
+    p.gX = b * cX;
+    p.gY = b * cY;
+    p.gXY = b * cXY;
+    p.g0 = b * c0;
+  }
+  return p;
+}
+template <int SCHEME, bool INDEP>
+__device__ __forceinline__ float policy_apply64(const float* __restrict__ T, const PolicyEval64& p, const SweepArgs& a,
+                                                const int16_t* __restrict__ L) {
+  if (p.out) return (float)((double)a.beta * (double)a.w_outside);
+  float wX = T[p.ox], wY = T[p.oy], wXY = T[p.ox + p.oy];
+  if (INDEP) {
+    const int me = L[0];
+    wX = L[p.ox] == me ? wX : a.w_outside;
+    wY = L[p.oy] == me ? wY : a.w_outside;
+    wXY = L[p.ox + p.oy] == me ? wXY : a.w_outside;
+  }
+  double v = __builtin_fma(p.gXY, (double)wXY, __builtin_fma(p.gY, (double)wY, p.gX * (double)wX));
+  if (SCHEME == kSL2) v = __builtin_fma(p.g0, (double)T[0], v);
+  return (float)v;
+}
+
 // First-ring update of one node. T points at the node in the LDS tile. EDGE adds the test for
 // feet that leave the box, which only happens on the outermost nodes.
 template <int SCHEME, bool EDGE, bool INDEP = false>
@@ -204,6 +257,7 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
   const float sy[4] = {1.0f, 1.0f, -1.0f, -1.0f};
   float best2 = -INFINITY;
   float bnum = -1.0f, bden = 1.0f;
+  int bidx = 0;  // the maximiser, whose value is then taken in FP64
   // SL3 denominator 1 - beta (1 - k|a_x|)(1 - k|a_y|) = (1 - beta) + beta k (|a_x|+|a_y|) - beta k^2 |a_x a_y|
   const float omb = 1.0f - a.beta, bk = a.beta * k, bk2 = -(a.beta * k2);
   const float4* __restrict__ ctab = (const float4*)__builtin_assume_aligned(ctrl, 64);
@@ -236,7 +290,10 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
         }
         if (SCHEME == kSL2) {
           if (EDGE) val = out ? a.w_outside - w00 : val;
-          best2 = fmaxf(best2, val);
+          if (val > best2) {
+            best2 = val;
+            bidx = m0 + u;
+          }
         } else {
           float den = __builtin_fmaf(bk2, fabsf(cm.z), __builtin_fmaf(bk, cm.w, omb));
           if (EDGE) {
@@ -247,13 +304,14 @@ __device__ __forceinline__ float ring1_update(const float* __restrict__ T, int L
           if (val * bden > bnum * den) {
             bnum = val;
             bden = den;
+            bidx = m0 + u;
           }
         }
       }
     }
   }
-  if (SCHEME == kSL2) return a.beta * (w00 + best2);
-  return a.beta * bnum / bden;
+  const PolicyEval64 p = policy_prepare64<SCHEME>(LW, k, ctab[bidx], a, lft, rgt, bot, top);
+  return policy_apply64<SCHEME, INDEP>(T, p, a, L);
 }
 
 
@@ -363,58 +421,6 @@ __device__ __forceinline__ void ring1_partial(const float* __restrict__ T, int L
 // same function (policy_apply64), so that a node whose control is still the maximiser gets bit for
 // bit the value a full iteration would give it. (Otherwise the two maps would have fixed points a
 // few ulp apart, and a tolerance near the FP32 resolution could never be met.)
-// The value of a node under one control in FP64 from the FP32 iterate, rounded once to FP32: the
-// bilinear weights of the foot's cell, s(1-t), (1-s)t, st and (1-s)(1-t) with s = k|a_x|,
-// t = k|a_y|, beta and (SL3) the implicit denominator 1 - beta (1-s)(1-t) folded in. The split
-// visits of the first-ring path choose the maximising control in FP32, then take its value from
-// here, in the full iterations and in the policy evaluations alike (the same bits for the same
-// control). Taking the maximum of 64 FP32-rounded candidates biases the value upward by about
-// their rounding error, at every step along a characteristic; recomputing the winner removes that
-// bias, which at 2049^2 had put the FP32 fixed point 1.6e-5 from the FP64 one.
-struct PolicyEval64 {
-  int ox, oy;              // LDS offsets of the east/west and north/south corners
-  double gX, gY, gXY, g0;  // weights of the corners X, Y, XY and of the node itself (SL2)
-  bool out;                // the foot leaves the box: beta w_outside
-};
-template <int SCHEME>
-__device__ __forceinline__ PolicyEval64 policy_prepare64(int LW, float k, float4 cm, const SweepArgs& a, bool lft,
-                                                         bool rgt, bool bot, bool top) {
-  PolicyEval64 p;
-  p.ox = cm.x >= 0.0f ? 1 : -1;
-  p.oy = cm.y >= 0.0f ? LW : -LW;
-  p.out = (lft & (cm.x < 0.0f)) | (rgt & (cm.x > 0.0f)) | (bot & (cm.y < 0.0f)) | (top & (cm.y > 0.0f));
-  const double s = (double)k * fabs((double)cm.x), t = (double)k * fabs((double)cm.y);
-  const double b = (double)a.beta;
-  const double cX = s * (1.0 - t), cY = (1.0 - s) * t, cXY = s * t, c0 = (1.0 - s) * (1.0 - t);
-  if (SCHEME == kSL3) {
-    const double g = b / (1.0 - b * c0);
-    p.gX = g * cX;
-    p.gY = g * cY;
-    p.gXY = g * cXY;
-    p.g0 = 0.0;
-  } else {
-    p.gX = b * cX;
-    p.gY = b * cY;
-    p.gXY = b * cXY;
-    p.g0 = b * c0;
-  }
-  return p;
-}
-template <int SCHEME, bool INDEP>
-__device__ __forceinline__ float policy_apply64(const float* __restrict__ T, const PolicyEval64& p, const SweepArgs& a,
-                                                const int16_t* __restrict__ L) {
-  if (p.out) return (float)((double)a.beta * (double)a.w_outside);
-  float wX = T[p.ox], wY = T[p.oy], wXY = T[p.ox + p.oy];
-  if (INDEP) {
-    const int me = L[0];
-    wX = L[p.ox] == me ? wX : a.w_outside;
-    wY = L[p.oy] == me ? wY : a.w_outside;
-    wXY = L[p.ox + p.oy] == me ? wXY : a.w_outside;
-  }
-  double v = __builtin_fma(p.gXY, (double)wXY, __builtin_fma(p.gY, (double)wY, p.gX * (double)wX));
-  if (SCHEME == kSL2) v = __builtin_fma(p.g0, (double)T[0], v);
-  return (float)v;
-}
 
 template <int DIFF, int SCHEME, bool INDEP, bool TRACK = false, bool GEN = false>
 __device__ __forceinline__ void general_partial(const float* __restrict__ tile, int LW, int node_li, int i, int j,

@@ -452,7 +452,7 @@ def arm_indep(ctx, seed: int, tol: float, patches: int, eps_list=(0.0, 1e-3, 1e-
 
 
 def arm_hdx(ctx, seed: int, tol: float, patches: int) -> dict:
-    """The headline workload with h = dx instead of dx / 1.5 (the survey's choice): drift feet up
+    """The headline workload with h = dx instead of dx / 1.5: drift feet up
     to 1.5 cells away, so the fine solve takes the general kernels; patchy step against the cold
     global Jacobi iteration. The integer labeler takes first-ring feet only, so this step runs
     without labels (the transmission-mode solve does not read them)."""
@@ -603,7 +603,7 @@ def main():
                          "balance (balanced patches on the step's workload), "
                          "learned (U-Net warm start at 1025^2), exit (the paper's exit-to-boundary experiments: "
                          "Table 0 on the GPU and the eps-threshold sweeps of Tables 1 and 2)")
-    ap.add_argument("--arms-out", default=os.path.join(ROOT, "gpurun_out", "bench_arms.json"),
+    ap.add_argument("--arms-out", default=os.path.join(ROOT, "_build", "bench_arms.json"),
                     help="file that receives the full record (every arm); the stdout line holds a summary")
     ap.add_argument("--bumps-n", type=int, default=4097)
     ap.add_argument("--learned-train", type=int, default=192, help="training solves of the learned arm")
@@ -626,8 +626,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the library runs on one device). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

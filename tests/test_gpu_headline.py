@@ -7,7 +7,7 @@ The step stops at a full-sweep change `tol`. With h = dx / 1.5 the a-posteriori 
 beta / (1 - beta) is about 1.5e3, so tol = 1e-6 alone bounds the error only to ~1.5e-3; measured,
 the stopping point is much closer. Two errors remain:
 * the stopping point's distance to the fixed point: 1.2e-5 at tol 1e-6, 9.8e-6 at 5e-7, 2.1e-6
-  at 2e-7 (the north star's 1e-5 from tol 5e-7 on);
+  at 2e-7 (within 1e-5 from tol 5e-7 on);
 * the distance between the fixed point of the FP32 iteration and the exact one: the updates take
   the maximising control in FP32 and its value in FP64 (policy_apply64), which leaves ~2e-6
   (2.2e-6 at tol 1e-7, the global Jacobi iteration likewise). With the FP32 maximum's own value

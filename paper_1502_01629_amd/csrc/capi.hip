@@ -1400,13 +1400,17 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     const int kBatch = tiles <= 1024 ? 8 : 16;
     if (!ctx->tctl) {
       HIP_TRY(ctx, hipMalloc(&ctx->tctl, tilectl_bytes()));
-      HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host, 64, hipHostMallocDefault));
+      HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host, kTileCtlHostBytes, hipHostMallocDefault));
       // grid <= 3 * cus (above)
       HIP_TRY(ctx, hipMalloc(&ctx->tacc, sizeof(unsigned long long) * 2 * 3 * std::max(1, ctx->cus)));
     }
     if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HIP_TRY(ctx, launch_tilectl_init(ctx->tctl, ctx->stream));
     HIP_TRY(ctx, launch_fill_u32((unsigned*)ctx->tacc, 0u, 4 * grid, ctx->stream));
+    // the passes' second array is the staging buffer (tiles * tw * th >= n * n floats) and the
+    // tile words the first `tiles` words of tchange; every tile starts in v
+    unsigned* tile_word = reinterpret_cast<unsigned*>(ctx->tchange);
+    HIP_TRY(ctx, launch_fill_u32(tile_word, 0u, tiles, ctx->stream));
     const bool timing = opts->collect_kernel_time != 0;
     if (timing && !ctx->tev[0])
       for (auto& e : ctx->tev) HIP_TRY(ctx, hipEventCreate(&e));
@@ -1421,7 +1425,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
       hipError_t e = hipSuccess;
       for (int b = 0; b < kBatch && e == hipSuccess; ++b) {
         e = launch_tilectl_pass(a, shape, P.diffusion, P.scheme, P.path, indep, opts->label,
-                                keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, ctx->tchange,
+                                keyed ? ctx->tkey : nullptr, ctx->tlist, tiles_x, tiles_y, ctx->buf, tile_word,
                                 ctx->tflag, max_inner, tol_inner, act, window, (float)tol, b & 1, ctx->tctl, grid,
                                 ev ? ctx->tev[2 * b] : nullptr, ev ? ctx->tev[2 * b + 1] : nullptr,
                                 opts->policy_sweeps, ctx->tacc, s);
@@ -1476,7 +1480,7 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
     } else {
       // Two replays in flight: the host reads the state copied after replay k while replay k + 1
       // runs, so the GPU never waits for the host; a replay after convergence is all no-ops.
-      if (!ctx->tctl_host2) HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host2, 64, hipHostMallocDefault));
+      if (!ctx->tctl_host2) HIP_TRY(ctx, hipHostMalloc(&ctx->tctl_host2, kTileCtlHostBytes, hipHostMallocDefault));
       if (!ctx->tdone[0]) {
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->tdone[0], hipEventDisableTiming));
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->tdone[1], hipEventDisableTiming));
@@ -1497,7 +1501,8 @@ int solve_tiles_impl(slhjb_ctx* ctx, const slhjb_problem* problem, const Prepare
       }
     }
     // the state after everything that ran (a replay in flight included), with the update counts
-    // of the visit workgroups summed into it
+    // of the visit workgroups summed into it; the tiles last written to the second array back in v
+    if (le == hipSuccess) le = launch_tile_gather(v, ctx->buf, tile_word, n, shape, ctx->stream);
     if (le == hipSuccess) le = launch_tilectl_sum(ctx->tacc, grid, ctx->tctl, ctx->stream);
     if (le == hipSuccess)
       le = hipMemcpyAsync(ctx->tctl_host, ctx->tctl, tilectl_bytes(), hipMemcpyDeviceToHost, ctx->stream);

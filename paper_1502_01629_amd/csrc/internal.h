@@ -121,17 +121,23 @@ hipError_t launch_coop_state_init(void* state, hipStream_t s);
 // `tchange` of the tile-solver launches holds 2 * tiles words: the move of each staged slot
 // (float, negative when its visit stopped unsettled), then the neighbour sides it flags (uint32,
 // bit (dy + 1) * 3 + dx + 1 for the neighbour at tile offset (dx, dy)).
-// Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes(). Layout of
-// the words the host reads: [9] done, [10] passes, [11] check sweeps, [7] resid bits, [12..13] updates,
-// [14..15] policy-evaluation updates. `pe`: policy-evaluation iterations after each full one
-// (split tile shapes only). The cooperative state: [6..7] updates, [8..9] policy updates.
+// Device-driven passes (graph-capturable): `ctl` is device memory of tilectl_bytes() (at most
+// kTileCtlHostBytes, the size of the host copies). Layout of the words the host reads: [9] done,
+// [10] passes, [11] check sweeps, [7] resid bits, [12..13] updates, [14..15] policy-evaluation
+// updates. `pe`: policy-evaluation iterations after each full one (split tile shapes only). The
+// cooperative state: [6..7] updates, [8..9] policy updates.
+// The passes keep the iterate in two arrays: a.w_in and w2 (n * n floats each), with one word per
+// tile (tile_word, zeroed by the caller before the first pass) naming the array that holds the
+// tile's current values; launch_tile_gather copies the tiles held in w2 back to w_in afterwards.
+constexpr size_t kTileCtlHostBytes = 128;
 size_t tilectl_bytes();
 hipError_t launch_tilectl_init(void* ctl, hipStream_t s);
 hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
-                               float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
-                               float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
+                               float* w2, unsigned* tile_word, uint8_t* flag, int max_inner, float tol_inner,
+                               float act, float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
                                hipEvent_t ev_after, int pe, unsigned long long* wg_acc, hipStream_t s);
+hipError_t launch_tile_gather(float* w, const float* w2, const unsigned* tile_word, int n, int shape, hipStream_t s);
 // `wg_acc`: 2 * grid counters (node updates, policy-evaluation updates per visit workgroup), zeroed
 // by the caller before the first pass; launch_tilectl_sum writes their totals to the pass state.
 hipError_t launch_tilectl_sum(const unsigned long long* wg_acc, int groups, void* ctl, hipStream_t s);

@@ -4,11 +4,13 @@
 // The grid is cut into tiles (32 x 16, 16 x 16 or 8 x 8 nodes). A pass takes a list of tiles; each workgroup stages
 // its tile and an interpolation halo in LDS and runs Jacobi iterations of the scheme on the
 // tile's FREE nodes, with the halo frozen, until no node moves by more than tol_inner (or
-// max_inner iterations). Results go to a staging buffer, so every tile of a pass reads the
-// iterate of the previous pass and the outcome does not depend on scheduling. A commit kernel
-// writes the staged tiles back and flags, for the next pass, each of the 8 neighbours whose halo
-// holds a node that moved by more than the activation threshold (the tile's strip of the
-// dependence radius on that side), and the tile itself when its visit stopped unsettled. The next pass takes the flagged tiles; with keys
+// max_inner iterations). Every tile of a pass reads the iterate as it was before the pass, so the
+// outcome does not depend on scheduling. The host-driven passes keep the iterate in two arrays:
+// a visit writes its tile into the array that does not hold the tile's current values and
+// flags, for the next pass, each of the 8 neighbours whose halo holds a node that moved by more
+// than the activation threshold (the tile's strip of the dependence radius on that side), and the
+// tile itself when its visit stopped unsettled. The cooperative and batched drivers stage the
+// results instead and write them back, and flag, in a commit step. The next pass takes the flagged tiles; with keys
 // (the arrival time of u_hat, min over the tile) only a band of them: those whose key is within
 // a window of the smallest flagged key. That is the order "by increasing u_hat" of the paper at
 // tile granularity, bucketed so that a whole ring of tiles runs at once, and it keeps tiles
@@ -43,7 +45,41 @@ __device__ __forceinline__ int dependence_radius(const SweepArgs& a) {
   return PATH == 1 ? 1 : a.halo;
 }
 
-template <int T, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
+// Direct write-back (host-driven passes). The iterate lives in two n x n arrays; word[t] holds
+// (p << 1) | a, where a names the array with tile t's current values and p the pass that wrote
+// them there. A visit in pass `seq` reads every node from the array that held it before the pass:
+// a word already stamped with `seq` belongs to a tile written in this pass, whose earlier values
+// are in the other array, which no visit of the pass writes. It then writes its own tile to the
+// array its word does not name and stamps the word. Words start at 0 and passes count from 1.
+struct TileDirect {
+  float* wa;       // the caller's iterate
+  float* wb;       // the second array, same layout
+  unsigned* word;  // [tiles]
+  int tiles_y;
+};
+
+__device__ __forceinline__ float direct_load(const TileDirect& D, size_t idx, int tile, unsigned seq) {
+  // the three loads are independent: the word decides which value is kept
+  const unsigned wd = D.word[tile];
+  const float va = D.wa[idx], vb = D.wb[idx];
+  const unsigned arr = (wd >> 1) == seq ? (wd & 1u) ^ 1u : (wd & 1u);
+  return arr ? vb : va;
+}
+
+// Flag the neighbours of tile tid named in `sides` (bit (dy + 1) * 3 + dx + 1 for offset (dx, dy))
+// and, if `self`, the tile itself.
+__device__ __forceinline__ void flag_around(int tid, int tiles_x, int tiles_y, unsigned sides, bool self,
+                                            uint8_t* __restrict__ flag) {
+  const int tx = tid % tiles_x, ty = tid / tiles_x;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int nx = tx + dx, ny = ty + dy;
+      const bool take = (dx | dy) == 0 ? self : ((sides >> ((dy + 1) * 3 + dx + 1)) & 1u) != 0u;
+      if (take && nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) flag[ny * tiles_x + nx] = 1;
+    }
+}
+
+template <int T, int S, int DIFF, int SCHEME, int PATH, bool INDEP, bool DIRECT>
 __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float* __restrict__ w,
                                                  const float* __restrict__ speed, const uint8_t* __restrict__ cls,
                                                  const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
@@ -51,7 +87,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
                                                  float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                                  float tol_inner, float act, unsigned* __restrict__ tsides,
                                                  unsigned long long& acc, float* lds, float* red, int pe,
-                                                 unsigned long long& pe_acc) {
+                                                 unsigned long long& pe_acc, const TileDirect& D, unsigned seq,
+                                                 float& tmax) {
   constexpr int TT = T * T, NT = TT * S;
   __shared__ unsigned sides_red[NT / 64];
   static_assert(TT % 64 == 0 && (S == 2 || S == 4), "split tile shape");
@@ -70,12 +107,18 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   const int node = threadIdx.x % TT, part = __builtin_amdgcn_readfirstlane(threadIdx.x / TT);
   const int tx = tid % tiles_x, ty = tid / tiles_x;
   const int x0 = tx * T, y0 = ty * T;
-  if (threadIdx.x == 0) flag[tid] = 0;
+  // direct write-back: the array holding this tile's values (its word is not stamped with this pass)
+  const unsigned own = DIRECT ? (D.word[tid] & 1u) : 0u;
+  if (!DIRECT && threadIdx.x == 0) flag[tid] = 0;  // direct: the selection cleared it
   for (int e = threadIdx.x; e < span; e += NT) {
     const int ly = e / LW, lx = e - ly * LW;
     const int gx = x0 - R + lx, gy = y0 - R + ly;
     const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
-    const float val = in ? w[(size_t)gy * n + gx] : 0.0f;
+    float val = 0.0f;
+    if (in) {
+      if (DIRECT) val = direct_load(D, (size_t)gy * n + gx, (gy / T) * tiles_x + gx / T, seq);
+      else val = w[(size_t)gy * n + gx];
+    }
     bufA[e] = val;
     bufB[e] = val;
     if (INDEP) labs[e] = in ? label[(size_t)gy * n + gx] : (int16_t)-32768;
@@ -89,7 +132,6 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   constexpr bool GEN = PATH == 2;
   if (gi < n && gj < n) {
     const size_t idx = (size_t)gj * n + gi;
-    w0 = w[idx];
     fr = cls[idx] == kFree;
     if (fr) kk = a.r * (speed ? speed[idx] : a.speed_const);
     if (GEN && fr) {
@@ -108,6 +150,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   const int slice = a.n_controls / S;  // the padded list length is a multiple of 4
   constexpr int QP = 4 / S;            // quadrants per part on the first-ring path
   __syncthreads();
+  if (gi < n && gj < n) w0 = bufA[li];  // the staged value
   float* cur = bufA;
   float* nxt = bufB;
   int it = 0, evals = 0;
@@ -216,7 +259,11 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   float moved = 0.0f;
   unsigned sides = 0u;
   if (part == 0) {
-    outbuf[(size_t)slot * TT + node] = cur[li];
+    if (DIRECT) {
+      if (gi < n && gj < n) (own ? D.wa : D.wb)[(size_t)gj * n + gi] = cur[li];
+    } else {
+      outbuf[(size_t)slot * TT + node] = cur[li];
+    }
     if (fr) moved = fabsf(cur[li] - w0);
     if (moved > act) sides = near_sides(lx, ly, T, T, dependence_radius<PATH>(a));
   }
@@ -238,8 +285,16 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
     // a visit that stopped at max_inner while still moving is marked by a negative sign; after a
     // single iteration (the check sweeps) that is a move beyond the activation threshold
     const bool unsettled = it >= max_inner && (max_inner > 1 || m > act);
-    tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
-    tsides[slot] = sd;
+    if (DIRECT) {
+      // what the commit step does with the staged move and sides
+      const float mm = unsettled ? fmaxf(m, 1e-30f) : m;
+      tmax = fmaxf(tmax, mm);
+      if (mm > act) flag_around(tid, tiles_x, D.tiles_y, sd, unsettled, flag);
+      D.word[tid] = (seq << 1) | (own ^ 1u);
+    } else {
+      tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
+      tsides[slot] = sd;
+    }
     acc += (unsigned long long)(it - evals) * (unsigned long long)free_total;
     pe_acc += (unsigned long long)evals * (unsigned long long)free_total;
   }
@@ -248,7 +303,7 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
 
 // One visit of tile `tid`, staged into slot `slot` of outbuf/tchange: Jacobi iterations in LDS
 // against the frozen halo until no node moves by more than tol_inner (or max_inner).
-template <int TW, int TH, int S, int DIFF, int SCHEME, int PATH, bool INDEP>
+template <int TW, int TH, int S, int DIFF, int SCHEME, int PATH, bool INDEP, bool DIRECT = false>
 __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __restrict__ w,
                                            const float* __restrict__ speed, const uint8_t* __restrict__ cls,
                                            const float4* __restrict__ ctrl, const int16_t* __restrict__ label,
@@ -256,12 +311,15 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
                                            float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
                                            float tol_inner, float act, unsigned* __restrict__ tsides,
                                            unsigned long long& acc, float* lds, float* red, int pe,
-                                           unsigned long long& pe_acc) {
+                                           unsigned long long& pe_acc, const TileDirect& D = TileDirect{},
+                                           unsigned seq = 0u, float* tmax = nullptr) {
+  float tmax_unused = 0.0f;
+  float& tm = tmax ? *tmax : tmax_unused;
   if constexpr (S > 1) {
     static_assert(TW == TH, "split tiles are square");
-    visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x, outbuf,
-                                                       tchange, flag, max_inner, tol_inner, act, tsides, acc, lds, red,
-                                                       pe, pe_acc);
+    visit_tile_split<TW, S, DIFF, SCHEME, PATH, INDEP, DIRECT>(a, w, speed, cls, ctrl, label, slot, tid, tiles_x,
+                                                               outbuf, tchange, flag, max_inner, tol_inner, act,
+                                                               tsides, acc, lds, red, pe, pe_acc, D, seq, tm);
     return;
   } else {
   (void)pe;
@@ -279,12 +337,17 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
   {
     const int tx = tid % tiles_x, ty = tid / tiles_x;
     const int x0 = tx * kTW, y0 = ty * kTH;
-    if (threadIdx.x == 0) flag[tid] = 0;
+    const unsigned own = DIRECT ? (D.word[tid] & 1u) : 0u;
+    if (!DIRECT && threadIdx.x == 0) flag[tid] = 0;
     for (int e = threadIdx.x; e < span; e += kThreads) {
       const int ly = e / LW, lx = e - ly * LW;
       const int gx = x0 - R + lx, gy = y0 - R + ly;
       const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
-      const float val = in ? w[(size_t)gy * n + gx] : 0.0f;
+      float val = 0.0f;
+      if (in) {
+        if (DIRECT) val = direct_load(D, (size_t)gy * n + gx, (gy / kTH) * tiles_x + gx / kTW, seq);
+        else val = w[(size_t)gy * n + gx];
+      }
       bufA[e] = val;
       bufB[e] = val;
       if (INDEP) labs[e] = in ? label[(size_t)gy * n + gx] : (int16_t)-32768;
@@ -307,7 +370,6 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       dn[r] = 0.0f;
       if (gi[r] < n && gj[r] < n) {
         const size_t idx = (size_t)gj[r] * n + gi[r];
-        w0[r] = w[idx];
         fr[r] = cls[idx] == kFree;
         if (fr[r]) kk[r] = a.r * (speed ? speed[idx] : a.speed_const);
         if (PATH == 2 && fr[r]) {
@@ -317,6 +379,9 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       }
     }
     __syncthreads();  // tile staged
+#pragma unroll
+    for (int r = 0; r < NPT; ++r)
+      if (gi[r] < n && gj[r] < n) w0[r] = bufA[li[r]];
     float* cur = bufA;
     float* nxt = bufB;
     int it = 0;
@@ -361,7 +426,11 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
     for (int r = 0; r < NPT; ++r) {
       const int q = threadIdx.x + r * kThreads;
       const float v = cur[li[r]];
-      outbuf[(size_t)slot * kTN + q] = v;
+      if (DIRECT) {
+        if (gi[r] < n && gj[r] < n) (own ? D.wa : D.wb)[(size_t)gj[r] * n + gi[r]] = v;
+      } else {
+        outbuf[(size_t)slot * kTN + q] = v;
+      }
       const float mv = fr[r] ? fabsf(v - w0[r]) : 0.0f;
       moved = fmaxf(moved, mv);
       if (mv > act) sides |= near_sides(q & (kTW - 1), q / kTW, kTW, kTH, dependence_radius<PATH>(a));
@@ -387,8 +456,15 @@ __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __re
       // a visit that stopped at max_inner while still moving is marked by a negative sign; after a
       // single iteration (the check sweeps) that is a move beyond the activation threshold
       const bool unsettled = it >= max_inner && (max_inner > 1 || m > act);
-      tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
-      tsides[slot] = sd;
+      if (DIRECT) {
+        const float mm = unsettled ? fmaxf(m, 1e-30f) : m;
+        tm = fmaxf(tm, mm);
+        if (mm > act) flag_around(tid, tiles_x, D.tiles_y, sd, unsettled, flag);
+        D.word[tid] = (seq << 1) | (own ^ 1u);
+      } else {
+        tchange[slot] = unsettled ? -fmaxf(m, 1e-30f) : m;
+        tsides[slot] = sd;
+      }
       acc += (unsigned long long)it * (unsigned long long)free_total;
     }
     __syncthreads();
@@ -416,14 +492,7 @@ __device__ __forceinline__ void commit_tile(int slot, int tid, int tw, int th, i
   if (threadIdx.x == 0) {
     const float m = fabsf(tc);
     tmax = fmaxf(tmax, m);
-    if (m > act) {
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int nx = tx + dx, ny = ty + dy;
-          const bool take = (dx | dy) == 0 ? tc < 0.0f : ((sides >> ((dy + 1) * 3 + dx + 1)) & 1u) != 0u;
-          if (take && nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) flag[ny * tiles_x + nx] = 1;
-        }
-    }
+    if (m > act) flag_around(tid, tiles_x, tiles_y, sides, tc < 0.0f, flag);
   }
 }
 
@@ -723,22 +792,32 @@ hipError_t launch_coop_state_init(void* state, hipStream_t s) {
 
 
 // ---- device-driven passes for graph capture ---------------------------------------------------
-// A pass is three launches with fixed arguments (parity q alternates between passes), so a batch
-// of passes can be captured once into a graph and replayed: select -> visit -> commit. The band
-// bound, the "nothing selected" jump, the check sweep when nothing is flagged and the final
-// decision all happen on the device; the host only reads `done` between replays.
+// A pass is two launches with fixed arguments (parity q alternates between passes), so a batch
+// of passes can be captured once into a graph and replayed: select -> visit. The visits write
+// their tiles directly (TileDirect) and flag the next pass's tiles themselves. The band bound, the
+// "nothing selected" jump, the check sweep when nothing is flagged and the final decision all
+// happen on the device; the host only reads `done` between replays.
+//
+// Who writes which word, so that no launch reads a word another workgroup of it writes:
+//   select p: done and resid (when pass p - 1 was a check sweep that met tol), seq (+1), its own
+//             count/nflag/kmin[q] (accumulated), the flags of the tiles it takes (cleared);
+//   visit p:  count/nflag/kmin/racc[q ^ 1] (reset for pass p + 1), passes, checks, checked,
+//             bound (band move), racc[q] (check sweep: one atomic max per workgroup).
 struct TileCtl {
   unsigned count[2];   // selected tiles of the pass with parity q
   unsigned nflag[2];   // flagged tiles seen by that selection
   unsigned kmin[2];    // bits of their smallest key
   unsigned bound;      // bits of the band bound B (-inf at start)
-  unsigned resid;      // bits of the residual of the last check sweep
-  unsigned checked;    // 1 after a check sweep, until the next selection reads it
+  unsigned resid;      // bits of the residual of the check sweep that ended the solve
+  unsigned checked;    // 1 if the last pass was a check sweep
   unsigned done;       // 1 once a check sweep met tol
   unsigned passes;     // passes that did work (check sweeps included)
   unsigned checks;     // check sweeps among them
   unsigned long long updates;
   unsigned long long pe_updates;  // policy-evaluation node updates
+  unsigned seq;        // number of the current pass (from 1), stamped into the tile words
+  unsigned racc[2];    // bits of the largest move of a check sweep with parity q
+  unsigned pad;
 };
 
 __global__ void tilectl_init_kernel(TileCtl* c) {
@@ -753,73 +832,90 @@ __global__ void tilectl_init_kernel(TileCtl* c) {
   c->checks = 0u;
   c->updates = 0ull;
   c->pe_updates = 0ull;
+  c->seq = 0u;
+  c->racc[0] = c->racc[1] = 0u;
+  c->pad = 0u;
 }
 
-// The outcome of the last check sweep (checked, resid) is written by the visit and commit
-// launches only, so every thread of this launch reads the same values and a workgroup takes one
-// branch as a whole.
-__global__ __launch_bounds__(kSelectThreads) void tilectl_select_kernel(const uint8_t* __restrict__ flag,
+// The outcome of the last pass (checked, racc) is written by the visit launches only, so every
+// thread of this launch reads the same values and a workgroup takes one branch as a whole.
+__global__ __launch_bounds__(kSelectThreads) void tilectl_select_kernel(uint8_t* __restrict__ flag,
                                                                         const float* __restrict__ key, int tiles,
                                                                         float tol, int q, int* __restrict__ list,
                                                                         TileCtl* __restrict__ c) {
   // the tile's flag and key do not depend on the pass words: all their loads go out together
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int tt = t < tiles ? t : tiles - 1;
-  unsigned done = c->done, checked = c->checked, resid = c->resid, bound = c->bound;
+  unsigned done = c->done, checked = c->checked, resid = c->racc[q ^ 1], bound = c->bound;
   unsigned fb = flag[tt];
   float kt = key ? key[tt] : INFINITY;
   SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(checked), "+s"(resid), "+s"(bound), "+v"(fb), "+v"(kt));
   if (done) return;
   if (checked && __uint_as_float(resid) <= tol) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->done = 1u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c->resid = resid;
+      c->done = 1u;
+    }
     return;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->seq += 1u;
   const bool fl = t < tiles && fb != 0u;
   const float B = key ? __uint_as_float(bound) : INFINITY;
   const float k = fl ? kt : INFINITY;
   const bool on = fl && (!key || k <= B);
   block_select(t, fl, on, k, key != nullptr, &c->count[q], &c->nflag[q], &c->kmin[q], list);
+  if (on) flag[t] = 0;  // the visit may flag it again
 }
 
 template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP,
           int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
 __global__ __launch_bounds__(NT) void tilectl_visit_kernel(
-    SweepArgs a, const float* __restrict__ w, const float* __restrict__ speed, const uint8_t* __restrict__ cls,
-    const float4* __restrict__ ctrl, const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x,
-    int tiles, float* __restrict__ outbuf, float* __restrict__ tchange, uint8_t* __restrict__ flag, int max_inner,
-    float tol_inner, float act, float window, int q, TileCtl* __restrict__ c, int pe,
-    unsigned long long* __restrict__ wg_acc) {
-  unsigned* tsides = reinterpret_cast<unsigned*>(tchange + tiles);
+    SweepArgs a, const float* __restrict__ speed, const uint8_t* __restrict__ cls, const float4* __restrict__ ctrl,
+    const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x, int tiles, TileDirect D,
+    uint8_t* __restrict__ flag, int max_inner, float tol_inner, float act, float window, int q,
+    TileCtl* __restrict__ c, int pe, unsigned long long* __restrict__ wg_acc) {
   // The first slot's tile is read with the pass words, so that the loads overlap: the grid has at
   // most `tiles` workgroups and the list `tiles` entries, and the value is used only if the slot
   // is taken.
   // The workgroup's update counters (wg_acc[2 b], wg_acc[2 b + 1], touched only by workgroup b of
   // each launch) are read here too and written once at the end.
-  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
+  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q], seq = c->seq;
   int first = list[blockIdx.x];
   unsigned long long acc0 = wg_acc[2 * blockIdx.x], pe_acc0 = wg_acc[2 * blockIdx.x + 1];
-  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first), "+s"(acc0), "+s"(pe_acc0));
+  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(seq), "+s"(first), "+s"(acc0), "+s"(pe_acc0));
   if (done) return;
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
   unsigned long long acc = 0ull, pe_acc = 0ull;
+  float tmax = 0.0f;  // thread 0: largest move of this workgroup's tiles (the check sweep's residual)
   const int cnt = (int)ucnt;
   const int nf = (int)unf;
+  const bool check = cnt == 0 && nf == 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the other parity's words serve the next pass; the previous pass's launches have read them
+    c->count[q ^ 1] = 0u;
+    c->nflag[q ^ 1] = 0u;
+    c->kmin[q ^ 1] = 0x7f800000u;
+    c->racc[q ^ 1] = 0u;
+    if (cnt > 0 || check) c->passes += 1u;
+    if (check) c->checks += 1u;
+    c->checked = check ? 1u : 0u;
+  }
   if (cnt > 0) {
     for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x)
-      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, slot,
-                                                    slot == (int)blockIdx.x ? first : list[slot], tiles_x, outbuf,
-                                                    tchange, flag, max_inner, tol_inner, act, tsides, acc, lds, red,
-                                                    pe, pe_acc);
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP, true>(
+          a, nullptr, speed, cls, ctrl, label, slot, slot == (int)blockIdx.x ? first : list[slot], tiles_x, nullptr,
+          nullptr, flag, max_inner, tol_inner, act, nullptr, acc, lds, red, pe, pe_acc, D, seq, &tmax);
   } else if (nf > 0) {
     // flagged tiles exist but none is in the band: move the band up to the smallest flagged key
     if (blockIdx.x == 0 && threadIdx.x == 0) c->bound = __float_as_uint(__uint_as_float(c->kmin[q]) + window);
   } else {
-    // nothing flagged: check sweep, one Jacobi iteration of every tile; its commit raises resid
-    if (blockIdx.x == 0 && threadIdx.x == 0) c->resid = 0u;
+    // nothing flagged: check sweep, one Jacobi iteration of every tile
     for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP>(a, w, speed, cls, ctrl, label, t, t, tiles_x, outbuf, tchange,
-                                                    flag, 1, 0.0f, act, tsides, acc, lds, red, 0, pe_acc);
+      visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, INDEP, true>(a, nullptr, speed, cls, ctrl, label, t, t, tiles_x,
+                                                               nullptr, nullptr, flag, 1, 0.0f, act, nullptr, acc, lds,
+                                                               red, 0, pe_acc, D, seq, &tmax);
+    if (threadIdx.x == 0 && tmax > 0.0f) atomicMax(&c->racc[q], __float_as_uint(tmax));  // one per workgroup
   }
   if (threadIdx.x == 0 && (acc | pe_acc) != 0ull) {
     wg_acc[2 * blockIdx.x] = acc0 + acc;
@@ -852,52 +948,10 @@ __global__ __launch_bounds__(256) void tilectl_sum_kernel(const unsigned long lo
   }
 }
 
-__global__ __launch_bounds__(kThreads) void tilectl_commit_kernel(const int* __restrict__ list, int tw, int th,
-                                                                  int tiles_x, int tiles_y, int n,
-                                                                  const float* __restrict__ outbuf,
-                                                                  const float* __restrict__ tchange, float act,
-                                                                  const uint8_t* __restrict__ cls,
-                                                                  float* __restrict__ w, uint8_t* __restrict__ flag,
-                                                                  int q, TileCtl* __restrict__ c) {
-  const int tiles = tiles_x * tiles_y;
-  const unsigned* tsides = reinterpret_cast<const unsigned*>(tchange + tiles);
-  // the first slot's tile, move and sides are read with the pass words, as in the visit launch
-  unsigned done = c->done, ucnt = c->count[q], unf = c->nflag[q];
-  int first = list[blockIdx.x];
-  float first_tc = tchange[blockIdx.x];
-  unsigned first_sides = tsides[blockIdx.x];
-  SLHJB_ISSUE_TOGETHER("+s"(done), "+s"(ucnt), "+s"(unf), "+s"(first), "+s"(first_tc), "+s"(first_sides));
-  if (done) return;
-  const int cnt = (int)ucnt;
-  const int nf = (int)unf;
-  if (cnt > 0) {
-    float unused = 0.0f;
-    for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
-      const bool pre = slot == (int)blockIdx.x;
-      commit_tile(slot, pre ? first : list[slot], tw, th, tiles_x, tiles_y, n, outbuf, pre ? first_tc : tchange[slot],
-                  pre ? first_sides : tsides[slot], act, cls, w, flag, unused);
-    }
-  } else if (nf == 0) {
-    float tmax = 0.0f;  // largest move of this workgroup's tiles (thread 0)
-    for (int t = blockIdx.x; t < tiles; t += gridDim.x)
-      commit_tile(t, t, tw, th, tiles_x, tiles_y, n, outbuf, tchange[t], tsides[t], act, cls, w, flag, tmax);
-    if (threadIdx.x == 0 && tmax > 0.0f) atomicMax(&c->resid, __float_as_uint(tmax));  // one per workgroup
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (cnt > 0 || nf == 0) c->passes += 1u;
-    if (cnt == 0 && nf == 0) c->checks += 1u;
-    c->checked = (cnt == 0 && nf == 0) ? 1u : 0u;
-    // the other parity's counters serve the next pass; they were last read by the previous pass
-    c->count[q ^ 1] = 0u;
-    c->nflag[q ^ 1] = 0u;
-    c->kmin[q ^ 1] = 0x7f800000u;
-  }
-}
-
 static_assert(offsetof(TileCtl, resid) == 7 * 4 && offsetof(TileCtl, done) == 9 * 4 &&
                   offsetof(TileCtl, passes) == 10 * 4 && offsetof(TileCtl, checks) == 11 * 4 &&
                   offsetof(TileCtl, checked) == 8 * 4 && offsetof(TileCtl, updates) == 12 * 4 &&
-                  offsetof(TileCtl, pe_updates) == 14 * 4 && sizeof(TileCtl) <= 64,
+                  offsetof(TileCtl, pe_updates) == 14 * 4 && sizeof(TileCtl) <= kTileCtlHostBytes,
               "host reads these words");
 size_t tilectl_bytes() { return sizeof(TileCtl); }
 
@@ -914,10 +968,9 @@ hipError_t launch_tilectl_init(void* ctl, hipStream_t s) {
 template <int TW, int TH, int SPL>
 static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int scheme, int path, bool indep,
                                       const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
-                                      float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,
-                                      float act, float window, float tol, int q, TileCtl* c, int grid,
-                                      hipEvent_t ev_before, hipEvent_t ev_after, int pe,
-                                      unsigned long long* wg_acc, hipStream_t s) {
+                                      const TileDirect& D, uint8_t* flag, int max_inner, float tol_inner, float act,
+                                      float window, float tol, int q, TileCtl* c, int grid, hipEvent_t ev_before,
+                                      hipEvent_t ev_after, int pe, unsigned long long* wg_acc, hipStream_t s) {
   const int tiles = tiles_x * tiles_y;
   tilectl_select_kernel<<<(tiles + kSelectThreads - 1) / kSelectThreads, kSelectThreads, 0, s>>>(flag, key, tiles,
                                                                                              tol, q, list, c);
@@ -925,27 +978,27 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
   const size_t lds = tile_pass_lds_bytes(sh, a.halo, indep);
   // With events the visit goes through hipExtLaunchKernel, which stamps them at the kernel's own
   // start and end (as a profiler measures it), not around the launch on the stream.
-#define SLHJB_TV(D, S, PA, IN)                                                                                   \
+#define SLHJB_TV(D_, S, PA, IN)                                                                                  \
   do {                                                                                                           \
     if (ev_before)                                                                                               \
-      hipExtLaunchKernelGGL((tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN>), dim3(grid), dim3(sh.threads),     \
-                            (std::uint32_t)lds, s, ev_before, ev_after, 0u, a, a.w_in, a.speed, a.cls, a.ctrl,   \
-                            label, (const int*)list, tiles_x, tiles, outbuf, tchange, flag, max_inner, tol_inner, \
-                            act, window, q, c, pe, wg_acc);                                                               \
+      hipExtLaunchKernelGGL((tilectl_visit_kernel<TW, TH, SPL, D_, S, PA, IN>), dim3(grid), dim3(sh.threads),    \
+                            (std::uint32_t)lds, s, ev_before, ev_after, 0u, a, a.speed, a.cls, a.ctrl, label,    \
+                            (const int*)list, tiles_x, tiles, D, flag, max_inner, tol_inner, act, window, q, c,  \
+                            pe, wg_acc);                                                                         \
     else                                                                                                         \
-      tilectl_visit_kernel<TW, TH, SPL, D, S, PA, IN><<<grid, sh.threads, lds, s>>>(                             \
-          a, a.w_in, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, outbuf, tchange, flag, max_inner,      \
-          tol_inner, act, window, q, c, pe, wg_acc);                                                                      \
+      tilectl_visit_kernel<TW, TH, SPL, D_, S, PA, IN><<<grid, sh.threads, lds, s>>>(                            \
+          a, a.speed, a.cls, a.ctrl, label, list, tiles_x, tiles, D, flag, max_inner, tol_inner, act, window, q, \
+          c, pe, wg_acc);                                                                                        \
   } while (0)
-#define SLHJB_TV_S(D, PA, IN)                      \
-  do {                                             \
-    if (scheme == kSL2) SLHJB_TV(D, kSL2, PA, IN); \
-    else SLHJB_TV(D, kSL3, PA, IN);                \
+#define SLHJB_TV_S(D_, PA, IN)                      \
+  do {                                              \
+    if (scheme == kSL2) SLHJB_TV(D_, kSL2, PA, IN); \
+    else SLHJB_TV(D_, kSL3, PA, IN);                \
   } while (0)
-#define SLHJB_TV_I(D, PA)               \
-  do {                                  \
-    if (indep) SLHJB_TV_S(D, PA, true); \
-    else SLHJB_TV_S(D, PA, false);      \
+#define SLHJB_TV_I(D_, PA)               \
+  do {                                   \
+    if (indep) SLHJB_TV_S(D_, PA, true); \
+    else SLHJB_TV_S(D_, PA, false);      \
   } while (0)
   if (path == 1) SLHJB_TV_I(kDiffNone, 1);
   else if (path == 2) {
@@ -959,24 +1012,43 @@ static void launch_tilectl_pass_shape(const SweepArgs& a, int diffusion, int sch
 #undef SLHJB_TV_I
 #undef SLHJB_TV_S
 #undef SLHJB_TV
-  tilectl_commit_kernel<<<grid, kThreads, 0, s>>>(list, TW, TH, tiles_x, tiles_y, a.n, outbuf, tchange, act, a.cls,
-                                                  const_cast<float*>(a.w_in), flag, q, c);
 }
 
 hipError_t launch_tilectl_pass(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
-                               float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner, float act,
-                               float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
+                               float* w2, unsigned* tile_word, uint8_t* flag, int max_inner, float tol_inner,
+                               float act, float window, float tol, int q, void* ctl, int grid, hipEvent_t ev_before,
                                hipEvent_t ev_after, int pe, unsigned long long* wg_acc, hipStream_t s) {
-  // the visit and commit launches read list[blockIdx.x] and tchange[blockIdx.x] unconditionally
+  // the visit launch reads list[blockIdx.x] unconditionally
   if (grid < 1 || grid > tiles_x * tiles_y) return hipErrorInvalidValue;
+  const TileDirect D{const_cast<float*>(a.w_in), w2, tile_word, tiles_y};
 #define SLHJB_CTL_CALL(TW, TH, SPL)                                                                                  \
-  launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y,      \
-                                         outbuf, tchange, flag, max_inner, tol_inner, act, window, tol, q,           \
-                                         (TileCtl*)ctl, grid, ev_before, ev_after, pe, wg_acc, s);                   \
+  launch_tilectl_pass_shape<TW, TH, SPL>(a, diffusion, scheme, path, indep, label, key, list, tiles_x, tiles_y, D,   \
+                                         flag, max_inner, tol_inner, act, window, tol, q, (TileCtl*)ctl, grid,       \
+                                         ev_before, ev_after, pe, wg_acc, s);                                        \
   break
   SLHJB_FOR_SHAPE(shape, SLHJB_CTL_CALL)
 #undef SLHJB_CTL_CALL
+  return hipGetLastError();
+}
+
+// After the passes: the tiles whose current values are in the second array are copied back.
+__global__ __launch_bounds__(kThreads) void tile_gather_kernel(float* __restrict__ w, const float* __restrict__ w2,
+                                                               const unsigned* __restrict__ tile_word, int n, int tw,
+                                                               int th, int tiles_x) {
+  const int64_t N = (int64_t)n * n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (int64_t)gridDim.x * kThreads) {
+    const int gy = (int)(i / n), gx = (int)(i - (int64_t)gy * n);
+    if (tile_word[(gy / th) * tiles_x + gx / tw] & 1u) w[i] = w2[i];
+  }
+}
+
+hipError_t launch_tile_gather(float* w, const float* w2, const unsigned* tile_word, int n, int shape, hipStream_t s) {
+  const TileShape sh = tile_shape_of(shape);
+  const int64_t N = (int64_t)n * n;
+  const int blocks = (int)std::min<int64_t>((N + kThreads - 1) / kThreads, 4096);
+  tile_gather_kernel<<<std::max(blocks, 1), kThreads, 0, s>>>(w, w2, tile_word, n, sh.tw, sh.th,
+                                                              (n + sh.tw - 1) / sh.tw);
   return hipGetLastError();
 }
 

@@ -423,17 +423,15 @@ __global__ __launch_bounds__(256) void label_visit_kernel(uint32_t* __restrict__
       if ((threadIdx.x & 63) == 0 && sides) atomicOr(&osides, sides);
       __syncthreads();  // uniform: `ever` is a block-wide OR
     }
-    if (threadIdx.x == 0 && ever) {
-      if (omask) atomicOr(&wmask[tid], omask);
-      // neighbours read this tile as their halo; the tile itself continues if it did not settle
+    if (threadIdx.x < 9 && ever) {
+      if (threadIdx.x == 0 && omask) atomicOr(&wmask[tid], omask);
+      // neighbours read this tile as their halo; the tile itself continues if it did not settle.
+      // Lane b = (dy + 1) * 3 + dx + 1 flags the tile at offset (dx, dy): nine stores at once.
       const unsigned sd = osides;
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int nx = tx + dx, ny = ty + dy;
-          if (nx < 0 || ny < 0 || nx >= tiles_x || ny >= tiles_y) continue;
-          const bool take = (dx | dy) == 0 ? !converged_here : ((sd >> ((dy + 1) * 3 + dx + 1)) & 1u) != 0u;
-          if (take) flag[ny * tiles_x + nx] = 1;
-        }
+      const int b = threadIdx.x, dx = b % 3 - 1, dy = b / 3 - 1;
+      const int nx = tx + dx, ny = ty + dy;
+      const bool take = b == 4 ? !converged_here : ((sd >> b) & 1u) != 0u;
+      if (take && nx >= 0 && ny >= 0 && nx < tiles_x && ny < tiles_y) flag[ny * tiles_x + nx] = 1;
     }
     __syncthreads();
   }

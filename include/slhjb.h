@@ -208,8 +208,9 @@ typedef struct {
 
 /* Solve from the guess in v (device float[n*n], overwritten) with the active-tile method: the
  * grid is cut into tiles (opts->tile_shape); a pass iterates each selected tile in LDS against its frozen
- * halo until no node moves by more than tol/2, commits, and flags the tile and its neighbours
- * when it moved by more than tol/2. The first pass takes every tile; with SLHJB_ORDER_KEYS a
+ * halo until no node moves by more than tol/2, writes it back (every tile of a pass reads the
+ * values from before the pass; the library keeps a second n*n array for that), and flags the tile
+ * and its neighbours when it moved by more than tol/2. The first pass takes every tile; with SLHJB_ORDER_KEYS a
  * pass takes only the flagged tiles whose key (minimum arrival time -ln(1 - v/V*)/lambda of the
  * start over the tile's FREE nodes, V* = l/lambda) is within key_slack of the smallest flagged
  * key: the nodes are processed by increasing u_hat, as the paper prescribes, in bands of tiles.
@@ -267,8 +268,9 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
  * slhjb_solve_tiles(problems[i], v[i], tol, max_passes, opts): its own band of u_hat keys, flags,
  * band moves and check sweeps, so a converged instance's values, stats[i].sweeps (passes) and
  * node_updates are bit-for-bit those of the single-instance call. The passes of all instances
- * still iterating share four launches (selection into one work list of (instance, tile) items,
- * per-instance decisions, visits, commits), captured 16 at a time in a HIP graph and replayed
+ * still iterating share three launches (selection into one work list of (instance, tile) items,
+ * per-instance decisions, visits that write their tiles back), captured 16 at a time in a HIP
+ * graph and replayed
  * until every instance has converged or made max_passes passes (the single-instance call checks
  * max_passes only between its graph replays, so an instance that does not converge may stop a few
  * passes apart). opts: order, max_inner, key_slack, tile_shape and policy_sweeps as for

@@ -1569,7 +1569,8 @@ struct slhjb_tiles_batch {
   char* d_inst = nullptr;
   char* d_state = nullptr;
   void* d_ctl = nullptr;
-  float *d_key = nullptr, *d_tchange = nullptr, *d_outbuf = nullptr;
+  float *d_key = nullptr, *d_w2 = nullptr;  // d_w2: the instances' second arrays, instance i at tile0[i] * tw * th
+  unsigned* d_word = nullptr;                // tile words, by global tile
   uint8_t* d_flag = nullptr;
   int *d_list = nullptr, *d_tile_inst = nullptr, *d_chk_inst = nullptr;
   unsigned* d_chk_off = nullptr;
@@ -1582,14 +1583,15 @@ void tiles_batch_free(slhjb_tiles_batch& b) {
   hipStreamSynchronize(b.ctx->stream);
   if (b.exec) hipGraphExecDestroy(b.exec);
   b.exec = nullptr;
-  for (void* q : {(void*)b.d_ctrl, (void*)b.d_inst, (void*)b.d_state, b.d_ctl, (void*)b.d_key, (void*)b.d_tchange,
-                  (void*)b.d_outbuf, (void*)b.d_flag, (void*)b.d_list, (void*)b.d_tile_inst, (void*)b.d_chk_inst,
+  for (void* q : {(void*)b.d_ctrl, (void*)b.d_inst, (void*)b.d_state, b.d_ctl, (void*)b.d_key, (void*)b.d_word,
+                  (void*)b.d_w2, (void*)b.d_flag, (void*)b.d_list, (void*)b.d_tile_inst, (void*)b.d_chk_inst,
                   (void*)b.d_chk_off})
     if (q) hipFree(q);
   b.d_ctrl = nullptr;
   b.d_inst = b.d_state = nullptr;
   b.d_ctl = nullptr;
-  b.d_key = b.d_tchange = b.d_outbuf = nullptr;
+  b.d_key = b.d_w2 = nullptr;
+  b.d_word = nullptr;
   b.d_flag = nullptr;
   b.d_list = b.d_tile_inst = b.d_chk_inst = nullptr;
   b.d_chk_off = nullptr;
@@ -1714,8 +1716,8 @@ int slhjb_tiles_batch_create(slhjb_ctx* ctx, const slhjb_problem* problems, int3
   TB_TRY(hipMalloc(&b.d_state, tb_state_bytes() * count));
   TB_TRY(hipMalloc(&b.d_ctl, tb_ctl_bytes()));
   TB_TRY(hipMalloc(&b.d_key, sizeof(float) * T));
-  TB_TRY(hipMalloc(&b.d_tchange, 2 * sizeof(float) * T));
-  TB_TRY(hipMalloc(&b.d_outbuf, sizeof(float) * tn * T));
+  TB_TRY(hipMalloc(&b.d_word, sizeof(unsigned) * T));
+  TB_TRY(hipMalloc(&b.d_w2, sizeof(float) * tn * T));  // instance i's tiles * tw * th >= n * n floats
   TB_TRY(hipMalloc(&b.d_flag, T));
   TB_TRY(hipMalloc(&b.d_list, sizeof(int) * T));
   TB_TRY(hipMalloc(&b.d_tile_inst, sizeof(int) * T));
@@ -1736,8 +1738,8 @@ int slhjb_tiles_batch_create(slhjb_ctx* ctx, const slhjb_problem* problems, int3
   hipError_t ce = hipSuccess;
   for (int p = 0; p < kTilesBatchPasses && ce == hipSuccess; ++p)
     ce = launch_tb_pass(b.shape, b.d_inst, b.d_state, count, max_chunks, b.d_flag, b.d_list, b.d_tile_inst,
-                        b.d_chk_inst, b.d_chk_off, b.d_ctl, T, b.d_outbuf, b.d_tchange, b.prep[0].diffusion,
-                        b.prep[0].scheme, b.prep[0].path, p & 1, b.grid, b.lds, ctx->cap_stream);
+                        b.d_chk_inst, b.d_chk_off, b.d_ctl, b.prep[0].diffusion, b.prep[0].scheme, b.prep[0].path,
+                        p & 1, b.grid, b.lds, ctx->cap_stream);
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
   if (ce == hipSuccess && ee == hipSuccess) ce = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
@@ -1765,8 +1767,9 @@ int slhjb_tiles_batch_run(slhjb_tiles_batch* b, double tol, int64_t max_passes, 
     a.resid = nullptr;
     a.flags = nullptr;
     a.ctrl = b->d_ctrl + (size_t)kCtrlCap * i;
-    tb_fill_inst(h_inst.data() + tb_inst_bytes() * i, a, b->keyed ? b->d_key + b->tile0[i] : nullptr, b->tiles_x[i],
-                 b->tiles_y[i], b->tile0[i], b->max_inner[i], b->pe, tol_inner, act, b->window[i], (float)tol,
+    tb_fill_inst(h_inst.data() + tb_inst_bytes() * i, a, b->d_w2 + (size_t)b->tile0[i] * sh.tw * sh.th,
+                 b->d_word + b->tile0[i], b->keyed ? b->d_key + b->tile0[i] : nullptr, b->tiles_x[i], b->tiles_y[i],
+                 b->tile0[i], b->max_inner[i], b->pe, tol_inner, act, b->window[i], (float)tol,
                  (long long)max_passes);
   }
   HIP_TRY(ctx, hipMemcpyAsync(b->d_inst, h_inst.data(), h_inst.size(), hipMemcpyHostToDevice, ctx->stream));
@@ -1782,6 +1785,7 @@ int slhjb_tiles_batch_run(slhjb_tiles_batch* b, double tol, int64_t max_passes, 
                                     b->lambda[i], b->d_key + b->tile0[i], ctx->stream));
   }
   HIP_TRY(ctx, launch_fill_u8(b->d_flag, 1, b->total_tiles, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32(b->d_word, 0u, b->total_tiles, ctx->stream));  // every tile starts in v
   HIP_TRY(ctx, launch_tb_init(b->d_state, count, b->d_ctl, ctx->stream));
   int64_t replays = 0;
   // every replay advances each instance still iterating by up to kTilesBatchPasses passes; an
@@ -1794,8 +1798,12 @@ int slhjb_tiles_batch_run(slhjb_tiles_batch* b, double tol, int64_t max_passes, 
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (b->h_ctl[kTBCtlActive] == 0u) break;
   }
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
+    // the tiles last written to the second array back in v, then v from w
+    HIP_TRY(ctx, launch_tile_gather(b->v[i], b->d_w2 + (size_t)b->tile0[i] * sh.tw * sh.th, b->d_word + b->tile0[i],
+                                    b->n[i], b->shape, ctx->stream));
     HIP_TRY(ctx, launch_w_to_v(b->v[i], b->v[i], (int64_t)b->n[i] * b->n[i], b->prep[i].vstar, ctx->stream));
+  }
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
   HIP_TRY(ctx, hipEventSynchronize(ctx->ev1));
   float ms = 0.0f;

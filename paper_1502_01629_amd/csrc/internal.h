@@ -143,7 +143,10 @@ hipError_t launch_tile_gather(float* w, const float* w2, const unsigned* tile_wo
 hipError_t launch_tilectl_sum(const unsigned long long* wg_acc, int groups, void* ctl, hipStream_t s);
 // The active-tile solver over a batch of instances (tiles.hip): per-instance descriptors
 // (tb_inst_bytes each, filled by tb_fill_inst) and pass states (tb_state_bytes each), one control
-// block (tb_ctl_bytes; word kTBCtlActive = instances still iterating). A pass is four launches.
+// block (tb_ctl_bytes; word kTBCtlActive = instances still iterating). A pass is three launches.
+// Each instance has a second array w2 (n * n floats) and one word per tile, as the single-instance
+// passes (launch_tilectl_pass); the caller zeroes the words before the first pass and gathers
+// each instance with launch_tile_gather after the last.
 struct TBResult {
   unsigned done, passes, checks;
   float resid;
@@ -153,14 +156,14 @@ constexpr int kTBCtlActive = 4;
 size_t tb_inst_bytes();
 size_t tb_state_bytes();
 size_t tb_ctl_bytes();
-void tb_fill_inst(void* dst, const SweepArgs& a, const float* key, int tiles_x, int tiles_y, int tile0, int max_inner,
-                  int pe, float tol_inner, float act, float window, float tol, long long max_passes);
+void tb_fill_inst(void* dst, const SweepArgs& a, float* w2, unsigned* word, const float* key, int tiles_x,
+                  int tiles_y, int tile0, int max_inner, int pe, float tol_inner, float act, float window, float tol,
+                  long long max_passes);
 void tb_read_state(const void* src, int i, TBResult* out);
 hipError_t launch_tb_init(void* st, int count, void* ctl, hipStream_t s);
 hipError_t launch_tb_pass(int shape, const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list,
-                          const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl, int total_tiles,
-                          float* outbuf, float* tchange, int diffusion, int scheme, int path, int q, int grid,
-                          size_t lds, hipStream_t s);
+                          const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl, int diffusion, int scheme,
+                          int path, int q, int grid, size_t lds, hipStream_t s);
 hipError_t launch_tile_solve_coop(const SweepArgs& a, int shape, int diffusion, int scheme, int path, bool indep,
                                   const int16_t* label, const float* key, int* list, int tiles_x, int tiles_y,
                                   float* outbuf, float* tchange, uint8_t* flag, int max_inner, float tol_inner,

@@ -873,9 +873,17 @@ __global__ __launch_bounds__(kSelectThreads) void tilectl_select_kernel(uint8_t*
   if (on) flag[t] = 0;  // the visit may flag it again
 }
 
+// Three workgroups per CU (the grid the drivers launch) need 3 NT / 256 waves per SIMD: for the
+// 512-thread visits at most 80 VGPRs, which the general path's direct write-back exceeds unless
+// asked (86: two workgroups per CU, the eps > 0 solves 8% slower; asked, 4 VGPRs spill and they
+// are 2-3% faster than with the staged write-back). The independent mode's general visits need
+// 100-235 VGPRs and would spill heavily: they keep the compiler's own allocation.
+template <int NT, bool INDEP = false>
+constexpr int kVisitWavesPerEU = NT == 512 && !INDEP ? 6 : 1;
+
 template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, bool INDEP,
           int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
-__global__ __launch_bounds__(NT) void tilectl_visit_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kVisitWavesPerEU<NT, INDEP>))) void tilectl_visit_kernel(
     SweepArgs a, const float* __restrict__ speed, const uint8_t* __restrict__ cls, const float4* __restrict__ ctrl,
     const int16_t* __restrict__ label, const int* __restrict__ list, int tiles_x, int tiles, TileDirect D,
     uint8_t* __restrict__ flag, int max_inner, float tol_inner, float act, float window, int q,
@@ -1059,21 +1067,25 @@ hipError_t launch_tile_gather(float* w, const float* w2, const unsigned* tile_wo
 }
 
 // ---- the active-tile solver over a batch of independent instances ---------------------------
-// Every instance runs exactly its own sequence of passes (selection in its band, visits, commits,
-// band moves and check sweeps, decided from its own pass words), so its result is that of the
-// single-instance solve; the passes of all instances still iterating share four launches:
+// Every instance runs exactly its own sequence of passes (selection in its band, visits, band
+// moves and check sweeps, decided from its own pass words), so its result is that of the
+// single-instance solve; the passes of all instances still iterating share three launches:
 //   select  one workgroup per (instance, 1024 tiles): flagged tiles in the instance's band join
 //           one combined work list (per-instance counts, smallest key and flagged count kept);
+//           their flags are cleared;
 //   plan    one workgroup: per instance the decision the single-instance visit launch takes
-//           (visits, band move, check sweep, stop), the pass bookkeeping its commit launch does,
-//           and the offsets of the check sweeps' tiles after the selected ones;
+//           (visits, band move, check sweep, stop) and its pass bookkeeping, the offsets of the
+//           check sweeps' tiles after the selected ones, and the pass number;
 //   visit   the items of the pass: the selected tiles, then every tile of each instance that
-//           makes a check sweep (one iteration); item j stages into slot j;
-//   commit  the same items written back, neighbours flagged, check residuals raised.
-// Global tile g belongs to instance tile_inst[g] as its tile g - tile0; flags, keys and the list
-// are indexed by g, the staging slots by item.
+//           makes a check sweep (one iteration); each writes its tile directly (TileDirect: the
+//           instance's w and its second array, one word per tile), flags its neighbours and, in
+//           a check sweep, raises the instance's residual.
+// Global tile g belongs to instance tile_inst[g] as its tile g - tile0; flags, keys, the list and
+// the tile words are indexed by g.
 struct TBInst {
   SweepArgs a;       // w_in: the instance's iterate w; ctrl: its padded control table
+  float* w2;         // the instance's second array (n * n)
+  unsigned* word;    // its tile words (tiles)
   const float* key;  // [tiles] (u_hat order) or NULL
   int tiles_x, tiles_y, tiles, tile0;
   int max_inner, pe;
@@ -1092,7 +1104,8 @@ struct TBCtl {
   unsigned checks;    // tiles of this pass's check sweeps (after the selected ones)
   unsigned nchk;      // instances making a check sweep this pass
   unsigned active;    // instances still iterating after this pass's decisions
-  unsigned pad[3];
+  unsigned seq;       // number of the current pass (from 1), stamped into the tile words
+  unsigned pad[2];
 };
 
 __global__ void tb_init_kernel(TBState* st, int count, TBCtl* ctl) {
@@ -1101,6 +1114,7 @@ __global__ void tb_init_kernel(TBState* st, int count, TBCtl* ctl) {
     ctl->count[0] = ctl->count[1] = 0u;
     ctl->checks = ctl->nchk = 0u;
     ctl->active = (unsigned)count;
+    ctl->seq = 0u;
   }
   if (i >= count) return;
   TBState& s = st[i];
@@ -1121,7 +1135,7 @@ __global__ void tb_init_kernel(TBState* st, int count, TBCtl* ctl) {
 
 __global__ __launch_bounds__(kSelectThreads) void tb_select_kernel(const TBInst* __restrict__ inst,
                                                                    TBState* __restrict__ st,
-                                                                   const uint8_t* __restrict__ flag, int q,
+                                                                   uint8_t* __restrict__ flag, int q,
                                                                    int* __restrict__ list, TBCtl* __restrict__ ctl) {
   constexpr int W = kSelectThreads / 64;
   __shared__ unsigned s_on[W], s_fl[W];
@@ -1168,7 +1182,10 @@ __global__ __launch_bounds__(kSelectThreads) void tb_select_kernel(const TBInst*
     s_base = total ? atomicAdd(&ctl->count[q], total) : 0u;
   }
   __syncthreads();
-  if (on) list[s_base + s_on[wave] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))] = tile0 + t;
+  if (on) {
+    list[s_base + s_on[wave] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))] = tile0 + t;
+    flag[tile0 + t] = 0;  // the visit may flag it again
+  }
 }
 
 // One workgroup of 1024 threads; instance i is handled by thread i % 1024 (in order of i).
@@ -1198,7 +1215,7 @@ __global__ __launch_bounds__(1024) void tb_plan_kernel(const TBInst* __restrict_
         } else if (nf > 0u) {
           s.bound = __float_as_uint(__uint_as_float(s.kmin[q]) + I.window);  // move the band
         } else {
-          mode = 2u;  // check sweep: its commits raise resid
+          mode = 2u;  // check sweep: its visits raise resid
           s.resid = 0u;
           my_tiles += (unsigned)I.tiles;
           my_n += 1u;
@@ -1252,6 +1269,7 @@ __global__ __launch_bounds__(1024) void tb_plan_kernel(const TBInst* __restrict_
   if (threadIdx.x == 0) {
     ctl->active = s_n[0];
     ctl->count[q ^ 1] = 0u;
+    ctl->seq += 1u;
   }
 }
 
@@ -1279,18 +1297,16 @@ __device__ __forceinline__ void tb_item(int j, int cnt, const int* __restrict__ 
 }
 
 template <int TW, int TH, int SPL, int DIFF, int SCHEME, int PATH, int NT = (SPL == 1 ? kThreads : TW * TH * SPL)>
-__global__ __launch_bounds__(NT) void tb_visit_kernel(const TBInst* __restrict__ inst, TBState* __restrict__ st,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kVisitWavesPerEU<NT>))) void tb_visit_kernel(const TBInst* __restrict__ inst, TBState* __restrict__ st,
                                                       const int* __restrict__ list,
                                                       const int* __restrict__ tile_inst,
                                                       const int* __restrict__ chk_inst,
                                                       const unsigned* __restrict__ chk_off, int q,
-                                                      const TBCtl* __restrict__ ctl, int total_tiles,
-                                                      float* __restrict__ outbuf, float* __restrict__ tchange,
-                                                      uint8_t* __restrict__ flag) {
-  unsigned* tsides = reinterpret_cast<unsigned*>(tchange + total_tiles);
+                                                      const TBCtl* __restrict__ ctl, uint8_t* __restrict__ flag) {
   const int cnt = (int)ctl->count[q];
   const int items = cnt + (int)ctl->checks;
   const int nchk = (int)ctl->nchk;
+  const unsigned seq = ctl->seq;
   extern __shared__ float lds[];
   __shared__ float red[NT / 64];
   for (int j = blockIdx.x; j < items; j += gridDim.x) {
@@ -1301,42 +1317,18 @@ __global__ __launch_bounds__(NT) void tb_visit_kernel(const TBInst* __restrict__
     tid = __builtin_amdgcn_readfirstlane(tid);
     const TBInst& I = inst[i];
     const SweepArgs a = I.a;
+    const TileDirect D{const_cast<float*>(a.w_in), I.w2, I.word, I.tiles_y};
     unsigned long long acc = 0ull, pe_acc = 0ull;
-    visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, false>(a, a.w_in, a.speed, a.cls, a.ctrl, nullptr, j, tid, I.tiles_x,
-                                                      outbuf, tchange, flag + I.tile0,
-                                                      check ? 1 : I.max_inner, check ? 0.0f : I.tol_inner, I.act,
-                                                      tsides, acc, lds, red, check ? 0 : I.pe, pe_acc);
+    float tmax = 0.0f;
+    visit_tile<TW, TH, SPL, DIFF, SCHEME, PATH, false, true>(
+        a, nullptr, a.speed, a.cls, a.ctrl, nullptr, j, tid, I.tiles_x, nullptr, nullptr, flag + I.tile0,
+        check ? 1 : I.max_inner, check ? 0.0f : I.tol_inner, I.act, nullptr, acc, lds, red, check ? 0 : I.pe, pe_acc,
+        D, seq, &tmax);
     if (threadIdx.x == 0) {
       if (acc) atomicAdd(&st[i].updates, acc);
       if (pe_acc) atomicAdd(&st[i].pe_updates, pe_acc);
+      if (check && tmax > 0.0f) atomicMax(&st[i].resid, __float_as_uint(tmax));
     }
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void tb_commit_kernel(const TBInst* __restrict__ inst,
-                                                             TBState* __restrict__ st, const int* __restrict__ list,
-                                                             const int* __restrict__ tile_inst,
-                                                             const int* __restrict__ chk_inst,
-                                                             const unsigned* __restrict__ chk_off, int q,
-                                                             const TBCtl* __restrict__ ctl, int total_tiles, int tw,
-                                                             int th, const float* __restrict__ outbuf,
-                                                             const float* __restrict__ tchange,
-                                                             uint8_t* __restrict__ flag) {
-  const unsigned* tsides = reinterpret_cast<const unsigned*>(tchange + total_tiles);
-  const int cnt = (int)ctl->count[q];
-  const int items = cnt + (int)ctl->checks;
-  const int nchk = (int)ctl->nchk;
-  for (int j = blockIdx.x; j < items; j += gridDim.x) {
-    int i, tid;
-    bool check;
-    tb_item(j, cnt, list, tile_inst, inst, chk_inst, chk_off, nchk, i, tid, check);
-    i = __builtin_amdgcn_readfirstlane(i);
-    tid = __builtin_amdgcn_readfirstlane(tid);
-    const TBInst& I = inst[i];
-    float tmax = 0.0f;
-    commit_tile(j, tid, tw, th, I.tiles_x, I.tiles_y, I.a.n, outbuf, tchange[j], tsides[j], I.act, I.a.cls,
-                const_cast<float*>(I.a.w_in), flag + I.tile0, tmax);
-    if (check && threadIdx.x == 0 && tmax > 0.0f) atomicMax(&st[i].resid, __float_as_uint(tmax));
   }
 }
 
@@ -1344,11 +1336,14 @@ size_t tb_inst_bytes() { return sizeof(TBInst); }
 size_t tb_state_bytes() { return sizeof(TBState); }
 size_t tb_ctl_bytes() { return sizeof(TBCtl); }
 
-void tb_fill_inst(void* dst, const SweepArgs& a, const float* key, int tiles_x, int tiles_y, int tile0, int max_inner,
-                  int pe, float tol_inner, float act, float window, float tol, long long max_passes) {
+void tb_fill_inst(void* dst, const SweepArgs& a, float* w2, unsigned* word, const float* key, int tiles_x,
+                  int tiles_y, int tile0, int max_inner, int pe, float tol_inner, float act, float window, float tol,
+                  long long max_passes) {
   TBInst I;
   memset(&I, 0, sizeof(I));
   I.a = a;
+  I.w2 = w2;
+  I.word = word;
   I.key = key;
   I.tiles_x = tiles_x;
   I.tiles_y = tiles_y;
@@ -1381,8 +1376,8 @@ hipError_t launch_tb_init(void* st, int count, void* ctl, hipStream_t s) {
 }
 
 template <int TW, int TH, int SPL>
-static hipError_t launch_tb_pass_shape(const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list, const int* tile_inst, int* chk_inst,
-                                       unsigned* chk_off, void* ctl, int total_tiles, float* outbuf, float* tchange,
+static hipError_t launch_tb_pass_shape(const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list,
+                                       const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl,
                                        int diffusion, int scheme, int path, int q, int grid, size_t lds,
                                        hipStream_t s) {
   const TBInst* I = (const TBInst*)inst;
@@ -1393,8 +1388,7 @@ static hipError_t launch_tb_pass_shape(const void* inst, void* st, int count, in
   tb_plan_kernel<<<1, 1024, 0, s>>>(I, S, count, q, chk_inst, chk_off, C);
   constexpr int NT = SPL == 1 ? kThreads : TW * TH * SPL;
 #define SLHJB_TBV(D, SC, PA)                                                                                   \
-  tb_visit_kernel<TW, TH, SPL, D, SC, PA><<<grid, NT, lds, s>>>(I, S, list, tile_inst, chk_inst, chk_off, q, C,  \
-                                                                total_tiles, outbuf, tchange, flag)
+  tb_visit_kernel<TW, TH, SPL, D, SC, PA><<<grid, NT, lds, s>>>(I, S, list, tile_inst, chk_inst, chk_off, q, C, flag)
 #define SLHJB_TBV_S(D, PA)             \
   do {                                 \
     if (scheme == kSL2) SLHJB_TBV(D, kSL2, PA); \
@@ -1407,20 +1401,16 @@ static hipError_t launch_tb_pass_shape(const void* inst, void* st, int count, in
   else SLHJB_TBV_S(kDiffRank1, 0);
 #undef SLHJB_TBV_S
 #undef SLHJB_TBV
-  tb_commit_kernel<<<grid, kThreads, 0, s>>>(I, S, list, tile_inst, chk_inst, chk_off, q, C, total_tiles, TW, TH,
-                                             outbuf, tchange, flag);
   return hipGetLastError();
 }
 
 hipError_t launch_tb_pass(int shape, const void* inst, void* st, int count, int max_chunks, uint8_t* flag, int* list,
-                          const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl, int total_tiles,
-                          float* outbuf, float* tchange, int diffusion, int scheme, int path, int q, int grid,
-                          size_t lds, hipStream_t s) {
+                          const int* tile_inst, int* chk_inst, unsigned* chk_off, void* ctl, int diffusion, int scheme,
+                          int path, int q, int grid, size_t lds, hipStream_t s) {
   if (count < 1 || count > 4096 || grid < 1 || max_chunks < 1) return hipErrorInvalidValue;
-#define SLHJB_TB_CALL(TW, TH, SPL)                                                                              \
-  return launch_tb_pass_shape<TW, TH, SPL>(inst, st, count, max_chunks, flag, list, tile_inst, chk_inst, \
-                                           chk_off, ctl, total_tiles, outbuf, tchange, diffusion, scheme, path, q, \
-                                           grid, lds, s)
+#define SLHJB_TB_CALL(TW, TH, SPL)                                                                                \
+  return launch_tb_pass_shape<TW, TH, SPL>(inst, st, count, max_chunks, flag, list, tile_inst, chk_inst, chk_off, \
+                                           ctl, diffusion, scheme, path, q, grid, lds, s)
   SLHJB_FOR_SHAPE(shape, SLHJB_TB_CALL)
 #undef SLHJB_TB_CALL
 }

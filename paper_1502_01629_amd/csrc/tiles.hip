@@ -5,12 +5,12 @@
 // its tile and an interpolation halo in LDS and runs Jacobi iterations of the scheme on the
 // tile's FREE nodes, with the halo frozen, until no node moves by more than tol_inner (or
 // max_inner iterations). Every tile of a pass reads the iterate as it was before the pass, so the
-// outcome does not depend on scheduling. The host-driven passes keep the iterate in two arrays:
-// a visit writes its tile into the array that does not hold the tile's current values and
-// flags, for the next pass, each of the 8 neighbours whose halo holds a node that moved by more
-// than the activation threshold (the tile's strip of the dependence radius on that side), and the
-// tile itself when its visit stopped unsettled. The cooperative and batched drivers stage the
-// results instead and write them back, and flag, in a commit step. The next pass takes the flagged tiles; with keys
+// outcome does not depend on scheduling. The graph-driven and batched passes keep the iterate in
+// two arrays: a visit writes its tile into the array that does not hold the tile's current values
+// and flags, for the next pass, each of the 8 neighbours whose halo holds a node that moved by
+// more than the activation threshold (the tile's strip of the dependence radius on that side), and
+// the tile itself when its visit stopped unsettled. The cooperative driver stages the results
+// instead and writes them back, and flags, in a commit step. The next pass takes the flagged tiles; with keys
 // (the arrival time of u_hat, min over the tile) only a band of them: those whose key is within
 // a window of the smallest flagged key. That is the order "by increasing u_hat" of the paper at
 // tile granularity, bucketed so that a whole ring of tiles runs at once, and it keeps tiles
@@ -45,7 +45,7 @@ __device__ __forceinline__ int dependence_radius(const SweepArgs& a) {
   return PATH == 1 ? 1 : a.halo;
 }
 
-// Direct write-back (host-driven passes). The iterate lives in two n x n arrays; word[t] holds
+// Direct write-back (graph-driven and batched passes). The iterate lives in two n x n arrays; word[t] holds
 // (p << 1) | a, where a names the array with tile t's current values and p the pass that wrote
 // them there. A visit in pass `seq` reads every node from the array that held it before the pass:
 // a word already stamped with `seq` belongs to a tile written in this pass, whose earlier values
@@ -303,7 +303,8 @@ __device__ __forceinline__ void visit_tile_split(const SweepArgs& a, const float
   __syncthreads();
 }
 
-// One visit of tile `tid`, staged into slot `slot` of outbuf/tchange: Jacobi iterations in LDS
+// One visit of tile `tid`, written directly (DIRECT) or staged into slot `slot` of outbuf/tchange:
+// Jacobi iterations in LDS
 // against the frozen halo until no node moves by more than tol_inner (or max_inner).
 template <int TW, int TH, int S, int DIFF, int SCHEME, int PATH, bool INDEP, bool DIRECT = false>
 __device__ __forceinline__ void visit_tile(const SweepArgs& a, const float* __restrict__ w,

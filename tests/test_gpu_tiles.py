@@ -121,8 +121,10 @@ def test_tiles_independent_patches_match_oracle(ctx, layout, shape):
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_persistent_and_host_driven_agree_bit_for_bit(ctx, order, shape):
-    """Both drivers read the previous pass's iterate in every visit and commit after all visits, so the
-    result does not depend on which workgroup visits which tile, nor on the driver."""
+    """Both drivers read the previous pass's iterate in every visit (the host-driven passes write
+    each tile to the other of two arrays, the cooperative kernel stages and commits after all
+    visits), so the result does not depend on which workgroup visits which tile, nor on the
+    driver."""
     from paper_1502_01629_amd import capi
 
     fine, coarse = I.scattered_problem(2, n=257, n_coarse=65)
@@ -138,6 +140,37 @@ def test_persistent_and_host_driven_agree_bit_for_bit(ctx, order, shape):
         out.append((v.cpu().numpy(), st["sweeps"], st["node_updates"]))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("eps,shape,pe", [(0.0, 4, 16), (0.008, 4, 8), (0.0, 1, 0)])
+@pytest.mark.parametrize("max_passes", [5, 37])
+def test_stopped_solve_matches_the_cooperative_driver(ctx, order, eps, shape, pe, max_passes):
+    """A solve stopped at max_passes before it converged. The batched driver (one instance) and the
+    cooperative driver both stop after exactly max_passes passes that did work; the first writes
+    tiles to the other of two arrays and gathers the ones left there at the end, the second
+    stages and commits after every pass. Their iterates must agree bit for bit, so the gather of
+    an unfinished solve is checked too."""
+    from paper_1502_01629_amd import capi
+
+    fine, coarse = I.scattered_problem(2, n=257, n_coarse=65, eps=eps)
+    dp = capi.DeviceProblem(fine, 1)
+    start = _uhat(fine, coarse) if order == 1 else fine.initial()
+    print(f"stopped solve order={order} eps={eps} shape={shape} pe={pe} max_passes={max_passes}", flush=True)
+    v_b = _dev(start)
+    stats, tot = ctx.solve_tiles_batch([dp], [v_b], tol=1e-9, max_passes=max_passes, order=order,
+                                       tile_shape=shape, policy_sweeps=pe)
+    v_c = _dev(start)
+    st = ctx.solve_tiles(dp, v_c, tol=1e-9, max_passes=max_passes, order=order, tile_shape=shape,
+                         policy_sweeps=pe, persistent=1)
+    # (the 16 x 16 one-node-per-lane tiles in plain order reach an exact FP32 fixed point within 37
+    # passes: then both drivers must have stopped at the same converged pass)
+    assert (tot["converged"] == 1) == (st["status"] == 0)
+    assert stats[0]["sweeps"] == st["sweeps"]
+    assert st["status"] == 0 or st["sweeps"] == max_passes
+    assert stats[0]["node_updates"] == st["node_updates"]
+    assert torch.equal(v_b, v_c)
+    assert not torch.equal(v_b, _dev(start))  # the passes did change the iterate
 
 
 @pytest.mark.parametrize("shape", [2, 4])

@@ -278,7 +278,8 @@ int slhjb_solve_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t cou
  * otherwise); collect_kernel_time is ignored. stats (nullable): slhjb_stats[count] (seconds = the
  * whole call); total (nullable): sweeps = passes over all instances, node_updates, replays,
  * seconds, converged. Returns SLHJB_OK if every instance converged, SLHJB_NOT_CONVERGED otherwise.
- * Needs device memory for the tile staging of all instances. Synchronises. */
+ * Needs device memory for a second copy of every instance's iterate (tiles * tile nodes floats per
+ * instance) and per-tile state. Synchronises. */
 int slhjb_solve_tiles_batch(slhjb_ctx* ctx, const slhjb_problem* problems, int32_t count, float* const* v,
                             double tol, int64_t max_passes, const slhjb_tile_opts* opts, slhjb_stats* stats,
                             slhjb_batch_stats* total);
